@@ -1,0 +1,270 @@
+"""Pins of the oracle's Haar prior, CG prox, power iteration, preconditioners,
+HQS/PGD loops and metrics against closed forms, dense linear algebra and the
+fixed-point characterisation of Proposition 1 (Sec. 3.3)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ndft, solver, wavelet, metrics
+
+
+# ----------------------------------------------------------------- Haar
+def test_haar_one_level_known_values():
+    x = np.array([[1.0, 3.0], [5.0, 7.0]])
+    c = wavelet.haar_forward(x, 1)
+    # 2x2 orthonormal Haar: approx = sum/2, then the three detail bands
+    assert np.allclose(c, [[8.0, -2.0], [-4.0, 0.0]])
+    v = np.array([[2.0, 4.0, 6.0, 8.0]] * 4)
+    c = wavelet.haar_forward(v, 2)
+    assert abs(c[0, 0] - v.sum() / 4) < 1e-14          # coarsest approx = sum / 2^J (2D)
+
+
+@pytest.mark.parametrize("shape,J", [((64, 64), 3), ((48, 80), 4), ((16, 16, 32), 4)])
+def test_haar_perfect_reconstruction_and_energy(shape, J):
+    x = synth.white_complex(shape, 30).astype(np.complex128)
+    c = wavelet.haar_forward(x, J)
+    assert abs(np.linalg.norm(c) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+    assert np.max(np.abs(wavelet.haar_inverse(c, J) - x)) < 1e-13
+
+
+def test_haar_matches_block_averages():
+    # approximation band after J levels = block sums / 2^J for 2^J x 2^J blocks
+    x = synth.white_complex((32, 32), 31).astype(np.complex128)
+    J = 3
+    c = wavelet.haar_forward(x, J)
+    blocks = x.reshape(4, 8, 4, 8).sum(axis=(1, 3)) / 2 ** J
+    assert np.allclose(c[:4, :4], blocks, atol=1e-13)
+
+
+def test_soft_threshold_is_l1_prox():
+    rng = np.random.default_rng(0)
+    tau = 0.3
+    for _ in range(20):
+        c = complex(*rng.normal(size=2))
+        s = wavelet.soft_threshold(np.array([c]), tau)[0]
+        # brute-force argmin_v tau|v| + 1/2|c - v|^2 over a fine grid around c
+        g = np.linspace(-3, 3, 1201)
+        V = g[:, None] + 1j * g[None, :]
+        obj = tau * np.abs(V) + 0.5 * np.abs(c - V) ** 2
+        vb = V.ravel()[np.argmin(obj)]
+        assert abs(s - vb) < 6e-3
+        # subgradient optimality: c - s in tau * d|s|
+        if s != 0:
+            assert abs((c - s) - tau * s / abs(s)) < 1e-12
+        else:
+            assert abs(c) <= tau
+
+
+def test_wavelet_prior_special_cases():
+    x = synth.white_complex((32, 32), 32).astype(np.complex128)
+    assert np.max(np.abs(wavelet.wavelet_denoise(x, 0.0, 2) - x)) < 1e-13
+    # huge threshold: only the approximation band survives = block means
+    y = wavelet.wavelet_denoise(x, 1e9, 2)
+    means = x.reshape(8, 4, 8, 4).mean(axis=(1, 3))
+    assert np.allclose(y, np.kron(means, np.ones((4, 4))), atol=1e-13)
+
+
+def test_wavelet_prior_is_prox_of_detail_l1():
+    # D(u) minimises tau*||detail(Hv)||_1 + 1/2||u - v||^2: random perturbations never do better
+    u = synth.white_complex((16, 16), 33).astype(np.complex128)
+    tau, J = 0.4, 2
+    v = wavelet.wavelet_denoise(u, tau, J)
+    f = lambda z: tau * wavelet.l1_detail(z, J) + 0.5 * np.linalg.norm(u - z) ** 2
+    f0 = f(v)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        d = (rng.normal(size=u.shape) + 1j * rng.normal(size=u.shape)) * 1e-3
+        assert f(v + d) >= f0 - 1e-12
+
+
+def test_default_levels():
+    assert wavelet.default_levels(64) == 3
+    assert wavelet.default_levels(320) == 4
+    assert wavelet.default_levels(128) == 4
+
+
+# ------------------------------------------------------------ operators
+def _tiny_problem(n=8, L=2, M=40, seed=40):
+    rng = np.random.default_rng(seed)
+    k = rng.uniform(-math.pi, math.pi, (M, 2)).astype(np.float32)
+    S = synth.smaps2d(n, L)
+    w = rng.uniform(0.5, 1.5, M)
+    A = ndft.dense_matrix((n, n), S, k)
+    Wd = np.kron(np.eye(L), np.diag(w))
+    Nmat = A.conj().T @ Wd @ A
+    normal = lambda v: ndft.normal(v, S, k, w)
+    return k, S, w, A, Nmat, normal
+
+
+def test_power_iteration_equals_max_eigenvalue():
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    lam, its = solver.opnorm(normal, (8, 8), seed=3, tol=1e-13, maxit=5000)
+    ev = np.linalg.eigvalsh(Nmat)
+    assert abs(lam - ev[-1]) < 1e-9 * ev[-1]
+    assert ev[0] > -1e-12          # PSD
+
+
+def test_normal_operator_hermitian_psd():
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    x = synth.white_complex((8, 8), 41)
+    q = np.vdot(x.astype(np.complex128), normal(x))
+    assert q.real > 0 and abs(q.imag) < 1e-12 * q.real
+    assert np.allclose(Nmat, Nmat.conj().T, atol=1e-13)
+
+
+@pytest.mark.parametrize("name,c0,c1,tmax_p", [("f1", 2.0, 1.0, 1.0), ("cheb", 4.0, 10 / 3, 1.2)])
+def test_preconditioner_polynomials(name, c0, c1, tmax_p):
+    assert solver.precond_coeffs(name) == (c0, c1)
+    t = np.linspace(1e-6, 1, 10001)
+    p = solver.precond_poly(name, t)
+    tp = t * p
+    assert tp.min() > 0 and tp.max() <= tmax_p + 1e-12
+    assert p.min() >= (1.0 if name == "f1" else 2.0 / 3.0) - 1e-12     # P is positive definite
+    # design rule: the spectral radius of Id - alpha P A^H A over a spectrum
+    # [t0, 1] is smaller than with P = Id
+    for t0 in (0.01, 0.05, 0.2):
+        sel = t >= t0
+        assert np.abs(1 - tp[sel]).max() < np.abs(1 - t[sel]).max()
+    if name == "f1":
+        assert np.allclose(1 - tp, (1 - t) ** 2)
+
+
+@pytest.mark.parametrize("precond", ["id", "f1", "cheb"])
+def test_cg_prox_converges_to_dense_solve(precond):
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    Lnorm = np.linalg.eigvalsh(Nmat)[-1]
+    c0, c1 = solver.precond_coeffs(precond)
+    P = c0 * np.eye(64) - c1 / Lnorm * Nmat
+    x = synth.white_complex((8, 8), 42).astype(np.complex128)
+    y = synth.white_complex((2, 40), 43).astype(np.complex128)
+    b0 = ndft.adjoint(y, S, k, w)
+    gamma = 0.7
+    u = solver.cg_prox(x, b0, gamma, normal, c0, c1 / Lnorm, n_cg=200)
+    # u = argmin gamma f_w(u) + 1/2 ||x - u||_P^2  <=>  (gamma N + P) u = P x + gamma b0
+    u_ref = np.linalg.solve(gamma * Nmat + P, P @ x.ravel() + gamma * b0.ravel())
+    assert np.max(np.abs(u.ravel() - u_ref)) < 1e-10
+    # stationarity of the prox objective
+    g = gamma * (A.conj().T @ (np.kron(np.eye(2), np.diag(w)) @ (A @ u.ravel() - y.ravel()))) + P @ (u.ravel() - x.ravel())
+    assert np.linalg.norm(g) < 1e-9
+
+
+@pytest.mark.parametrize("precond,c0p", [("id", 1.0), ("f1", 1.0), ("cheb", 2.0 / 3.0)])
+def test_cg_prox_closed_form_identity_normal(precond, c0p):
+    """Full Cartesian sampling with SoS-1 maps gives A^H A = I, ||N|| = 1, so
+    P = c0' I and the prox has the closed form (c0' x + gamma b0)/(gamma + c0'),
+    reached by one CG step."""
+    n = 8
+    S = synth.smaps2d(n, 3).astype(np.complex128)
+    S /= np.sqrt((np.abs(S) ** 2).sum(0))
+    k = synth.cartesian2d(n, np.float64)
+    normal = lambda v: ndft.normal(v, S, k)
+    x = synth.white_complex((n, n), 44).astype(np.complex128)
+    b0 = synth.white_complex((n, n), 45).astype(np.complex128)
+    c0, c1 = solver.precond_coeffs(precond)
+    gamma = 0.37
+    u = solver.cg_prox(x, b0, gamma, normal, c0, c1 * 1.0, n_cg=1)
+    assert np.max(np.abs(u - (c0p * x + gamma * b0) / (gamma + c0p))) < 1e-12
+
+
+def test_dc_residual_two_forms():
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    x = synth.white_complex((8, 8), 46).astype(np.complex128)
+    y = synth.white_complex((2, 40), 47).astype(np.complex128)
+    b0 = ndft.adjoint(y, S, k, w)
+    yw2 = float((w[None] * np.abs(y) ** 2).sum())
+    r_direct = float((w[None] * np.abs(ndft.forward(x, S, k) - y) ** 2).sum())
+    r_fast = solver.dc_residual(x, normal(x), b0, yw2)
+    assert abs(r_direct - r_fast) < 1e-12 * r_direct
+
+
+def test_hqs_identity_prior_is_proximal_point_to_least_squares():
+    """P = Id and D = identity: HQS is the proximal-point method on f, whose
+    iterates approach a least-squares solution (textbook)."""
+    k, S, w, A, Nmat, normal = _tiny_problem(M=120)
+    y = synth.white_complex((2, 120), 48).astype(np.complex128)
+    b0 = ndft.adjoint(y, S, k, w)
+    x = solver.hqs(b0, normal, [1.0] * 60, lam=5.0, precond="id", n_cg=300,
+                   prior=lambda u, s: u, opnorm_value=np.linalg.eigvalsh(Nmat)[-1])
+    x_ls = np.linalg.lstsq(Nmat, b0.ravel(), rcond=None)[0]
+    assert np.linalg.norm(Nmat @ x.ravel() - b0.ravel()) < 1e-8 * np.linalg.norm(b0)
+    assert np.linalg.norm(x.ravel() - x_ls) < 1e-6 * np.linalg.norm(x_ls)
+
+
+def test_proposition1_fixed_points():
+    """Proposition 1 with D = prox_g (g = tau * l1 of Haar details, convex),
+    P = Id, constant gamma and sigma:
+    * HQS's u-iterate converges to argmin gamma f + (Moreau envelope of g),
+      i.e. gamma grad f(u*) + u* - prox_g(u*) = 0;
+    * PnP-PGD converges to argmin gamma f + g, i.e. x* = prox_g(x* - gamma grad f(x*))."""
+    n = 8
+    rng = np.random.default_rng(49)
+    M = 200          # 400 equations for 64 unknowns: f is strongly convex
+    k = rng.uniform(-math.pi, math.pi, (M, 2))
+    S = synth.smaps2d(n, 2)
+    normal = lambda v: ndft.normal(v, S, k)
+    xt, _ = synth.phantom2d(n, 5)
+    y = ndft.forward(xt, S, k) + synth.complex_noise((2, M), 1e-4, 6)
+    b0 = ndft.adjoint(y, S, k)
+    Ln, _ = solver.opnorm(normal, (n, n), tol=1e-12)
+    tau = 0.02
+    prox_g = lambda v, s: wavelet.wavelet_denoise(v, tau, 2)
+    gamma = 1.0 / Ln
+    rep = solver.HQSReport()
+    solver.hqs(b0, normal, [1.0] * 200, lam=gamma, precond="id", n_cg=70, prior=prox_g,
+               opnorm_value=Ln, report=rep)
+    u = rep.u_last
+    res = gamma * (normal(u) - b0) + u - prox_g(u, 1.0)
+    assert np.linalg.norm(res) < 1e-10 * np.linalg.norm(u)
+    # PGD fixed point (step gamma < 2/L)
+    x = solver.pgd(b0, normal, b0, gamma, 300, prox_g, 1.0)
+    fp = prox_g(x - gamma * (normal(x) - b0), 1.0)
+    assert np.linalg.norm(fp - x) < 1e-10 * np.linalg.norm(x)
+    # and the two limits differ (the paper's point)
+    assert np.linalg.norm(prox_g(u, 1.0) - x) > 1e-6 * np.linalg.norm(x)
+
+
+def test_hqs_fallback_on_bad_prior():
+    """A prior that returns garbage raises the residual; the fallback
+    (wavelet) takes over and the final result equals the all-wavelet run."""
+    k, S, w, A, Nmat, normal = _tiny_problem(M=100)
+    y = synth.white_complex((2, 100), 50).astype(np.complex128)
+    b0 = ndft.adjoint(y, S, k, w)
+    yw2 = float((w[None] * np.abs(y) ** 2).sum())
+    Ln = np.linalg.eigvalsh(Nmat)[-1]
+    wav = lambda u, s: wavelet.wavelet_denoise(u, 0.1 * s, 1)
+    bad = lambda u, s: u * 0 + np.nan
+    sig = synth.geometric_sigmas(0.1, 0.01, 6)
+    rep = solver.HQSReport()
+    xa = solver.hqs(b0, normal, sig, 3.0, "f1", 3, bad, Ln, yw2=yw2, fallback=wav, rise_tol=0.5, report=rep)
+    xb = solver.hqs(b0, normal, sig, 3.0, "f1", 3, wav, Ln, yw2=yw2)
+    assert all(rep.fallback)
+    assert np.max(np.abs(xa - xb)) < 1e-13
+
+
+def test_geometric_schedule():
+    s = synth.geometric_sigmas(0.1, 0.005, 30)
+    assert abs(s[0] - 0.1) < 1e-15 and abs(s[-1] - 0.005) < 1e-15
+    assert abs(s[1] / s[0] - 0.90186) < 1e-5
+
+
+# -------------------------------------------------------------- metrics
+def test_psnr_constant_offset():
+    x = np.ones((16, 16)) * 0.8
+    xh = x + 0.01
+    roi = np.ones_like(x, dtype=bool)
+    assert abs(metrics.psnr(xh, x, roi) - 20 * math.log10(0.8 / 0.01)) < 1e-9
+    roi[:8] = False
+    assert abs(metrics.psnr(xh, x, roi) - 20 * math.log10(0.8 / 0.01)) < 1e-9
+
+
+def test_ssim_identical_and_constant():
+    x, _ = synth.phantom2d(32, 3)
+    assert abs(metrics.ssim(x, x) - 1) < 1e-12
+    a = np.full((20, 20), 0.5)
+    b = np.full((20, 20), 1.0)
+    # constant images: variances 0 -> SSIM = luminance term (2ab + C1)/(a^2 + b^2 + C1)
+    C1 = (0.01 * 1.0) ** 2
+    exp = (2 * 0.5 * 1.0 + C1) / (0.25 + 1.0 + C1)
+    assert abs(metrics.ssim(a, b) - exp) < 1e-12
