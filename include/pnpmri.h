@@ -1,0 +1,195 @@
+/*
+ * pnpmri.h -- C ABI of the MI355X (gfx950) non-Cartesian MRI PnP-HQS library.
+ *
+ * The library computes the multicoil non-Cartesian forward model of the
+ * paper "Robust Plug-and-Play Methods for Highly Accelerated Non-Cartesian
+ * MRI Reconstruction" (Sec. 2.1, Eq. 1: y_l = F_Omega S_l x + e_l), its
+ * adjoint, the normal operator of the (density-weighted) data term
+ * (Sec. 2.2), the F-1 / Chebyshev / identity preconditioned proximal step
+ * solved by conjugate gradients (Sec. 3.4) and the annealed PnP-HQS loop
+ * (Sec. 3.3) with a Haar soft-threshold prior.
+ *
+ * Conventions (every entry point)
+ *   - Complex data is complex64, interleaved (re, im): pnp_c64, the same
+ *     memory layout as torch.complex64.
+ *   - Images are row-major with x fastest: [ny][nx] or [nz][ny][nx].  The
+ *     shape arrays below list the sizes SLOWEST FIRST (ny, nx) / (nz, ny, nx).
+ *     Pixel index i along an axis of size n is the centred coordinate
+ *     r = i - n/2.
+ *   - Coil maps are [L][image]; k-space data is [L][M] (coil-major).
+ *   - The trajectory is float32 [M][d] ordered (kx, ky[, kz]) in radians per
+ *     pixel; the operator is 2*pi periodic in k, any finite value is valid.
+ *   - Forward operator:  y_l[m] = N^{-1/2} sum_r S_l[r] x[r] exp(-i <k_m, r>)
+ *     Adjoint with DCF:  x[r]  = N^{-1/2} sum_l conj(S_l[r]) sum_m w_m y_l[m] exp(+i <k_m, r>)
+ *     (orthonormal scaling; w = 1 when dcf is NULL).  Both are evaluated by
+ *     Kaiser-Bessel gridding (kernel width 6, oversampling 2, Beatty's beta)
+ *     in FP32 with FP64-tabulated coordinates, kernel weights, twiddles and
+ *     deapodisation; the relative L2 error against the exact NDFT is about
+ *     1e-5 (KB alias error plus FP32 rounding).
+ *   - Every pointer argument named *_dev / data array is DEVICE memory owned
+ *     by the caller, unless marked "host".  The library never frees or keeps
+ *     caller memory beyond the call.  Opaque handles (pnp_plan, pnp_prior)
+ *     own their own device allocations, released by the matching destroy.
+ *   - Every compute call is asynchronous on the given HIP stream and enqueues
+ *     nothing when it returns an error.  Calls that return host scalars
+ *     (pnp_opnorm, pnp_hqs_solve with a report or a computed norm) wait for
+ *     the stream before returning.
+ *   - Workspace: the caller passes device scratch memory of at least the
+ *     size the matching *_workspace_bytes query reports (256-byte aligned).
+ *   - Errors: every call returns a pnp_status; pnp_last_error() gives a
+ *     message for the calling thread's last failure.  Arguments are checked
+ *     before anything is enqueued; no C++ exception crosses this ABI.
+ *   - Calls on one plan from several streams at once must use separate
+ *     workspaces; a plan itself is read-only after creation.
+ */
+#ifndef PNPMRI_H
+#define PNPMRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } pnp_c64;
+
+typedef int32_t pnp_status;
+#define PNP_OK                 0
+#define PNP_ERR_ARG           -1   /* NULL pointer or invalid scalar argument  */
+#define PNP_ERR_SHAPE         -2   /* unsupported or inconsistent sizes        */
+#define PNP_ERR_UNSUPPORTED   -3   /* valid request this build cannot serve    */
+#define PNP_ERR_DEVICE        -4   /* HIP runtime error (text in last_error)   */
+#define PNP_ERR_WORKSPACE     -5   /* workspace smaller than required          */
+#define PNP_ERR_NUMERIC       -6   /* non-finite input or CG/norm breakdown    */
+
+#define PNP_PRECOND_ID    0        /* P = Id                                  */
+#define PNP_PRECOND_F1    1        /* P = 2 - alpha A^H D_w A                 */
+#define PNP_PRECOND_CHEB  2        /* P = 4 - (10/3) alpha A^H D_w A          */
+
+/* Message describing the calling thread's most recent failure ("" if none).
+ * Valid until the thread's next call into the library. */
+const char* pnp_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t pnp_version(void);
+
+/* ------------------------------------------------------------------ plan */
+typedef struct pnp_plan pnp_plan;
+
+/* Plan the gridded operator for one trajectory (Sec. 2.1: F_Omega depends
+ * only on the sampling trajectory Omega, so it is planned once and reused by
+ * every coil, iteration and slice with that trajectory).
+ *   out      host: receives the new handle
+ *   ndim     2 or 3
+ *   shape    host int32[ndim], slowest first; every size even, 4..1024, and
+ *            2*size may only have prime factors 2, 3 and 5
+ *   M        number of samples (>= 1)
+ *   traj     device float32 [M][ndim], (kx, ky[, kz]) radians per pixel,
+ *            all finite (checked; PNP_ERR_NUMERIC otherwise)
+ *   stream   stream the set-up kernels run on; the call waits for it.
+ * Set-up converts the coordinates to grid units in FP64, tabulates the
+ * 6 kernel weights per sample and axis, bins samples into oversampled-grid
+ * tiles and builds FFT twiddle and deapodisation tables. */
+pnp_status pnp_plan_create(pnp_plan** out, int32_t ndim, const int32_t* shape, int64_t M,
+                           const float* traj, hipStream_t stream);
+pnp_status pnp_plan_destroy(pnp_plan* plan);
+
+/* Plan facts (host): oversampled grid size per axis (slowest first), number
+ * of tiles and tile entries (sample-tile pairs). */
+pnp_status pnp_plan_info(const pnp_plan* plan, int32_t* grid_shape, int32_t* n_tiles,
+                         int64_t* n_entries);
+
+/* Workspace bytes needed by pnp_forward / pnp_adjoint / pnp_normal /
+ * pnp_opnorm for L coils. */
+pnp_status pnp_workspace_bytes(const pnp_plan* plan, int32_t L, size_t* bytes);
+
+/* Forward operator A (Eq. 1 without noise): y[L][M] = F_Omega S_l x.
+ *   x      device pnp_c64 [N] image;  smaps device pnp_c64 [L][N]
+ *   y      device pnp_c64 [L][M] output (fully overwritten) */
+pnp_status pnp_forward(const pnp_plan* plan, const pnp_c64* x, const pnp_c64* smaps, int32_t L,
+                       pnp_c64* y, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint with density weighting A^H D_w (Sec. 3.4 notation A^H):
+ *   y      device pnp_c64 [L][M];  dcf device float [M] or NULL (w = 1)
+ *   x      device pnp_c64 [N] output (fully overwritten) */
+pnp_status pnp_adjoint(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                       const float* dcf, pnp_c64* x, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Normal operator of the weighted data term, out = A^H D_w A x (Sec. 3.4).
+ * x and out may not alias. */
+pnp_status pnp_normal(const pnp_plan* plan, const pnp_c64* x, const pnp_c64* smaps, int32_t L,
+                      const float* dcf, pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Operator norm ||A^H D_w A||_2 by `iters` power iterations from a seeded
+ * complex Gaussian start (Sec. 3.4: alpha = 1/norm normalises the F-1 and
+ * Chebyshev preconditioners).  Norms and Rayleigh quotients in FP64.
+ *   norm_out  host double; the call waits for the stream. */
+pnp_status pnp_opnorm(const pnp_plan* plan, const pnp_c64* smaps, int32_t L, const float* dcf,
+                      int32_t iters, uint64_t seed, double* norm_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* ----------------------------------------------------------------- prior */
+typedef struct pnp_prior pnp_prior;
+
+/* Haar soft-threshold prior D_sigma(u): orthonormal Haar analysis with
+ * `levels` levels (0: min(4, floor(log2 n) - 3)), complex soft threshold
+ * c*max(0, 1 - tau/|c|) of every detail coefficient with tau = kappa*sigma,
+ * synthesis.  It is the proximal operator of tau*||details||_1 (Sec. 2.2,
+ * Eq. 3's prox definition) and the plug-in denoiser of the plain method. */
+pnp_status pnp_prior_wavelet(pnp_prior** out, int32_t levels, double kappa);
+pnp_status pnp_prior_destroy(pnp_prior* prior);
+
+/* Apply a prior once: out = D_sigma(in), image of the given shape (slowest
+ * first).  in and out may alias.  Image sides must be divisible by
+ * 2^levels. */
+pnp_status pnp_prior_apply(const pnp_prior* prior, int32_t ndim, const int32_t* shape,
+                           const pnp_c64* in, pnp_c64* out, double sigma, hipStream_t stream);
+
+/* ------------------------------------------------------------------- HQS */
+typedef struct {
+  uint32_t struct_size;      /* sizeof(pnp_hqs_opts)                          */
+  int32_t precond;           /* PNP_PRECOND_*                                 */
+  int32_t n_cg;              /* CG steps per proximal step (>= 1)             */
+  int32_t opnorm_iters;      /* power iterations when opnorm <= 0             */
+  double lambda;             /* gamma_k = lambda * sigma_k  (> 0)             */
+  double opnorm;             /* ||A^H D_w A|| if > 0, else computed           */
+  uint64_t opnorm_seed;      /* seed of the power-iteration start vector      */
+  const pnp_c64* x0;         /* device [N] start image, NULL: x0 = A^H D_w y  */
+  double rise_tol;           /* fallback when rho_k > (1+rise_tol) rho_{k-1}  */
+} pnp_hqs_opts;
+
+typedef struct {
+  uint32_t struct_size;      /* sizeof(pnp_hqs_report)                        */
+  int32_t capacity;          /* length of the host arrays below (>= n_out)    */
+  double* rho;               /* host [n_out]: ||D_w^{1/2}(A x_k - y)||^2      */
+  int32_t* fallback;         /* host [n_out]: 1 where the fallback prior ran  */
+  double opnorm_used;        /* out: the operator norm used                   */
+} pnp_hqs_report;
+
+/* Workspace bytes for pnp_hqs_solve. */
+pnp_status pnp_hqs_workspace_bytes(const pnp_plan* plan, int32_t L, size_t* bytes);
+
+/* Annealed preconditioned PnP-HQS (Sec. 3.3-3.4):
+ *   b0 = A^H D_w y;  x = x0 (or b0)
+ *   for k = 0..n_out-1:  gamma = lambda*sigma[k]
+ *       u = prox^P_{gamma f}(x) by exactly n_cg CG steps on
+ *           (gamma A^H D_w A + P) u = P x + gamma b0, started at u = x
+ *       x = D_{sigma[k]}(u)
+ * with P = c0 - c1 alpha A^H D_w A (Id: 1,0; F-1: 2,1; Chebyshev: 4,10/3),
+ * alpha = 1/opnorm.  CG inner products, step sizes and residual norms are
+ * FP64 and stay on the device (no host synchronisation inside the loop).
+ *   y       device pnp_c64 [L][M];  smaps device [L][N];  dcf device [M]|NULL
+ *   sigmas  host double [n_out] (positive)
+ *   x_out   device pnp_c64 [N]: x_{n_out}
+ *   report  host or NULL; when given the call waits for the stream. */
+pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                         const float* dcf, const pnp_prior* prior, const double* sigmas,
+                         int32_t n_out, const pnp_hqs_opts* opts, pnp_c64* x_out,
+                         pnp_hqs_report* report, void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PNPMRI_H */

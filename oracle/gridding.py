@@ -128,20 +128,29 @@ class KBGridding:
         return y
 
     def _spread(self, v):
-        H = np.zeros(self.K, dtype=np.complex128)
+        # H[j] = sum over samples and taps landing on j of weight * v (bincount
+        # accumulates the same sums as an explicit loop over taps)
+        G = int(np.prod(self.K))
+        re = np.zeros(G)
+        im = np.zeros(G)
         W = self.W
         if self.d == 2:
             for a in range(W):
                 for b in range(W):
-                    np.add.at(H, (self.idx[0][:, a], self.idx[1][:, b]),
-                              self.wts[0][:, a] * self.wts[1][:, b] * v)
+                    flat = self.idx[0][:, a] * self.K[1] + self.idx[1][:, b]
+                    c = self.wts[0][:, a] * self.wts[1][:, b] * v
+                    re += np.bincount(flat, c.real, G)
+                    im += np.bincount(flat, c.imag, G)
         else:
             for a in range(W):
                 for b in range(W):
-                    for c in range(W):
-                        np.add.at(H, (self.idx[0][:, a], self.idx[1][:, b], self.idx[2][:, c]),
-                                  self.wts[0][:, a] * self.wts[1][:, b] * self.wts[2][:, c] * v)
-        return H
+                    for cc in range(W):
+                        flat = ((self.idx[0][:, a] * self.K[1] + self.idx[1][:, b]) * self.K[2]
+                                + self.idx[2][:, cc])
+                        c = self.wts[0][:, a] * self.wts[1][:, b] * self.wts[2][:, cc] * v
+                        re += np.bincount(flat, c.real, G)
+                        im += np.bincount(flat, c.imag, G)
+        return (re + 1j * im).reshape(self.K)
 
     def forward(self, x, smaps):
         x = np.asarray(x, dtype=np.complex128)

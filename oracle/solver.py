@@ -70,6 +70,22 @@ def opnorm(normal, shape, seed: int = 0, tol: float = 1e-12, maxit: int = 1000):
     return lam, maxit
 
 
+def opnorm_lanczos(normal, shape, tol: float = 1e-10, seed: int = 0):
+    """||A^H D_w A||_2 as the largest eigenvalue of the Hermitian PSD normal
+    operator by implicitly restarted Lanczos (ARPACK through scipy), which
+    needs far fewer operator applications than power iteration when the top
+    of the spectrum is clustered."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    n = int(np.prod(shape))
+    op = LinearOperator((n, n), matvec=lambda v: np.ravel(normal(np.reshape(v, shape))),
+                        dtype=np.complex128)
+    rng = np.random.default_rng(seed)
+    v0 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    val = eigsh(op, k=1, which="LA", tol=tol, v0=v0, return_eigenvectors=False)
+    return float(val[0])
+
+
 def cg_prox(x, b0, gamma: float, normal, c0: float, c1a: float, n_cg: int,
             Nx=None, trace=None):
     """prox^P_{gamma f}(x) by exactly ``n_cg`` CG steps (fewer only if the

@@ -1,0 +1,280 @@
+// C ABI: argument validation, error reporting and dispatch.  Nothing is
+// enqueued before every argument has been checked; internal failures are
+// converted to status codes here and never cross the ABI as exceptions.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.hpp"
+
+namespace pnp {
+
+static thread_local std::string g_err;
+
+void set_error_text(const std::string& s) { g_err = s; }
+
+void fail(pnp_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  throw Failure{code};
+}
+
+void fail_hip(hipError_t e, const char* what, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what,
+           file, line);
+  g_err = buf;
+  throw Failure{PNP_ERR_DEVICE};
+}
+
+}  // namespace pnp
+
+using namespace pnp;
+
+namespace {
+
+template <class F>
+pnp_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    f();
+    return PNP_OK;
+  } catch (const Failure& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return PNP_ERR_DEVICE;
+  } catch (...) {
+    g_err = "unexpected internal error";
+    return PNP_ERR_DEVICE;
+  }
+}
+
+void need(const void* ptr, const char* name) {
+  if (!ptr) fail(PNP_ERR_ARG, "%s must not be NULL", name);
+}
+
+void check_plan_L(const pnp_plan* p, int32_t L) {
+  need(p, "plan");
+  if (L < 1) fail(PNP_ERR_SHAPE, "L must be >= 1 (got %d)", L);
+}
+
+void check_ws(size_t have, size_t need_bytes, const void* ws) {
+  if (have < need_bytes)
+    fail(PNP_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the required %zu", have, need_bytes);
+  if (((uintptr_t)ws & 255) != 0) fail(PNP_ERR_ARG, "workspace must be 256-byte aligned");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pnp_last_error(void) { return g_err.c_str(); }
+
+int32_t pnp_version(void) { return 100; }
+
+pnp_status pnp_plan_create(pnp_plan** out, int32_t ndim, const int32_t* shape, int64_t M,
+                           const float* traj, hipStream_t stream) {
+  return guarded([&] {
+    need(out, "out");
+    need(shape, "shape");
+    need(traj, "traj");
+    *out = nullptr;
+    *out = plan_create(ndim, shape, M, traj, stream);
+  });
+}
+
+pnp_status pnp_plan_destroy(pnp_plan* plan) {
+  return guarded([&] { plan_destroy(plan); });
+}
+
+pnp_status pnp_plan_info(const pnp_plan* p, int32_t* grid_shape, int32_t* n_tiles, int64_t* n_entries) {
+  return guarded([&] {
+    need(p, "plan");
+    if (grid_shape)
+      for (int a = 0; a < p->ndim; ++a) grid_shape[a] = p->ax[p->ndim - 1 - a].K;
+    if (n_tiles) *n_tiles = p->ntiles;
+    if (n_entries) *n_entries = p->E;
+  });
+}
+
+pnp_status pnp_workspace_bytes(const pnp_plan* p, int32_t L, size_t* bytes) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(bytes, "bytes");
+    *bytes = opnorm_workspace_bytes(p, L);
+  });
+}
+
+pnp_status pnp_forward(const pnp_plan* p, const pnp_c64* x, const pnp_c64* smaps, int32_t L, pnp_c64* y,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(x, "x");
+    need(smaps, "smaps");
+    need(y, "y");
+    need(ws, "ws");
+    check_ws(ws_bytes, op_workspace_bytes(p, L), ws);
+    op_forward(p, (const float2*)x, (const float2*)smaps, L, (float2*)y, op_workspace(p, L, ws), stream);
+  });
+}
+
+pnp_status pnp_adjoint(const pnp_plan* p, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                       const float* dcf, pnp_c64* x, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(y, "y");
+    need(smaps, "smaps");
+    need(x, "x");
+    need(ws, "ws");
+    check_ws(ws_bytes, op_workspace_bytes(p, L), ws);
+    op_adjoint(p, (const float2*)y, (const float2*)smaps, L, dcf, (float2*)x, op_workspace(p, L, ws),
+               stream);
+  });
+}
+
+pnp_status pnp_normal(const pnp_plan* p, const pnp_c64* x, const pnp_c64* smaps, int32_t L,
+                      const float* dcf, pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(x, "x");
+    need(smaps, "smaps");
+    need(out, "out");
+    need(ws, "ws");
+    if ((const void*)x == (const void*)out) fail(PNP_ERR_ARG, "x and out must not alias");
+    check_ws(ws_bytes, op_workspace_bytes(p, L), ws);
+    op_normal(p, (const float2*)x, (const float2*)smaps, L, dcf, (float2*)out, op_workspace(p, L, ws),
+              stream);
+  });
+}
+
+pnp_status pnp_opnorm(const pnp_plan* p, const pnp_c64* smaps, int32_t L, const float* dcf,
+                      int32_t iters, uint64_t seed, double* norm_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(smaps, "smaps");
+    need(norm_out, "norm_out");
+    need(ws, "ws");
+    if (iters < 1) fail(PNP_ERR_ARG, "iters must be >= 1");
+    check_ws(ws_bytes, opnorm_workspace_bytes(p, L), ws);
+    const double v = power_iteration(p, (const float2*)smaps, L, dcf, iters, seed, ws, stream);
+    if (!std::isfinite(v)) fail(PNP_ERR_NUMERIC, "power iteration produced a non-finite norm");
+    *norm_out = v;
+  });
+}
+
+pnp_status pnp_prior_wavelet(pnp_prior** out, int32_t levels, double kappa) {
+  return guarded([&] {
+    need(out, "out");
+    if (levels < 0 || levels > 8) fail(PNP_ERR_ARG, "levels must be in 0..8");
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) fail(PNP_ERR_ARG, "kappa must be finite and >= 0");
+    pnp_prior* p = new pnp_prior();
+    p->kind = 0;
+    p->levels = levels;
+    p->kappa = kappa;
+    *out = p;
+  });
+}
+
+pnp_status pnp_prior_destroy(pnp_prior* prior) {
+  return guarded([&] { delete prior; });
+}
+
+pnp_status pnp_prior_apply(const pnp_prior* prior, int32_t ndim, const int32_t* shape, const pnp_c64* in,
+                           pnp_c64* out, double sigma, hipStream_t stream) {
+  return guarded([&] {
+    need(prior, "prior");
+    need(shape, "shape");
+    need(in, "in");
+    need(out, "out");
+    if (ndim != 2 && ndim != 3) fail(PNP_ERR_SHAPE, "ndim must be 2 or 3");
+    if (!(sigma >= 0.0) || !std::isfinite(sigma)) fail(PNP_ERR_ARG, "sigma must be finite and >= 0");
+    int n[3] = {1, 1, 1};
+    int nmin = 1 << 30;
+    for (int a = 0; a < ndim; ++a) {
+      n[a] = shape[ndim - 1 - a];
+      if (n[a] < 2) fail(PNP_ERR_SHAPE, "image sides must be >= 2");
+      nmin = std::min(nmin, n[a]);
+    }
+    const int J = prior->levels > 0 ? prior->levels : wavelet_default_levels(nmin);
+    wavelet_apply(ndim, n, J, (float)(prior->kappa * sigma), (const float2*)in, (float2*)out, stream);
+  });
+}
+
+pnp_status pnp_hqs_workspace_bytes(const pnp_plan* p, int32_t L, size_t* bytes) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(bytes, "bytes");
+    *bytes = hqs_workspace_bytes(p, L);
+  });
+}
+
+pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                         const float* dcf, const pnp_prior* prior, const double* sigmas, int32_t n_out,
+                         const pnp_hqs_opts* opts, pnp_c64* x_out, pnp_hqs_report* report, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(y, "y");
+    need(smaps, "smaps");
+    need(prior, "prior");
+    need(sigmas, "sigmas");
+    need(opts, "opts");
+    need(x_out, "x_out");
+    need(ws, "ws");
+    if (opts->struct_size < sizeof(pnp_hqs_opts)) fail(PNP_ERR_ARG, "opts.struct_size too small");
+    if (n_out < 1) fail(PNP_ERR_SHAPE, "n_out must be >= 1");
+    if (opts->precond < 0 || opts->precond > 2) fail(PNP_ERR_ARG, "unknown preconditioner %d", opts->precond);
+    if (opts->n_cg < 1) fail(PNP_ERR_ARG, "n_cg must be >= 1");
+    if (!(opts->lambda > 0.0) || !std::isfinite(opts->lambda)) fail(PNP_ERR_ARG, "lambda must be > 0");
+    for (int k = 0; k < n_out; ++k)
+      if (!(sigmas[k] > 0.0) || !std::isfinite(sigmas[k])) fail(PNP_ERR_ARG, "sigma[%d] must be > 0", k);
+    if (report) {
+      if (report->struct_size < sizeof(pnp_hqs_report)) fail(PNP_ERR_ARG, "report.struct_size too small");
+      if (report->capacity < n_out) fail(PNP_ERR_ARG, "report capacity %d < n_out %d", report->capacity, n_out);
+      need(report->rho, "report.rho");
+    }
+    if ((const void*)x_out == (const void*)y || (const void*)x_out == (const void*)smaps)
+      fail(PNP_ERR_ARG, "x_out must not alias y or smaps");
+    check_ws(ws_bytes, hqs_workspace_bytes(p, L), ws);
+    double nrm = opts->opnorm;
+    if (!(nrm > 0.0)) {
+      const int its = opts->opnorm_iters > 0 ? opts->opnorm_iters : 50;
+      nrm = power_iteration(p, (const float2*)smaps, L, dcf, its, opts->opnorm_seed, ws, stream);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) fail(PNP_ERR_NUMERIC, "operator norm is %g", nrm);
+    }
+    HQSArgs a;
+    a.y = (const float2*)y;
+    a.smaps = (const float2*)smaps;
+    a.L = L;
+    a.dcf = dcf;
+    a.prior = prior;
+    a.sigmas = sigmas;
+    a.n_out = n_out;
+    a.precond = opts->precond;
+    a.n_cg = opts->n_cg;
+    a.lambda = opts->lambda;
+    a.opnorm = nrm;
+    a.x0 = (const float2*)opts->x0;
+    a.x_out = (float2*)x_out;
+    int bad = 0;
+    hqs_solve(p, a, ws, stream, report ? report->rho : nullptr, report ? &bad : nullptr);
+    if (report) {
+      report->opnorm_used = nrm;
+      if (report->fallback)
+        for (int k = 0; k < n_out; ++k) report->fallback[k] = 0;
+      if (bad) fail(PNP_ERR_NUMERIC, "CG breakdown (non-positive or non-finite <p, Mp>)");
+    }
+  });
+}
+
+}  // extern "C"

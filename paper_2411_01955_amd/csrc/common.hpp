@@ -1,0 +1,161 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "pnpmri.h"
+
+namespace pnp {
+
+// ---------------------------------------------------------------- errors
+// Internal failures are thrown as pnp::Failure and converted to a status at
+// the C ABI (no exception crosses it).
+struct Failure {
+  pnp_status code;
+};
+
+[[noreturn]] void fail(pnp_status code, const char* fmt, ...);
+[[noreturn]] void fail_hip(hipError_t e, const char* what, const char* file, int line);
+void set_error_text(const std::string& s);
+
+#define PNP_HIP(call)                                                  \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) ::pnp::fail_hip(e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define PNP_CHECK_LAUNCH() PNP_HIP(hipGetLastError())
+
+// --------------------------------------------------------- complex helpers
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cfma(float s, float2 a, float2 acc) {
+  return make_float2(fmaf(s, a.x, acc.x), fmaf(s, a.y, acc.y));
+}
+
+// ------------------------------------------------------------ FFT plan
+constexpr int kMaxRadices = 16;
+
+// One 1D FFT length: its radix sequence (Stockham order) and the device
+// table of the K-th roots of unity exp(-2*pi*i*t/K), t = 0..K-1, tabulated
+// in FP64 and rounded to FP32.
+struct FFTDesc {
+  int K;
+  int nrad;
+  int rad[kMaxRadices];
+  const float2* tw;
+};
+
+// Factor K into radices 8, 4, 2, 5, 3 (largest power-of-two radices first).
+// Returns false when K has another prime factor.
+bool fft_factor(int K, FFTDesc* d);
+
+// ------------------------------------------------------------------- plan
+struct Axis {
+  int n;             // image size along the axis
+  int K;             // oversampled grid size (2n)
+  FFTDesc fft;       // length-K transform
+  float* deapod;     // device [n]: I0(beta) / Phi((i - n/2)/K)
+};
+
+}  // namespace pnp
+
+// The opaque plan handle of the ABI.
+struct pnp_plan {
+  int ndim;
+  pnp::Axis ax[3];          // internal axis order: 0 = x (fastest), 1 = y, 2 = z
+  int64_t M;
+  int W;                    // kernel width (6)
+  double beta;              // Kaiser-Bessel shape
+  int tile;                 // tile edge (grid columns) along the tiled axes
+  int ntx, nty;             // tiles along x and y (nty = 1 in 2D)
+  int ntiles;
+  int slots;                // max tiles a sample touches (2 in 2D, 4 in 3D)
+  int64_t E;                // number of (sample, tile) entries
+  int max_tile_entries;
+  int device;
+  // device arrays (inside one allocation `block`)
+  int4* j0;                 // [M] wrapped first tap index per axis (x, y, z)
+  float* wts;               // [M][ndim][W] kernel weights phi(g - j) / I0(beta)
+  int32_t* tile_off;        // [ntiles + 1]
+  int32_t* ent_sample;      // [E] sample of each entry, grouped by tile
+  int32_t* sample_ent;      // [M][slots] entry indices of a sample (-1: none)
+  void* block;
+  size_t block_bytes;
+};
+
+struct pnp_prior {
+  int kind;                 // 0 = Haar wavelet
+  int levels;               // 0 = default rule
+  double kappa;
+};
+
+namespace pnp {
+
+// -------------------------------------------------------- launchers (host)
+// Workspace layout of the gridded operator for L coils.
+struct OpWorkspace {
+  float2* mid;     // [L][rows][Kx]  half-transformed grid (2D) / [L][nz][ny][Kx]... (3D)
+  float2* ypart;   // [L][E]         per-entry partial interpolation sums
+  float2* ytmp;    // [L][M]         k-space scratch for the normal operator
+  float2* part;    // [G][N]         per-coil-group partial images
+  size_t bytes;
+};
+size_t op_workspace_bytes(const pnp_plan* p, int L);
+OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws);
+
+void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y,
+                const OpWorkspace& w, hipStream_t s);
+void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf,
+                float2* x, const OpWorkspace& w, hipStream_t s);
+void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,
+               float2* out, const OpWorkspace& w, hipStream_t s);
+
+int64_t image_size(const pnp_plan* p);
+
+// Haar prior
+void wavelet_apply(int ndim, const int* n_xyz, int levels, float tau, const float2* in, float2* out,
+                   hipStream_t s);
+int wavelet_default_levels(int nmin);
+
+// plan
+pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* traj, hipStream_t s);
+void plan_destroy(pnp_plan* p);
+
+// solver
+size_t hqs_workspace_bytes(const pnp_plan* p, int L);
+size_t opnorm_workspace_bytes(const pnp_plan* p, int L);
+double power_iteration(const pnp_plan* p, const float2* smaps, int L, const float* dcf, int iters,
+                       uint64_t seed, void* ws, hipStream_t s);
+
+struct HQSArgs {
+  const float2* y;
+  const float2* smaps;
+  int L;
+  const float* dcf;
+  const pnp_prior* prior;
+  const double* sigmas;   // host [n_out]
+  int n_out;
+  int precond;
+  int n_cg;
+  double lambda;
+  double opnorm;
+  const float2* x0;
+  float2* x_out;
+};
+// Runs the loop; when rho_host is given, also the final residual, and waits.
+void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
+               int* bad_host);
+
+}  // namespace pnp

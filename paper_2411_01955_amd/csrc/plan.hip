@@ -1,0 +1,379 @@
+// Trajectory plan: grid coordinates, kernel weights, tile binning, FFT and
+// deapodisation tables.
+//
+// Kaiser-Bessel gridding (the NUFFT is left open by the paper, Sec. 2.1):
+//   grid coordinate  g = k * K / (2 pi)               (FP64)
+//   taps             j = floor(g - W/2) + 1 + t, t = 0..W-1, wrapped mod K
+//   weight           phi(g - j) = I0(beta sqrt(1 - (2(g-j)/W)^2)) / I0(beta)
+//   deapodisation    I0(beta) / Phi(r/K),  Phi(nu) = W sinh(z)/z,
+//                    z = sqrt(beta^2 - (pi W nu)^2),  r = i - n/2
+//   beta             Beatty's rule pi sqrt((W/osf)^2 (osf - 1/2)^2 - 0.8)
+// All tables are evaluated in FP64 on the device and rounded to FP32 once.
+//
+// Tiles: the last transformed axis (y in 2D, z in 3D) is kept whole in LDS;
+// the other grid axes are cut into tiles of `tile` columns.  Every sample is
+// listed once per tile its W x W footprint touches (at most 2 in 2D, 4 in
+// 3D), grouped by tile with a counting sort, so that interpolation and
+// spreading work tile by tile out of LDS.
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pnp {
+
+namespace {
+
+__device__ double bessel_i0(double z) {
+  // power series sum_k ((z/2)^2)^k / (k!)^2, converges for every z
+  const double q = 0.25 * z * z;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 400; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+__global__ void k_twiddles(float2* tw, int K) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K) return;
+  double s, c;
+  sincospi(-2.0 * (double)t / (double)K, &s, &c);
+  tw[t] = make_float2((float)c, (float)s);
+}
+
+__global__ void k_deapod(float* dp, int n, int K, int W, double beta) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double nu = (double)(i - n / 2) / (double)K;
+  const double a = M_PI * W * nu;
+  const double z2 = beta * beta - a * a;
+  double Phi;
+  if (z2 > 0) {
+    double z = sqrt(z2);
+    Phi = W * sinh(z) / z;
+  } else if (z2 < 0) {
+    double z = sqrt(-z2);
+    Phi = W * sin(z) / z;
+  } else {
+    Phi = W;
+  }
+  dp[i] = (float)(bessel_i0(beta) / Phi);
+}
+
+__device__ __forceinline__ int wrapi(long long j, int K) {
+  long long r = j % K;
+  return (int)(r < 0 ? r + K : r);
+}
+
+// Per sample: FP64 grid coordinates -> wrapped first tap, FP32 weights, and
+// the tiles the footprint touches (counted with atomics).
+__global__ void k_plan_samples(const float* __restrict__ traj, long long M, int ndim, int Kx, int Ky,
+                               int Kz, int W, double beta, int tile, int ntx, int nty,
+                               int4* __restrict__ j0, float* __restrict__ wts,
+                               int* __restrict__ tile_count, int* __restrict__ sample_tiles,
+                               int slots) {
+  long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int Kd[3] = {Kx, Ky, Kz};
+  int jj[3] = {0, 0, 0};
+  const double inv_i0b = 1.0 / bessel_i0(beta);
+  for (int a = 0; a < ndim; ++a) {
+    const double g = (double)traj[m * ndim + a] * (double)Kd[a] / (2.0 * M_PI);
+    const double f = floor(g - 0.5 * W) + 1.0;
+    for (int t = 0; t < W; ++t) {
+      const double u = g - (f + t);
+      const double q = 2.0 * u / W;
+      const double arg = fmax(1.0 - q * q, 0.0);
+      wts[(m * ndim + a) * W + t] = (float)(bessel_i0(beta * sqrt(arg)) * inv_i0b);
+    }
+    jj[a] = wrapi((long long)f, Kd[a]);
+  }
+  j0[m] = make_int4(jj[0], jj[1], jj[2], 0);
+  // tiles along x (and y in 3D) touched by taps j0 .. j0 + W - 1 (mod K)
+  int tx[2], ty[2];
+  int nxs = 0, nys = 0;
+  tx[nxs++] = jj[0] / tile;
+  {
+    int e = jj[0] + W - 1;
+    if (e >= Kx) e -= Kx;
+    int t1 = e / tile;
+    if (t1 != tx[0]) tx[nxs++] = t1;
+  }
+  if (ndim == 3) {
+    ty[nys++] = jj[1] / tile;
+    int e = jj[1] + W - 1;
+    if (e >= Ky) e -= Ky;
+    int t1 = e / tile;
+    if (t1 != ty[0]) ty[nys++] = t1;
+  } else {
+    ty[nys++] = 0;
+  }
+  int s = 0;
+  for (int b = 0; b < nys; ++b)
+    for (int a = 0; a < nxs; ++a) {
+      const int tid = ty[b] * ntx + tx[a];
+      sample_tiles[m * slots + s++] = tid;
+      atomicAdd(&tile_count[tid], 1);
+    }
+  for (; s < slots; ++s) sample_tiles[m * slots + s] = -1;
+}
+
+__global__ void k_scan_tiles(const int* __restrict__ count, int ntiles, int* __restrict__ off,
+                             int* __restrict__ cursor, int* __restrict__ maxc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int acc = 0, mx = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    off[t] = acc;
+    cursor[t] = 0;
+    acc += count[t];
+    mx = count[t] > mx ? count[t] : mx;
+  }
+  off[ntiles] = acc;
+  *maxc = mx;
+}
+
+__global__ void k_scatter(long long M, int slots, const int* __restrict__ sample_tiles,
+                          const int* __restrict__ off, int* __restrict__ cursor,
+                          int* __restrict__ ent_sample, int* __restrict__ sample_ent) {
+  long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  for (int s = 0; s < slots; ++s) {
+    const int t = sample_tiles[m * slots + s];
+    if (t < 0) {
+      sample_ent[m * slots + s] = -1;
+      continue;
+    }
+    const int pos = atomicAdd(&cursor[t], 1);
+    const int e = off[t] + pos;
+    ent_sample[e] = (int)m;
+    sample_ent[m * slots + s] = e;
+  }
+}
+
+// Sort each tile's entries by sample index (insertion sort in LDS for tiles
+// up to 4096 entries, larger tiles keep atomic order), then refresh the
+// sample -> entry map.  Deterministic entry order makes forward results
+// and the spread's access pattern reproducible.
+__global__ void k_sort_tiles(const int* __restrict__ off, int* __restrict__ ent_sample) {
+  __shared__ int buf[4096];
+  const int t = blockIdx.x;
+  const int b = off[t], e = off[t + 1];
+  const int n = e - b;
+  if (n <= 1 || n > 4096) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = ent_sample[b + i];
+  __syncthreads();
+  // rank sort: position of element i = number of smaller elements (values unique per tile)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int v = buf[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) r += buf[j] < v;
+    ent_sample[b + r] = v;
+  }
+}
+
+__global__ void k_refresh_sample_ent(long long E, int slots, const int* __restrict__ ent_sample,
+                                     const int* __restrict__ off, const int* __restrict__ sample_tiles,
+                                     int ntiles, int* __restrict__ sample_ent) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  // tile of entry e: binary search in off
+  int lo = 0, hi = ntiles;  // off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int m = ent_sample[e];
+  for (int s = 0; s < slots; ++s)
+    if (sample_tiles[(long long)m * slots + s] == lo) sample_ent[(long long)m * slots + s] = (int)e;
+}
+
+__global__ void k_check_finite(const float* __restrict__ v, long long n, int* __restrict__ bad) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(v[i])) atomicOr(bad, 1);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+bool fft_factor(int K, FFTDesc* d) {
+  d->K = K;
+  d->nrad = 0;
+  int r = K;
+  const int order[5] = {8, 4, 2, 5, 3};
+  for (int oi = 0; oi < 5; ++oi) {
+    const int R = order[oi];
+    while (r % R == 0) {
+      if (d->nrad >= kMaxRadices) return false;
+      d->rad[d->nrad++] = R;
+      r /= R;
+    }
+  }
+  return r == 1;
+}
+
+int64_t image_size(const pnp_plan* p) {
+  int64_t N = 1;
+  for (int a = 0; a < p->ndim; ++a) N *= p->ax[a].n;
+  return N;
+}
+
+static int choose_tile(int K) {
+  const int pref[] = {8, 12, 10, 6, 16, 15, 9, 18, 20, 24, 25, 27, 30, 32};
+  for (int t : pref)
+    if (K % t == 0) return t;
+  return 0;
+}
+
+pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* traj,
+                      hipStream_t stream) {
+  if (ndim != 2 && ndim != 3) fail(PNP_ERR_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
+  if (M < 1) fail(PNP_ERR_SHAPE, "M must be >= 1 (got %lld)", (long long)M);
+  if (M > (int64_t)1 << 30) fail(PNP_ERR_SHAPE, "M too large (%lld)", (long long)M);
+  pnp_plan* p = new pnp_plan();
+  p->ndim = ndim;
+  p->M = M;
+  p->W = 6;
+  const double osf = 2.0;
+  p->beta = M_PI * std::sqrt((p->W / osf) * (p->W / osf) * (osf - 0.5) * (osf - 0.5) - 0.8);
+  p->block = nullptr;
+  try {
+    for (int a = 0; a < 3; ++a) {
+      p->ax[a].n = 1;
+      p->ax[a].K = 1;
+      p->ax[a].deapod = nullptr;
+      p->ax[a].fft.tw = nullptr;
+      p->ax[a].fft.nrad = 0;
+    }
+    for (int a = 0; a < ndim; ++a) {
+      const int n = shape[ndim - 1 - a];
+      if (n < 4 || n > 1024 || (n & 1))
+        fail(PNP_ERR_SHAPE, "image size %d unsupported (even, 4..1024)", n);
+      p->ax[a].n = n;
+      p->ax[a].K = 2 * n;
+      if (!fft_factor(2 * n, &p->ax[a].fft))
+        fail(PNP_ERR_SHAPE, "grid size %d must have only prime factors 2, 3, 5", 2 * n);
+    }
+    if (ndim == 3) fail(PNP_ERR_UNSUPPORTED, "3D plans are not available in this build");
+    p->tile = choose_tile(p->ax[0].K);
+    if (ndim == 3 && choose_tile(p->ax[1].K) != p->tile)
+      fail(PNP_ERR_SHAPE, "3D x and y grids need a common tile size");
+    if (p->tile == 0) fail(PNP_ERR_SHAPE, "no tile size divides grid size %d", p->ax[0].K);
+    p->ntx = p->ax[0].K / p->tile;
+    p->nty = ndim == 3 ? p->ax[1].K / p->tile : 1;
+    p->ntiles = p->ntx * p->nty;
+    p->slots = ndim == 3 ? 4 : 2;
+
+    PNP_HIP(hipGetDevice(&p->device));
+
+    // validate the trajectory on the device
+    {
+      int* bad = nullptr;
+      PNP_HIP(hipMalloc((void**)&bad, sizeof(int)));
+      PNP_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
+      const long long nv = M * ndim;
+      k_check_finite<<<(unsigned)((nv + 255) / 256), 256, 0, stream>>>(traj, nv, bad);
+      PNP_CHECK_LAUNCH();
+      int hbad = 0;
+      PNP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+      PNP_HIP(hipStreamSynchronize(stream));
+      PNP_HIP(hipFree(bad));
+      if (hbad) fail(PNP_ERR_NUMERIC, "trajectory holds non-finite coordinates");
+    }
+
+    // one allocation: tables + per-sample data + entries (E <= slots*M)
+    const int64_t Emax = (int64_t)p->slots * M;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      size_t o = off;
+      off += align256(bytes);
+      return o;
+    };
+    size_t o_tw[3], o_dp[3];
+    for (int a = 0; a < ndim; ++a) {
+      o_tw[a] = take(sizeof(float2) * p->ax[a].K);
+      o_dp[a] = take(sizeof(float) * p->ax[a].n);
+    }
+    const size_t o_j0 = take(sizeof(int4) * M);
+    const size_t o_w = take(sizeof(float) * M * ndim * p->W);
+    const size_t o_off = take(sizeof(int) * (p->ntiles + 1));
+    const size_t o_es = take(sizeof(int) * Emax);
+    const size_t o_se = take(sizeof(int) * M * p->slots);
+    // set-up scratch (freed below)
+    size_t soff = 0;
+    const size_t s_cnt = soff; soff += align256(sizeof(int) * p->ntiles);
+    const size_t s_cur = soff; soff += align256(sizeof(int) * p->ntiles);
+    const size_t s_max = soff; soff += align256(sizeof(int));
+    const size_t s_st = soff; soff += align256(sizeof(int) * M * p->slots);
+
+    PNP_HIP(hipMalloc(&p->block, off));
+    p->block_bytes = off;
+    char* base = (char*)p->block;
+    for (int a = 0; a < ndim; ++a) {
+      p->ax[a].fft.tw = (const float2*)(base + o_tw[a]);
+      p->ax[a].deapod = (float*)(base + o_dp[a]);
+    }
+    p->j0 = (int4*)(base + o_j0);
+    p->wts = (float*)(base + o_w);
+    p->tile_off = (int32_t*)(base + o_off);
+    p->ent_sample = (int32_t*)(base + o_es);
+    p->sample_ent = (int32_t*)(base + o_se);
+
+    char* scratch = nullptr;
+    PNP_HIP(hipMalloc((void**)&scratch, soff));
+    int* cnt = (int*)(scratch + s_cnt);
+    int* cur = (int*)(scratch + s_cur);
+    int* mx = (int*)(scratch + s_max);
+    int* st = (int*)(scratch + s_st);
+
+    for (int a = 0; a < ndim; ++a) {
+      const int K = p->ax[a].K, n = p->ax[a].n;
+      k_twiddles<<<(K + 255) / 256, 256, 0, stream>>>((float2*)p->ax[a].fft.tw, K);
+      PNP_CHECK_LAUNCH();
+      k_deapod<<<(n + 255) / 256, 256, 0, stream>>>(p->ax[a].deapod, n, K, p->W, p->beta);
+      PNP_CHECK_LAUNCH();
+    }
+    PNP_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * p->ntiles, stream));
+    const unsigned gM = (unsigned)((M + 255) / 256);
+    k_plan_samples<<<gM, 256, 0, stream>>>(traj, M, ndim, p->ax[0].K, p->ax[1].K, p->ax[2].K, p->W,
+                                           p->beta, p->tile, p->ntx, p->nty, p->j0, p->wts, cnt, st,
+                                           p->slots);
+    PNP_CHECK_LAUNCH();
+    k_scan_tiles<<<1, 64, 0, stream>>>(cnt, p->ntiles, p->tile_off, cur, mx);
+    PNP_CHECK_LAUNCH();
+    k_scatter<<<gM, 256, 0, stream>>>(M, p->slots, st, p->tile_off, cur, p->ent_sample, p->sample_ent);
+    PNP_CHECK_LAUNCH();
+    int hE = 0, hmax = 0;
+    PNP_HIP(hipMemcpyAsync(&hE, p->tile_off + p->ntiles, sizeof(int), hipMemcpyDeviceToHost, stream));
+    PNP_HIP(hipMemcpyAsync(&hmax, mx, sizeof(int), hipMemcpyDeviceToHost, stream));
+    PNP_HIP(hipStreamSynchronize(stream));
+    p->E = hE;
+    p->max_tile_entries = hmax;
+    k_sort_tiles<<<p->ntiles, 256, 0, stream>>>(p->tile_off, p->ent_sample);
+    PNP_CHECK_LAUNCH();
+    if (p->E > 0) {
+      k_refresh_sample_ent<<<(unsigned)((p->E + 255) / 256), 256, 0, stream>>>(
+          p->E, p->slots, p->ent_sample, p->tile_off, st, p->ntiles, p->sample_ent);
+      PNP_CHECK_LAUNCH();
+    }
+    PNP_HIP(hipStreamSynchronize(stream));
+    PNP_HIP(hipFree(scratch));
+  } catch (...) {
+    if (p->block) (void)hipFree(p->block);
+    delete p;
+    throw;
+  }
+  return p;
+}
+
+void plan_destroy(pnp_plan* p) {
+  if (!p) return;
+  if (p->block) (void)hipFree(p->block);
+  delete p;
+}
+
+}  // namespace pnp

@@ -1,0 +1,428 @@
+// Conjugate-gradient proximal step, power iteration and the annealed
+// PnP-HQS loop (Sec. 3.3-3.4), with every scalar kept on the device.
+//
+// Vectors are complex64; inner products, step sizes (alpha, beta), the
+// residual norms and the data-consistency residual are accumulated in FP64:
+// each vector kernel writes one FP64 partial per block (fixed grid), and a
+// one-block finalize kernel sums the partials in a fixed order and updates
+// the scalar state, so results are deterministic and no host round trip is
+// needed inside the loop.
+//
+// The prox system (Sec. 3.4, read with the density weighting D_w):
+//   M u = b,  M = gamma N + P = c0 I + (gamma - c1 alpha) N,  N = A^H D_w A,
+//   b = P x + gamma b0,  b0 = A^H D_w y,  started at u = x so that
+//   r0 = gamma (b0 - N x).  Each CG step costs one normal operator.
+// The residual rho(x) = ||D_w^{1/2}(A x - y)||^2 = <x,Nx> - 2 Re<x,b0> + ||y||_w^2
+// comes for free from the N x that r0 needs.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pnp {
+
+constexpr int kRedBlocks = 256;
+constexpr int kRedThreads = 256;
+constexpr int kMaxOuter = 1024;
+
+struct DevScalars {
+  double rr;        // <r, r>
+  double pq;        // Re <p, M p>
+  double alpha;     // CG step
+  double beta;      // CG direction update
+  double yw2;       // ||y||^2_w
+  double lam;       // power iteration: Rayleigh quotient
+  double inv;       // power iteration: 1/||w||
+  int bad;          // set when a CG denominator is not positive / finite
+  int pad;
+};
+
+namespace {
+
+__device__ __forceinline__ double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum `Q` values over the block; thread 0 writes them to parts[blockIdx.x*Q + q].
+template <int Q>
+__device__ void block_partials(double (&v)[Q], double* __restrict__ parts) {
+  __shared__ double sh[Q][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double s = warp_sum(v[q]);
+    if (lane == 0) sh[q][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kRedThreads / 64; ++w) s += sh[q][w];
+      parts[blockIdx.x * Q + q] = s;
+    }
+  }
+}
+
+// Sum parts[b*Q + q] over b in fixed order; result in out[q] (thread 0 sees it).
+template <int Q>
+__device__ void finalize_sum(const double* __restrict__ parts, int nb, double (&out)[Q]) {
+  __shared__ double sh[Q][kRedThreads];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += parts[b * Q + q];
+    sh[q][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) out[q] = sh[q][0];
+}
+
+__device__ __forceinline__ double re_dot(float2 a, float2 b) {
+  return (double)a.x * b.x + (double)a.y * b.y;
+}
+
+// u = x; r = gamma (b0 - Nx); p = r;  partials |r|^2, Re<x,Nx>, Re<x,b0>
+__global__ void __launch_bounds__(kRedThreads)
+k_cg_init(long long N, const float2* __restrict__ x, const float2* __restrict__ Nx,
+          const float2* __restrict__ b0, float gamma, float2* __restrict__ u, float2* __restrict__ r,
+          float2* __restrict__ p, double* __restrict__ parts) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 xv = x[i], nv = Nx[i], bv = b0[i];
+    const float2 rv = make_float2(gamma * (bv.x - nv.x), gamma * (bv.y - nv.y));
+    u[i] = xv;
+    r[i] = rv;
+    p[i] = rv;
+    acc[0] += re_dot(rv, rv);
+    acc[1] += re_dot(xv, nv);
+    acc[2] += re_dot(xv, bv);
+  }
+  block_partials<3>(acc, parts);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_fin_init(const double* __restrict__ parts, int nb, DevScalars* sc, double* __restrict__ rho_out) {
+  double s[3];
+  finalize_sum<3>(parts, nb, s);
+  if (threadIdx.x == 0) {
+    sc->rr = s[0];
+    if (rho_out) *rho_out = s[1] - 2.0 * s[2] + sc->yw2;
+  }
+}
+
+// q = c0 p + cg Np;  partial Re<p, q>
+__global__ void __launch_bounds__(kRedThreads)
+k_cg_q(long long N, const float2* __restrict__ p, const float2* __restrict__ Np, float c0, float cg,
+       float2* __restrict__ q, double* __restrict__ parts) {
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 pv = p[i], nv = Np[i];
+    const float2 qv = make_float2(c0 * pv.x + cg * nv.x, c0 * pv.y + cg * nv.y);
+    q[i] = qv;
+    acc[0] += re_dot(pv, qv);
+  }
+  block_partials<1>(acc, parts);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_fin_alpha(const double* __restrict__ parts, int nb, DevScalars* sc) {
+  double s[1];
+  finalize_sum<1>(parts, nb, s);
+  if (threadIdx.x == 0) {
+    sc->pq = s[0];
+    if (sc->rr == 0.0) {
+      sc->alpha = 0.0;
+    } else if (!(s[0] > 0.0) || !isfinite(s[0]) || !isfinite(sc->rr)) {
+      sc->alpha = 0.0;
+      sc->bad = 1;
+    } else {
+      sc->alpha = sc->rr / s[0];
+    }
+  }
+}
+
+// u += alpha p; r -= alpha q;  partial |r|^2
+__global__ void __launch_bounds__(kRedThreads)
+k_cg_update(long long N, float2* __restrict__ u, float2* __restrict__ r, const float2* __restrict__ p,
+            const float2* __restrict__ q, const DevScalars* __restrict__ sc, double* __restrict__ parts) {
+  const float a = (float)sc->alpha;
+  double acc[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 pv = p[i], qv = q[i];
+    float2 uv = u[i], rv = r[i];
+    uv = make_float2(fmaf(a, pv.x, uv.x), fmaf(a, pv.y, uv.y));
+    rv = make_float2(fmaf(-a, qv.x, rv.x), fmaf(-a, qv.y, rv.y));
+    u[i] = uv;
+    r[i] = rv;
+    acc[0] += re_dot(rv, rv);
+  }
+  block_partials<1>(acc, parts);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_fin_beta(const double* __restrict__ parts, int nb, DevScalars* sc) {
+  double s[1];
+  finalize_sum<1>(parts, nb, s);
+  if (threadIdx.x == 0) {
+    sc->beta = sc->rr > 0.0 ? s[0] / sc->rr : 0.0;
+    sc->rr = s[0];
+  }
+}
+
+// p = r + beta p
+__global__ void k_cg_p(long long N, float2* __restrict__ p, const float2* __restrict__ r,
+                       const DevScalars* __restrict__ sc) {
+  const float bt = (float)sc->beta;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 rv = r[i], pv = p[i];
+    p[i] = make_float2(fmaf(bt, pv.x, rv.x), fmaf(bt, pv.y, rv.y));
+  }
+}
+
+// ||y||_w^2 partials over L*M entries
+__global__ void __launch_bounds__(kRedThreads)
+k_wnorm(long long M, int L, const float2* __restrict__ y, const float* __restrict__ dcf,
+        double* __restrict__ parts) {
+  double acc[1] = {0.0};
+  const long long T = M * L;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < T;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long m = t % M;
+    const float2 v = y[t];
+    const double w = dcf ? (double)dcf[m] : 1.0;
+    acc[0] += w * re_dot(v, v);
+  }
+  block_partials<1>(acc, parts);
+}
+
+__global__ void k_fin_yw2(const double* __restrict__ parts, int nb, DevScalars* sc) {
+  double s[1];
+  finalize_sum<1>(parts, nb, s);
+  if (threadIdx.x == 0) {
+    sc->yw2 = s[0];
+    sc->bad = 0;
+  }
+}
+
+// ---- power iteration
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  // splitmix64 finaliser (Steele, Lea, Flood 2014)
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_randn(long long N, uint64_t seed, float2* __restrict__ v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const uint64_t h1 = mix64(seed ^ mix64((uint64_t)i * 2));
+    const uint64_t h2 = mix64(seed ^ mix64((uint64_t)i * 2 + 1));
+    const double u1 = ((h1 >> 11) + 1) * (1.0 / 9007199254740993.0);  // (0, 1]
+    const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    v[i] = make_float2((float)(rad * cs), (float)(rad * sn));
+  }
+}
+
+// partials Re<v, w>, |w|^2
+__global__ void __launch_bounds__(kRedThreads)
+k_dot_vw(long long N, const float2* __restrict__ v, const float2* __restrict__ w,
+         double* __restrict__ parts) {
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 a = v[i], b = w[i];
+    acc[0] += re_dot(a, b);
+    acc[1] += re_dot(b, b);
+  }
+  block_partials<2>(acc, parts);
+}
+
+__global__ void k_fin_power(const double* __restrict__ parts, int nb, DevScalars* sc) {
+  double s[2];
+  finalize_sum<2>(parts, nb, s);
+  if (threadIdx.x == 0) {
+    sc->lam = s[0];
+    sc->inv = s[1] > 0.0 ? 1.0 / sqrt(s[1]) : 0.0;
+  }
+}
+
+__global__ void k_scale_into(long long N, const float2* __restrict__ w, const DevScalars* __restrict__ sc,
+                             float2* __restrict__ v) {
+  const float s = (float)sc->inv;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x)
+    v[i] = cscale(w[i], s);
+}
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+unsigned vec_blocks(long long N) {
+  long long b = (N + kRedThreads - 1) / kRedThreads;
+  return (unsigned)std::min<long long>(std::max<long long>(b, 1), kRedBlocks);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host side
+struct SolverWs {
+  OpWorkspace op;
+  float2 *b0, *Nv, *u, *r, *p, *q;
+  double* parts;
+  DevScalars* sc;
+  double* rho;   // [kMaxOuter + 1]
+};
+
+size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
+  const int64_t N = image_size(p);
+  size_t b = al(op_workspace_bytes(p, L));
+  b += 6 * al(sizeof(float2) * N);
+  b += al(sizeof(double) * 4 * kRedBlocks);
+  b += al(sizeof(DevScalars));
+  b += al(sizeof(double) * (kMaxOuter + 1));
+  return b;
+}
+
+static SolverWs solver_ws(const pnp_plan* p, int L, void* ws) {
+  SolverWs w;
+  const int64_t N = image_size(p);
+  char* c = (char*)ws;
+  w.op = op_workspace(p, L, c);
+  c += al(op_workspace_bytes(p, L));
+  float2** vecs[6] = {&w.b0, &w.Nv, &w.u, &w.r, &w.p, &w.q};
+  for (auto v : vecs) {
+    *v = (float2*)c;
+    c += al(sizeof(float2) * N);
+  }
+  w.parts = (double*)c;
+  c += al(sizeof(double) * 4 * kRedBlocks);
+  w.sc = (DevScalars*)c;
+  c += al(sizeof(DevScalars));
+  w.rho = (double*)c;
+  return w;
+}
+
+size_t opnorm_workspace_bytes(const pnp_plan* p, int L) { return hqs_workspace_bytes(p, L); }
+
+// Power iteration: v <- N v / ||N v||, `iters` times; returns the last
+// Rayleigh quotient Re<v, N v> (|v| = 1).  Synchronises the stream.
+double power_iteration(const pnp_plan* p, const float2* smaps, int L, const float* dcf, int iters,
+                       uint64_t seed, void* ws, hipStream_t s) {
+  SolverWs w = solver_ws(p, L, ws);
+  const long long N = image_size(p);
+  const unsigned nb = vec_blocks(N);
+  float2* v = w.u;
+  float2* Nv = w.Nv;
+  hipLaunchKernelGGL(k_randn, dim3(nb), dim3(kRedThreads), 0, s, N, seed, Nv);
+  PNP_CHECK_LAUNCH();
+  // normalise the start vector: use k_dot_vw(Nv, Nv) -> inv = 1/|Nv|
+  hipLaunchKernelGGL(k_dot_vw, dim3(nb), dim3(kRedThreads), 0, s, N, Nv, Nv, w.parts);
+  hipLaunchKernelGGL(k_fin_power, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
+  hipLaunchKernelGGL(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, Nv, w.sc, v);
+  PNP_CHECK_LAUNCH();
+  for (int it = 0; it < iters; ++it) {
+    op_normal(p, v, smaps, L, dcf, Nv, w.op, s);
+    hipLaunchKernelGGL(k_dot_vw, dim3(nb), dim3(kRedThreads), 0, s, N, v, Nv, w.parts);
+    hipLaunchKernelGGL(k_fin_power, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
+    hipLaunchKernelGGL(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, Nv, w.sc, v);
+    PNP_CHECK_LAUNCH();
+  }
+  DevScalars h;
+  PNP_HIP(hipMemcpyAsync(&h, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  PNP_HIP(hipStreamSynchronize(s));
+  return h.lam;
+}
+
+static void apply_prior(const pnp_plan* p, const pnp_prior* prior, const float2* u, float2* x,
+                        double sigma, hipStream_t s) {
+  int n[3] = {p->ax[0].n, p->ax[1].n, p->ax[2].n};
+  int nmin = n[0];
+  for (int a = 1; a < p->ndim; ++a) nmin = std::min(nmin, n[a]);
+  const int J = prior->levels > 0 ? prior->levels : wavelet_default_levels(nmin);
+  wavelet_apply(p->ndim, n, J, (float)(prior->kappa * sigma), u, x, s);
+}
+
+// Returns 0 or a CG breakdown flag (only checked when `report` requested).
+void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
+               int* bad_host) {
+  if (a.n_out > kMaxOuter) fail(PNP_ERR_SHAPE, "n_out %d exceeds %d", a.n_out, kMaxOuter);
+  SolverWs w = solver_ws(p, a.L, ws);
+  const long long N = image_size(p);
+  const unsigned nb = vec_blocks(N);
+  static const double c0s[3] = {1.0, 2.0, 4.0};
+  static const double c1s[3] = {0.0, 1.0, 10.0 / 3.0};
+  const double c0 = c0s[a.precond];
+  const double c1a = c1s[a.precond] / a.opnorm;
+
+  // b0 = A^H D_w y, ||y||_w^2
+  op_adjoint(p, a.y, a.smaps, a.L, a.dcf, w.b0, w.op, s);
+  {
+    const long long T = p->M * a.L;
+    const unsigned nbk = (unsigned)std::min<long long>((T + kRedThreads - 1) / kRedThreads, kRedBlocks);
+    hipLaunchKernelGGL(k_wnorm, dim3(std::max(nbk, 1u)), dim3(kRedThreads), 0, s, (long long)p->M,
+                       a.L, a.y, a.dcf, w.parts);
+    hipLaunchKernelGGL(k_fin_yw2, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)std::max(nbk, 1u), w.sc);
+    PNP_CHECK_LAUNCH();
+  }
+  float2* x = a.x_out;
+  PNP_HIP(hipMemcpyAsync(x, a.x0 ? a.x0 : w.b0, sizeof(float2) * N, hipMemcpyDeviceToDevice, s));
+
+  for (int k = 0; k < a.n_out; ++k) {
+    const double gamma = a.lambda * a.sigmas[k];
+    const float cg = (float)(gamma - c1a);
+    op_normal(p, x, a.smaps, a.L, a.dcf, w.Nv, w.op, s);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, x, w.Nv, w.b0, (float)gamma,
+                       w.u, w.r, w.p, w.parts);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc, w.rho + k);
+    PNP_CHECK_LAUNCH();
+    for (int j = 0; j < a.n_cg; ++j) {
+      op_normal(p, w.p, a.smaps, a.L, a.dcf, w.Nv, w.op, s);
+      hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(kRedThreads), 0, s, N, w.p, w.Nv, (float)c0, cg, w.q,
+                         w.parts);
+      hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
+      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kRedThreads), 0, s, N, w.u, w.r, w.p, w.q, w.sc,
+                         w.parts);
+      hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
+      if (j + 1 < a.n_cg)
+        hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(kRedThreads), 0, s, N, w.p, w.r, w.sc);
+      PNP_CHECK_LAUNCH();
+    }
+    apply_prior(p, a.prior, w.u, x, a.sigmas[k], s);
+  }
+  if (rho_host) {
+    // residual of the final image (one extra normal operator)
+    op_normal(p, x, a.smaps, a.L, a.dcf, w.Nv, w.op, s);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, x, w.Nv, w.b0, 0.0f, w.u,
+                       w.r, w.p, w.parts);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc,
+                       w.rho + a.n_out);
+    PNP_CHECK_LAUNCH();
+    std::vector<double> r(a.n_out + 1);
+    DevScalars h;
+    PNP_HIP(hipMemcpyAsync(r.data(), w.rho, sizeof(double) * (a.n_out + 1), hipMemcpyDeviceToHost, s));
+    PNP_HIP(hipMemcpyAsync(&h, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    PNP_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < a.n_out; ++k) rho_host[k] = r[k + 1];
+    if (bad_host) *bad_host = h.bad;
+  }
+}
+
+}  // namespace pnp

@@ -1,0 +1,128 @@
+// Haar soft-threshold prior D_sigma(u) (the plain method's plug-in denoiser).
+//
+// An orthonormal Haar transform with J levels never mixes pixels of
+// different 2^J x 2^J (x 2^J) blocks, so the whole prior -- J analysis
+// levels, soft threshold of the detail coefficients, J synthesis levels --
+// runs block by block in LDS with one read and one write of the image.
+// Within a block the coefficients sit in the usual pyramid layout; the
+// single coarsest approximation coefficient of a block (index 0) is the
+// only one left unthresholded.  Soft threshold: c * max(0, 1 - tau/|c|).
+#include "common.hpp"
+
+namespace pnp {
+
+namespace {
+
+constexpr float kInvSqrt2 = 0.70710678118654752440f;
+
+// One analysis (INV=false) or synthesis (INV=true) step along `axis` on the
+// leading m^ndim region of a B^ndim block, src -> dst (whole block copied).
+template <bool INV>
+__device__ void haar_step(const float2* __restrict__ src, float2* __restrict__ dst, int ndim, int B,
+                          int m, int axis) {
+  const int total = ndim == 3 ? B * B * B : B * B;
+  const int h = m >> 1;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int q[3];
+    q[0] = t % B;                       // x
+    q[1] = (t / B) % B;                 // y
+    q[2] = ndim == 3 ? t / (B * B) : 0; // z
+    const bool in = q[0] < m && q[1] < m && (ndim == 2 || q[2] < m);
+    if (!in) {
+      dst[t] = src[t];
+      continue;
+    }
+    const int stride = axis == 0 ? 1 : (axis == 1 ? B : B * B);
+    const int qa = q[axis];
+    const int base = t - qa * stride;
+    float2 o;
+    if (!INV) {
+      const int k = qa < h ? qa : qa - h;
+      const float2 e = src[base + (2 * k) * stride];
+      const float2 od = src[base + (2 * k + 1) * stride];
+      o = qa < h ? make_float2((e.x + od.x) * kInvSqrt2, (e.y + od.y) * kInvSqrt2)
+                 : make_float2((e.x - od.x) * kInvSqrt2, (e.y - od.y) * kInvSqrt2);
+    } else {
+      const int k = qa >> 1;
+      const float2 lo = src[base + k * stride];
+      const float2 hi = src[base + (h + k) * stride];
+      o = (qa & 1) ? make_float2((lo.x - hi.x) * kInvSqrt2, (lo.y - hi.y) * kInvSqrt2)
+                   : make_float2((lo.x + hi.x) * kInvSqrt2, (lo.y + hi.y) * kInvSqrt2);
+    }
+    dst[t] = o;
+  }
+}
+
+__global__ void k_haar_prior(const float2* __restrict__ in, float2* __restrict__ out, int ndim,
+                             int nx, int ny, int nz, int J, float tau) {
+  extern __shared__ float2 lds[];
+  const int B = 1 << J;
+  const int total = ndim == 3 ? B * B * B : B * B;
+  float2* a = lds;
+  float2* b = lds + total;
+  const int bx = nx / B, by = ny / B;
+  const int blk = blockIdx.x;
+  const int ox = (blk % bx) * B;
+  const int oy = ((blk / bx) % by) * B;
+  const int oz = ndim == 3 ? (blk / (bx * by)) * B : 0;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int x = t % B, y = (t / B) % B, z = ndim == 3 ? t / (B * B) : 0;
+    a[t] = in[((long long)(oz + z) * ny + (oy + y)) * nx + ox + x];
+  }
+  __syncthreads();
+  for (int l = 0; l < J; ++l) {
+    const int m = B >> l;
+    for (int ax = 0; ax < ndim; ++ax) {
+      haar_step<false>(a, b, ndim, B, m, ax);
+      __syncthreads();
+      float2* t = a; a = b; b = t;
+    }
+  }
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    if (t == 0) continue;
+    const float2 c = a[t];
+    const float mag = sqrtf(c.x * c.x + c.y * c.y);
+    const float f = mag > tau ? 1.0f - tau / mag : 0.0f;
+    a[t] = make_float2(c.x * f, c.y * f);
+  }
+  __syncthreads();
+  for (int l = J - 1; l >= 0; --l) {
+    const int m = B >> l;
+    for (int ax = ndim - 1; ax >= 0; --ax) {
+      haar_step<true>(a, b, ndim, B, m, ax);
+      __syncthreads();
+      float2* t = a; a = b; b = t;
+    }
+  }
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int x = t % B, y = (t / B) % B, z = ndim == 3 ? t / (B * B) : 0;
+    out[((long long)(oz + z) * ny + (oy + y)) * nx + ox + x] = a[t];
+  }
+}
+
+}  // namespace
+
+int wavelet_default_levels(int nmin) {
+  int lg = 0;
+  while ((2 << lg) <= nmin) ++lg;  // floor(log2 nmin)
+  int J = lg - 3;
+  if (J > 4) J = 4;
+  if (J < 1) J = 1;
+  return J;
+}
+
+void wavelet_apply(int ndim, const int* n, int levels, float tau, const float2* in, float2* out,
+                   hipStream_t s) {
+  const int B = 1 << levels;
+  for (int a = 0; a < ndim; ++a)
+    if (n[a] % B) fail(PNP_ERR_SHAPE, "image side %d not divisible by 2^%d", n[a], levels);
+  long long blocks = 1;
+  for (int a = 0; a < ndim; ++a) blocks *= n[a] / B;
+  const int total = ndim == 3 ? B * B * B : B * B;
+  const size_t lds = sizeof(float2) * 2 * total;
+  hipLaunchKernelGGL(k_haar_prior, dim3((unsigned)blocks), dim3(256), lds, s, in, out, ndim, n[0],
+                     n[1], ndim == 3 ? n[2] : 1, levels, tau);
+  PNP_CHECK_LAUNCH();
+}
+
+}  // namespace pnp

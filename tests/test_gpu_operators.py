@@ -1,0 +1,151 @@
+"""GPU parity of A, A^H D_w and A^H D_w A against the exact FP64 NDFT oracle.
+
+Bar: relative L2 error <= 2e-5 per operator application (FP32 Kaiser-Bessel
+gridding, W = 6, oversampling 2, against the exact transform)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ndft
+from tests.gpu_util import rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def pnp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_01955_amd as pnp
+    pnp.load()
+    return pnp
+
+
+def _case(n, L, traj, seed, dcf=None):
+    x, _ = synth.phantom2d(n, seed)
+    S = synth.smaps2d(n, L)
+    return x, S, traj, dcf
+
+
+def _run_ops(pnp, shape, x, S, k, dcf, label):
+    say(f"[ops] {label}: shape={shape} L={S.shape[0]} M={k.shape[0]}")
+    plan = pnp.Plan(to_dev(k), shape)
+    xd, Sd = to_dev(x), to_dev(S)
+    dd = to_dev(dcf) if dcf is not None else None
+    y = to_np(plan.forward(xd, Sd))
+    y_ref = ndft.forward(x, S, k)
+    e_f = rel_l2(y, y_ref)
+    yin = synth.white_complex((S.shape[0], k.shape[0]), 77)
+    xa = to_np(plan.adjoint(to_dev(yin), Sd, dd))
+    xa_ref = ndft.adjoint(yin, S, k, dcf)
+    e_a = rel_l2(xa, xa_ref)
+    xn = to_np(plan.normal(xd, Sd, dd))
+    xn_ref = ndft.adjoint(y_ref, S, k, dcf)
+    e_n = rel_l2(xn, xn_ref)
+    say(f"   forward {e_f:.3e}  adjoint {e_a:.3e}  normal {e_n:.3e}  info={plan.info()}")
+    return e_f, e_a, e_n
+
+
+def test_tiny_radial_64(pnp):
+    w = synth.config_tiny()
+    x, S, k, _ = _case(w.n, w.L, w.traj.k, 1001)
+    errs = _run_ops(pnp, (w.n, w.n), x, S, k, None, "64x64 L4 radial 16x128")
+    assert max(errs) < TOL
+
+
+def test_clinical_spiral_320_with_dcf(pnp):
+    w = synth.config_clinical()
+    dcf = synth.voronoi_dcf(w.traj, w.n)
+    x, S, k, _ = _case(w.n, w.L, w.traj.k, 1002)
+    errs = _run_ops(pnp, (w.n, w.n), x, S, k, dcf, "320x320 L16 spiral 32x400 + Voronoi DCF")
+    assert max(errs) < TOL
+
+
+@pytest.mark.parametrize("shape,L,M", [((48, 80), 5, 1000), ((8, 8), 1, 37), ((12, 20), 3, 333),
+                                       ((96, 96), 6, 2049)])
+def test_ragged_shapes_and_coils(pnp, shape, L, M):
+    rng = np.random.default_rng(sum(shape) + L)
+    k = rng.uniform(-math.pi, math.pi, (M, 2)).astype(np.float32)
+    x = synth.white_complex(shape, 5)
+    S = synth.white_complex((L,) + shape, 6)
+    dcf = rng.uniform(0.2, 2.0, M).astype(np.float32)
+    errs = _run_ops(pnp, shape, x, S, k, dcf, f"ragged {shape} L{L} M{M}")
+    assert max(errs) < TOL
+
+
+def test_samples_on_the_boundary_and_outside(pnp):
+    """k = -pi, +pi, exact grid points and |k| > pi (the operator is 2*pi periodic)."""
+    n = 32
+    pts = [(-math.pi, -math.pi), (math.pi, 0.0), (0.0, 0.0), (-math.pi, math.pi / 2),
+           (2 * math.pi / n, -4 * math.pi / n), (3.5, -3.9), (9.0, -7.0), (1e-7, -1e-7)]
+    k = np.array(pts, dtype=np.float32)
+    x = synth.white_complex((n, n), 8)
+    S = synth.smaps2d(n, 2)
+    errs = _run_ops(pnp, (n, n), x, S, k, None, "boundary samples")
+    assert max(errs) < TOL
+
+
+def test_full_cartesian_identity(pnp):
+    """Full Cartesian sampling with SoS-1 maps: A^H A = I (up to the KB error)."""
+    n = 32
+    k = synth.cartesian2d(n)
+    x = synth.white_complex((n, n), 9)
+    S = synth.smaps2d(n, 4)
+    plan = pnp.Plan(to_dev(k), (n, n))
+    xn = to_np(plan.normal(to_dev(x), to_dev(S)))
+    sos = (np.abs(S.astype(np.complex128)) ** 2).sum(0)
+    assert rel_l2(xn, sos * x) < TOL
+
+
+def test_adjoint_identity_on_gpu(pnp):
+    n, L, M = 64, 4, 3000
+    rng = np.random.default_rng(3)
+    k = rng.uniform(-math.pi, math.pi, (M, 2)).astype(np.float32)
+    x = synth.white_complex((n, n), 10)
+    S = synth.smaps2d(n, L)
+    yv = synth.white_complex((L, M), 11)
+    plan = pnp.Plan(to_dev(k), (n, n))
+    Sd = to_dev(S)
+    Ax = to_np(plan.forward(to_dev(x), Sd)).astype(np.complex128)
+    Ahy = to_np(plan.adjoint(to_dev(yv), Sd)).astype(np.complex128)
+    lhs = np.vdot(Ax, yv.astype(np.complex128))
+    rhs = np.vdot(x.astype(np.complex128), Ahy)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5
+
+
+def test_zero_input_gives_zero(pnp):
+    w = synth.config_tiny()
+    plan = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    import torch
+    x = torch.zeros((w.n, w.n), dtype=torch.complex64, device="cuda")
+    S = to_dev(synth.smaps2d(w.n, w.L))
+    assert np.abs(to_np(plan.forward(x, S))).max() == 0.0
+    assert np.abs(to_np(plan.normal(x, S))).max() == 0.0
+
+
+def test_plan_rejects_nonfinite_trajectory(pnp):
+    import torch
+    k = torch.zeros((10, 2), dtype=torch.float32, device="cuda")
+    k[3, 1] = float("nan")
+    with pytest.raises(pnp.PnPError) as ei:
+        pnp.Plan(k, (16, 16))
+    assert ei.value.status == -6
+
+
+def test_workspace_too_small_is_rejected(pnp):
+    import ctypes as C
+    import torch
+    from paper_2411_01955_amd import _lib
+    w = synth.config_tiny()
+    plan = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    x = to_dev(synth.white_complex((w.n, w.n), 1))
+    S = to_dev(synth.smaps2d(w.n, w.L))
+    y = torch.empty((w.L, w.traj.k.shape[0]), dtype=torch.complex64, device="cuda")
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    st = _lib.load().pnp_forward(plan.handle, C.c_void_p(x.data_ptr()), C.c_void_p(S.data_ptr()), w.L,
+                                 C.c_void_p(y.data_ptr()), C.c_void_p(ws.data_ptr()), 1024, None)
+    assert st == -5

@@ -1,0 +1,106 @@
+"""GPU parity of the Haar prior, the power iteration and annealed PnP-HQS
+against the FP64 oracle (exact NDFT operator).  Bar for the final HQS image:
+relative L2 <= 1e-4."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ndft, solver, wavelet
+from tests.golden import make_golden
+from tests.gpu_util import rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pnp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_01955_amd as pnp
+    pnp.load()
+    return pnp
+
+
+@pytest.mark.parametrize("shape,J,tau", [((64, 64), 3, 0.05), ((320, 320), 4, 0.02), ((48, 80), 4, 0.3),
+                                         ((16, 8), 2, 0.0), ((32, 32), 2, 1e9)])
+def test_wavelet_prior_matches_oracle(pnp, shape, J, tau):
+    u = synth.white_complex(shape, 3) * 0.3
+    prior = pnp.WaveletPrior(J, 1.0)
+    out = to_np(prior(to_dev(u), tau))
+    ref = wavelet.wavelet_denoise(u, tau, J)
+    say(f"[wavelet] {shape} J={J} tau={tau}: rel {rel_l2(out, ref):.2e}")
+    assert rel_l2(out, ref) < 1e-6
+
+
+def test_wavelet_prior_in_place(pnp):
+    u = synth.white_complex((64, 64), 4)
+    ref = wavelet.wavelet_denoise(u, 0.2, 3)
+    d = to_dev(u)
+    pnp.WaveletPrior(3, 2.0)(d, 0.1, out=d)
+    assert rel_l2(to_np(d), ref) < 1e-6
+
+
+def _problem(w, seed):
+    x, roi = synth.phantom2d(w.n, seed)
+    S = synth.smaps2d(w.n, w.L)
+    k = w.traj.k
+    dcf = synth.voronoi_dcf(w.traj, w.n) if w.dcf else None
+    nu = synth.noise_variance(x, S)
+    y = ndft.forward(x, S, k) + synth.complex_noise((w.L, k.shape[0]), nu, synth.SEED_NOISE + seed)
+    return x, roi, S, k, dcf, y.astype(np.complex64)
+
+
+def test_opnorm_matches_oracle(pnp):
+    w = synth.config_tiny()
+    x, roi, S, k, dcf, y = _problem(w, 1)
+    ref, its = solver.opnorm(lambda v: ndft.normal(v, S, k, dcf), (w.n, w.n), tol=1e-12, maxit=3000)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    got = plan.opnorm(to_dev(S), None, iters=400, seed=5)
+    say(f"[opnorm] oracle {ref:.8f} ({its} its)  gpu {got:.8f}")
+    assert abs(got - ref) / ref < 2e-4
+
+
+def _hqs_case(pnp, w, seed, precond, lam_L, kappa, n_out=None):
+    x, roi, S, k, dcf, y = _problem(w, seed)
+    normal = lambda v: ndft.normal(v, S, k, dcf)
+    # The operator norm only parameterises the problem (alpha = 1/norm) and is
+    # handed to both sides: the clinical value is the oracle's stored Lanczos
+    # result, the tiny one a converged oracle power iteration.
+    if w.n == 320:
+        Ln = make_golden.load_opnorm()
+    else:
+        Ln, _ = solver.opnorm(normal, (w.n, w.n), tol=1e-12, maxit=3000)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, n_out or w.n_out)
+    lam = lam_L / Ln
+    b0 = ndft.adjoint(y, S, k, dcf)
+    yw2 = float(((dcf if dcf is not None else 1.0) * np.abs(y.astype(np.complex128)) ** 2).sum())
+
+    def prior_o(u, s):
+        say(f"   oracle outer step sigma={s:.4f}")
+        return wavelet.wavelet_denoise(u, kappa * s)
+    rep_o = solver.HQSReport()
+    x_ref = solver.hqs(b0, normal, sig, lam, precond, w.n_cg, prior_o, Ln, yw2=yw2, report=rep_o)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    xg, rep = pnp.hqs_solve(plan, to_dev(y), to_dev(S), to_dev(dcf) if dcf is not None else None,
+                            pnp.WaveletPrior(0, kappa), sig, lam, precond, w.n_cg, opnorm=Ln, report=True)
+    xg = to_np(xg)
+    e = rel_l2(xg, x_ref)
+    e_rho = max(abs(a - b) / abs(b) for a, b in zip(rep["rho"], rep_o.rho))
+    say(f"[hqs] {w.name} seed={seed} P={precond} n_out={len(sig)}: image rel {e:.3e}, rho rel {e_rho:.2e}")
+    return e, e_rho
+
+
+@pytest.mark.parametrize("precond", ["f1", "cheb", "id"])
+def test_hqs_tiny_matches_oracle(pnp, precond):
+    e, e_rho = _hqs_case(pnp, synth.config_tiny(), 1, precond, 30.0, 1.0)
+    assert e < 1e-4
+    assert e_rho < 1e-3
+
+
+def test_hqs_clinical_short_schedule_matches_oracle(pnp):
+    """320x320, 16 coils, spiral + Voronoi DCF; 3 outer x 5 CG steps
+    (18 normal operators in the oracle) to keep the CPU side short."""
+    e, e_rho = _hqs_case(pnp, synth.config_clinical(), 2, "f1", 30.0, 1.0, n_out=3)
+    assert e < 1e-4
+    assert e_rho < 1e-3
