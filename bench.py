@@ -1,0 +1,269 @@
+"""Benchmark: annealed PnP-HQS on the clinical workload, one MI355X.
+
+One *step* = one full annealed PnP-HQS reconstruction of a 320x320 slice
+with 16 coils from a variable-density spiral (32 interleaves x 400 samples,
+AF 8) with Voronoi density weighting: b0 = A^H D_w y, then 30 outer
+iterations of (5-step CG proximal solve in the F-1 metric + Haar prior),
+i.e. 180 applications of the normal operator A^H D_w A.  Inputs are seeded
+synthetic phantoms already resident in HBM.
+
+Printed JSON line:
+* ``value``  effective A^H A bandwidth over the whole step:
+             180 * B_alg / step time, B_alg = the algorithmic bytes of one
+             normal operator (x, coil maps twice, output, trajectory, DCF and
+             four crossings of the oversampled coil grids);
+* ``roofline``  the dominant kernel's algorithmic bytes per launch over its
+             mean launch time (HIP events around each launch, recorded on the
+             kernel's stream over a second pass of the same steps), against
+             8 TB/s; ``traffic`` from the committed rocprofv3 counter summary
+             when it matches the current kernel sources;
+* ``cpu_baseline``  the FP64 oracle (exact NDFT) timed on the host on one
+             outer HQS iteration of the same slice (6 normal operators),
+             scaled to the same unit.
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+LAM_TIMES_NORM = 30.0
+KAPPA = 1.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical.json")
+KERNEL_SOURCES = ["paper_2411_01955_amd/csrc/nufft2d.hip", "paper_2411_01955_amd/csrc/fft_lds.hpp",
+                  "paper_2411_01955_amd/csrc/plan.hip"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def b_alg_normal(n, L, M, d=2):
+    """Algorithmic bytes of one normal operator A^H D_w A (complex64 = 8 B):
+    x + coil maps (forward and adjoint) + output + trajectory (twice) + DCF +
+    4 crossings of the L oversampled (2n)^d grids."""
+    N = n ** d
+    G = (2 * n) ** d
+    return 8 * N + 2 * 8 * L * N + 8 * N + 2 * 4 * d * M + 4 * M + 4 * 8 * L * G
+
+
+def kernel_bytes(n, L, M, E, groups):
+    """Algorithmic (compulsory) bytes per launch of each kernel of the fused
+    2D operator (half-transformed grid mid[L][n][2n] crosses HBM twice per
+    direction; per-sample plan data j0 16 B + weights 48 B; entries 4 B)."""
+    N = n * n
+    mid = 8 * L * n * 2 * n
+    rec = 64 * E                      # packed per-entry taps and weights
+    out = {
+        "k_rows_fwd": 8 * N + 8 * L * N + mid,
+        "k_cols_fwd_interp": mid + 8 * L * E + rec,
+        "k_gather_entries": 8 * L * E + 8 * L * M + 8 * M,
+        "k_cols_adj_spread": 8 * L * M + 4 * M + rec + mid,
+        "k_rows_adj": mid + 8 * L * N + 8 * groups * N,
+        "k_sum_groups": 8 * groups * N + 8 * N,
+    }
+    out["k_rows_fwd_fs"] = out["k_rows_fwd"]
+    out["k_cols_fwd_fs"] = out["k_cols_fwd_interp"]
+    out["k_cols_adj_fs"] = out["k_cols_adj_spread"]
+    out["k_rows_adj_fs"] = out["k_rows_adj"]
+    return out
+
+
+def _kname(s: str) -> str:
+    """Trace names of templated kernels carry '(name<K1, K2>)'."""
+    s = s.strip("()")
+    return s.split("<")[0]
+
+
+def cpu_baseline(w, x, S, dcf, y, b_alg):
+    """Oracle (exact NDFT, numpy/OpenBLAS FP64) on one outer HQS iteration of
+    the same slice: 1 + n_cg normal operators plus the CG vector work."""
+    from oracle import ndft, solver, wavelet
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    k = w.traj.k
+    normal = lambda v: ndft.normal(v, S, k, dcf)
+    b0 = ndft.adjoint(y, S, k, dcf)
+    t0 = time.perf_counter()
+    solver.hqs(b0, normal, [w.sigma0], 1.0, "f1", w.n_cg,
+               lambda u, s: wavelet.wavelet_denoise(u, KAPPA * s), 17.0)
+    dt = time.perf_counter() - t0
+    n_ops = 1 + w.n_cg + 1          # the loop also forms N x of its result
+    gbps = n_ops * b_alg / dt / 1e9
+    return {"value": round(gbps, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one outer HQS iteration (1+{w.n_cg} CG normal operators + prior + residual "
+                      f"operator) of the 320x320/16-coil spiral slice, exact FP64 NDFT, {dt:.1f} s; "
+                      f"scaled as {n_ops} x B_alg / time; a full 30-iteration slice would take "
+                      f"~{dt * w.n_out:.0f} s",
+            "seconds_per_slice_extrapolated": round(dt * w.n_out, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 512 MiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--seed", type=int, default=1002)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
+              "of this workload would shard across GPUs as described in DESIGN.md, but no multi-GPU "
+              "path is built or measured.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2411_01955_amd as pnp
+
+    dev = torch.device("cuda:0")
+    w = synth.config_clinical()
+    n, L = w.n, w.L
+    k = w.traj.k
+    M = k.shape[0]
+    x_true, roi = synth.phantom2d(n, args.seed)
+    S = synth.smaps2d(n, L)
+    dcf = synth.voronoi_dcf(w.traj, n)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)
+
+    kt = torch.from_numpy(k).to(dev)
+    xd = torch.from_numpy(x_true).to(dev)
+    Sd = torch.from_numpy(S).to(dev)
+    dd = torch.from_numpy(dcf).to(dev)
+    plan = pnp.Plan(kt, (n, n))
+    info = plan.info()
+    # simulated acquisition (Sec. 4.1): y = A x + e, nu = 1e-4 max sum_l |S_l x|^2
+    y = plan.forward(xd, Sd)
+    nu = synth.noise_variance(x_true, S)
+    y += torch.from_numpy(synth.complex_noise((L, M), nu, synth.SEED_NOISE + args.seed)).to(dev)
+    nrm = plan.opnorm(Sd, dd, iters=100, seed=1)
+    lam = LAM_TIMES_NORM / nrm
+    prior = pnp.WaveletPrior(0, KAPPA)
+    out = torch.empty((n, n), dtype=torch.complex64, device=dev)
+    ws, _ = plan.workspace(L, "hqs")
+
+    def step():
+        pnp.hqs_solve(plan, y, Sd, dd, prior, sig, lam, "f1", w.n_cg, opnorm=nrm, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    n_normal = w.n_out * (1 + w.n_cg)
+    B = b_alg_normal(n, L, M)
+    value = n_normal * B / (ms / 1e3) / 1e9
+
+    # quality of the reconstruction (outside the timed region)
+    xr = out.cpu().numpy()
+    from_mag = np.abs(xr)
+    err = from_mag[roi] - np.abs(x_true)[roi]
+    psnr = 20 * math.log10(np.abs(x_true)[roi].max() / math.sqrt(np.mean(err ** 2)))
+
+    # normal operator alone, back to back
+    tmp = torch.empty_like(xd)
+    for _ in range(5):
+        plan.normal(xd, Sd, dd, out=tmp)
+    torch.cuda.synchronize()
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.normal(xd, Sd, dd, out=tmp)
+    torch.cuda.synchronize()
+    normal_us = (time.perf_counter() - t0) * 1e6 / reps
+
+    # traced pass: per-kernel durations with HIP events on the launch stream
+    pnp.trace_enable(True)
+    pnp.trace_read()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tr = {}
+    for kname, (c, t) in pnp.trace_read().items():
+        c0, t0 = tr.get(_kname(kname), (0, 0.0))
+        tr[_kname(kname)] = (c0 + c, t0 + t)
+    pnp.trace_enable(False)
+    groups = (L + 3) // 4
+    kb = kernel_bytes(n, L, M, info["entries"], groups)
+    dom = max((kname for kname in tr if kname in kb), key=lambda kname: tr[kname][1])
+    launches, tot_ms = tr[dom]
+    avg_s = tot_ms / launches / 1e3
+    achieved = kb[dom] / avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tf = json.load(f)
+        ent = tf.get("kernels", {}).get(dom)
+        if ent and tf.get("source_hash") == kernel_source_hash():
+            traffic = ent.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom,
+                "alg_bytes_per_launch": kb[dom], "avg_launch_us": round(avg_s * 1e6, 2)}
+    kernel_table = {kname: {"launches": c, "avg_us": round(t / c * 1e3, 2),
+                            "share": round(t / sum(v[1] for v in tr.values()), 4)}
+                    for kname, (c, t) in sorted(tr.items(), key=lambda kv: -kv[1][1])}
+
+    if args.calib_copy:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, x_true, S, dcf, y.cpu().numpy(), B)
+
+    line = {
+        "metric": "NUFFT A^H A GB/s; slices/s to fixed PSNR, learned vs wavelet HQS",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "coils": L, "samples": M, "outer": w.n_out, "cg": w.n_cg,
+                   "prior": "haar", "precond": "f1", "dcf": "voronoi", "normal_ops_per_step": n_normal,
+                   "b_alg_bytes": B},
+        "slices_per_s": round(1e3 / ms, 3),
+        "psnr_db": round(psnr, 3),
+        "normal_op_us": round(normal_us, 2),
+        "normal_op_GBps": round(B / (normal_us * 1e-6) / 1e9, 1),
+        "roofline": roofline,
+        "kernels": kernel_table,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,6 +75,18 @@ const char* pnp_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t pnp_version(void);
 
+/* Kernel tracing (instrumentation, not part of the method).  While enabled
+ * (on != 0), every kernel the library launches is bracketed by two HIP
+ * events recorded on the kernel's own stream.  pnp_trace_read waits for the
+ * recorded events, writes a NUL-terminated JSON object
+ *   {"kernel_name": [launch_count, total_milliseconds], ...}
+ * into buf (host, len bytes), stores the size needed (including the NUL) in
+ * *needed when needed is not NULL, and clears the totals.  buf may be NULL
+ * to query the size only (the totals are then lost: query with a large
+ * buffer instead).  PNP_ERR_ARG when buf is too small. */
+pnp_status pnp_trace_enable(int32_t on);
+pnp_status pnp_trace_read(char* buf, size_t len, size_t* needed);
+
 /* ------------------------------------------------------------------ plan */
 typedef struct pnp_plan pnp_plan;
 

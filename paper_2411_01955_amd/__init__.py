@@ -18,7 +18,21 @@ import ctypes as C
 
 from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, check, load
 
-__all__ = ["Plan", "WaveletPrior", "hqs_solve", "PnPError", "load"]
+__all__ = ["Plan", "WaveletPrior", "hqs_solve", "PnPError", "load", "trace_enable", "trace_read"]
+
+
+def trace_enable(on: bool = True):
+    """Start/stop bracketing every library kernel with HIP events."""
+    check(load().pnp_trace_enable(1 if on else 0))
+
+
+def trace_read():
+    """{kernel: (launches, total_ms)} since the last read (waits for the events)."""
+    import json
+    buf = C.create_string_buffer(1 << 20)
+    need = C.c_size_t()
+    check(load().pnp_trace_read(buf, len(buf), C.byref(need)))
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def _torch():

@@ -52,6 +52,8 @@ _dbl = C.c_double
 SIGNATURES = {
     "pnp_last_error": (C.c_char_p, []),
     "pnp_version": (_i32, []),
+    "pnp_trace_enable": (_i32, [_i32]),
+    "pnp_trace_read": (_i32, [C.c_char_p, _sz, C.POINTER(_sz)]),
     "pnp_plan_create": (_i32, [C.POINTER(_vp), _i32, C.POINTER(_i32), _i64, _vp, _vp]),
     "pnp_plan_destroy": (_i32, [_vp]),
     "pnp_plan_info": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i64)]),
@@ -76,6 +78,9 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch's HIP runtime must be the one in the process before the library
+    # is mapped, so that both share a single runtime (same soname).
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build it with `python -m paper_2411_01955_amd.build` "

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "common.hpp"
+#include "trace.hpp"
 
 namespace pnp {
 
@@ -80,6 +81,23 @@ extern "C" {
 const char* pnp_last_error(void) { return g_err.c_str(); }
 
 int32_t pnp_version(void) { return 100; }
+
+pnp_status pnp_trace_enable(int32_t on) {
+  return guarded([&] { trace_enable(on != 0); });
+}
+
+pnp_status pnp_trace_read(char* buf, size_t len, size_t* needed) {
+  return guarded([&] {
+    const std::string s = trace_read_json();
+    if (needed) *needed = s.size() + 1;
+    if (buf && len) {
+      const size_t n = std::min(len - 1, s.size());
+      memcpy(buf, s.data(), n);
+      buf[n] = 0;
+      if (n < s.size()) fail(PNP_ERR_ARG, "trace buffer of %zu bytes is too small (%zu needed)", len, s.size() + 1);
+    }
+  });
+}
 
 pnp_status pnp_plan_create(pnp_plan** out, int32_t ndim, const int32_t* shape, int64_t M,
                            const float* traj, hipStream_t stream) {

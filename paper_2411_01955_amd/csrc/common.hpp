@@ -69,6 +69,14 @@ struct Axis {
   float* deapod;     // device [n]: I0(beta) / Phi((i - n/2)/K)
 };
 
+// One (sample, tile) entry, packed for a single 64-byte load in the 2D
+// kernels: idx = (first x tap, first y tap, sample, 0), w0..w2 = the 6 x
+// weights followed by the 6 y weights.
+struct alignas(16) EntryRec {
+  int4 idx;
+  float4 w0, w1, w2;
+};
+
 }  // namespace pnp
 
 // The opaque plan handle of the ABI.
@@ -89,8 +97,10 @@ struct pnp_plan {
   int4* j0;                 // [M] wrapped first tap index per axis (x, y, z)
   float* wts;               // [M][ndim][W] kernel weights phi(g - j) / I0(beta)
   int32_t* tile_off;        // [ntiles + 1]
+  int32_t* row_start;       // [ntiles][K_last + 1] first entry per first-tap row
   int32_t* ent_sample;      // [E] sample of each entry, grouped by tile
   int32_t* sample_ent;      // [M][slots] entry indices of a sample (-1: none)
+  pnp::EntryRec* rec;       // [E] packed taps and weights, grouped by tile (2D)
   void* block;
   size_t block_bytes;
 };
@@ -109,6 +119,7 @@ struct OpWorkspace {
   float2* mid;     // [L][rows][Kx]  half-transformed grid (2D) / [L][nz][ny][Kx]... (3D)
   float2* ypart;   // [L][E]         per-entry partial interpolation sums
   float2* ytmp;    // [L][M]         k-space scratch for the normal operator
+  float2* yent;    // [L][E]         weighted k-space values in entry order
   float2* part;    // [G][N]         per-coil-group partial images
   size_t bytes;
 };
@@ -121,6 +132,20 @@ void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, 
                 float2* x, const OpWorkspace& w, hipStream_t s);
 void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,
                float2* out, const OpWorkspace& w, hipStream_t s);
+
+// Normal operator as used inside the solver: the input is x, or (when r is
+// given) the CG direction p' = r + (*beta) x, which is also stored to pnew;
+// the result is left as op_groups(L) partial images in w.part ([G][N],
+// summed by the consumer).
+struct NormalIn {
+  const float2* x;
+  const float2* r;
+  float2* pnew;
+  const double* beta;
+};
+int op_groups(int L);
+void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
+                     const float* dcf, const OpWorkspace& w, hipStream_t s);
 
 int64_t image_size(const pnp_plan* p);
 

@@ -2,26 +2,30 @@
 // step fused so that the oversampled grid never travels through HBM:
 //
 //   forward  A x   (Eq. 1, y_l = F_Omega S_l x)
-//     k_rows_fwd       pre (x * S_l * deapod) + zero pad + row FFT (along x)
-//                      -> mid[l][iy][Kx]       (only the ny image rows exist)
-//     k_cols_fwd_interp  strip of `tile` grid columns: column FFT (along y)
-//                      in LDS, then type-2 interpolation of the samples whose
-//                      footprint touches the strip -> per-entry partial sums
-//     k_gather_entries   y_l[m] = N^{-1/2} * sum of the sample's partials
+//     rows_fwd        pre (x * S_l * deapod) + zero pad + row FFT (along x)
+//                     -> mid[l][iy][Kx]       (only the ny image rows exist)
+//     cols_fwd        strip of `tile` grid columns: column FFT (along y) in
+//                     LDS, then type-2 interpolation of the entries (samples
+//                     whose footprint touches the strip) -> per-entry partials
+//     k_gather_entries  y_l[m] = N^{-1/2} * sum of the sample's partials
 //   adjoint  A^H D_w y
-//     k_cols_adj_spread  strip: type-1 spread of w_m y_l[m] into LDS with LDS
-//                      atomics, column inverse FFT, keep the ny image rows
-//                      -> mid[l][iy][Kx]
-//     k_rows_adj       row inverse FFT, crop, deapod, conj(S_l), coil sum
-//                      -> per-coil-group partial images
-//     k_sum_groups     out = N^{-1/2} sum over coil groups
+//     cols_adj        strip: type-1 spread of w_m y_l[m] into LDS (LDS
+//                     atomics), column inverse FFT, keep the ny image rows
+//                     -> mid[l][iy][Kx]
+//     rows_adj        row inverse FFT, crop, deapod, conj(S_l), sum over the
+//                     coils of the workgroup -> per-coil-group partial images
+//     k_sum_groups    out = sum over coil groups
 //
-// Pixel r = i - n/2 sits at grid index r mod K; grid index j is frequency
-// j (mod K).  Kernel weights and deapodisation come from the plan.
+// Two implementations of the transforms: grid sizes with a register
+// factorisation K = K1*K2 (fft_reg.hpp) use the four-step kernels (*_fs),
+// all others the LDS Stockham kernels.  Pixel r = i - n/2 sits at grid index
+// r mod K; grid index j is frequency j (mod K).
 #include <algorithm>
 
 #include "common.hpp"
 #include "fft_lds.hpp"
+#include "fft_reg.hpp"
+#include "trace.hpp"
 
 namespace pnp {
 
@@ -43,8 +47,114 @@ __device__ __forceinline__ int grid_of_img(int i, int n, int K) {
   return r < 0 ? r + K : r;
 }
 
+// Image input of the forward row pass: the image x, or -- inside CG -- the
+// direction update p' = r + beta p computed on the fly (x = p, beta read
+// from the device scalars); the workgroups of coil group 0 store p'.
+struct ImgIn {
+  const float2* x;
+  const float2* r;      // nullptr: plain image input
+  float2* pnew;
+  const double* beta;
+};
+
+__device__ __forceinline__ float img_beta(const ImgIn& in) {
+  return in.r ? (float)*in.beta : 0.f;
+}
+__device__ __forceinline__ float2 img_at(const ImgIn& in, long long pix, float bt, bool store) {
+  if (!in.r) return in.x[pix];
+  const float2 rv = in.r[pix], pv = in.x[pix];
+  const float2 v = make_float2(fmaf(bt, pv.x, rv.x), fmaf(bt, pv.y, rv.y));
+  if (store) in.pnew[pix] = v;
+  return v;
+}
+
+// k-space input of the adjoint column pass: y[l][m], or -- inside the
+// normal operator -- the sum of the sample's interpolation partials.
+struct KIn {
+  const float2* y;          // [L][M]; nullptr: use the partials
+  const float2* ypart;      // [L][E]
+  const int* sample_ent;    // [M][2]
+  long long M, E;
+};
+
+__device__ __forceinline__ float2 k_at(const KIn& in, int l, int m) {
+  if (in.y) return in.y[(long long)l * in.M + m];
+  const int e0 = in.sample_ent[2 * (long long)m], e1 = in.sample_ent[2 * (long long)m + 1];
+  float2 v = make_float2(0.f, 0.f);
+  if (e0 >= 0) v = in.ypart[(long long)l * in.E + e0];
+  if (e1 >= 0) v = cadd(v, in.ypart[(long long)l * in.E + e1]);
+  return v;
+}
+
+struct Taps {
+  int jx, jy, m;
+  float wx[6], wy[6];
+};
+
+__device__ __forceinline__ Taps load_taps(const EntryRec* __restrict__ rec, int e) {
+  const EntryRec r = rec[e];
+  Taps t;
+  t.jx = r.idx.x;
+  t.jy = r.idx.y;
+  t.m = r.idx.z;
+  t.wx[0] = r.w0.x; t.wx[1] = r.w0.y; t.wx[2] = r.w0.z; t.wx[3] = r.w0.w;
+  t.wx[4] = r.w1.x; t.wx[5] = r.w1.y;
+  t.wy[0] = r.w1.z; t.wy[1] = r.w1.w;
+  t.wy[2] = r.w2.x; t.wy[3] = r.w2.y; t.wy[4] = r.w2.z; t.wy[5] = r.w2.w;
+  return t;
+}
+
+// type-2 interpolation of one entry from a strip held in LDS as columns
+// g[c*GS + row], c < tile (grid columns c0 + c)
+__device__ __forceinline__ float2 interp_entry(const Taps& t, const float2* __restrict__ g, int GS,
+                                               int c0, int tile, int Kx, int Ky) {
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int ta = 0; ta < 6; ++ta) {
+    int col = t.jx + ta;
+    if (col >= Kx) col -= Kx;
+    const int c = col - c0;
+    if ((unsigned)c < (unsigned)tile) {
+      float2 sum = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int tb = 0; tb < 6; ++tb) {
+        int row = t.jy + tb;
+        if (row >= Ky) row -= Ky;
+        sum = cfma(t.wy[tb], g[c * GS + row], sum);
+      }
+      acc = cfma(t.wx[ta], sum, acc);
+    }
+  }
+  return acc;
+}
+
+// type-1 spread of one entry into the LDS strip (LDS float atomics)
+__device__ __forceinline__ void spread_entry(const Taps& t, float2 v, float2* g, int GS, int c0,
+                                             int tile, int Kx, int Ky) {
+#pragma unroll
+  for (int ta = 0; ta < 6; ++ta) {
+    int col = t.jx + ta;
+    if (col >= Kx) col -= Kx;
+    const int c = col - c0;
+    if ((unsigned)c < (unsigned)tile) {
+      const float2 vx = cscale(v, t.wx[ta]);
+#pragma unroll
+      for (int tb = 0; tb < 6; ++tb) {
+        int row = t.jy + tb;
+        if (row >= Ky) row -= Ky;
+        float* dst = reinterpret_cast<float*>(&g[c * GS + row]);
+        atomicAdd(dst, vx.x * t.wy[tb]);
+        atomicAdd(dst + 1, vx.y * t.wy[tb]);
+      }
+    }
+  }
+}
+
+// =====================================================================
+// Generic path: LDS Stockham transforms (any 2,3,5-smooth K)
+// =====================================================================
 __global__ void __launch_bounds__(kThreads)
-k_rows_fwd(const float2* __restrict__ x, const float2* __restrict__ S, int L, int nx, int ny,
+k_rows_fwd(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
            const float* __restrict__ dax, const float* __restrict__ day, FFTDesc fd,
            float2* __restrict__ mid) {
   extern __shared__ float2 lds[];
@@ -56,6 +166,7 @@ k_rows_fwd(const float2* __restrict__ x, const float2* __restrict__ S, int L, in
   float2* a = lds;
   float2* b = lds + kRowCoils * Kx;
   const float sy = day[iy];
+  const float bt = img_beta(in);
   for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
     const int li = t / Kx;
     const int j = t - li * Kx;
@@ -63,7 +174,8 @@ k_rows_fwd(const float2* __restrict__ x, const float2* __restrict__ S, int L, in
     float2 v = make_float2(0.f, 0.f);
     if (ix >= 0) {
       const long long pix = (long long)iy * nx + ix;
-      v = cscale(cmul(S[(long long)(l0 + li) * N + pix], x[pix]), dax[ix] * sy);
+      const float2 xv = img_at(in, pix, bt, li == 0 && blockIdx.y == 0);
+      v = cscale(cmul(S[(long long)(l0 + li) * N + pix], xv), dax[ix] * sy);
     }
     a[li * Kx + j] = v;
   }
@@ -78,9 +190,8 @@ k_rows_fwd(const float2* __restrict__ x, const float2* __restrict__ S, int L, in
 
 __global__ void __launch_bounds__(kThreads)
 k_cols_fwd_interp(const float2* __restrict__ mid, int nx, int ny, int Kx, FFTDesc fd, int tile,
-                  int LS, const int* __restrict__ tile_off, const int* __restrict__ ent_sample,
-                  const int4* __restrict__ j0, const float* __restrict__ wts, long long E,
-                  float2* __restrict__ ypart) {
+                  int LS, const int* __restrict__ tile_off, const EntryRec* __restrict__ rec,
+                  long long E, float2* __restrict__ ypart) {
   extern __shared__ float2 lds[];
   const int Ky = fd.K;
   const int s = blockIdx.x;
@@ -100,49 +211,15 @@ k_cols_fwd_interp(const float2* __restrict__ mid, int nx, int ny, int Kx, FFTDes
   const float2* g = lds_fft<false>(a, b, tile, LS, fd);
   const int e0 = tile_off[s], e1 = tile_off[s + 1];
   for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int m = ent_sample[e];
-    const int4 jj = j0[m];
-    const float* w = wts + (long long)m * 12;
-    float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int ta = 0; ta < 6; ++ta) {
-      int col = jj.x + ta;
-      if (col >= Kx) col -= Kx;
-      const int c = col - c0;
-      if ((unsigned)c < (unsigned)tile) {
-        float2 sum = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int tb = 0; tb < 6; ++tb) {
-          int row = jj.y + tb;
-          if (row >= Ky) row -= Ky;
-          sum = cfma(w[6 + tb], g[c * LS + row], sum);
-        }
-        acc = cfma(w[ta], sum, acc);
-      }
-    }
-    ypart[(long long)l * E + e] = acc;
+    const Taps t = load_taps(rec, e);
+    ypart[(long long)l * E + e] = interp_entry(t, g, LS, c0, tile, Kx, Ky);
   }
 }
 
-__global__ void k_gather_entries(const float2* __restrict__ ypart, const int* __restrict__ sample_ent,
-                                 long long M, long long E, int L, float scale, float2* __restrict__ y) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= M * L) return;
-  const int l = (int)(t / M);
-  const long long m = t - (long long)l * M;
-  const int e0 = sample_ent[m * 2];
-  const int e1 = sample_ent[m * 2 + 1];
-  float2 v = make_float2(0.f, 0.f);
-  if (e0 >= 0) v = ypart[(long long)l * E + e0];
-  if (e1 >= 0) v = cadd(v, ypart[(long long)l * E + e1]);
-  y[t] = cscale(v, scale);
-}
-
 __global__ void __launch_bounds__(kThreads)
-k_cols_adj_spread(const float2* __restrict__ y, const float* __restrict__ dcf, float scale,
-                  long long M, int nx, int ny, int Kx, FFTDesc fd, int tile, int LS,
-                  const int* __restrict__ tile_off, const int* __restrict__ ent_sample,
-                  const int4* __restrict__ j0, const float* __restrict__ wts,
+k_cols_adj_spread(const float2* __restrict__ yent, long long E,
+                  int nx, int ny, int Kx, FFTDesc fd, int tile, int LS,
+                  const int* __restrict__ tile_off, const EntryRec* __restrict__ rec,
                   float2* __restrict__ mid) {
   extern __shared__ float2 lds[];
   const int Ky = fd.K;
@@ -155,29 +232,8 @@ k_cols_adj_spread(const float2* __restrict__ y, const float* __restrict__ dcf, f
   __syncthreads();
   const int e0 = tile_off[s], e1 = tile_off[s + 1];
   for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int m = ent_sample[e];
-    const int4 jj = j0[m];
-    const float* w = wts + (long long)m * 12;
-    float2 v = y[(long long)l * M + m];
-    const float sc = dcf ? dcf[m] * scale : scale;
-    v = cscale(v, sc);
-#pragma unroll
-    for (int ta = 0; ta < 6; ++ta) {
-      int col = jj.x + ta;
-      if (col >= Kx) col -= Kx;
-      const int c = col - c0;
-      if ((unsigned)c < (unsigned)tile) {
-        const float2 vx = cscale(v, w[ta]);
-#pragma unroll
-        for (int tb = 0; tb < 6; ++tb) {
-          int row = jj.y + tb;
-          if (row >= Ky) row -= Ky;
-          float* dst = reinterpret_cast<float*>(&a[c * LS + row]);
-          atomicAdd(dst, vx.x * w[6 + tb]);
-          atomicAdd(dst + 1, vx.y * w[6 + tb]);
-        }
-      }
-    }
+    const Taps t = load_taps(rec, e);
+    spread_entry(t, yent[(long long)l * E + e], a, LS, c0, tile, Kx, Ky);
   }
   __syncthreads();
   const float2* g = lds_fft<true>(a, b, tile, LS, fd);
@@ -191,7 +247,7 @@ k_cols_adj_spread(const float2* __restrict__ y, const float* __restrict__ dcf, f
 
 __global__ void __launch_bounds__(kThreads)
 k_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
-           const float* __restrict__ dax, const float* __restrict__ day, FFTDesc fd, float scale,
+           const float* __restrict__ dax, const float* __restrict__ day, FFTDesc fd,
            float2* __restrict__ part) {
   extern __shared__ float2 lds[];
   const int Kx = fd.K;
@@ -209,18 +265,350 @@ k_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L, 
   }
   __syncthreads();
   const float2* r = lds_fft<true>(a, b, nl, Kx, fd);
-  const float sy = day[iy] * scale;
+  const float sy = day[iy];
   for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
     const int jx = grid_of_img(ix, nx, Kx);
     const long long pix = (long long)iy * nx + ix;
     float2 acc = make_float2(0.f, 0.f);
-    for (int li = 0; li < nl; ++li) {
-      const float2 sv = S[(long long)(l0 + li) * N + pix];
-      const float2 gv = r[li * Kx + jx];
-      acc = cadd(acc, cmulc(sv, gv));
-    }
+    for (int li = 0; li < nl; ++li)
+      acc = cadd(acc, cmulc(S[(long long)(l0 + li) * N + pix], r[li * Kx + jx]));
     part[(long long)g * N + pix] = cscale(acc, dax[ix] * sy);
   }
+}
+
+// =====================================================================
+// Register path: four-step transforms, K = K1*K2
+// =====================================================================
+template <int K1, int K2>
+struct FS {
+  static constexpr int K = K1 * K2;
+  static constexpr int AS = K2 + 1;                 // LDS row stride of the transpose
+  static constexpr int LA = K1 * AS;                // one line's transpose block
+  static constexpr int CS = ((LA + 13) / 16) * 16 + 2;   // column stride, = 2 mod 16
+  static constexpr int GS = ((K + 13) / 16) * 16 + 2;    // grid column stride, = 2 mod 16
+  static constexpr int CSTR = CS > GS ? CS : GS;         // strip LDS per column
+};
+
+template <int K1, int K2, bool INV>
+__device__ __forceinline__ void fs_twiddle(float2 (&v)[K1], int t, const float2* __restrict__ tw) {
+#pragma unroll
+  for (int k1 = 1; k1 < K1; ++k1) {
+    float2 w = tw[t * k1];
+    if (INV) w.y = -w.y;
+    v[k1] = cmul(v[k1], w);
+  }
+}
+
+template <int K1, int K2>
+__global__ void __launch_bounds__(kRowCoils * K1)
+k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
+              const float* __restrict__ dax, const float* __restrict__ day,
+              const float2* __restrict__ tw, float2* __restrict__ mid) {
+  using F = FS<K1, K2>;
+  __shared__ float2 A[kRowCoils * F::LA];
+  const int line = threadIdx.x / K1;
+  const int t = threadIdx.x % K1;
+  const int iy = blockIdx.x;
+  const int l = blockIdx.y * kRowCoils + line;
+  const bool active = l < L;
+  const long long N = (long long)nx * ny;
+  float2* Al = A + line * F::LA;
+  if (active && t < K2) {
+    float2 v[K1];
+    const float sy = day[iy];
+    const float bt = img_beta(in);
+    const bool store = line == 0 && blockIdx.y == 0;
+    const float2* Sl = S + (long long)l * N + (long long)iy * nx;
+    const long long row0 = (long long)iy * nx;
+#pragma unroll
+    for (int n1 = 0; n1 < K1; ++n1) {
+      const int ix = img_of_grid(n1 * K2 + t, nx, F::K);
+      v[n1] = ix >= 0 ? cscale(cmul(Sl[ix], img_at(in, row0 + ix, bt, store)), dax[ix] * sy)
+                      : make_float2(0.f, 0.f);
+    }
+    reg::dft<K1, false>(v);
+    fs_twiddle<K1, K2, false>(v, t, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) Al[k1 * F::AS + t] = v[k1];
+  }
+  __syncthreads();
+  if (active) {
+    float2 u[K2];
+#pragma unroll
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = Al[t * F::AS + n2];
+    reg::dft<K2, false>(u);
+    float2* dst = mid + ((long long)l * ny + iy) * F::K;
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) dst[t + K1 * k2] = u[k2];
+  }
+}
+
+template <int K1, int K2>
+__global__ void __launch_bounds__(8 * K1)
+k_cols_fwd_fs(const float2* __restrict__ mid, int nx, int ny, int Kx, const float2* __restrict__ tw,
+              int tile, const int* __restrict__ tile_off, const EntryRec* __restrict__ rec, long long E,
+              float2* __restrict__ ypart) {
+  using F = FS<K1, K2>;
+  __shared__ float2 lds[8 * F::CSTR];
+  const int c = threadIdx.x % 8;
+  const int t = threadIdx.x / 8;
+  const int s = blockIdx.x;
+  const int l = blockIdx.y;
+  const int c0 = s * tile;
+  const bool colok = c < tile;
+  if (colok && t < K2) {
+    float2 v[K1];
+#pragma unroll
+    for (int n1 = 0; n1 < K1; ++n1) {
+      const int iy = img_of_grid(n1 * K2 + t, ny, F::K);
+      v[n1] = iy >= 0 ? mid[((long long)l * ny + iy) * Kx + c0 + c] : make_float2(0.f, 0.f);
+    }
+    reg::dft<K1, false>(v);
+    fs_twiddle<K1, K2, false>(v, t, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];
+  }
+  __syncthreads();
+  float2 u[K2];
+  if (colok) {
+#pragma unroll
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
+    reg::dft<K2, false>(u);
+  }
+  __syncthreads();
+  if (colok) {
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) lds[c * F::GS + t + K1 * k2] = u[k2];
+  }
+  __syncthreads();
+  const int e0 = tile_off[s], e1 = tile_off[s + 1];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const Taps tp = load_taps(rec, e);
+    ypart[(long long)l * E + e] = interp_entry(tp, lds, F::GS, c0, tile, Kx, F::K);
+  }
+}
+
+constexpr int kSpreadChunk = 256;   // entries staged in LDS at a time
+constexpr int kAdjThreads = 512;    // spread uses all waves, the FFT the first 8*K1 threads
+constexpr int kAdjWaves = kAdjThreads / 64;
+constexpr int kSpreadIlp = 8;       // entries in flight per lane in the gather loop
+
+// Type-1 spread by gathering: wave w owns the 8x8 grid-point blocks
+// (rows 8*rb .. 8*rb+7 of the strip's 8 columns) with rb = w, w + 8, ...;
+// lane (row lr = lane/8, column lc = lane%8) accumulates in registers every
+// entry whose first row tap lies within 5 rows above its block (entries are
+// sorted by first row tap, row_start indexes them), reading the entry's taps,
+// weights and weighted k-space value from LDS as broadcasts.  Each grid
+// point is written once: no atomics, deterministic summation order.
+template <int K1, int K2>
+__global__ void __launch_bounds__(kAdjThreads)
+k_cols_adj_fs(const float2* __restrict__ yent, long long E,
+              int nx, int ny, int Kx, const float2* __restrict__ tw, int tile,
+              const int* __restrict__ tile_off, const int* __restrict__ row_start,
+              const EntryRec* __restrict__ rec, float2* __restrict__ mid) {
+  using F = FS<K1, K2>;
+  constexpr int NRB = F::K / 8;                                  // row blocks per strip
+  constexpr int RBW = (NRB + kAdjWaves - 1) / kAdjWaves;         // row blocks per wave
+  __shared__ float2 lds[8 * F::CSTR];
+  __shared__ EntryRec srec[kSpreadChunk];
+  __shared__ float2 sval[kSpreadChunk];
+  __shared__ int srs[F::K + 1];
+  const int c = threadIdx.x % 8;
+  const int t = threadIdx.x / 8;           // FFT threads: t < K1
+  const int s = blockIdx.x;
+  const int l = blockIdx.y;
+  const int c0 = s * tile;
+  const bool colok = c < tile && t < K1;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lr = lane >> 3, lc = lane & 7;
+  int gc = c0 + lc;
+  if (gc >= Kx) gc -= Kx;
+  for (int i = threadIdx.x; i <= F::K; i += blockDim.x) srs[i] = row_start[(long long)s * (F::K + 1) + i];
+  float2 acc[RBW];
+#pragma unroll
+  for (int k = 0; k < RBW; ++k) acc[k] = make_float2(0.f, 0.f);
+  const int e0 = tile_off[s], e1 = tile_off[s + 1];
+  const float* srec_f = reinterpret_cast<const float*>(srec);
+  for (int cb = e0; cb < e1; cb += kSpreadChunk) {
+    const int n = min(kSpreadChunk, e1 - cb);
+    __syncthreads();  // previous chunk consumed (and srs staged)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      srec[i] = rec[cb + i];
+      sval[i] = yent[(long long)l * E + cb + i];
+    }
+    __syncthreads();
+    const int ce = cb + n;
+#pragma unroll
+    for (int k = 0; k < RBW; ++k) {
+      const int rb = wave + k * kAdjWaves;
+      if (rb < NRB) {
+        const int r0 = rb * 8;
+        const int row = r0 + lr;
+        const int lo = r0 - 5, hi = r0 + 8;
+        int ra0, rb0, ra1, rb1;
+        if (lo >= 0) {
+          ra0 = srs[lo]; rb0 = srs[hi]; ra1 = 0; rb1 = 0;
+        } else {
+          ra0 = srs[F::K + lo]; rb0 = srs[F::K]; ra1 = srs[0]; rb1 = srs[hi];
+        }
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+          const int ea = max(part ? ra1 : ra0, cb);
+          const int eb = min(part ? rb1 : rb0, ce);
+          // kSpreadIlp independent entries per step: all LDS reads of a step
+          // are issued before any is consumed; out-of-range entries are
+          // clamped to a valid index and masked to zero weight
+          for (int e = ea; e < eb; e += kSpreadIlp) {
+            int ii[kSpreadIlp], dxc[kSpreadIlp], dyc[kSpreadIlp];
+            bool ok[kSpreadIlp];
+            int4 idx[kSpreadIlp];
+#pragma unroll
+            for (int u = 0; u < kSpreadIlp; ++u) {
+              ii[u] = min(e + u, eb - 1) - cb;
+              idx[u] = srec[ii[u]].idx;
+            }
+#pragma unroll
+            for (int u = 0; u < kSpreadIlp; ++u) {
+              int dx = gc - idx[u].x;
+              dx += dx < 0 ? Kx : 0;
+              int dy = row - idx[u].y;
+              dy += dy < 0 ? F::K : 0;
+              ok[u] = dx < 6 && dy < 6 && e + u < eb;
+              dxc[u] = ok[u] ? dx : 0;
+              dyc[u] = ok[u] ? dy : 0;
+            }
+            float wx[kSpreadIlp], wy[kSpreadIlp];
+            float2 sv[kSpreadIlp];
+#pragma unroll
+            for (int u = 0; u < kSpreadIlp; ++u) {
+              wx[u] = srec_f[16 * ii[u] + 4 + dxc[u]];
+              wy[u] = srec_f[16 * ii[u] + 10 + dyc[u]];
+              sv[u] = sval[ii[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kSpreadIlp; ++u) {
+              const float wgt = ok[u] ? wx[u] * wy[u] : 0.f;
+              acc[k] = make_float2(fmaf(wgt, sv[u].x, acc[k].x), fmaf(wgt, sv[u].y, acc[k].y));
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (lc < tile) {
+#pragma unroll
+    for (int k = 0; k < RBW; ++k) {
+      const int rb = wave + k * kAdjWaves;
+      if (rb < NRB) lds[lc * F::GS + rb * 8 + lr] = acc[k];
+    }
+  }
+  __syncthreads();
+  float2 v[K1];
+  if (colok && t < K2) {
+#pragma unroll
+    for (int n1 = 0; n1 < K1; ++n1) v[n1] = lds[c * F::GS + n1 * K2 + t];
+  }
+  __syncthreads();
+  if (colok && t < K2) {
+    reg::dft<K1, true>(v);
+    fs_twiddle<K1, K2, true>(v, t, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];
+  }
+  __syncthreads();
+  if (colok) {
+    float2 u[K2];
+#pragma unroll
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
+    reg::dft<K2, true>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) {
+      const int iy = img_of_grid(t + K1 * k2, ny, F::K);
+      if (iy >= 0) mid[((long long)l * ny + iy) * Kx + c0 + c] = u[k2];
+    }
+  }
+}
+
+template <int K1, int K2>
+__global__ void __launch_bounds__(kRowCoils * K1)
+k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
+              const float* __restrict__ dax, const float* __restrict__ day,
+              const float2* __restrict__ tw, float2* __restrict__ part) {
+  using F = FS<K1, K2>;
+  __shared__ float2 A[kRowCoils * F::LA];
+  const int line = threadIdx.x / K1;
+  const int t = threadIdx.x % K1;
+  const int iy = blockIdx.x;
+  const int g = blockIdx.y;
+  const int l = g * kRowCoils + line;
+  const bool active = l < L;
+  const long long N = (long long)nx * ny;
+  float2* Al = A + line * F::LA;
+  if (active && t < K2) {
+    float2 v[K1];
+    const float2* src = mid + ((long long)l * ny + iy) * F::K;
+#pragma unroll
+    for (int n1 = 0; n1 < K1; ++n1) v[n1] = src[n1 * K2 + t];
+    reg::dft<K1, true>(v);
+    fs_twiddle<K1, K2, true>(v, t, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) Al[k1 * F::AS + t] = v[k1];
+  }
+  __syncthreads();
+  float2 u[K2];
+  if (active) {
+#pragma unroll
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = Al[t * F::AS + n2];
+    reg::dft<K2, true>(u);
+  }
+  __syncthreads();
+  // per-coil contributions conj(S_l) * crop(row) into LDS (reusing A), then coil sum
+  float2* Z = A;
+  if (active) {
+    const float2* Sl = S + (long long)l * N + (long long)iy * nx;
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) {
+      const int ix = img_of_grid(t + K1 * k2, nx, F::K);
+      if (ix >= 0) Z[line * nx + ix] = cmulc(Sl[ix], u[k2]);
+    }
+  }
+  __syncthreads();
+  const int nl = min(kRowCoils, L - g * kRowCoils);
+  const float sy = day[iy];
+  for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+    float2 acc = Z[ix];
+    for (int li = 1; li < nl; ++li) acc = cadd(acc, Z[li * nx + ix]);
+    part[(long long)g * N + (long long)iy * nx + ix] = cscale(acc, dax[ix] * sy);
+  }
+}
+
+// =====================================================================
+// yent[l][e] = scale * w_m * y_l[m] for the sample m of entry e (y given, or
+// the sum of the sample's interpolation partials inside the normal operator)
+__global__ void k_entry_values(KIn kin, const EntryRec* __restrict__ rec, const float* __restrict__ dcf,
+                               float scale, int L, float2* __restrict__ yent) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)L * kin.E) return;
+  const int l = (int)(t / kin.E);
+  const long long e = t - (long long)l * kin.E;
+  const int m = rec[e].idx.z;
+  yent[t] = cscale(k_at(kin, l, m), dcf ? dcf[m] * scale : scale);
+}
+
+__global__ void k_gather_entries(const float2* __restrict__ ypart, const int* __restrict__ sample_ent,
+                                 long long M, long long E, int L, float scale, float2* __restrict__ y) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * L) return;
+  const int l = (int)(t / M);
+  const long long m = t - (long long)l * M;
+  const int e0 = sample_ent[m * 2];
+  const int e1 = sample_ent[m * 2 + 1];
+  float2 v = make_float2(0.f, 0.f);
+  if (e0 >= 0) v = ypart[(long long)l * E + e0];
+  if (e1 >= 0) v = cadd(v, ypart[(long long)l * E + e1]);
+  y[t] = cscale(v, scale);
 }
 
 __global__ void k_sum_groups(const float2* __restrict__ part, int G, long long N,
@@ -244,16 +632,65 @@ void set_lds_limit(const void* fn, size_t bytes) {
     PNP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
+// ------------------------------------------------- register-path launchers
+template <int K1, int K2>
+struct FSLaunch {
+  static void rows_fwd(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
+                       hipStream_t s) {
+    const int G = (L + kRowCoils - 1) / kRowCoils;
+    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, in, S, L,
+               p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, mid);
+  }
+  static void cols_fwd(const pnp_plan* p, int L, const float2* mid, float2* ypart, hipStream_t s) {
+    PNP_LAUNCH((k_cols_fwd_fs<K1, K2>), dim3(p->ntx, L), dim3(8 * K1), 0, s, mid, p->ax[0].n,
+               p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off, p->rec,
+               (long long)p->E, ypart);
+  }
+  static void cols_adj(const pnp_plan* p, int L, const float2* yent, float2* mid, hipStream_t s) {
+    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(p->ntx, L), dim3(kAdjThreads), 0, s, yent, (long long)p->E,
+               p->ax[0].n, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off,
+               p->row_start, p->rec, mid);
+  }
+  static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
+                       hipStream_t s) {
+    const int G = (L + kRowCoils - 1) / kRowCoils;
+    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, mid, S, L,
+               p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, part);
+  }
+};
+
+// Calls FSLaunch<K1,K2>::fn(args...) for the register factorisation of K.
+#define PNP_FS_DISPATCH(K, fn, ...)                                     \
+  [&]() -> bool {                                                       \
+    switch (K) {                                                        \
+      case 128: FSLaunch<16, 8>::fn(__VA_ARGS__); return true;          \
+      case 192: FSLaunch<16, 12>::fn(__VA_ARGS__); return true;         \
+      case 256: FSLaunch<16, 16>::fn(__VA_ARGS__); return true;         \
+      case 512: FSLaunch<32, 16>::fn(__VA_ARGS__); return true;         \
+      case 640: FSLaunch<32, 20>::fn(__VA_ARGS__); return true;         \
+      case 768: FSLaunch<32, 24>::fn(__VA_ARGS__); return true;         \
+      case 1024: FSLaunch<32, 32>::fn(__VA_ARGS__); return true;        \
+      default: return false;                                            \
+    }                                                                   \
+  }()
+
+bool fs_ok(const pnp_plan* p) {
+  return p->tile <= 8 && four_step_k1(p->ax[0].K) && four_step_k1(p->ax[1].K);
+}
+
 }  // namespace
+
+int op_groups(int L) { return (L + kRowCoils - 1) / kRowCoils; }
 
 size_t op_workspace_bytes(const pnp_plan* p, int L) {
   const int Kx = p->ax[0].K;
   const int64_t N = image_size(p);
-  const int G = (L + kRowCoils - 1) / kRowCoils;
+  const int G = op_groups(L);
   size_t b = 0;
   b += al(sizeof(float2) * (size_t)L * p->ax[1].n * Kx);   // mid
   b += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));  // ypart
   b += al(sizeof(float2) * (size_t)L * p->M);             // ytmp
+  b += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));  // yent
   b += al(sizeof(float2) * (size_t)G * N);                 // part
   return b;
 }
@@ -262,7 +699,7 @@ OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws) {
   OpWorkspace w;
   const int Kx = p->ax[0].K;
   const int64_t N = image_size(p);
-  const int G = (L + kRowCoils - 1) / kRowCoils;
+  const int G = op_groups(L);
   char* c = (char*)ws;
   w.mid = (float2*)c;
   c += al(sizeof(float2) * (size_t)L * p->ax[1].n * Kx);
@@ -270,6 +707,8 @@ OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws) {
   c += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));
   w.ytmp = (float2*)c;
   c += al(sizeof(float2) * (size_t)L * p->M);
+  w.yent = (float2*)c;
+  c += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));
   w.part = (float2*)c;
   c += al(sizeof(float2) * (size_t)G * N);
   w.bytes = (size_t)(c - (char*)ws);
@@ -283,73 +722,102 @@ static void check_lds(const pnp_plan* p) {
          p->ax[0].K, need);
 }
 
-static void launch_forward_grid(const pnp_plan* p, const float2* x, const float2* smaps, int L,
+// image -> per-entry interpolation partials in w.ypart
+static void forward_to_partials(const pnp_plan* p, const ImgIn& in, const float2* smaps, int L,
                                 const OpWorkspace& w, hipStream_t s) {
   const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
-  const int G = (L + kRowCoils - 1) / kRowCoils;
+  if (fs_ok(p)) {
+    PNP_FS_DISPATCH(Kx, rows_fwd, p, in, smaps, L, w.mid, s);
+    PNP_FS_DISPATCH(p->ax[1].K, cols_fwd, p, L, w.mid, w.ypart, s);
+    return;
+  }
+  const int G = op_groups(L);
   check_lds(p);
   {
     const size_t lds = rows_lds(Kx);
     set_lds_limit((const void*)k_rows_fwd, lds);
-    hipLaunchKernelGGL(k_rows_fwd, dim3(ny, G), dim3(kThreads), lds, s, x, smaps, L, nx, ny,
-                       p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft, w.mid);
-    PNP_CHECK_LAUNCH();
+    PNP_LAUNCH(k_rows_fwd, dim3(ny, G), dim3(kThreads), lds, s, in, smaps, L, nx, ny, p->ax[0].deapod,
+               p->ax[1].deapod, p->ax[0].fft, w.mid);
   }
   {
     const size_t lds = cols_lds(p);
     set_lds_limit((const void*)k_cols_fwd_interp, lds);
-    hipLaunchKernelGGL(k_cols_fwd_interp, dim3(p->ntx, L), dim3(kThreads), lds, s, w.mid, nx, ny,
-                       Kx, p->ax[1].fft, p->tile, col_stride(p->ax[1].K), p->tile_off,
-                       p->ent_sample, p->j0, p->wts, (long long)p->E, w.ypart);
-    PNP_CHECK_LAUNCH();
+    PNP_LAUNCH(k_cols_fwd_interp, dim3(p->ntx, L), dim3(kThreads), lds, s, w.mid, nx, ny, Kx,
+               p->ax[1].fft, p->tile, col_stride(p->ax[1].K), p->tile_off, p->rec, (long long)p->E,
+               w.ypart);
+  }
+}
+
+// k-space (y or partials) -> per-coil-group partial images in `dst` [G][N]
+static void adjoint_to_groups(const pnp_plan* p, const KIn& kin, const float2* smaps, int L,
+                              const float* dcf, float scale, float2* dst, const OpWorkspace& w,
+                              hipStream_t s) {
+  const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
+  const int G = op_groups(L);
+  // weighted k-space values in entry order (coalesced staging in the spread)
+  {
+    const long long tot = (long long)L * p->E;
+    if (tot > 0)
+      PNP_LAUNCH(k_entry_values, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, kin, p->rec, dcf,
+                 scale, L, w.yent);
+  }
+  if (fs_ok(p)) {
+    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, s);
+    PNP_FS_DISPATCH(Kx, rows_adj, p, L, w.mid, smaps, dst, s);
+    return;
+  }
+  check_lds(p);
+  {
+    const size_t lds = cols_lds(p);
+    set_lds_limit((const void*)k_cols_adj_spread, lds);
+    PNP_LAUNCH(k_cols_adj_spread, dim3(p->ntx, L), dim3(kThreads), lds, s, w.yent, (long long)p->E, nx,
+               ny, Kx, p->ax[1].fft, p->tile, col_stride(p->ax[1].K), p->tile_off, p->rec, w.mid);
+  }
+  {
+    const size_t lds = rows_lds(Kx);
+    set_lds_limit((const void*)k_rows_adj, lds);
+    PNP_LAUNCH(k_rows_adj, dim3(ny, G), dim3(kThreads), lds, s, w.mid, smaps, L, nx, ny,
+               p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft, dst);
   }
 }
 
 void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y,
                 const OpWorkspace& w, hipStream_t s) {
-  launch_forward_grid(p, x, smaps, L, w, s);
+  forward_to_partials(p, ImgIn{x, nullptr, nullptr, nullptr}, smaps, L, w, s);
   const long long tot = p->M * L;
   const float scale = (float)(1.0 / std::sqrt((double)image_size(p)));
-  hipLaunchKernelGGL(k_gather_entries, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     w.ypart, p->sample_ent, (long long)p->M, (long long)p->E, L, scale, y);
-  PNP_CHECK_LAUNCH();
+  PNP_LAUNCH(k_gather_entries, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, w.ypart,
+             p->sample_ent, (long long)p->M, (long long)p->E, L, scale, y);
 }
 
 void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf,
                 float2* x, const OpWorkspace& w, hipStream_t s) {
-  const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
-  const int G = (L + kRowCoils - 1) / kRowCoils;
+  const int G = op_groups(L);
   const int64_t N = image_size(p);
   const float scale = (float)(1.0 / std::sqrt((double)N));
-  check_lds(p);
-  {
-    const size_t lds = cols_lds(p);
-    set_lds_limit((const void*)k_cols_adj_spread, lds);
-    hipLaunchKernelGGL(k_cols_adj_spread, dim3(p->ntx, L), dim3(kThreads), lds, s, y, dcf, scale,
-                       (long long)p->M, nx, ny, Kx, p->ax[1].fft, p->tile, col_stride(p->ax[1].K),
-                       p->tile_off, p->ent_sample, p->j0, p->wts, w.mid);
-    PNP_CHECK_LAUNCH();
-  }
-  {
-    const size_t lds = rows_lds(Kx);
-    set_lds_limit((const void*)k_rows_adj, lds);
-    float2* dst = G == 1 ? x : w.part;
-    hipLaunchKernelGGL(k_rows_adj, dim3(ny, G), dim3(kThreads), lds, s, w.mid, smaps, L, nx, ny,
-                       p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft, 1.0f, dst);
-    PNP_CHECK_LAUNCH();
-  }
-  if (G > 1) {
-    hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
-                       (long long)N, x);
-    PNP_CHECK_LAUNCH();
-  }
-  (void)scale;
+  float2* dst = G == 1 ? x : w.part;
+  adjoint_to_groups(p, KIn{y, nullptr, nullptr, (long long)p->M, (long long)p->E}, smaps, L, dcf,
+                    scale, dst, w, s);
+  if (G > 1)
+    PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
+               (long long)N, x);
+}
+
+void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
+                     const float* dcf, const OpWorkspace& w, hipStream_t s) {
+  forward_to_partials(p, ImgIn{in.x, in.r, in.pnew, in.beta}, smaps, L, w, s);
+  const float scale = (float)(1.0 / (double)image_size(p));   // both N^{-1/2} factors
+  adjoint_to_groups(p, KIn{nullptr, w.ypart, p->sample_ent, (long long)p->M, (long long)p->E}, smaps,
+                    L, dcf, scale, w.part, w, s);
 }
 
 void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,
                float2* out, const OpWorkspace& w, hipStream_t s) {
-  op_forward(p, x, smaps, L, w.ytmp, w, s);
-  op_adjoint(p, w.ytmp, smaps, L, dcf, out, w, s);
+  op_normal_parts(p, NormalIn{x, nullptr, nullptr, nullptr}, smaps, L, dcf, w, s);
+  const int G = op_groups(L);
+  const int64_t N = image_size(p);
+  PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
+             (long long)N, out);
 }
 
 }  // namespace pnp

@@ -15,6 +15,7 @@
 // listed once per tile its W x W footprint touches (at most 2 in 2D, 4 in
 // 3D), grouped by tile with a counting sort, so that interpolation and
 // spreading work tile by tile out of LDS.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -154,24 +155,70 @@ __global__ void k_scatter(long long M, int slots, const int* __restrict__ sample
   }
 }
 
-// Sort each tile's entries by sample index (insertion sort in LDS for tiles
-// up to 4096 entries, larger tiles keep atomic order), then refresh the
-// sample -> entry map.  Deterministic entry order makes forward results
-// and the spread's access pattern reproducible.
-__global__ void k_sort_tiles(const int* __restrict__ off, int* __restrict__ ent_sample) {
-  __shared__ int buf[4096];
-  const int t = blockIdx.x;
-  const int b = off[t], e = off[t + 1];
-  const int n = e - b;
-  if (n <= 1 || n > 4096) return;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = ent_sample[b + i];
-  __syncthreads();
-  // rank sort: position of element i = number of smaller elements (values unique per tile)
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int v = buf[i];
-    int r = 0;
-    for (int j = 0; j < n; ++j) r += buf[j] < v;
-    ent_sample[b + r] = v;
+__device__ __forceinline__ int tile_of_entry(const int* __restrict__ off, int ntiles, long long e) {
+  int lo = 0, hi = ntiles;  // off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int row_of(const int4 j, int ra) { return ra == 1 ? j.y : j.z; }
+
+// Within every tile, order the entries by the first tap along the axis kept
+// whole in LDS (y in 2D, z in 3D) -- a counting sort into row buckets --
+// and, inside a bucket, by sample index.  row_start[t][r] is the first
+// entry of tile t whose first tap is row r (absolute entry index).
+__global__ void k_row_hist(long long E, const int* __restrict__ off, int ntiles,
+                           const int* __restrict__ ent, const int4* __restrict__ j0, int ra, int R,
+                           int* __restrict__ rcnt) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int t = tile_of_entry(off, ntiles, e);
+  atomicAdd(&rcnt[(long long)t * R + row_of(j0[ent[e]], ra)], 1);
+}
+
+__global__ void k_row_scan(const int* __restrict__ off, int ntiles, int R, const int* __restrict__ rcnt,
+                           int* __restrict__ rstart, int* __restrict__ rcur) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int acc = off[t];
+  for (int r = 0; r < R; ++r) {
+    rstart[(long long)t * (R + 1) + r] = acc;
+    rcur[(long long)t * R + r] = 0;
+    acc += rcnt[(long long)t * R + r];
+  }
+  rstart[(long long)t * (R + 1) + R] = acc;
+}
+
+__global__ void k_row_scatter(long long E, const int* __restrict__ off, int ntiles,
+                              const int* __restrict__ ent_in, const int4* __restrict__ j0, int ra, int R,
+                              const int* __restrict__ rstart, int* __restrict__ rcur,
+                              int* __restrict__ ent_out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int t = tile_of_entry(off, ntiles, e);
+  const int m = ent_in[e];
+  const int r = row_of(j0[m], ra);
+  const int pos = rstart[(long long)t * (R + 1) + r] + atomicAdd(&rcur[(long long)t * R + r], 1);
+  ent_out[pos] = m;
+}
+
+// insertion sort of each (tile, row) bucket by sample index (buckets are short)
+__global__ void k_bucket_sort(int ntiles, int R, const int* __restrict__ rstart, int* __restrict__ ent) {
+  const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= (long long)ntiles * R) return;
+  const long long t = b / R, r = b % R;
+  const int s = rstart[t * (R + 1) + r], e = rstart[t * (R + 1) + r + 1];
+  for (int i = s + 1; i < e; ++i) {
+    const int v = ent[i];
+    int j = i - 1;
+    while (j >= s && ent[j] > v) {
+      ent[j + 1] = ent[j];
+      --j;
+    }
+    ent[j + 1] = v;
   }
 }
 
@@ -180,15 +227,27 @@ __global__ void k_refresh_sample_ent(long long E, int slots, const int* __restri
                                      int ntiles, int* __restrict__ sample_ent) {
   long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= E) return;
-  // tile of entry e: binary search in off
-  int lo = 0, hi = ntiles;  // off[lo] <= e < off[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (off[mid] <= e) lo = mid; else hi = mid;
-  }
+  const int lo = tile_of_entry(off, ntiles, e);
   const int m = ent_sample[e];
   for (int s = 0; s < slots; ++s)
     if (sample_tiles[(long long)m * slots + s] == lo) sample_ent[(long long)m * slots + s] = (int)e;
+}
+
+// Packed per-entry records (2D): taps, sample and the 12 weights in tile order.
+__global__ void k_build_records(long long E, const int* __restrict__ ent_sample,
+                                const int4* __restrict__ j0, const float* __restrict__ wts,
+                                EntryRec* __restrict__ rec) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int m = ent_sample[e];
+  const int4 jj = j0[m];
+  const float* w = wts + (long long)m * 12;
+  EntryRec r;
+  r.idx = make_int4(jj.x, jj.y, m, 0);
+  r.w0 = make_float4(w[0], w[1], w[2], w[3]);
+  r.w1 = make_float4(w[4], w[5], w[6], w[7]);
+  r.w2 = make_float4(w[8], w[9], w[10], w[11]);
+  rec[e] = r;
 }
 
 __global__ void k_check_finite(const float* __restrict__ v, long long n, int* __restrict__ bad) {
@@ -287,6 +346,8 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
 
     // one allocation: tables + per-sample data + entries (E <= slots*M)
     const int64_t Emax = (int64_t)p->slots * M;
+    const int ra = ndim - 1;                 // axis kept whole in LDS (y in 2D, z in 3D)
+    const int R = p->ax[ra].K;
     size_t off = 0;
     auto take = [&](size_t bytes) {
       size_t o = off;
@@ -301,14 +362,19 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     const size_t o_j0 = take(sizeof(int4) * M);
     const size_t o_w = take(sizeof(float) * M * ndim * p->W);
     const size_t o_off = take(sizeof(int) * (p->ntiles + 1));
+    const size_t o_rs = take(sizeof(int) * (size_t)p->ntiles * (R + 1));
     const size_t o_es = take(sizeof(int) * Emax);
     const size_t o_se = take(sizeof(int) * M * p->slots);
+    const size_t o_rec = take(sizeof(EntryRec) * (ndim == 2 ? Emax : 1));
     // set-up scratch (freed below)
     size_t soff = 0;
     const size_t s_cnt = soff; soff += align256(sizeof(int) * p->ntiles);
     const size_t s_cur = soff; soff += align256(sizeof(int) * p->ntiles);
     const size_t s_max = soff; soff += align256(sizeof(int));
     const size_t s_st = soff; soff += align256(sizeof(int) * M * p->slots);
+    const size_t s_rc = soff; soff += align256(sizeof(int) * (size_t)p->ntiles * R);
+    const size_t s_ru = soff; soff += align256(sizeof(int) * (size_t)p->ntiles * R);
+    const size_t s_tmp = soff; soff += align256(sizeof(int) * Emax);
 
     PNP_HIP(hipMalloc(&p->block, off));
     p->block_bytes = off;
@@ -320,15 +386,23 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     p->j0 = (int4*)(base + o_j0);
     p->wts = (float*)(base + o_w);
     p->tile_off = (int32_t*)(base + o_off);
+    p->row_start = (int32_t*)(base + o_rs);
     p->ent_sample = (int32_t*)(base + o_es);
     p->sample_ent = (int32_t*)(base + o_se);
+    p->rec = (EntryRec*)(base + o_rec);
 
-    char* scratch = nullptr;
-    PNP_HIP(hipMalloc((void**)&scratch, soff));
-    int* cnt = (int*)(scratch + s_cnt);
-    int* cur = (int*)(scratch + s_cur);
-    int* mx = (int*)(scratch + s_max);
-    int* st = (int*)(scratch + s_st);
+    struct Scratch {
+      char* ptr = nullptr;
+      ~Scratch() { if (ptr) (void)hipFree(ptr); }
+    } scratch;
+    PNP_HIP(hipMalloc((void**)&scratch.ptr, soff));
+    int* cnt = (int*)(scratch.ptr + s_cnt);
+    int* cur = (int*)(scratch.ptr + s_cur);
+    int* mx = (int*)(scratch.ptr + s_max);
+    int* st = (int*)(scratch.ptr + s_st);
+    int* rcnt = (int*)(scratch.ptr + s_rc);
+    int* rcur = (int*)(scratch.ptr + s_ru);
+    int* etmp = (int*)(scratch.ptr + s_tmp);
 
     for (int a = 0; a < ndim; ++a) {
       const int K = p->ax[a].K, n = p->ax[a].n;
@@ -338,6 +412,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
       PNP_CHECK_LAUNCH();
     }
     PNP_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * p->ntiles, stream));
+    PNP_HIP(hipMemsetAsync(rcnt, 0, sizeof(int) * (size_t)p->ntiles * R, stream));
     const unsigned gM = (unsigned)((M + 255) / 256);
     k_plan_samples<<<gM, 256, 0, stream>>>(traj, M, ndim, p->ax[0].K, p->ax[1].K, p->ax[2].K, p->W,
                                            p->beta, p->tile, p->ntx, p->nty, p->j0, p->wts, cnt, st,
@@ -345,7 +420,8 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     PNP_CHECK_LAUNCH();
     k_scan_tiles<<<1, 64, 0, stream>>>(cnt, p->ntiles, p->tile_off, cur, mx);
     PNP_CHECK_LAUNCH();
-    k_scatter<<<gM, 256, 0, stream>>>(M, p->slots, st, p->tile_off, cur, p->ent_sample, p->sample_ent);
+    // entries grouped by tile (arbitrary order) into etmp
+    k_scatter<<<gM, 256, 0, stream>>>(M, p->slots, st, p->tile_off, cur, etmp, p->sample_ent);
     PNP_CHECK_LAUNCH();
     int hE = 0, hmax = 0;
     PNP_HIP(hipMemcpyAsync(&hE, p->tile_off + p->ntiles, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -353,15 +429,32 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     PNP_HIP(hipStreamSynchronize(stream));
     p->E = hE;
     p->max_tile_entries = hmax;
-    k_sort_tiles<<<p->ntiles, 256, 0, stream>>>(p->tile_off, p->ent_sample);
+    const unsigned gE = (unsigned)std::max<int64_t>(1, (p->E + 255) / 256);
+    // order each tile by (first row tap, sample): row buckets + bucket sort
+    k_row_hist<<<gE, 256, 0, stream>>>(p->E, p->tile_off, p->ntiles, etmp, p->j0, ra, R, rcnt);
     PNP_CHECK_LAUNCH();
-    if (p->E > 0) {
-      k_refresh_sample_ent<<<(unsigned)((p->E + 255) / 256), 256, 0, stream>>>(
-          p->E, p->slots, p->ent_sample, p->tile_off, st, p->ntiles, p->sample_ent);
+    k_row_scan<<<(p->ntiles + 63) / 64, 64, 0, stream>>>(p->tile_off, p->ntiles, R, rcnt, p->row_start,
+                                                          rcur);
+    PNP_CHECK_LAUNCH();
+    k_row_scatter<<<gE, 256, 0, stream>>>(p->E, p->tile_off, p->ntiles, etmp, p->j0, ra, R, p->row_start,
+                                          rcur, p->ent_sample);
+    PNP_CHECK_LAUNCH();
+    {
+      const long long nb = (long long)p->ntiles * R;
+      k_bucket_sort<<<(unsigned)((nb + 255) / 256), 256, 0, stream>>>(p->ntiles, R, p->row_start,
+                                                                     p->ent_sample);
       PNP_CHECK_LAUNCH();
     }
+    if (p->E > 0) {
+      k_refresh_sample_ent<<<gE, 256, 0, stream>>>(p->E, p->slots, p->ent_sample, p->tile_off, st,
+                                                   p->ntiles, p->sample_ent);
+      PNP_CHECK_LAUNCH();
+      if (ndim == 2) {
+        k_build_records<<<gE, 256, 0, stream>>>(p->E, p->ent_sample, p->j0, p->wts, p->rec);
+        PNP_CHECK_LAUNCH();
+      }
+    }
     PNP_HIP(hipStreamSynchronize(stream));
-    PNP_HIP(hipFree(scratch));
   } catch (...) {
     if (p->block) (void)hipFree(p->block);
     delete p;

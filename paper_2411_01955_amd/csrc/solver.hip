@@ -2,16 +2,17 @@
 // PnP-HQS loop (Sec. 3.3-3.4), with every scalar kept on the device.
 //
 // Vectors are complex64; inner products, step sizes (alpha, beta), the
-// residual norms and the data-consistency residual are accumulated in FP64:
-// each vector kernel writes one FP64 partial per block (fixed grid), and a
-// one-block finalize kernel sums the partials in a fixed order and updates
-// the scalar state, so results are deterministic and no host round trip is
-// needed inside the loop.
+// residual norms and the data-consistency residual are accumulated in FP64.
+// Each reduction kernel writes one FP64 partial per block; the last block to
+// finish (atomic ticket) sums the partials in a fixed order and updates the
+// scalar state, so results are deterministic, there is no separate
+// finalisation launch and no host round trip inside the loop.
 //
 // The prox system (Sec. 3.4, read with the density weighting D_w):
 //   M u = b,  M = gamma N + P = c0 I + (gamma - c1 alpha) N,  N = A^H D_w A,
 //   b = P x + gamma b0,  b0 = A^H D_w y,  started at u = x so that
-//   r0 = gamma (b0 - N x).  Each CG step costs one normal operator.
+//   r0 = gamma (b0 - N x).  Each CG step costs one normal operator, whose
+//   first pass also forms the new direction p = r + beta p.
 // The residual rho(x) = ||D_w^{1/2}(A x - y)||^2 = <x,Nx> - 2 Re<x,b0> + ||y||_w^2
 // comes for free from the N x that r0 needs.
 #include <algorithm>
@@ -19,6 +20,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "trace.hpp"
 
 namespace pnp {
 
@@ -35,7 +37,7 @@ struct DevScalars {
   double lam;       // power iteration: Rayleigh quotient
   double inv;       // power iteration: 1/||w||
   int bad;          // set when a CG denominator is not positive / finite
-  int pad;
+  unsigned cnt;     // last-block ticket (reset by the last block)
 };
 
 namespace {
@@ -45,14 +47,19 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
-// Sum `Q` values over the block; thread 0 writes them to parts[blockIdx.x*Q + q].
+// Block-reduce Q values into parts[blockIdx.x*Q + q]; the last block to
+// arrive sums all blocks' partials (fixed order) into out[] and returns true
+// (for every thread of that block).
 template <int Q>
-__device__ void block_partials(double (&v)[Q], double* __restrict__ parts) {
+__device__ bool reduce_last(double (&v)[Q], double* __restrict__ parts, unsigned* cnt,
+                            double (&out)[Q]) {
   __shared__ double sh[Q][kRedThreads / 64];
+  __shared__ double fin[Q][kRedThreads];
+  __shared__ bool last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    double s = warp_sum(v[q]);
+    const double s = warp_sum(v[q]);
     if (lane == 0) sh[q][wid] = s;
   }
   __syncthreads();
@@ -60,47 +67,72 @@ __device__ void block_partials(double (&v)[Q], double* __restrict__ parts) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       double s = 0.0;
-      for (int w = 0; w < kRedThreads / 64; ++w) s += sh[q][w];
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[q][w];
       parts[blockIdx.x * Q + q] = s;
     }
+    __threadfence();
+    const unsigned prev = atomicAdd(cnt, 1u);
+    last = prev == gridDim.x - 1;
   }
-}
-
-// Sum parts[b*Q + q] over b in fixed order; result in out[q] (thread 0 sees it).
-template <int Q>
-__device__ void finalize_sum(const double* __restrict__ parts, int nb, double (&out)[Q]) {
-  __shared__ double sh[Q][kRedThreads];
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  const volatile double* vp = parts;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += parts[b * Q + q];
-    sh[q][threadIdx.x] = s;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s += vp[b * Q + q];
+    fin[q][threadIdx.x] = s;
   }
   __syncthreads();
   for (int w = kRedThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+      for (int q = 0; q < Q; ++q) fin[q][threadIdx.x] += fin[q][threadIdx.x + w];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) out[q] = sh[q][0];
+  for (int q = 0; q < Q; ++q) out[q] = fin[q][0];
+  if (threadIdx.x == 0) *cnt = 0u;
+  return true;
 }
 
 __device__ __forceinline__ double re_dot(float2 a, float2 b) {
   return (double)a.x * b.x + (double)a.y * b.y;
 }
 
-// u = x; r = gamma (b0 - Nx); p = r;  partials |r|^2, Re<x,Nx>, Re<x,b0>
+__device__ __forceinline__ float2 sum_groups(const float2* __restrict__ part, int G, long long N,
+                                             long long i) {
+  float2 v = part[i];
+  for (int g = 1; g < G; ++g) v = cadd(v, part[(long long)g * N + i]);
+  return v;
+}
+
+__global__ void k_init_scalars(DevScalars* sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->rr = sc->pq = sc->alpha = sc->beta = sc->yw2 = sc->lam = sc->inv = 0.0;
+    sc->bad = 0;
+    sc->cnt = 0u;
+  }
+}
+
+__global__ void k_copy(long long N, const float2* __restrict__ a, float2* __restrict__ b) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// Nx = sum of the normal operator's partial images; u = x; r = gamma (b0 - Nx);
+// p = r.  Last block: rr = <r,r>, rho(x) = <x,Nx> - 2 Re<x,b0> + ||y||_w^2.
 __global__ void __launch_bounds__(kRedThreads)
-k_cg_init(long long N, const float2* __restrict__ x, const float2* __restrict__ Nx,
+k_cg_init(long long N, int G, const float2* __restrict__ x, const float2* __restrict__ part,
           const float2* __restrict__ b0, float gamma, float2* __restrict__ u, float2* __restrict__ r,
-          float2* __restrict__ p, double* __restrict__ parts) {
+          float2* __restrict__ p, double* __restrict__ parts, DevScalars* sc, double* rho_out) {
   double acc[3] = {0.0, 0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
-    const float2 xv = x[i], nv = Nx[i], bv = b0[i];
+    const float2 xv = x[i], nv = sum_groups(part, G, N, i), bv = b0[i];
     const float2 rv = make_float2(gamma * (bv.x - nv.x), gamma * (bv.y - nv.y));
     u[i] = xv;
     r[i] = rv;
@@ -109,39 +141,27 @@ k_cg_init(long long N, const float2* __restrict__ x, const float2* __restrict__ 
     acc[1] += re_dot(xv, nv);
     acc[2] += re_dot(xv, bv);
   }
-  block_partials<3>(acc, parts);
-}
-
-__global__ void __launch_bounds__(kRedThreads)
-k_fin_init(const double* __restrict__ parts, int nb, DevScalars* sc, double* __restrict__ rho_out) {
   double s[3];
-  finalize_sum<3>(parts, nb, s);
-  if (threadIdx.x == 0) {
+  if (reduce_last<3>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
     sc->rr = s[0];
     if (rho_out) *rho_out = s[1] - 2.0 * s[2] + sc->yw2;
   }
 }
 
-// q = c0 p + cg Np;  partial Re<p, q>
+// q = c0 p + cg N p;  last block: alpha = rr / Re<p, q>
 __global__ void __launch_bounds__(kRedThreads)
-k_cg_q(long long N, const float2* __restrict__ p, const float2* __restrict__ Np, float c0, float cg,
-       float2* __restrict__ q, double* __restrict__ parts) {
+k_cg_q(long long N, int G, const float2* __restrict__ p, const float2* __restrict__ part, float c0,
+       float cg, float2* __restrict__ q, double* __restrict__ parts, DevScalars* sc) {
   double acc[1] = {0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
-    const float2 pv = p[i], nv = Np[i];
+    const float2 pv = p[i], nv = sum_groups(part, G, N, i);
     const float2 qv = make_float2(c0 * pv.x + cg * nv.x, c0 * pv.y + cg * nv.y);
     q[i] = qv;
     acc[0] += re_dot(pv, qv);
   }
-  block_partials<1>(acc, parts);
-}
-
-__global__ void __launch_bounds__(kRedThreads)
-k_fin_alpha(const double* __restrict__ parts, int nb, DevScalars* sc) {
   double s[1];
-  finalize_sum<1>(parts, nb, s);
-  if (threadIdx.x == 0) {
+  if (reduce_last<1>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
     sc->pq = s[0];
     if (sc->rr == 0.0) {
       sc->alpha = 0.0;
@@ -154,10 +174,10 @@ k_fin_alpha(const double* __restrict__ parts, int nb, DevScalars* sc) {
   }
 }
 
-// u += alpha p; r -= alpha q;  partial |r|^2
+// u += alpha p; r -= alpha q;  last block: beta = <r,r>_new / <r,r>, rr updated
 __global__ void __launch_bounds__(kRedThreads)
 k_cg_update(long long N, float2* __restrict__ u, float2* __restrict__ r, const float2* __restrict__ p,
-            const float2* __restrict__ q, const DevScalars* __restrict__ sc, double* __restrict__ parts) {
+            const float2* __restrict__ q, double* __restrict__ parts, DevScalars* sc) {
   const float a = (float)sc->alpha;
   double acc[1] = {0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
@@ -170,34 +190,17 @@ k_cg_update(long long N, float2* __restrict__ u, float2* __restrict__ r, const f
     r[i] = rv;
     acc[0] += re_dot(rv, rv);
   }
-  block_partials<1>(acc, parts);
-}
-
-__global__ void __launch_bounds__(kRedThreads)
-k_fin_beta(const double* __restrict__ parts, int nb, DevScalars* sc) {
   double s[1];
-  finalize_sum<1>(parts, nb, s);
-  if (threadIdx.x == 0) {
+  if (reduce_last<1>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
     sc->beta = sc->rr > 0.0 ? s[0] / sc->rr : 0.0;
     sc->rr = s[0];
   }
 }
 
-// p = r + beta p
-__global__ void k_cg_p(long long N, float2* __restrict__ p, const float2* __restrict__ r,
-                       const DevScalars* __restrict__ sc) {
-  const float bt = (float)sc->beta;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
-    const float2 rv = r[i], pv = p[i];
-    p[i] = make_float2(fmaf(bt, pv.x, rv.x), fmaf(bt, pv.y, rv.y));
-  }
-}
-
-// ||y||_w^2 partials over L*M entries
+// ||y||_w^2 over L*M entries
 __global__ void __launch_bounds__(kRedThreads)
 k_wnorm(long long M, int L, const float2* __restrict__ y, const float* __restrict__ dcf,
-        double* __restrict__ parts) {
+        double* __restrict__ parts, DevScalars* sc) {
   double acc[1] = {0.0};
   const long long T = M * L;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < T;
@@ -207,16 +210,8 @@ k_wnorm(long long M, int L, const float2* __restrict__ y, const float* __restric
     const double w = dcf ? (double)dcf[m] : 1.0;
     acc[0] += w * re_dot(v, v);
   }
-  block_partials<1>(acc, parts);
-}
-
-__global__ void k_fin_yw2(const double* __restrict__ parts, int nb, DevScalars* sc) {
   double s[1];
-  finalize_sum<1>(parts, nb, s);
-  if (threadIdx.x == 0) {
-    sc->yw2 = s[0];
-    sc->bad = 0;
-  }
+  if (reduce_last<1>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) sc->yw2 = s[0];
 }
 
 // ---- power iteration
@@ -242,24 +237,21 @@ __global__ void k_randn(long long N, uint64_t seed, float2* __restrict__ v) {
   }
 }
 
-// partials Re<v, w>, |w|^2
+// w = sum of partial images (or w itself when part == nullptr);
+// last block: lam = Re<v, w>, inv = 1/||w||
 __global__ void __launch_bounds__(kRedThreads)
-k_dot_vw(long long N, const float2* __restrict__ v, const float2* __restrict__ w,
-         double* __restrict__ parts) {
+k_pow_dot(long long N, int G, const float2* __restrict__ v, const float2* __restrict__ part,
+          float2* __restrict__ w, double* __restrict__ parts, DevScalars* sc) {
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
-    const float2 a = v[i], b = w[i];
-    acc[0] += re_dot(a, b);
+    const float2 b = part ? sum_groups(part, G, N, i) : w[i];
+    if (part) w[i] = b;
+    acc[0] += v ? re_dot(v[i], b) : 0.0;
     acc[1] += re_dot(b, b);
   }
-  block_partials<2>(acc, parts);
-}
-
-__global__ void k_fin_power(const double* __restrict__ parts, int nb, DevScalars* sc) {
   double s[2];
-  finalize_sum<2>(parts, nb, s);
-  if (threadIdx.x == 0) {
+  if (reduce_last<2>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
     sc->lam = s[0];
     sc->inv = s[1] > 0.0 ? 1.0 / sqrt(s[1]) : 0.0;
   }
@@ -285,7 +277,7 @@ unsigned vec_blocks(long long N) {
 // ------------------------------------------------------------ host side
 struct SolverWs {
   OpWorkspace op;
-  float2 *b0, *Nv, *u, *r, *p, *q;
+  float2 *b0, *Nv, *u, *r, *p, *p2, *q;
   double* parts;
   DevScalars* sc;
   double* rho;   // [kMaxOuter + 1]
@@ -294,7 +286,7 @@ struct SolverWs {
 size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
   const int64_t N = image_size(p);
   size_t b = al(op_workspace_bytes(p, L));
-  b += 6 * al(sizeof(float2) * N);
+  b += 7 * al(sizeof(float2) * N);
   b += al(sizeof(double) * 4 * kRedBlocks);
   b += al(sizeof(DevScalars));
   b += al(sizeof(double) * (kMaxOuter + 1));
@@ -307,7 +299,7 @@ static SolverWs solver_ws(const pnp_plan* p, int L, void* ws) {
   char* c = (char*)ws;
   w.op = op_workspace(p, L, c);
   c += al(op_workspace_bytes(p, L));
-  float2** vecs[6] = {&w.b0, &w.Nv, &w.u, &w.r, &w.p, &w.q};
+  float2** vecs[7] = {&w.b0, &w.Nv, &w.u, &w.r, &w.p, &w.p2, &w.q};
   for (auto v : vecs) {
     *v = (float2*)c;
     c += al(sizeof(float2) * N);
@@ -328,22 +320,18 @@ double power_iteration(const pnp_plan* p, const float2* smaps, int L, const floa
                        uint64_t seed, void* ws, hipStream_t s) {
   SolverWs w = solver_ws(p, L, ws);
   const long long N = image_size(p);
+  const int G = op_groups(L);
   const unsigned nb = vec_blocks(N);
   float2* v = w.u;
-  float2* Nv = w.Nv;
-  hipLaunchKernelGGL(k_randn, dim3(nb), dim3(kRedThreads), 0, s, N, seed, Nv);
-  PNP_CHECK_LAUNCH();
-  // normalise the start vector: use k_dot_vw(Nv, Nv) -> inv = 1/|Nv|
-  hipLaunchKernelGGL(k_dot_vw, dim3(nb), dim3(kRedThreads), 0, s, N, Nv, Nv, w.parts);
-  hipLaunchKernelGGL(k_fin_power, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
-  hipLaunchKernelGGL(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, Nv, w.sc, v);
-  PNP_CHECK_LAUNCH();
+  PNP_LAUNCH(k_init_scalars, dim3(1), dim3(64), 0, s, w.sc);
+  PNP_LAUNCH(k_randn, dim3(nb), dim3(kRedThreads), 0, s, N, seed, w.Nv);
+  PNP_LAUNCH(k_pow_dot, dim3(nb), dim3(kRedThreads), 0, s, N, G, (const float2*)nullptr,
+             (const float2*)nullptr, w.Nv, w.parts, w.sc);
+  PNP_LAUNCH(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, w.sc, v);
   for (int it = 0; it < iters; ++it) {
-    op_normal(p, v, smaps, L, dcf, Nv, w.op, s);
-    hipLaunchKernelGGL(k_dot_vw, dim3(nb), dim3(kRedThreads), 0, s, N, v, Nv, w.parts);
-    hipLaunchKernelGGL(k_fin_power, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
-    hipLaunchKernelGGL(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, Nv, w.sc, v);
-    PNP_CHECK_LAUNCH();
+    op_normal_parts(p, NormalIn{v, nullptr, nullptr, nullptr}, smaps, L, dcf, w.op, s);
+    PNP_LAUNCH(k_pow_dot, dim3(nb), dim3(kRedThreads), 0, s, N, G, v, w.op.part, w.Nv, w.parts, w.sc);
+    PNP_LAUNCH(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, w.sc, v);
   }
   DevScalars h;
   PNP_HIP(hipMemcpyAsync(&h, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
@@ -360,61 +348,58 @@ static void apply_prior(const pnp_plan* p, const pnp_prior* prior, const float2*
   wavelet_apply(p->ndim, n, J, (float)(prior->kappa * sigma), u, x, s);
 }
 
-// Returns 0 or a CG breakdown flag (only checked when `report` requested).
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
                int* bad_host) {
   if (a.n_out > kMaxOuter) fail(PNP_ERR_SHAPE, "n_out %d exceeds %d", a.n_out, kMaxOuter);
   SolverWs w = solver_ws(p, a.L, ws);
   const long long N = image_size(p);
+  const int G = op_groups(a.L);
   const unsigned nb = vec_blocks(N);
   static const double c0s[3] = {1.0, 2.0, 4.0};
   static const double c1s[3] = {0.0, 1.0, 10.0 / 3.0};
   const double c0 = c0s[a.precond];
   const double c1a = c1s[a.precond] / a.opnorm;
 
+  PNP_LAUNCH(k_init_scalars, dim3(1), dim3(64), 0, s, w.sc);
   // b0 = A^H D_w y, ||y||_w^2
   op_adjoint(p, a.y, a.smaps, a.L, a.dcf, w.b0, w.op, s);
   {
     const long long T = p->M * a.L;
-    const unsigned nbk = (unsigned)std::min<long long>((T + kRedThreads - 1) / kRedThreads, kRedBlocks);
-    hipLaunchKernelGGL(k_wnorm, dim3(std::max(nbk, 1u)), dim3(kRedThreads), 0, s, (long long)p->M,
-                       a.L, a.y, a.dcf, w.parts);
-    hipLaunchKernelGGL(k_fin_yw2, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)std::max(nbk, 1u), w.sc);
-    PNP_CHECK_LAUNCH();
+    const unsigned nbk =
+        (unsigned)std::max<long long>(1, std::min<long long>((T + kRedThreads - 1) / kRedThreads, kRedBlocks));
+    PNP_LAUNCH(k_wnorm, dim3(nbk), dim3(kRedThreads), 0, s, (long long)p->M, a.L, a.y, a.dcf, w.parts,
+               w.sc);
   }
   float2* x = a.x_out;
-  PNP_HIP(hipMemcpyAsync(x, a.x0 ? a.x0 : w.b0, sizeof(float2) * N, hipMemcpyDeviceToDevice, s));
+  PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, a.x0 ? a.x0 : w.b0, x);
 
   for (int k = 0; k < a.n_out; ++k) {
     const double gamma = a.lambda * a.sigmas[k];
     const float cg = (float)(gamma - c1a);
-    op_normal(p, x, a.smaps, a.L, a.dcf, w.Nv, w.op, s);
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, x, w.Nv, w.b0, (float)gamma,
-                       w.u, w.r, w.p, w.parts);
-    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc, w.rho + k);
-    PNP_CHECK_LAUNCH();
+    op_normal_parts(p, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma,
+               w.u, w.r, w.p, w.parts, w.sc, w.rho + k);
+    float2* pc = w.p;
+    float2* pn = w.p2;
     for (int j = 0; j < a.n_cg; ++j) {
-      op_normal(p, w.p, a.smaps, a.L, a.dcf, w.Nv, w.op, s);
-      hipLaunchKernelGGL(k_cg_q, dim3(nb), dim3(kRedThreads), 0, s, N, w.p, w.Nv, (float)c0, cg, w.q,
-                         w.parts);
-      hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
-      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kRedThreads), 0, s, N, w.u, w.r, w.p, w.q, w.sc,
-                         w.parts);
-      hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc);
-      if (j + 1 < a.n_cg)
-        hipLaunchKernelGGL(k_cg_p, dim3(nb), dim3(kRedThreads), 0, s, N, w.p, w.r, w.sc);
-      PNP_CHECK_LAUNCH();
+      if (j == 0) {
+        op_normal_parts(p, NormalIn{pc, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+      } else {
+        // p <- r + beta p, formed inside the operator's first pass
+        op_normal_parts(p, NormalIn{pc, w.r, pn, &w.sc->beta}, a.smaps, a.L, a.dcf, w.op, s);
+        std::swap(pc, pn);
+      }
+      PNP_LAUNCH(k_cg_q, dim3(nb), dim3(kRedThreads), 0, s, N, G, pc, w.op.part, (float)c0, cg, w.q,
+                 w.parts, w.sc);
+      PNP_LAUNCH(k_cg_update, dim3(nb), dim3(kRedThreads), 0, s, N, w.u, w.r, pc, w.q, w.parts, w.sc);
     }
     apply_prior(p, a.prior, w.u, x, a.sigmas[k], s);
   }
   if (rho_host) {
     // residual of the final image (one extra normal operator)
-    op_normal(p, x, a.smaps, a.L, a.dcf, w.Nv, w.op, s);
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, x, w.Nv, w.b0, 0.0f, w.u,
-                       w.r, w.p, w.parts);
-    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc,
-                       w.rho + a.n_out);
-    PNP_CHECK_LAUNCH();
+    op_normal_parts(p, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, 0.0f, w.u, w.r,
+               w.p, w.parts, w.sc, w.rho + a.n_out);
     std::vector<double> r(a.n_out + 1);
     DevScalars h;
     PNP_HIP(hipMemcpyAsync(r.data(), w.rho, sizeof(double) * (a.n_out + 1), hipMemcpyDeviceToHost, s));

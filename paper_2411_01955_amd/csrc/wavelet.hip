@@ -8,6 +8,7 @@
 // single coarsest approximation coefficient of a block (index 0) is the
 // only one left unthresholded.  Soft threshold: c * max(0, 1 - tau/|c|).
 #include "common.hpp"
+#include "trace.hpp"
 
 namespace pnp {
 
@@ -120,7 +121,7 @@ void wavelet_apply(int ndim, const int* n, int levels, float tau, const float2* 
   for (int a = 0; a < ndim; ++a) blocks *= n[a] / B;
   const int total = ndim == 3 ? B * B * B : B * B;
   const size_t lds = sizeof(float2) * 2 * total;
-  hipLaunchKernelGGL(k_haar_prior, dim3((unsigned)blocks), dim3(256), lds, s, in, out, ndim, n[0],
+  PNP_LAUNCH(k_haar_prior, dim3((unsigned)blocks), dim3(256), lds, s, in, out, ndim, n[0],
                      n[1], ndim == 3 ? n[2] : 1, levels, tau);
   PNP_CHECK_LAUNCH();
 }
