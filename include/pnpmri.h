@@ -142,6 +142,28 @@ pnp_status pnp_opnorm(const pnp_plan* plan, const pnp_c64* smaps, int32_t L, con
                       int32_t iters, uint64_t seed, double* norm_out, void* ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* ------------------------------------------------------------- Toeplitz */
+typedef struct pnp_toeplitz pnp_toeplitz;
+
+/* Toeplitz embedding of the normal operator A^H D_w A (2D; grid sides in
+ * {128, 192, 256, 512, 640, 768, 1024}, i.e. image sides 64, 96, 128, 256,
+ * 320, 384, 512).  The normal operator of Sec. 3.4 is a convolution with the
+ * point-spread function psf[d] = N^{-1} sum_m w_m exp(+i <k_m, d>); embedded
+ * in the 2n x 2n grid it is crop(IFFT(T * FFT(pad(z)))) per coil with a real
+ * transfer function T.  T is formed once here, exactly in FP64 from the
+ * plan's trajectory and `dcf` (device float [M] or NULL), then rounded to
+ * FP32.  Applying it needs no interpolation and no Kaiser-Bessel
+ * approximation.  The handle keeps a pointer to `plan`: destroy it first.
+ * The call waits for `stream`. */
+pnp_status pnp_toeplitz_create(pnp_toeplitz** out, const pnp_plan* plan, const float* dcf,
+                               hipStream_t stream);
+pnp_status pnp_toeplitz_destroy(pnp_toeplitz* tp);
+
+/* out = A^H D_w A x through the Toeplitz embedding (same layouts and
+ * workspace size as pnp_normal; x and out may not alias). */
+pnp_status pnp_normal_toeplitz(const pnp_toeplitz* tp, const pnp_c64* x, const pnp_c64* smaps,
+                               int32_t L, pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ----------------------------------------------------------------- prior */
 typedef struct pnp_prior pnp_prior;
 
@@ -170,6 +192,8 @@ typedef struct {
   uint64_t opnorm_seed;      /* seed of the power-iteration start vector      */
   const pnp_c64* x0;         /* device [N] start image, NULL: x0 = A^H D_w y  */
   double rise_tol;           /* fallback when rho_k > (1+rise_tol) rho_{k-1}  */
+  const pnp_toeplitz* toeplitz;  /* NULL: gridded normal operator; else the
+                                    Toeplitz one (built with the same dcf)   */
 } pnp_hqs_opts;
 
 typedef struct {

@@ -18,7 +18,8 @@ import ctypes as C
 
 from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, check, load
 
-__all__ = ["Plan", "WaveletPrior", "hqs_solve", "PnPError", "load", "trace_enable", "trace_read"]
+__all__ = ["Plan", "Toeplitz", "WaveletPrior", "hqs_solve", "PnPError", "load", "trace_enable",
+           "trace_read"]
 
 
 def trace_enable(on: bool = True):
@@ -172,6 +173,42 @@ class Plan:
         return v.value
 
 
+class Toeplitz:
+    """Toeplitz embedding of A^H D_w A for one plan and DCF (2D)."""
+
+    def __init__(self, plan: Plan, dcf=None):
+        _need_f32(dcf, "dcf", (plan.M,))
+        self.plan = plan
+        self._dcf = dcf
+        h = C.c_void_p()
+        check(load().pnp_toeplitz_create(C.byref(h), plan.handle, _ptr(dcf), _stream()))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def normal(self, x, smaps, out=None):
+        L = self.plan._L(smaps)
+        _need_c64(x, "x", self.plan.shape)
+        o = out if out is not None else _torch().empty(self.plan.shape, dtype=_torch().complex64, device=x.device)
+        _need_c64(o, "out", self.plan.shape)
+        ws, nb = self.plan.workspace(L)
+        check(load().pnp_normal_toeplitz(self._h, _ptr(x), _ptr(smaps), L, _ptr(o), _ptr(ws), nb, _stream()))
+        return o
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pnp_toeplitz_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class WaveletPrior:
     """Haar soft-threshold prior, tau = kappa * sigma (levels 0: default rule)."""
 
@@ -207,8 +244,9 @@ class WaveletPrior:
 
 def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str = "f1", n_cg: int = 5,
               opnorm: float = 0.0, opnorm_iters: int = 50, opnorm_seed: int = 0, x0=None,
-              report: bool = False, out=None, rise_tol: float = 0.0):
-    """Annealed preconditioned PnP-HQS; returns (x, report dict or None)."""
+              report: bool = False, out=None, rise_tol: float = 0.0, toeplitz: "Toeplitz" = None):
+    """Annealed preconditioned PnP-HQS; returns (x, report dict or None).
+    With ``toeplitz`` the CG steps use the Toeplitz normal operator."""
     torch = _torch()
     L = plan._L(smaps)
     _need_c64(y, "y", (L, plan.M))
@@ -217,8 +255,11 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
         _need_c64(x0, "x0", plan.shape)
     n_out = len(sigmas)
     sig = (C.c_double * n_out)(*[float(s) for s in sigmas])
+    if toeplitz is not None and toeplitz.plan is not plan:
+        raise ValueError("toeplitz was built for another plan")
     o = HQSOpts(C.sizeof(HQSOpts), PRECOND[precond.lower()], int(n_cg), int(opnorm_iters), float(lam),
-                float(opnorm), int(opnorm_seed), x0.data_ptr() if x0 is not None else None, float(rise_tol))
+                float(opnorm), int(opnorm_seed), x0.data_ptr() if x0 is not None else None, float(rise_tol),
+                toeplitz.handle.value if toeplitz is not None else None)
     x = out if out is not None else torch.empty(plan.shape, dtype=torch.complex64, device=y.device)
     _need_c64(x, "out", plan.shape)
     ws, nb = plan.workspace(L, "hqs")

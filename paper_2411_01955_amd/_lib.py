@@ -28,6 +28,7 @@ class HQSOpts(C.Structure):
         ("opnorm_seed", C.c_uint64),
         ("x0", C.c_void_p),
         ("rise_tol", C.c_double),
+        ("toeplitz", C.c_void_p),
     ]
 
 
@@ -62,6 +63,9 @@ SIGNATURES = {
     "pnp_adjoint": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "pnp_normal": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
     "pnp_opnorm": (_i32, [_vp, _vp, _i32, _vp, _i32, _u64, C.POINTER(_dbl), _vp, _sz, _vp]),
+    "pnp_toeplitz_create": (_i32, [C.POINTER(_vp), _vp, _vp, _vp]),
+    "pnp_toeplitz_destroy": (_i32, [_vp]),
+    "pnp_normal_toeplitz": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "pnp_prior_wavelet": (_i32, [C.POINTER(_vp), _i32, _dbl]),
     "pnp_prior_destroy": (_i32, [_vp]),
     "pnp_prior_apply": (_i32, [_vp, _i32, C.POINTER(_i32), _vp, _vp, _dbl, _vp]),

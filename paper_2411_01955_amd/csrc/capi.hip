@@ -184,9 +184,39 @@ pnp_status pnp_opnorm(const pnp_plan* p, const pnp_c64* smaps, int32_t L, const 
     need(ws, "ws");
     if (iters < 1) fail(PNP_ERR_ARG, "iters must be >= 1");
     check_ws(ws_bytes, opnorm_workspace_bytes(p, L), ws);
-    const double v = power_iteration(p, (const float2*)smaps, L, dcf, iters, seed, ws, stream);
+    const double v = power_iteration(p, nullptr, (const float2*)smaps, L, dcf, iters, seed, ws, stream);
     if (!std::isfinite(v)) fail(PNP_ERR_NUMERIC, "power iteration produced a non-finite norm");
     *norm_out = v;
+  });
+}
+
+pnp_status pnp_toeplitz_create(pnp_toeplitz** out, const pnp_plan* plan, const float* dcf,
+                               hipStream_t stream) {
+  return guarded([&] {
+    need(out, "out");
+    need(plan, "plan");
+    *out = nullptr;
+    *out = toeplitz_create(plan, plan->traj, dcf, stream);
+  });
+}
+
+pnp_status pnp_toeplitz_destroy(pnp_toeplitz* tp) {
+  return guarded([&] { toeplitz_destroy(tp); });
+}
+
+pnp_status pnp_normal_toeplitz(const pnp_toeplitz* tp, const pnp_c64* x, const pnp_c64* smaps, int32_t L,
+                               pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need(tp, "toeplitz");
+    check_plan_L(tp->plan, L);
+    need(x, "x");
+    need(smaps, "smaps");
+    need(out, "out");
+    need(ws, "ws");
+    if ((const void*)x == (const void*)out) fail(PNP_ERR_ARG, "x and out must not alias");
+    check_ws(ws_bytes, op_workspace_bytes(tp->plan, L), ws);
+    op_normal_toep(tp, (const float2*)x, (const float2*)smaps, L, (float2*)out,
+                   op_workspace(tp->plan, L, ws), stream);
   });
 }
 
@@ -263,11 +293,14 @@ pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* sma
     }
     if ((const void*)x_out == (const void*)y || (const void*)x_out == (const void*)smaps)
       fail(PNP_ERR_ARG, "x_out must not alias y or smaps");
+    if (opts->toeplitz && opts->toeplitz->plan != p)
+      fail(PNP_ERR_ARG, "opts.toeplitz was built for another plan");
     check_ws(ws_bytes, hqs_workspace_bytes(p, L), ws);
     double nrm = opts->opnorm;
     if (!(nrm > 0.0)) {
       const int its = opts->opnorm_iters > 0 ? opts->opnorm_iters : 50;
-      nrm = power_iteration(p, (const float2*)smaps, L, dcf, its, opts->opnorm_seed, ws, stream);
+      nrm = power_iteration(p, opts->toeplitz, (const float2*)smaps, L, dcf, its, opts->opnorm_seed, ws,
+                            stream);
       if (!(nrm > 0.0) || !std::isfinite(nrm)) fail(PNP_ERR_NUMERIC, "operator norm is %g", nrm);
     }
     HQSArgs a;
@@ -284,6 +317,7 @@ pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* sma
     a.opnorm = nrm;
     a.x0 = (const float2*)opts->x0;
     a.x_out = (float2*)x_out;
+    a.toep = opts->toeplitz;
     int bad = 0;
     hqs_solve(p, a, ws, stream, report ? report->rho : nullptr, report ? &bad : nullptr);
     if (report) {

@@ -101,6 +101,7 @@ struct pnp_plan {
   int32_t* ent_sample;      // [E] sample of each entry, grouped by tile
   int32_t* sample_ent;      // [M][slots] entry indices of a sample (-1: none)
   pnp::EntryRec* rec;       // [E] packed taps and weights, grouped by tile (2D)
+  float* traj;              // [M][ndim] copy of the trajectory (radians)
   void* block;
   size_t block_bytes;
 };
@@ -109,6 +110,13 @@ struct pnp_prior {
   int kind;                 // 0 = Haar wavelet
   int levels;               // 0 = default rule
   double kappa;
+};
+
+// Toeplitz embedding of A^H D_w A for one (plan, DCF): the real transfer
+// function T[Ky][Kx] on the 2n x 2n grid, pre-scaled by 1/(Kx Ky).
+struct pnp_toeplitz {
+  const pnp_plan* plan;
+  float* T;
 };
 
 namespace pnp {
@@ -147,6 +155,16 @@ int op_groups(int L);
 void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
                      const float* dcf, const OpWorkspace& w, hipStream_t s);
 
+// Toeplitz normal operator (2D, register-FFT grid sizes): same contract as
+// op_normal_parts / op_normal, with D_w folded into T.
+bool toeplitz_supported(const pnp_plan* p);
+pnp_toeplitz* toeplitz_create(const pnp_plan* p, const float* traj, const float* dcf, hipStream_t s);
+void toeplitz_destroy(pnp_toeplitz* tp);
+void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
+                          const OpWorkspace& w, hipStream_t s);
+void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps, int L, float2* out,
+                    const OpWorkspace& w, hipStream_t s);
+
 int64_t image_size(const pnp_plan* p);
 
 // Haar prior
@@ -161,8 +179,8 @@ void plan_destroy(pnp_plan* p);
 // solver
 size_t hqs_workspace_bytes(const pnp_plan* p, int L);
 size_t opnorm_workspace_bytes(const pnp_plan* p, int L);
-double power_iteration(const pnp_plan* p, const float2* smaps, int L, const float* dcf, int iters,
-                       uint64_t seed, void* ws, hipStream_t s);
+double power_iteration(const pnp_plan* p, const pnp_toeplitz* tp, const float2* smaps, int L,
+                       const float* dcf, int iters, uint64_t seed, void* ws, hipStream_t s);
 
 struct HQSArgs {
   const float2* y;
@@ -178,6 +196,7 @@ struct HQSArgs {
   double opnorm;
   const float2* x0;
   float2* x_out;
+  const pnp_toeplitz* toep;   // nullptr: gridded normal operator
 };
 // Runs the loop; when rho_host is given, also the final residual, and waits.
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,

@@ -315,7 +315,7 @@ k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
   float2* Al = A + line * F::LA;
   if (active && t < K2) {
     float2 v[K1];
-    const float sy = day[iy];
+    const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
     const float bt = img_beta(in);
     const bool store = line == 0 && blockIdx.y == 0;
     const float2* Sl = S + (long long)l * N + (long long)iy * nx;
@@ -323,7 +323,7 @@ k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
 #pragma unroll
     for (int n1 = 0; n1 < K1; ++n1) {
       const int ix = img_of_grid(n1 * K2 + t, nx, F::K);
-      v[n1] = ix >= 0 ? cscale(cmul(Sl[ix], img_at(in, row0 + ix, bt, store)), dax[ix] * sy)
+      v[n1] = ix >= 0 ? cscale(cmul(Sl[ix], img_at(in, row0 + ix, bt, store)), (dax ? dax[ix] : 1.f) * sy)
                       : make_float2(0.f, 0.f);
     }
     reg::dft<K1, false>(v);
@@ -576,11 +576,80 @@ k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int 
   }
   __syncthreads();
   const int nl = min(kRowCoils, L - g * kRowCoils);
-  const float sy = day[iy];
+  const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
   for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
     float2 acc = Z[ix];
     for (int li = 1; li < nl; ++li) acc = cadd(acc, Z[li * nx + ix]);
-    part[(long long)g * N + (long long)iy * nx + ix] = cscale(acc, dax[ix] * sy);
+    part[(long long)g * N + (long long)iy * nx + ix] = cscale(acc, (dax ? dax[ix] : 1.f) * sy);
+  }
+}
+
+// Toeplitz column pass: for a strip of grid columns, the zero-padded column
+// FFT, multiplication by the real transfer function T, and the inverse
+// column FFT, all in registers with two LDS transposes:
+//   forward   n = n1*K2 + n2, k = k1 + K1*k2   (as in the other kernels)
+//   inverse   k = k1 + K1*k2, r = r2 + K2*r1:  thread k1 runs the inverse
+//             DFT over k2, twiddle exp(+2 pi i k1 r2 / K), transpose,
+//             thread r2 runs the inverse DFT over k1 -> y[r2 + K2*r1].
+// Only the ny image rows are read and written (in place in mid).
+template <int K1, int K2>
+__global__ void __launch_bounds__(8 * K1)
+k_cols_toep_fs(float2* __restrict__ mid, int ny, int Kx, const float2* __restrict__ tw, int tile,
+               const float* __restrict__ T) {
+  using F = FS<K1, K2>;
+  constexpr int AS2 = K1 + 1;          // row stride of the second transpose
+  __shared__ float2 lds[8 * F::CS];
+  const int c = threadIdx.x % 8;
+  const int t = threadIdx.x / 8;
+  const int c0 = blockIdx.x * tile;
+  const int l = blockIdx.y;
+  const bool colok = c < tile;
+  float2* col = mid + (long long)l * ny * Kx + c0 + c;
+  if (colok && t < K2) {
+    float2 v[K1];
+#pragma unroll
+    for (int n1 = 0; n1 < K1; ++n1) {
+      const int iy = img_of_grid(n1 * K2 + t, ny, F::K);
+      v[n1] = iy >= 0 ? col[(long long)iy * Kx] : make_float2(0.f, 0.f);
+    }
+    reg::dft<K1, false>(v);
+    fs_twiddle<K1, K2, false>(v, t, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];
+  }
+  __syncthreads();
+  float2 u[K2];
+  if (colok) {
+#pragma unroll
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
+    reg::dft<K2, false>(u);                         // u[k2] = X[t + K1*k2]
+    const float* Tc = T + c0 + c;
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], Tc[(long long)(t + K1 * k2) * Kx]);
+    reg::dft<K2, true>(u);                          // u[r2] = sum_k2 Y exp(+...)
+#pragma unroll
+    for (int r2 = 1; r2 < K2; ++r2) {
+      float2 w = tw[t * r2];
+      w.y = -w.y;
+      u[r2] = cmul(u[r2], w);
+    }
+  }
+  __syncthreads();
+  if (colok) {
+#pragma unroll
+    for (int r2 = 0; r2 < K2; ++r2) lds[c * F::CS + r2 * AS2 + t] = u[r2];
+  }
+  __syncthreads();
+  if (colok && t < K2) {
+    float2 z[K1];
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) z[k1] = lds[c * F::CS + t * AS2 + k1];
+    reg::dft<K1, true>(z);                          // z[r1] = y[t + K2*r1]
+#pragma unroll
+    for (int r1 = 0; r1 < K1; ++r1) {
+      const int iy = img_of_grid(t + K2 * r1, ny, F::K);
+      if (iy >= 0) col[(long long)iy * Kx] = z[r1];
+    }
   }
 }
 
@@ -656,6 +725,25 @@ struct FSLaunch {
     const int G = (L + kRowCoils - 1) / kRowCoils;
     PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, mid, S, L,
                p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, part);
+  }
+  // Toeplitz variants: no deapodisation, column pass = FFT * T * IFFT
+  static void rows_fwd_toep(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
+                            hipStream_t s) {
+    const int G = (L + kRowCoils - 1) / kRowCoils;
+    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, in, S, L,
+               p->ax[0].n, p->ax[1].n, (const float*)nullptr, (const float*)nullptr, p->ax[0].fft.tw,
+               mid);
+  }
+  static void cols_toep(const pnp_plan* p, int L, const float* T, float2* mid, hipStream_t s) {
+    PNP_LAUNCH((k_cols_toep_fs<K1, K2>), dim3(p->ntx, L), dim3(8 * K1), 0, s, mid, p->ax[1].n, p->ax[0].K,
+               p->ax[1].fft.tw, p->tile, T);
+  }
+  static void rows_adj_toep(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
+                            hipStream_t s) {
+    const int G = (L + kRowCoils - 1) / kRowCoils;
+    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, mid, S, L,
+               p->ax[0].n, p->ax[1].n, (const float*)nullptr, (const float*)nullptr, p->ax[0].fft.tw,
+               part);
   }
 };
 
@@ -809,6 +897,26 @@ void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps,
   const float scale = (float)(1.0 / (double)image_size(p));   // both N^{-1/2} factors
   adjoint_to_groups(p, KIn{nullptr, w.ypart, p->sample_ent, (long long)p->M, (long long)p->E}, smaps,
                     L, dcf, scale, w.part, w, s);
+}
+
+bool toeplitz_supported(const pnp_plan* p) { return p->ndim == 2 && fs_ok(p); }
+
+void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
+                          const OpWorkspace& w, hipStream_t s) {
+  const pnp_plan* p = tp->plan;
+  const ImgIn im{in.x, in.r, in.pnew, in.beta};
+  PNP_FS_DISPATCH(p->ax[0].K, rows_fwd_toep, p, im, smaps, L, w.mid, s);
+  PNP_FS_DISPATCH(p->ax[1].K, cols_toep, p, L, tp->T, w.mid, s);
+  PNP_FS_DISPATCH(p->ax[0].K, rows_adj_toep, p, L, w.mid, smaps, w.part, s);
+}
+
+void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps, int L, float2* out,
+                    const OpWorkspace& w, hipStream_t s) {
+  op_normal_toep_parts(tp, NormalIn{x, nullptr, nullptr, nullptr}, smaps, L, w, s);
+  const int G = op_groups(L);
+  const int64_t N = image_size(tp->plan);
+  PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
+             (long long)N, out);
 }
 
 void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,

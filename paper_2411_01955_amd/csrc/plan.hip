@@ -366,6 +366,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     const size_t o_es = take(sizeof(int) * Emax);
     const size_t o_se = take(sizeof(int) * M * p->slots);
     const size_t o_rec = take(sizeof(EntryRec) * (ndim == 2 ? Emax : 1));
+    const size_t o_traj = take(sizeof(float) * M * ndim);
     // set-up scratch (freed below)
     size_t soff = 0;
     const size_t s_cnt = soff; soff += align256(sizeof(int) * p->ntiles);
@@ -390,6 +391,8 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     p->ent_sample = (int32_t*)(base + o_es);
     p->sample_ent = (int32_t*)(base + o_se);
     p->rec = (EntryRec*)(base + o_rec);
+    p->traj = (float*)(base + o_traj);
+    PNP_HIP(hipMemcpyAsync(p->traj, traj, sizeof(float) * M * ndim, hipMemcpyDeviceToDevice, stream));
 
     struct Scratch {
       char* ptr = nullptr;

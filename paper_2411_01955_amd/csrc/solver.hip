@@ -316,8 +316,19 @@ size_t opnorm_workspace_bytes(const pnp_plan* p, int L) { return hqs_workspace_b
 
 // Power iteration: v <- N v / ||N v||, `iters` times; returns the last
 // Rayleigh quotient Re<v, N v> (|v| = 1).  Synchronises the stream.
-double power_iteration(const pnp_plan* p, const float2* smaps, int L, const float* dcf, int iters,
-                       uint64_t seed, void* ws, hipStream_t s) {
+// Normal operator with the result left as coil-group partial images: the
+// Toeplitz embedding when given, else the gridded operator.
+static void normal_parts(const pnp_plan* p, const pnp_toeplitz* tp, const NormalIn& in,
+                         const float2* smaps, int L, const float* dcf, const OpWorkspace& w,
+                         hipStream_t s) {
+  if (tp)
+    op_normal_toep_parts(tp, in, smaps, L, w, s);
+  else
+    op_normal_parts(p, in, smaps, L, dcf, w, s);   // gridded
+}
+
+double power_iteration(const pnp_plan* p, const pnp_toeplitz* tp, const float2* smaps, int L,
+                       const float* dcf, int iters, uint64_t seed, void* ws, hipStream_t s) {
   SolverWs w = solver_ws(p, L, ws);
   const long long N = image_size(p);
   const int G = op_groups(L);
@@ -329,7 +340,7 @@ double power_iteration(const pnp_plan* p, const float2* smaps, int L, const floa
              (const float2*)nullptr, w.Nv, w.parts, w.sc);
   PNP_LAUNCH(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, w.sc, v);
   for (int it = 0; it < iters; ++it) {
-    op_normal_parts(p, NormalIn{v, nullptr, nullptr, nullptr}, smaps, L, dcf, w.op, s);
+    normal_parts(p, tp, NormalIn{v, nullptr, nullptr, nullptr}, smaps, L, dcf, w.op, s);
     PNP_LAUNCH(k_pow_dot, dim3(nb), dim3(kRedThreads), 0, s, N, G, v, w.op.part, w.Nv, w.parts, w.sc);
     PNP_LAUNCH(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, w.sc, v);
   }
@@ -376,17 +387,17 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   for (int k = 0; k < a.n_out; ++k) {
     const double gamma = a.lambda * a.sigmas[k];
     const float cg = (float)(gamma - c1a);
-    op_normal_parts(p, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+    normal_parts(p, a.toep, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma,
                w.u, w.r, w.p, w.parts, w.sc, w.rho + k);
     float2* pc = w.p;
     float2* pn = w.p2;
     for (int j = 0; j < a.n_cg; ++j) {
       if (j == 0) {
-        op_normal_parts(p, NormalIn{pc, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+        normal_parts(p, a.toep, NormalIn{pc, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
       } else {
         // p <- r + beta p, formed inside the operator's first pass
-        op_normal_parts(p, NormalIn{pc, w.r, pn, &w.sc->beta}, a.smaps, a.L, a.dcf, w.op, s);
+        normal_parts(p, a.toep, NormalIn{pc, w.r, pn, &w.sc->beta}, a.smaps, a.L, a.dcf, w.op, s);
         std::swap(pc, pn);
       }
       PNP_LAUNCH(k_cg_q, dim3(nb), dim3(kRedThreads), 0, s, N, G, pc, w.op.part, (float)c0, cg, w.q,
@@ -397,7 +408,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   }
   if (rho_host) {
     // residual of the final image (one extra normal operator)
-    op_normal_parts(p, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+    normal_parts(p, a.toep, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, 0.0f, w.u, w.r,
                w.p, w.parts, w.sc, w.rho + a.n_out);
     std::vector<double> r(a.n_out + 1);

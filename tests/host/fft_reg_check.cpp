@@ -58,7 +58,54 @@ static void four() {
   printf("\n");
 }
 
+// Toeplitz column chain as the kernel runs it: forward four-step, multiply
+// by a real T[k], inverse with k = k1 + K1*k2, r = r2 + K2*r1 (inverse DFT
+// over k2 by thread k1, twiddle exp(+2 pi i k1 r2/K), inverse DFT over k1
+// by thread r2).  Prints input, T and y = sum_k T[k] X[k] exp(+2 pi i k r/K).
+template <int K1, int K2>
+static void toep() {
+  constexpr int K = K1 * K2;
+  std::vector<float2> x(K), tw(K), A(K1 * (K2 + 1)), B(K2 * (K1 + 1)), Y(K);
+  std::vector<float> T(K);
+  for (int i = 0; i < K; ++i) x[i] = make_float2(rnd(), rnd());
+  for (int i = 0; i < K; ++i) T[i] = rnd();
+  for (int t = 0; t < K; ++t)
+    tw[t] = make_float2((float)std::cos(-2.0 * M_PI * t / K), (float)std::sin(-2.0 * M_PI * t / K));
+  for (int n2 = 0; n2 < K2; ++n2) {
+    float2 v[K1];
+    for (int n1 = 0; n1 < K1; ++n1) v[n1] = x[n1 * K2 + n2];
+    reg::dft<K1, false>(v);
+    for (int k1 = 1; k1 < K1; ++k1) v[k1] = cmul(v[k1], tw[n2 * k1]);
+    for (int k1 = 0; k1 < K1; ++k1) A[k1 * (K2 + 1) + n2] = v[k1];
+  }
+  for (int k1 = 0; k1 < K1; ++k1) {
+    float2 u[K2];
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = A[k1 * (K2 + 1) + n2];
+    reg::dft<K2, false>(u);
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], T[k1 + K1 * k2]);
+    reg::dft<K2, true>(u);
+    for (int r2 = 1; r2 < K2; ++r2) {
+      float2 w = tw[k1 * r2];
+      w.y = -w.y;
+      u[r2] = cmul(u[r2], w);
+    }
+    for (int r2 = 0; r2 < K2; ++r2) B[r2 * (K1 + 1) + k1] = u[r2];
+  }
+  for (int r2 = 0; r2 < K2; ++r2) {
+    float2 z[K1];
+    for (int k1 = 0; k1 < K1; ++k1) z[k1] = B[r2 * (K1 + 1) + k1];
+    reg::dft<K1, true>(z);
+    for (int r1 = 0; r1 < K1; ++r1) Y[r2 + K2 * r1] = z[r1];
+  }
+  printf("toep %d 0", K);
+  for (int i = 0; i < K; ++i) printf(" %.9g %.9g", x[i].x, x[i].y);
+  for (int i = 0; i < K; ++i) printf(" %.9g 0", T[i]);
+  for (int i = 0; i < K; ++i) printf(" %.9g %.9g", Y[i].x, Y[i].y);
+  printf("\n");
+}
+
 int main() {
+  toep<16, 8>(); toep<32, 20>(); toep<32, 24>(); toep<32, 32>();
   one<2, false>(); one<3, false>(); one<4, false>(); one<5, false>(); one<6, false>();
   one<8, false>(); one<10, false>(); one<12, false>(); one<16, false>(); one<20, false>();
   one<24, false>(); one<32, false>();

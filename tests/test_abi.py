@@ -82,6 +82,6 @@ def test_prior_validation_and_lifecycle(lib):
 
 def test_struct_sizes_match_header():
     from paper_2411_01955_amd._lib import HQSOpts, HQSReport
-    # uint32 + 3 int32 + 2 double + uint64 + pointer + double
-    assert C.sizeof(HQSOpts) == 56
+    # uint32 + 3 int32 + 2 double + uint64 + pointer + double + pointer
+    assert C.sizeof(HQSOpts) == 64
     assert C.sizeof(HQSReport) == 32

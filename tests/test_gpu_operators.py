@@ -149,3 +149,47 @@ def test_workspace_too_small_is_rejected(pnp):
     st = _lib.load().pnp_forward(plan.handle, C.c_void_p(x.data_ptr()), C.c_void_p(S.data_ptr()), w.L,
                                  C.c_void_p(y.data_ptr()), C.c_void_p(ws.data_ptr()), 1024, None)
     assert st == -5
+
+
+# ------------------------------------------------- Toeplitz normal operator
+def _toep_case(pnp, shape, k, S, dcf, x, label, tol):
+    plan = pnp.Plan(to_dev(k), shape)
+    tp = pnp.Toeplitz(plan, to_dev(dcf) if dcf is not None else None)
+    got = to_np(tp.normal(to_dev(x), to_dev(S)))
+    ref = ndft.normal(x, S, k, dcf)
+    e = rel_l2(got, ref)
+    say(f"[toeplitz] {label}: rel {e:.3e}")
+    assert e < tol
+    return e
+
+
+def test_toeplitz_tiny_radial(pnp):
+    w = synth.config_tiny()
+    x, _ = synth.phantom2d(w.n, 1001)
+    _toep_case(pnp, (w.n, w.n), w.traj.k, synth.smaps2d(w.n, w.L), None, x, "64x64 L4 radial", 2e-6)
+
+
+def test_toeplitz_clinical_spiral_dcf(pnp):
+    w = synth.config_clinical()
+    x, _ = synth.phantom2d(w.n, 1002)
+    dcf = synth.voronoi_dcf(w.traj, w.n)
+    _toep_case(pnp, (w.n, w.n), w.traj.k, synth.smaps2d(w.n, w.L), dcf, x, "320x320 L16 spiral+DCF", 2e-6)
+
+
+def test_toeplitz_ragged(pnp):
+    rng = np.random.default_rng(12)
+    shape, L, M = (96, 96), 5, 1777
+    k = rng.uniform(-math.pi, math.pi, (M, 2)).astype(np.float32)
+    k[:3] = [[-math.pi, -math.pi], [math.pi, 0.0], [0.0, 0.0]]
+    dcf = rng.uniform(0.2, 2.0, M).astype(np.float32)
+    x = synth.white_complex(shape, 13)
+    S = synth.white_complex((L,) + shape, 14)
+    _toep_case(pnp, shape, k, S, dcf, x, "96x96 L5 random+weights", 2e-6)
+
+
+def test_toeplitz_rejects_unsupported_size(pnp):
+    k = np.zeros((10, 2), np.float32)
+    plan = pnp.Plan(to_dev(k), (48, 80))
+    with pytest.raises(pnp.PnPError) as ei:
+        pnp.Toeplitz(plan)
+    assert ei.value.status == -3
