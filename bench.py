@@ -44,7 +44,8 @@ LAM_TIMES_NORM = 1e4
 KAPPA = 0.75
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical.json")
 KERNEL_SOURCES = ["paper_2411_01955_amd/csrc/nufft2d.hip", "paper_2411_01955_amd/csrc/fft_lds.hpp",
-                  "paper_2411_01955_amd/csrc/plan.hip"]
+                  "paper_2411_01955_amd/csrc/fft_reg.hpp", "paper_2411_01955_amd/csrc/plan.hip",
+                  "paper_2411_01955_amd/csrc/toeplitz.hip", "paper_2411_01955_amd/csrc/solver.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -130,6 +131,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (counter calibration for rocprofv3)")
     ap.add_argument("--seed", type=int, default=1002)
+    ap.add_argument("--reps", type=int, default=200,
+                    help="back-to-back repetitions when timing the normal operators alone")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
@@ -193,7 +196,7 @@ def main():
     # normal operator alone, back to back: gridded and Toeplitz-embedded
     tmp = torch.empty_like(xd)
 
-    def time_op(fn, reps=200):
+    def time_op(fn, reps=max(1, args.reps)):
         for _ in range(5):
             fn()
         torch.cuda.synchronize()
