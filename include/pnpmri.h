@@ -181,6 +181,101 @@ pnp_status pnp_prior_destroy(pnp_prior* prior);
 pnp_status pnp_prior_apply(const pnp_prior* prior, int32_t ndim, const int32_t* shape,
                            const pnp_c64* in, pnp_c64* out, double sigma, hipStream_t stream);
 
+/* ------------------------------------------------------------------ UNet
+ * The learned denoiser D_sigma of the plug-and-play prior (Sec. 2.3: a
+ * denoiser acting on complex images through their real and imaginary parts
+ * as two channels, conditioned on the noise level; Sec. 4.2: trained with a
+ * supervised l1 loss and Adam).  Fixed architecture, widths 32/64/128/256:
+ *   encoder  per scale two 3x3 convolutions + ReLU, 2x2 max-pool between
+ *   decoder  2x2 stride-2 transposed convolution, concatenation [skip, up],
+ *            two 3x3 convolutions + ReLU
+ *   output   1x1 convolution to 2 channels;  D_sigma(u) = u + output
+ * Input channels: Re u, Im u, sigma (a constant map).  Convolutions pad with
+ * zeros ('same').  Weights and activations BF16 (round to nearest even),
+ * products accumulated in FP32 on the matrix cores, master weights and Adam
+ * moments FP32.
+ *
+ * Parameters are one flat FP32 array of pnp_unet_param_count() floats; layer
+ * i (pnp_unet_layer_info) stores its weights at w_offset as
+ *   3x3 / 1x1 convolution   W[cout][taps][cin_padded]   (tap = 3*(dy+1)+(dx+1))
+ *   transposed convolution  W[cout][4][cin]             (tap = 2*a + b, output
+ *                                                          pixel (2i+a, 2j+b))
+ * and its bias [cout] at b_offset.  Only the first layer is padded (3 input
+ * channels stored as 8); its padding weights must be zero and stay zero.
+ * Images are complex64 [B][H][W]; H and W must be multiples of 8. */
+typedef struct pnp_unet pnp_unet;
+
+enum { PNP_UNET_CONV3 = 0, PNP_UNET_CONV1 = 1, PNP_UNET_UP = 2 };
+enum { PNP_UNET_PARAMS = 0, PNP_UNET_GRAD = 1, PNP_UNET_ADAM_M = 2, PNP_UNET_ADAM_V = 3 };
+
+typedef struct {
+  int32_t kind;              /* PNP_UNET_CONV3 / CONV1 / UP                   */
+  int32_t cin, cin_padded, cout, taps;
+  int64_t w_offset, b_offset;   /* floats into the flat parameter array       */
+} pnp_unet_layer;
+
+int32_t pnp_unet_layer_count(void);
+int64_t pnp_unet_param_count(void);
+pnp_status pnp_unet_layer_info(int32_t i, pnp_unet_layer* out);
+
+/* Create a network on the current device from `params` (device FP32
+ * [pnp_unet_param_count()], copied).  Adam moments start at zero, step 0.
+ * The network owns its parameter, gradient, moment and BF16 buffers. */
+pnp_status pnp_unet_create(pnp_unet** out, const float* params, hipStream_t stream);
+pnp_status pnp_unet_destroy(pnp_unet* net);
+
+/* Copy one of the network's FP32 arrays (PNP_UNET_PARAMS / GRAD / ADAM_M /
+ * ADAM_V) to or from device memory (gradients can only be read).  Setting
+ * the parameters refreshes the BF16 copies.  Used for checkpoint / resume
+ * together with the Adam step counter. */
+pnp_status pnp_unet_set(pnp_unet* net, int32_t which, const float* src, hipStream_t stream);
+pnp_status pnp_unet_get(pnp_unet* net, int32_t which, float* dst, hipStream_t stream);
+pnp_status pnp_unet_get_step(const pnp_unet* net, int64_t* step);
+pnp_status pnp_unet_set_step(pnp_unet* net, int64_t step);
+
+/* Workspace for a batch of B images H x W; train != 0 adds the gradient
+ * buffers needed by pnp_unet_backward. */
+pnp_status pnp_unet_workspace_bytes(int32_t B, int32_t H, int32_t W, int32_t train, size_t* bytes);
+
+/* out[b] = D_{sigma[b]}(u[b]) for b < B.  u, out: device complex64
+ * [B][H][W] (may not alias); sigma: device float [B].  The activations
+ * stay in `ws` for a following pnp_unet_backward on the same inputs. */
+pnp_status pnp_unet_forward(const pnp_unet* net, const pnp_c64* u, const float* sigma, int32_t B, int32_t H,
+                            int32_t W, pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* l1 training loss of the preceding pnp_unet_forward (same net, inputs and a
+ * train-sized ws): loss = mean over the 2BHW real values of
+ * |D(u) - target| (device double, overwritten); the gradient of the loss
+ * with respect to every parameter replaces the network's gradient array
+ * (sign(0) = 0; ReLU'(0) = 0; a max-pool routes to the first maximum in the
+ * window order (0,0), (0,1), (1,0), (1,1)). */
+pnp_status pnp_unet_backward(pnp_unet* net, const pnp_c64* u, const pnp_c64* target, int32_t B, int32_t H,
+                             int32_t W, double* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step on the FP32 master weights with the current gradients
+ * (bias-corrected moments: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * w -= lr/(1-b1^t) * m / (sqrt(v/(1-b2^t)) + eps)), then the BF16 copies
+ * are refreshed.  Increments the step counter t. */
+pnp_status pnp_unet_adam_step(pnp_unet* net, double lr, double beta1, double beta2, double eps,
+                              hipStream_t stream);
+
+/* Inspection: device address and [B][H][W][C] shape of activation `id` in a
+ * workspace sized for (B, H, W, train).  Forward ids 0..18: x0 e1a c1 d1a
+ * d1b p1 e2a c2 d2a d2b p2 e3a c3 d3a d3b p3 ba bb out (c* hold [skip, up];
+ * out is FP32 [2]); with train, 19..36: the gradients gout gd1b gd1a gc1 gd2b
+ * gd2a gc2 gd3b gd3a gc3 gbb gba gp3 ge3a gp2 ge2a gp1 ge1a (BF16). */
+pnp_status pnp_unet_tensor(int32_t B, int32_t H, int32_t W, int32_t train, void* ws, int32_t id, void** ptr,
+                           int32_t* dims);
+
+/* Learned prior D_sigma(u) = UNet(u, kappa*sigma) for images of `shape`
+ * (2D [ny][nx]; 3D [nz][ny][nx] is denoised slice by slice).  With a
+ * `fallback` (a wavelet prior), pnp_hqs_solve replaces the UNet output by
+ * the fallback's whenever it is not finite or its data-consistency residual
+ * rho_k exceeds (1 + opts.rise_tol) rho_{k-1}.  Allocates its forward
+ * workspace; keeps pointers to `net` and `fallback` (destroy them last). */
+pnp_status pnp_prior_unet(pnp_prior** out, const pnp_unet* net, int32_t ndim, const int32_t* shape, double kappa,
+                          const pnp_prior* fallback);
+
 /* ------------------------------------------------------------------- HQS */
 typedef struct {
   uint32_t struct_size;      /* sizeof(pnp_hqs_opts)                          */

@@ -11,15 +11,22 @@ and the current HIP stream.
     nrm = plan.opnorm(smaps, dcf)        # ||A^H D_w A||   (power iteration)
     x, rep = hqs_solve(plan, y, smaps, dcf, WaveletPrior(0, kappa), sigmas,
                        lam=..., precond="f1", n_cg=5)
+
+    net = UNet(pack_unet_params(params))  # learned denoiser (BF16 MFMA kernels)
+    d = net.forward(u, sigma)              # u + UNet([Re u, Im u, sigma])
+    loss = net.backward(u, target)         # l1 loss, gradients into the net
+    net.adam_step(1e-4)
+    prior = UNetPrior(net, (ny, nx), kappa, fallback=WaveletPrior(0, kw))
 """
 from __future__ import annotations
 
 import ctypes as C
 
-from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, check, load
+from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, UNET_BUF, UNetLayer, check, load
 
-__all__ = ["Plan", "Toeplitz", "WaveletPrior", "hqs_solve", "PnPError", "load", "trace_enable",
-           "trace_read"]
+__all__ = ["Plan", "Toeplitz", "WaveletPrior", "UNet", "UNetPrior", "hqs_solve", "PnPError", "load",
+           "trace_enable", "trace_read", "unet_layers", "pack_unet_params", "unpack_unet_params",
+           "UNET_LAYER_NAMES", "UNET_TENSORS"]
 
 
 def trace_enable(on: bool = True):
@@ -274,3 +281,212 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
     if report:
         return x, {"rho": list(rho), "fallback": list(fb), "opnorm": rep.opnorm_used}
     return x, None
+
+
+# ------------------------------------------------------------------ UNet
+UNET_LAYER_NAMES = ("e1a", "e1b", "e2a", "e2b", "e3a", "e3b", "ba", "bb", "up3", "d3a", "d3b",
+                    "up2", "d2a", "d2b", "up1", "d1a", "d1b", "out")
+# workspace tensor ids of pnp_unet_tensor
+UNET_TENSORS = ("x0", "e1a", "c1", "d1a", "d1b", "p1", "e2a", "c2", "d2a", "d2b", "p2", "e3a", "c3",
+                "d3a", "d3b", "p3", "ba", "bb", "out",
+                "gout", "gd1b", "gd1a", "gc1", "gd2b", "gd2a", "gc2", "gd3b", "gd3a", "gc3", "gbb", "gba",
+                "gp3", "ge3a", "gp2", "ge2a", "gp1", "ge1a")
+
+
+def unet_layers():
+    """[{name, kind, cin, cin_padded, cout, taps, w_offset, b_offset}] of the library's network."""
+    lib = load()
+    out = []
+    for i in range(lib.pnp_unet_layer_count()):
+        li = UNetLayer()
+        check(lib.pnp_unet_layer_info(i, C.byref(li)))
+        out.append({"name": UNET_LAYER_NAMES[i], "kind": ("conv3", "conv1", "up")[li.kind], "cin": li.cin,
+                    "cin_padded": li.cin_padded, "cout": li.cout, "taps": li.taps, "w_offset": li.w_offset,
+                    "b_offset": li.b_offset})
+    return out
+
+
+def pack_unet_params(params):
+    """{name: (W[cout][taps][cin], b[cout])} -> flat float32 numpy array in
+    the library's layout (input channels zero-padded where it pads them)."""
+    import numpy as np
+    flat = np.zeros(int(load().pnp_unet_param_count()), dtype=np.float32)
+    for l in unet_layers():
+        W, b = params[l["name"]]
+        W = np.asarray(W)
+        if W.shape != (l["cout"], l["taps"], l["cin"]):
+            raise ValueError(f"{l['name']}: weight shape {W.shape}, expected {(l['cout'], l['taps'], l['cin'])}")
+        Wp = np.zeros((l["cout"], l["taps"], l["cin_padded"]), dtype=np.float32)
+        Wp[:, :, :l["cin"]] = W
+        flat[l["w_offset"]:l["w_offset"] + Wp.size] = Wp.ravel()
+        flat[l["b_offset"]:l["b_offset"] + l["cout"]] = np.asarray(b, dtype=np.float32)
+    return flat
+
+
+def unpack_unet_params(flat):
+    """Inverse of pack_unet_params (float64 arrays; padding dropped)."""
+    import numpy as np
+    flat = np.asarray(flat, dtype=np.float64)
+    out = {}
+    for l in unet_layers():
+        n = l["cout"] * l["taps"] * l["cin_padded"]
+        W = flat[l["w_offset"]:l["w_offset"] + n].reshape(l["cout"], l["taps"], l["cin_padded"])
+        out[l["name"]] = (W[:, :, :l["cin"]].copy(), flat[l["b_offset"]:l["b_offset"] + l["cout"]].copy())
+    return out
+
+
+class UNet:
+    """The learned denoiser on the current device (BF16 weights and
+    activations, FP32 accumulation, FP32 master weights and Adam moments).
+    ``params``: flat float32 parameters (numpy or CUDA tensor) in the
+    library layout, or a {name: (W, b)} dict."""
+
+    def __init__(self, params):
+        torch = _torch()
+        import numpy as np
+        if isinstance(params, dict):
+            params = pack_unet_params(params)
+        if isinstance(params, np.ndarray):
+            params = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda()
+        self.n_params = int(load().pnp_unet_param_count())
+        if tuple(params.shape) != (self.n_params,) or params.dtype != torch.float32 or not params.is_cuda:
+            raise ValueError(f"params must be CUDA float32 [{self.n_params}]")
+        h = C.c_void_p()
+        check(load().pnp_unet_create(C.byref(h), _ptr(params.contiguous()), _stream()))
+        self._h = h
+        self._ws = {}
+        self._loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, B, H, W, train):
+        torch = _torch()
+        key = (B, H, W, bool(train))
+        if key not in self._ws:
+            n = C.c_size_t()
+            check(load().pnp_unet_workspace_bytes(B, H, W, 1 if train else 0, C.byref(n)))
+            self._ws[key] = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        w = self._ws[key]
+        return w, w.numel()
+
+    def _sigma(self, sigma, B):
+        torch = _torch()
+        if not isinstance(sigma, torch.Tensor):
+            sigma = torch.full((B,), float(sigma), dtype=torch.float32, device="cuda") \
+                if not hasattr(sigma, "__len__") else torch.tensor(sigma, dtype=torch.float32, device="cuda")
+        _need_f32(sigma, "sigma", (B,))
+        return sigma
+
+    def forward(self, u, sigma, out=None, train=False):
+        """u + UNet([Re u, Im u, sigma]) for u [B][H][W] (or [H][W]); sigma per image."""
+        _need_c64(u, "u")
+        u3 = u if u.dim() == 3 else u.reshape((1,) + tuple(u.shape))
+        B, H, W = (int(s) for s in u3.shape)
+        sig = self._sigma(sigma, B)
+        o = out if out is not None else _torch().empty_like(u)
+        _need_c64(o, "out", tuple(u.shape))
+        ws, nb = self.workspace(B, H, W, train)
+        check(load().pnp_unet_forward(self._h, _ptr(u3), _ptr(sig), B, H, W, _ptr(o), _ptr(ws), nb, _stream()))
+        return o
+
+    def backward(self, u, target):
+        """l1 loss of the preceding ``forward(u, sigma, train=True)``; fills the
+        gradients.  Returns the loss as a CUDA float64 tensor [1]."""
+        _need_c64(u, "u")
+        u3 = u if u.dim() == 3 else u.reshape((1,) + tuple(u.shape))
+        _need_c64(target, "target", tuple(u.shape))
+        B, H, W = (int(s) for s in u3.shape)
+        ws, nb = self.workspace(B, H, W, True)
+        check(load().pnp_unet_backward(self._h, _ptr(u3), _ptr(target), B, H, W, _ptr(self._loss), _ptr(ws), nb,
+                                       _stream()))
+        return self._loss
+
+    def adam_step(self, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8):
+        check(load().pnp_unet_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream()))
+
+    def get(self, which="params"):
+        t = _torch().empty(self.n_params, dtype=_torch().float32, device="cuda")
+        check(load().pnp_unet_get(self._h, UNET_BUF[which], _ptr(t), _stream()))
+        return t
+
+    def set(self, which, values):
+        torch = _torch()
+        import numpy as np
+        if isinstance(values, np.ndarray):
+            values = torch.from_numpy(np.ascontiguousarray(values, dtype=np.float32)).cuda()
+        _need_f32(values, which, (self.n_params,))
+        check(load().pnp_unet_set(self._h, UNET_BUF[which], _ptr(values), _stream()))
+
+    @property
+    def step(self):
+        v = C.c_int64()
+        check(load().pnp_unet_get_step(self._h, C.byref(v)))
+        return v.value
+
+    @step.setter
+    def step(self, value):
+        check(load().pnp_unet_set_step(self._h, int(value)))
+
+    def tensor(self, name, B, H, W, train):
+        """View of a workspace activation as a CUDA tensor [B][h][w][C]
+        (bfloat16; FP32 for 'out')."""
+        torch = _torch()
+        ws, _ = self.workspace(B, H, W, train)
+        p = C.c_void_p()
+        dims = (C.c_int32 * 4)()
+        check(load().pnp_unet_tensor(B, H, W, 1 if train else 0, _ptr(ws), UNET_TENSORS.index(name), C.byref(p),
+                                     dims))
+        off = p.value - ws.data_ptr()
+        n = dims[0] * dims[1] * dims[2] * dims[3]
+        dt, es = (torch.float32, 4) if name == "out" else (torch.bfloat16, 2)
+        return ws[off:off + n * es].view(dt).view(tuple(dims))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pnp_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UNetPrior:
+    """Learned prior D_sigma(u) = UNet(u, kappa*sigma) for images of ``shape``,
+    with an optional wavelet ``fallback`` used by hqs_solve where the
+    data-consistency residual rises by more than ``rise_tol``."""
+
+    def __init__(self, net: UNet, shape, kappa: float = 1.0, fallback: "WaveletPrior" = None):
+        self.net, self.fallback = net, fallback
+        self.shape = tuple(int(s) for s in shape)
+        h = C.c_void_p()
+        shp = (C.c_int32 * len(self.shape))(*self.shape)
+        check(load().pnp_prior_unet(C.byref(h), net.handle, len(self.shape), shp, float(kappa),
+                                    fallback.handle if fallback is not None else None))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __call__(self, u, sigma, out=None):
+        _need_c64(u, "u", self.shape)
+        o = out if out is not None else _torch().empty_like(u)
+        shp = (C.c_int32 * u.dim())(*u.shape)
+        check(load().pnp_prior_apply(self._h, u.dim(), shp, _ptr(u), _ptr(o), float(sigma), _stream()))
+        return o
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pnp_prior_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -42,6 +42,20 @@ class HQSReport(C.Structure):
     ]
 
 
+class UNetLayer(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("cin", C.c_int32),
+        ("cin_padded", C.c_int32),
+        ("cout", C.c_int32),
+        ("taps", C.c_int32),
+        ("w_offset", C.c_int64),
+        ("b_offset", C.c_int64),
+    ]
+
+
+UNET_BUF = {"params": 0, "grad": 1, "adam_m": 2, "adam_v": 3}
+
 _vp = C.c_void_p
 _i32 = C.c_int32
 _i64 = C.c_int64
@@ -72,6 +86,21 @@ SIGNATURES = {
     "pnp_hqs_workspace_bytes": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "pnp_hqs_solve": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, C.POINTER(_dbl), _i32,
                              C.POINTER(HQSOpts), _vp, C.POINTER(HQSReport), _vp, _sz, _vp]),
+    "pnp_unet_layer_count": (_i32, []),
+    "pnp_unet_param_count": (_i64, []),
+    "pnp_unet_layer_info": (_i32, [_i32, C.POINTER(UNetLayer)]),
+    "pnp_unet_create": (_i32, [C.POINTER(_vp), _vp, _vp]),
+    "pnp_unet_destroy": (_i32, [_vp]),
+    "pnp_unet_set": (_i32, [_vp, _i32, _vp, _vp]),
+    "pnp_unet_get": (_i32, [_vp, _i32, _vp, _vp]),
+    "pnp_unet_get_step": (_i32, [_vp, C.POINTER(_i64)]),
+    "pnp_unet_set_step": (_i32, [_vp, _i64]),
+    "pnp_unet_workspace_bytes": (_i32, [_i32, _i32, _i32, _i32, C.POINTER(_sz)]),
+    "pnp_unet_forward": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp]),
+    "pnp_unet_backward": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp]),
+    "pnp_unet_adam_step": (_i32, [_vp, _dbl, _dbl, _dbl, _dbl, _vp]),
+    "pnp_unet_tensor": (_i32, [_i32, _i32, _i32, _i32, _vp, _i32, C.POINTER(_vp), C.POINTER(_i32)]),
+    "pnp_prior_unet": (_i32, [C.POINTER(_vp), _vp, _i32, C.POINTER(_i32), _dbl, _vp]),
 }
 
 _lib = None

@@ -234,7 +234,40 @@ pnp_status pnp_prior_wavelet(pnp_prior** out, int32_t levels, double kappa) {
 }
 
 pnp_status pnp_prior_destroy(pnp_prior* prior) {
-  return guarded([&] { delete prior; });
+  return guarded([&] {
+    if (prior && prior->ws) PNP_HIP(hipFree(prior->ws));
+    delete prior;
+  });
+}
+
+pnp_status pnp_prior_unet(pnp_prior** out, const pnp_unet* net, int32_t ndim, const int32_t* shape, double kappa,
+                          const pnp_prior* fallback) {
+  return guarded([&] {
+    need(out, "out");
+    need(net, "net");
+    need(shape, "shape");
+    if (ndim != 2 && ndim != 3) fail(PNP_ERR_SHAPE, "ndim must be 2 or 3");
+    if (!(kappa > 0.0) || !std::isfinite(kappa)) fail(PNP_ERR_ARG, "kappa must be finite and > 0");
+    if (fallback && fallback->kind != 0) fail(PNP_ERR_ARG, "the fallback must be a wavelet prior");
+    const int B = ndim == 3 ? shape[0] : 1, H = shape[ndim - 2], W = shape[ndim - 1];
+    const size_t bytes = unet_ws_bytes(B, H, W, false);
+    void* ws = nullptr;
+    PNP_HIP(hipMalloc(&ws, bytes));
+    pnp_prior* p = new (std::nothrow) pnp_prior();
+    if (!p) {
+      (void)hipFree(ws);
+      fail(PNP_ERR_DEVICE, "host allocation failed");
+    }
+    p->kind = 1;
+    p->kappa = kappa;
+    p->net = net;
+    p->fallback = fallback;
+    p->batch = B;
+    p->ny = H;
+    p->nx = W;
+    p->ws = ws;
+    *out = p;
+  });
 }
 
 pnp_status pnp_prior_apply(const pnp_prior* prior, int32_t ndim, const int32_t* shape, const pnp_c64* in,
@@ -247,14 +280,11 @@ pnp_status pnp_prior_apply(const pnp_prior* prior, int32_t ndim, const int32_t* 
     if (ndim != 2 && ndim != 3) fail(PNP_ERR_SHAPE, "ndim must be 2 or 3");
     if (!(sigma >= 0.0) || !std::isfinite(sigma)) fail(PNP_ERR_ARG, "sigma must be finite and >= 0");
     int n[3] = {1, 1, 1};
-    int nmin = 1 << 30;
     for (int a = 0; a < ndim; ++a) {
       n[a] = shape[ndim - 1 - a];
       if (n[a] < 2) fail(PNP_ERR_SHAPE, "image sides must be >= 2");
-      nmin = std::min(nmin, n[a]);
     }
-    const int J = prior->levels > 0 ? prior->levels : wavelet_default_levels(nmin);
-    wavelet_apply(ndim, n, J, (float)(prior->kappa * sigma), (const float2*)in, (float2*)out, stream);
+    prior_apply(prior, ndim, n, (const float2*)in, (float2*)out, sigma, stream);
   });
 }
 
@@ -318,15 +348,126 @@ pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* sma
     a.x0 = (const float2*)opts->x0;
     a.x_out = (float2*)x_out;
     a.toep = opts->toeplitz;
+    a.rise_tol = opts->rise_tol;
+    if (prior->fallback && (!(opts->rise_tol >= 0.0) || !std::isfinite(opts->rise_tol)))
+      fail(PNP_ERR_ARG, "rise_tol must be finite and >= 0 for a prior with a fallback");
     int bad = 0;
-    hqs_solve(p, a, ws, stream, report ? report->rho : nullptr, report ? &bad : nullptr);
+    hqs_solve(p, a, ws, stream, report ? report->rho : nullptr, report ? &bad : nullptr,
+              report ? report->fallback : nullptr);
     if (report) {
       report->opnorm_used = nrm;
-      if (report->fallback)
-        for (int k = 0; k < n_out; ++k) report->fallback[k] = 0;
       if (bad) fail(PNP_ERR_NUMERIC, "CG breakdown (non-positive or non-finite <p, Mp>)");
     }
   });
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ UNet
+int32_t pnp_unet_layer_count(void) { return unet_layer_count(); }
+
+int64_t pnp_unet_param_count(void) { return unet_param_count(); }
+
+pnp_status pnp_unet_layer_info(int32_t i, pnp_unet_layer* out) {
+  return guarded([&] {
+    need(out, "out");
+    unet_layer_info(i, out);
+  });
+}
+
+pnp_status pnp_unet_create(pnp_unet** out, const float* params, hipStream_t stream) {
+  return guarded([&] {
+    need(out, "out");
+    need(params, "params");
+    *out = unet_create(params, stream);
+  });
+}
+
+pnp_status pnp_unet_destroy(pnp_unet* net) {
+  return guarded([&] { unet_destroy(net); });
+}
+
+pnp_status pnp_unet_set(pnp_unet* net, int32_t which, const float* src, hipStream_t stream) {
+  return guarded([&] {
+    need(net, "net");
+    need(src, "src");
+    if (which == PNP_UNET_GRAD) fail(PNP_ERR_ARG, "gradients are written by pnp_unet_backward only");
+    unet_set(net, which, src, stream);
+  });
+}
+
+pnp_status pnp_unet_get(pnp_unet* net, int32_t which, float* dst, hipStream_t stream) {
+  return guarded([&] {
+    need(net, "net");
+    need(dst, "dst");
+    unet_get(net, which, dst, stream);
+  });
+}
+
+pnp_status pnp_unet_get_step(const pnp_unet* net, int64_t* step) {
+  return guarded([&] {
+    need(net, "net");
+    need(step, "step");
+    *step = unet_step(const_cast<pnp_unet*>(net));
+  });
+}
+
+pnp_status pnp_unet_set_step(pnp_unet* net, int64_t step) {
+  return guarded([&] {
+    need(net, "net");
+    if (step < 0) fail(PNP_ERR_ARG, "step must be >= 0");
+    unet_step(net) = step;
+  });
+}
+
+pnp_status pnp_unet_workspace_bytes(int32_t B, int32_t H, int32_t W, int32_t train, size_t* bytes) {
+  return guarded([&] {
+    need(bytes, "bytes");
+    *bytes = unet_ws_bytes(B, H, W, train != 0);
+  });
+}
+
+pnp_status pnp_unet_forward(const pnp_unet* net, const pnp_c64* u, const float* sigma, int32_t B, int32_t H,
+                            int32_t W, pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need(net, "net");
+    need(u, "u");
+    need(sigma, "sigma");
+    need(out, "out");
+    check_ws(ws_bytes, unet_ws_bytes(B, H, W, false), ws);
+    unet_forward(net, (const float2*)u, sigma, 0.f, B, H, W, (float2*)out, ws, stream);
+  });
+}
+
+pnp_status pnp_unet_backward(pnp_unet* net, const pnp_c64* u, const pnp_c64* target, int32_t B, int32_t H,
+                             int32_t W, double* loss, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need(net, "net");
+    need(u, "u");
+    need(target, "target");
+    need(loss, "loss");
+    check_ws(ws_bytes, unet_ws_bytes(B, H, W, true), ws);
+    unet_backward(net, (const float2*)u, (const float2*)target, B, H, W, loss, ws, stream);
+  });
+}
+
+pnp_status pnp_unet_adam_step(pnp_unet* net, double lr, double beta1, double beta2, double eps,
+                              hipStream_t stream) {
+  return guarded([&] {
+    need(net, "net");
+    if (!(lr >= 0.0) || !std::isfinite(lr)) fail(PNP_ERR_ARG, "lr must be finite and >= 0");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+      fail(PNP_ERR_ARG, "betas must lie in [0, 1)");
+    if (!(eps > 0.0)) fail(PNP_ERR_ARG, "eps must be > 0");
+    unet_adam(net, lr, beta1, beta2, eps, stream);
+  });
+}
+
+pnp_status pnp_unet_tensor(int32_t B, int32_t H, int32_t W, int32_t train, void* ws, int32_t id, void** ptr,
+                           int32_t* dims) {
+  return guarded([&] {
+    need(ptr, "ptr");
+    need(dims, "dims");
+    unet_tensor(B, H, W, train != 0, ws, id, ptr, dims);
+  });
+}

@@ -106,10 +106,16 @@ struct pnp_plan {
   size_t block_bytes;
 };
 
+struct pnp_unet;
+
 struct pnp_prior {
-  int kind;                 // 0 = Haar wavelet
-  int levels;               // 0 = default rule
-  double kappa;
+  int kind;                 // 0 = Haar wavelet, 1 = UNet
+  int levels;               // wavelet: 0 = default rule
+  double kappa;             // wavelet: tau = kappa*sigma; UNet: conditioning level kappa*sigma
+  const pnp_unet* net;      // UNet
+  const pnp_prior* fallback;   // UNet: prior used where the residual rises (or nullptr)
+  int batch, ny, nx;        // UNet: image shape the workspace was sized for
+  void* ws;                 // UNet: forward workspace (owned)
 };
 
 // Toeplitz embedding of A^H D_w A for one (plan, DCF): the real transfer
@@ -172,6 +178,29 @@ void wavelet_apply(int ndim, const int* n_xyz, int levels, float tau, const floa
                    hipStream_t s);
 int wavelet_default_levels(int nmin);
 
+// UNet (learned prior)
+long long unet_param_count();
+long long unet_real_param_count();
+int unet_layer_count();
+void unet_layer_info(int i, pnp_unet_layer* out);
+size_t unet_ws_bytes(int B, int H, int W, bool train);
+pnp_unet* unet_create(const float* params, hipStream_t s);
+void unet_destroy(pnp_unet* net);
+void unet_set(pnp_unet* net, int which, const float* src, hipStream_t s);
+void unet_get(pnp_unet* net, int which, float* dst, hipStream_t s);
+long long& unet_step(pnp_unet* net);
+// out = u + UNet(u, sigma) for a batch of B images H x W; sigma: device [B]
+// or nullptr (then sigma_c for every image); out may be nullptr (training).
+void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, float sigma_c, int B, int H, int W,
+                  float2* out, void* ws, hipStream_t s);
+void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, int H, int W, double* loss,
+                   void* ws, hipStream_t s);
+void unet_adam(pnp_unet* net, double lr, double b1, double b2, double eps, hipStream_t s);
+void unet_tensor(int B, int H, int W, bool train, void* ws, int id, void** ptr, int32_t dims[4]);
+// Apply any prior to an image of the plan's shape (u and x may alias for the wavelet only).
+void prior_apply(const pnp_prior* prior, int ndim, const int* n_xyz, const float2* u, float2* x, double sigma,
+                 hipStream_t s);
+
 // plan
 pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* traj, hipStream_t s);
 void plan_destroy(pnp_plan* p);
@@ -197,9 +226,11 @@ struct HQSArgs {
   const float2* x0;
   float2* x_out;
   const pnp_toeplitz* toep;   // nullptr: gridded normal operator
+  double rise_tol;            // fallback test of a prior that has a fallback
 };
 // Runs the loop; when rho_host is given, also the final residual, and waits.
+// fb_host [n_out] (or nullptr) receives 1 where the fallback prior ran.
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
-               int* bad_host);
+               int* bad_host, int* fb_host);
 
 }  // namespace pnp

@@ -350,17 +350,32 @@ double power_iteration(const pnp_plan* p, const pnp_toeplitz* tp, const float2* 
   return h.lam;
 }
 
-static void apply_prior(const pnp_plan* p, const pnp_prior* prior, const float2* u, float2* x,
-                        double sigma, hipStream_t s) {
-  int n[3] = {p->ax[0].n, p->ax[1].n, p->ax[2].n};
+void prior_apply(const pnp_prior* prior, int ndim, const int* n, const float2* u, float2* x, double sigma,
+                 hipStream_t s) {
+  if (prior->kind == 1) {
+    const int B = ndim == 3 ? n[2] : 1;
+    if (B != prior->batch || n[1] != prior->ny || n[0] != prior->nx)
+      fail(PNP_ERR_SHAPE, "UNet prior was created for %d x %d x %d images, not %d x %d x %d", prior->batch,
+           prior->ny, prior->nx, B, n[1], n[0]);
+    if (u == x) fail(PNP_ERR_ARG, "the UNet prior cannot run in place");
+    unet_forward(prior->net, u, nullptr, (float)(prior->kappa * sigma), B, n[1], n[0], x, prior->ws, s);
+    return;
+  }
   int nmin = n[0];
-  for (int a = 1; a < p->ndim; ++a) nmin = std::min(nmin, n[a]);
+  for (int a = 1; a < ndim; ++a) nmin = std::min(nmin, n[a]);
   const int J = prior->levels > 0 ? prior->levels : wavelet_default_levels(nmin);
-  wavelet_apply(p->ndim, n, J, (float)(prior->kappa * sigma), u, x, s);
+  wavelet_apply(ndim, n, J, (float)(prior->kappa * sigma), u, x, s);
+}
+
+static double read_scalar(const double* d, hipStream_t s) {
+  double h = 0.0;
+  PNP_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  PNP_HIP(hipStreamSynchronize(s));
+  return h;
 }
 
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
-               int* bad_host) {
+               int* bad_host, int* fb_host) {
   if (a.n_out > kMaxOuter) fail(PNP_ERR_SHAPE, "n_out %d exceeds %d", a.n_out, kMaxOuter);
   SolverWs w = solver_ws(p, a.L, ws);
   const long long N = image_size(p);
@@ -384,12 +399,29 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   float2* x = a.x_out;
   PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, a.x0 ? a.x0 : w.b0, x);
 
+  const int nd[3] = {p->ax[0].n, p->ax[1].n, p->ax[2].n};
+  // A prior with a fallback is checked after every outer iteration: when the
+  // new image is not finite or its residual rho_k exceeds (1 + rise_tol)
+  // rho_{k-1}, it is replaced by the fallback prior's output.  This needs
+  // one host read of rho per outer iteration; the normal operator of the
+  // accepted image is reused by the next iteration's CG start.
+  const bool guard = a.prior->fallback != nullptr;
+  bool started = false;   // N x and the CG start of iteration k already done
+  double rho_prev = 0.0;
+  if (fb_host)
+    for (int k = 0; k < a.n_out; ++k) fb_host[k] = 0;
+  auto cg_start = [&](double gamma, double* rho_out) {
+    normal_parts(p, a.toep, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
+    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u, w.r,
+               w.p, w.parts, w.sc, rho_out);
+  };
+
   for (int k = 0; k < a.n_out; ++k) {
     const double gamma = a.lambda * a.sigmas[k];
     const float cg = (float)(gamma - c1a);
-    normal_parts(p, a.toep, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
-    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma,
-               w.u, w.r, w.p, w.parts, w.sc, w.rho + k);
+    if (!started) cg_start(gamma, w.rho + k);
+    started = false;
+    if (guard && k == 0) rho_prev = read_scalar(w.rho, s);
     float2* pc = w.p;
     float2* pn = w.p2;
     for (int j = 0; j < a.n_cg; ++j) {
@@ -404,7 +436,21 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
                  w.parts, w.sc);
       PNP_LAUNCH(k_cg_update, dim3(nb), dim3(kRedThreads), 0, s, N, w.u, w.r, pc, w.q, w.parts, w.sc);
     }
-    apply_prior(p, a.prior, w.u, x, a.sigmas[k], s);
+    prior_apply(a.prior, p->ndim, nd, w.u, x, a.sigmas[k], s);
+    if (!guard) continue;
+    // candidate from the fallback, kept in Nv (free during the solve)
+    prior_apply(a.prior->fallback, p->ndim, nd, w.u, w.Nv, a.sigmas[k], s);
+    const double gnext = k + 1 < a.n_out ? a.lambda * a.sigmas[k + 1] : 0.0;
+    cg_start(gnext, w.rho + k + 1);
+    double rho = read_scalar(w.rho + k + 1, s);
+    if (!(rho <= (1.0 + a.rise_tol) * rho_prev)) {
+      PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, x);
+      cg_start(gnext, w.rho + k + 1);
+      rho = read_scalar(w.rho + k + 1, s);
+      if (fb_host) fb_host[k] = 1;
+    }
+    rho_prev = rho;
+    started = true;
   }
   if (rho_host) {
     // residual of the final image (one extra normal operator)

@@ -1,0 +1,347 @@
+// BF16 MFMA contractions of the UNet denoiser (forward and backward).
+//
+// Every convolution-like step is one GEMM C[M][N] = sum_k A(m,k) B(k,n)
+// computed by k_mfma_gemm<View>: a 64x64 output tile per 256-thread
+// workgroup (four waves, each a 32x32 quarter made of 2x2 16x16 MFMA
+// blocks), K consumed 32 at a time with v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation), operands staged through LDS with the next K-step's global
+// loads issued before the current step's MFMAs.
+//
+// A `View` describes one contraction:
+//   AK / BK        false: loadA(m, k) / loadB(k, n) return 8 consecutive-k
+//                  BF16 values of one row m / column n (operand contiguous in k)
+//                  true:  loadA(k, m) / loadB(k, n) return 8 consecutive-m / -n
+//                  values at one k (operand contiguous in m / n)
+//   k_lo(z), k_hi(z)  the K range handled by grid slice z (split-K)
+//   store(m, n, v) the epilogue (bias, ReLU, ReLU-derivative mask, BF16 or
+//                  FP32 output, FP32 atomics for split-K weight gradients)
+// Activations are NHWC BF16 with a per-tensor channel stride and offset, so
+// the concatenated skip connections are channel slices, never copies.
+// Channel counts, strides and offsets are multiples of 8 (16-byte loads).
+#pragma once
+
+#include <cstring>
+
+#include "common.hpp"
+
+namespace pnp {
+namespace unet {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN)
+__host__ __device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ __forceinline__ float bf2f(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+// a BF16 value is > 0 (ReLU derivative of a stored ReLU output)
+__device__ __forceinline__ bool bf_pos(uint16_t h) { return h != 0 && !(h & 0x8000u); }
+
+// An activation slice: NHWC, `cs` channels per pixel in memory, the slice
+// starts at channel `co` and has `c` channels.
+struct Act {
+  uint16_t* p;
+  int cs, co, c;
+};
+
+struct Geo {
+  int B, H, W;   // batch and spatial size of the pixel space
+  __device__ int P() const { return B * H * W; }
+};
+
+__device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// ------------------------------------------------------------ the GEMM
+template <class View>
+__global__ void __launch_bounds__(256) k_mfma_gemm(View v) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[64][40];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64][40];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  // loader coordinates: k-contiguous operands load row r = tid/4, k offset
+  // 8*(tid%4); m/n-contiguous operands load k = tid/8, rows 8*(tid%8)..+7
+  const int rr = tid >> 2, rk = (tid & 3) * 8;
+  const int tk = tid >> 3, tr = (tid & 7) * 8;
+  const int klo = v.k_lo(blockIdx.z), khi = v.k_hi(blockIdx.z);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto fetch = [&](int k0, uint4& a, uint4& b) {
+    if constexpr (View::AK) a = v.loadA(k0 + tk, m0 + tr);
+    else a = v.loadA(m0 + rr, k0 + rk);
+    if constexpr (View::BK) b = v.loadB(k0 + tk, n0 + tr);
+    else b = v.loadB(k0 + rk, n0 + rr);
+  };
+  auto put = [&](uint16_t (*S)[40], const uint4& val, bool kmajor) {
+    if (!kmajor) {
+      *reinterpret_cast<uint4*>(&S[rr][rk]) = val;
+    } else {
+      const uint32_t w[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        S[tr + 2 * i][tk] = (uint16_t)(w[i] & 0xffffu);
+        S[tr + 2 * i + 1][tk] = (uint16_t)(w[i] >> 16);
+      }
+    }
+  };
+
+  uint4 na = zero4(), nb = zero4();
+  if (klo < khi) fetch(klo, na, nb);
+  for (int k0 = klo; k0 < khi; k0 += 32) {
+    put(As, na, View::AK);
+    put(Bs, nb, View::BK);
+    __syncthreads();
+    if (k0 + 32 < khi) fetch(k0 + 32, na, nb);
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // output block layout: lane holds rows 4*(lane/16) + q (q < 4) of column lane%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
+}
+
+// Offsets of the 3x3 taps (t = 3*(dy+1) + (dx+1)); a 1x1 convolution has one
+// tap at offset 0.
+__device__ __forceinline__ int tap_dy(int taps, int t) { return taps == 9 ? t / 3 - 1 : 0; }
+__device__ __forceinline__ int tap_dx(int taps, int t) { return taps == 9 ? t % 3 - 1 : 0; }
+
+// ReLU-derivative mask of a backward epilogue: channel n < mc of pixel m is
+// kept only where the forward ReLU output (mask slice) is positive.
+struct Mask {
+  const uint16_t* p;   // nullptr: no mask
+  int cs, co, mc;
+  __device__ bool keep(int m, int n) const {
+    return !p || n >= mc || bf_pos(p[(long long)m * cs + co + n]);
+  }
+};
+
+// ------------------------------------------------------------ views
+// Convolution ('same' zero padding, 3x3 or 1x1), forward:
+//   out[p][n] = bias[n] + sum_{t, c} in[p + off(t)][c] W[n][t][c]
+//   m = pixel, k = t*Cp + c, n = output channel.
+struct ConvFwd {
+  static constexpr bool AK = false, BK = false;
+  Act in;
+  const uint16_t* W;      // [Cout][taps][Cp] BF16
+  const float* bias;      // [Cout] FP32
+  Act out;                // BF16 output slice (unused when out_f32 is set)
+  float* out_f32;         // [P][Cout] FP32 output, or nullptr
+  Geo g;
+  int taps, Cp, Cout, relu;
+  __device__ int k_lo(int) const { return 0; }
+  __device__ int k_hi(int) const { return taps * Cp; }
+  __device__ uint4 loadA(int m, int k) const {
+    if (m >= g.P() || k >= taps * Cp) return zero4();
+    const int t = k / Cp, c = k - t * Cp;
+    const int x = m % g.W + tap_dx(taps, t), y = (m / g.W) % g.H + tap_dy(taps, t);
+    if ((unsigned)y >= (unsigned)g.H || (unsigned)x >= (unsigned)g.W) return zero4();
+    const long long pix = ((long long)(m / (g.W * g.H)) * g.H + y) * g.W + x;
+    return ld16(in.p + pix * in.cs + in.co + c);
+  }
+  __device__ uint4 loadB(int k, int n) const {
+    if (n >= Cout || k >= taps * Cp) return zero4();
+    return ld16(W + (long long)n * taps * Cp + k);
+  }
+  __device__ void store(int m, int n, float val) const {
+    if (m >= g.P() || n >= Cout) return;
+    val += bias[n];
+    if (relu) val = fmaxf(val, 0.f);
+    if (out_f32)
+      out_f32[(long long)m * Cout + n] = val;
+    else
+      out.p[(long long)m * out.cs + out.co + n] = f2bf(val);
+  }
+};
+
+// Convolution, gradient of the input:
+//   dIn[q][c] = sum_{t, o} dZ[q - off(t)][o] W[o][t][c]
+//   m = pixel q, k = t*Coutp + o, n = c; B read from WT[Cin][taps][Coutp].
+struct ConvDX {
+  static constexpr bool AK = false, BK = false;
+  Act dz;                 // gradient at the conv output (ReLU mask applied), c <= Coutp
+  const uint16_t* WT;     // [Cin][taps][Coutp] BF16
+  Act dx;                 // BF16 output slice
+  Mask mask;              // ReLU mask of the input's producer
+  Geo g;
+  int taps, Coutp, Cin;
+  __device__ int k_lo(int) const { return 0; }
+  __device__ int k_hi(int) const { return taps * Coutp; }
+  __device__ uint4 loadA(int m, int k) const {
+    if (m >= g.P() || k >= taps * Coutp) return zero4();
+    const int t = k / Coutp, c = k - t * Coutp;
+    const int x = m % g.W - tap_dx(taps, t), y = (m / g.W) % g.H - tap_dy(taps, t);
+    if ((unsigned)y >= (unsigned)g.H || (unsigned)x >= (unsigned)g.W) return zero4();
+    const long long pix = ((long long)(m / (g.W * g.H)) * g.H + y) * g.W + x;
+    return ld16(dz.p + pix * dz.cs + dz.co + c);
+  }
+  __device__ uint4 loadB(int k, int n) const {
+    if (n >= Cin || k >= taps * Coutp) return zero4();
+    return ld16(WT + (long long)n * taps * Coutp + k);
+  }
+  __device__ void store(int m, int n, float val) const {
+    if (m >= g.P() || n >= Cin) return;
+    if (!mask.keep(m, n)) val = 0.f;
+    dx.p[(long long)m * dx.cs + dx.co + n] = f2bf(val);
+  }
+};
+
+// Convolution, gradient of the weights and bias, split over pixels:
+//   dW[o][t][c] += sum_p dZ[p][o] in[p + off(t)][c],   db[o] += sum_p dZ[p][o]
+//   m = o, n = t*Cin + c (n = taps*Cin is the bias column), k = pixel.
+struct ConvDW {
+  static constexpr bool AK = true, BK = true;
+  Act dz, in;
+  float* dW;              // [Cout][taps][Cin] then db[Cout], FP32, accumulated
+  Geo g;
+  int taps, Cin, Cout, kchunk;
+  __device__ int k_lo(int z) const { return z * kchunk; }
+  __device__ int k_hi(int z) const { return min((z + 1) * kchunk, g.P()); }
+  __device__ uint4 loadA(int k, int m) const {
+    if (m >= Cout || k >= g.P()) return zero4();
+    return ld16(dz.p + (long long)k * dz.cs + dz.co + m);
+  }
+  __device__ uint4 loadB(int k, int n) const {
+    if (k >= g.P() || n > taps * Cin) return zero4();
+    if (n == taps * Cin) return make_uint4(0x3f80u, 0u, 0u, 0u);   // BF16 1.0 in the bias column
+    const int t = n / Cin, c = n - t * Cin;
+    const int x = k % g.W + tap_dx(taps, t), y = (k / g.W) % g.H + tap_dy(taps, t);
+    if ((unsigned)y >= (unsigned)g.H || (unsigned)x >= (unsigned)g.W) return zero4();
+    const long long pix = ((long long)(k / (g.W * g.H)) * g.H + y) * g.W + x;
+    return ld16(in.p + pix * in.cs + in.co + c);
+  }
+  __device__ void store(int m, int n, float val) const {
+    if (m >= Cout || n > taps * Cin) return;
+    if (n == taps * Cin)
+      atomicAdd(&dW[(long long)Cout * taps * Cin + m], val);
+    else
+      atomicAdd(&dW[(long long)m * taps * Cin + n], val);
+  }
+};
+
+// Output pixel of the 2x2 stride-2 transposed convolution for input pixel m
+// (geometry g) and tap t = 2a + b.
+__device__ __forceinline__ long long up_pix(const Geo& g, int m, int t) {
+  const int j = m % g.W, i = (m / g.W) % g.H, b = m / (g.W * g.H);
+  return ((long long)b * 2 * g.H + 2 * i + (t >> 1)) * (2 * g.W) + 2 * j + (t & 1);
+}
+
+// 2x2 stride-2 transposed convolution, forward; grid slice z = tap t:
+//   out[2i+a][2j+b][n] = bias[n] + sum_c in[i][j][c] W[n][t][c]
+//   m = input pixel, k = c, n = output channel.
+struct UpFwd {
+  static constexpr bool AK = false, BK = false;
+  Act in;
+  const uint16_t* W;      // [Cout][4][Cin] BF16
+  const float* bias;
+  Act out;                // BF16 slice at twice the resolution
+  Geo g;                  // input geometry
+  int Cin, Cout;
+  __device__ int k_lo(int) const { return 0; }
+  __device__ int k_hi(int) const { return Cin; }
+  __device__ uint4 loadA(int m, int k) const {
+    if (m >= g.P() || k >= Cin) return zero4();
+    return ld16(in.p + (long long)m * in.cs + in.co + k);
+  }
+  __device__ uint4 loadB(int k, int n) const {
+    if (n >= Cout || k >= Cin) return zero4();
+    return ld16(W + ((long long)n * 4 + blockIdx.z) * Cin + k);
+  }
+  __device__ void store(int m, int n, float val) const {
+    if (m >= g.P() || n >= Cout) return;
+    out.p[up_pix(g, m, blockIdx.z) * out.cs + out.co + n] = f2bf(val + bias[n]);
+  }
+};
+
+// Transposed convolution, gradient of the input:
+//   dIn[i][j][c] = sum_{t, o} dOut[2i+a][2j+b][o] W[o][t][c]
+//   m = input pixel, k = t*Cout + o, n = c; B read from WT[Cin][4][Cout].
+struct UpDX {
+  static constexpr bool AK = false, BK = false;
+  Act dout;               // slice at twice the resolution
+  const uint16_t* WT;
+  Act dx;
+  Mask mask;
+  Geo g;                  // input geometry
+  int Cin, Cout;
+  __device__ int k_lo(int) const { return 0; }
+  __device__ int k_hi(int) const { return 4 * Cout; }
+  __device__ uint4 loadA(int m, int k) const {
+    if (m >= g.P() || k >= 4 * Cout) return zero4();
+    const int t = k / Cout, o = k - t * Cout;
+    return ld16(dout.p + up_pix(g, m, t) * dout.cs + dout.co + o);
+  }
+  __device__ uint4 loadB(int k, int n) const {
+    if (n >= Cin || k >= 4 * Cout) return zero4();
+    return ld16(WT + (long long)n * 4 * Cout + k);
+  }
+  __device__ void store(int m, int n, float val) const {
+    if (m >= g.P() || n >= Cin) return;
+    if (!mask.keep(m, n)) val = 0.f;
+    dx.p[(long long)m * dx.cs + dx.co + n] = f2bf(val);
+  }
+};
+
+// Transposed convolution, gradient of the weights and bias; grid slice
+// z = t * splits + split:
+//   dW[o][t][c] += sum_{i,j} dOut[2i+a][2j+b][o] in[i][j][c],  db[o] += dOut sums
+//   m = o, n = c (n = Cin is the bias column), k = input pixel.
+struct UpDW {
+  static constexpr bool AK = true, BK = true;
+  Act dout, in;
+  float* dW;              // [Cout][4][Cin] then db[Cout]
+  Geo g;                  // input geometry
+  int Cin, Cout, kchunk, splits;
+  __device__ int k_lo(int z) const { return (z % splits) * kchunk; }
+  __device__ int k_hi(int z) const { return min((z % splits + 1) * kchunk, g.P()); }
+  __device__ uint4 loadA(int k, int m) const {
+    if (m >= Cout || k >= g.P()) return zero4();
+    return ld16(dout.p + up_pix(g, k, blockIdx.z / splits) * dout.cs + dout.co + m);
+  }
+  __device__ uint4 loadB(int k, int n) const {
+    if (k >= g.P() || n > Cin) return zero4();
+    if (n == Cin) return make_uint4(0x3f80u, 0u, 0u, 0u);
+    return ld16(in.p + (long long)k * in.cs + in.co + n);
+  }
+  __device__ void store(int m, int n, float val) const {
+    if (m >= Cout || n > Cin) return;
+    if (n == Cin)
+      atomicAdd(&dW[(long long)Cout * 4 * Cin + m], val);
+    else
+      atomicAdd(&dW[((long long)m * 4 + blockIdx.z / splits) * Cin + n], val);
+  }
+};
+
+}  // namespace unet
+}  // namespace pnp

@@ -361,3 +361,31 @@ def batched_slice_table(count: int = 24):
             tr = spiral2d(max(1, round(N / (af * S))), S)
         out.append(dict(index=i, n=n, L=L, af=af, traj=tr))
     return out
+
+
+# ------------------------------------------------------ denoiser training data
+def he_normal(shapes: dict, seed: int, last_scale: dict | None = None) -> dict:
+    """Seeded He-normal weights for {name: (weight shape, bias shape)}:
+    W ~ N(0, 2 / fan_in) with fan_in = prod(weight shape[1:]), biases zero;
+    `last_scale` multiplies the named layers' weights.  Float32 values."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name in shapes:
+        ws, bs = shapes[name]
+        fan_in = int(np.prod(ws[1:]))
+        w = rng.standard_normal(ws) * math.sqrt(2.0 / fan_in)
+        w *= (last_scale or {}).get(name, 1.0)
+        out[name] = (w.astype(np.float32).astype(np.float64), np.zeros(bs))
+    return out
+
+
+def denoise_pairs(images: np.ndarray, sigma_lo: float, sigma_hi: float, seed: int):
+    """Noisy copies of `images` [B, H, W] complex: sigma_b ~ U(lo, hi) per
+    image, independent N(0, sigma_b^2) noise on the real and imaginary parts.
+    Returns (noisy complex64, sigma float32 [B])."""
+    rng = np.random.default_rng(seed)
+    B = images.shape[0]
+    sig = rng.uniform(sigma_lo, sigma_hi, B).astype(np.float32)
+    n = rng.standard_normal((2,) + images.shape)
+    noisy = images + sig[:, None, None] * (n[0] + 1j * n[1])
+    return noisy.astype(np.complex64), sig
