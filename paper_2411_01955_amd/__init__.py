@@ -21,12 +21,13 @@ and the current HIP stream.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, UNET_BUF, UNetLayer, check, load
 
 __all__ = ["Plan", "Toeplitz", "WaveletPrior", "UNet", "UNetPrior", "hqs_solve", "PnPError", "load",
            "trace_enable", "trace_read", "unet_layers", "pack_unet_params", "unpack_unet_params",
-           "UNET_LAYER_NAMES", "UNET_TENSORS"]
+           "UNET_LAYER_NAMES", "UNET_TENSORS", "trained_unet", "TRAINED_WEIGHTS"]
 
 
 def trace_enable(on: bool = True):
@@ -284,6 +285,18 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
 
 
 # ------------------------------------------------------------------ UNet
+# Parameters trained by train_unet.py (2,000 seeded 320 x 320 phantoms, 100
+# epochs, batch 10, 128 x 128 patches, sigma ~ U(0.001, 0.1), Adam 1e-4).
+TRAINED_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_phantom.npz")
+
+
+def trained_unet(path: str = TRAINED_WEIGHTS) -> "UNet":
+    """The UNet with the packaged trained parameters."""
+    import numpy as np
+    with np.load(path, allow_pickle=False) as z:
+        return UNet(z["params"].astype(np.float32))
+
+
 UNET_LAYER_NAMES = ("e1a", "e1b", "e2a", "e2b", "e3a", "e3b", "ba", "bb", "up3", "d3a", "d3b",
                     "up2", "d2a", "d2b", "up1", "d1a", "d1b", "out")
 # workspace tensor ids of pnp_unet_tensor
