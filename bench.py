@@ -19,7 +19,16 @@ Printed JSON line:
              when it matches the current kernel sources;
 * ``cpu_baseline``  the FP64 oracle (exact NDFT) timed on the host on one
              outer HQS iteration of the same slice (6 normal operators),
-             scaled to the same unit.
+             scaled to the same unit;
+* ``psnr_race``  slices/s to a fixed PSNR, learned (UNet, wavelet fallback)
+             vs wavelet HQS: the target is the mean final PSNR of wavelet-HQS
+             (30 iterations) over held-out phantoms, rounded down to 0.5 dB;
+             per slice and method a logged run finds the first outer
+             iteration k* that reaches it (30 if none does), and a timed run
+             of exactly k* iterations gives seconds per slice;
+* ``unet``   the denoiser's forward (320x320, batch 1 and 24) and training
+             step (batch 10 x 128x128, forward + backward + Adam) in TFLOP/s
+             and as a fraction of the 2.5 PFLOP/s dense BF16 MFMA peak.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
 """
@@ -39,9 +48,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 # hyperparameters tuned once on training phantoms (seeds 0..4): lambda*||N||, Haar threshold factor
 LAM_TIMES_NORM = 1e4
 KAPPA = 0.75
+KAPPA_UNET = 1.0       # UNet conditioning level = kappa * sigma_k
+RISE_TOL = 0.5         # wavelet fallback when the residual rises by more than 50%
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical.json")
 KERNEL_SOURCES = ["paper_2411_01955_amd/csrc/nufft2d.hip", "paper_2411_01955_amd/csrc/fft_lds.hpp",
                   "paper_2411_01955_amd/csrc/fft_reg.hpp", "paper_2411_01955_amd/csrc/plan.hip",
@@ -96,6 +108,132 @@ def _kname(s: str) -> str:
     return s.split("<")[0]
 
 
+UNET_LEVEL = {"e1a": 0, "e1b": 0, "e2a": 1, "e2b": 1, "e3a": 2, "e3b": 2, "ba": 3, "bb": 3, "up3": 3,
+              "d3a": 2, "d3b": 2, "up2": 2, "d2a": 1, "d2b": 1, "up1": 1, "d1a": 0, "d1b": 0, "out": 0}
+
+
+def unet_flops(layers, B, H, W, backward=False):
+    """Multiply-add FLOPs (x2) of the UNet's contractions for a batch of B
+    images H x W (real input channels; transposed convs per input pixel and
+    tap).  The backward pass is the input- and weight-gradient contractions
+    (twice the forward, without the first layer's input gradient)."""
+    fwd = 0
+    first = 0
+    for l in layers:
+        P = B * (H >> UNET_LEVEL[l["name"]]) * (W >> UNET_LEVEL[l["name"]])
+        f = 2 * P * l["taps"] * l["cin"] * l["cout"]
+        fwd += f
+        if l["name"] == "e1a":
+            first = f
+    return fwd + (2 * fwd - first if backward else 0)
+
+
+def psnr_roi(xr, x, roi):
+    e = np.abs(xr)[roi] - np.abs(x)[roi]
+    return 20 * math.log10(np.abs(x)[roi].max() / math.sqrt(np.mean(e ** 2)))
+
+
+def psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, n_slices):
+    """Slices/s to a fixed PSNR, learned vs wavelet HQS, on held-out phantoms."""
+    import synth
+    n, L = w.n, w.L
+    M = w.traj.k.shape[0]
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)
+    lam = LAM_TIMES_NORM / nrm
+    wav = pnp.WaveletPrior(0, KAPPA)
+    net = pnp.trained_unet()
+    lrn = pnp.UNetPrior(net, (n, n), KAPPA_UNET, fallback=wav)
+    methods = {"wavelet": wav, "learned": lrn}
+    slices = []
+    for i in range(n_slices):
+        seed = synth.SEED_HELDOUT + i
+        x, roi = synth.phantom2d(n, seed)
+        y = plan.forward(torch.from_numpy(x).cuda(), Sd)
+        y += torch.from_numpy(synth.complex_noise((L, M), synth.noise_variance(x, S), synth.SEED_NOISE + seed)).cuda()
+        slices.append((x, roi, y))
+
+    def solve(prior, y, sigmas, x0=None):
+        return pnp.hqs_solve(plan, y, Sd, dd, prior, sigmas, lam, "f1", w.n_cg, opnorm=nrm, x0=x0, toeplitz=toep,
+                             rise_tol=RISE_TOL)[0]
+
+    # logged runs: one-iteration solves chained through x0 are the same iterates
+    curves = {m: [] for m in methods}
+    for x, roi, y in slices:
+        for m, prior in methods.items():
+            xk, c = None, []
+            for k in range(len(sig)):
+                xk = solve(prior, y, sig[k:k + 1], xk).clone()
+                c.append(psnr_roi(xk.cpu().numpy(), x, roi))
+            curves[m].append(c)
+    final = {m: float(np.mean([c[-1] for c in curves[m]])) for m in methods}
+    target = math.floor(final["wavelet"] * 2) / 2
+    out = {"target_psnr_db": target, "slices": n_slices, "held_out_seeds": f"{synth.SEED_HELDOUT}.."
+           f"{synth.SEED_HELDOUT + n_slices - 1}", "final_psnr_db": {m: round(v, 2) for m, v in final.items()}}
+    for m, prior in methods.items():
+        ks = [next((k + 1 for k, v in enumerate(c) if v >= target), len(sig)) for c in curves[m]]
+        reached = sum(1 for c in curves[m] if max(c) >= target)
+        solve(prior, slices[0][2], sig[:2])       # warm-up
+        torch.cuda.synchronize()
+        secs = []
+        for (x, roi, y), k in zip(slices, ks):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            solve(prior, y, sig[:k])
+            b.record()
+            torch.cuda.synchronize()
+            secs.append(a.elapsed_time(b) / 1e3)
+        out[m] = {"slices_per_s": round(1.0 / float(np.mean(secs)), 2), "mean_outer_iterations": round(float(np.mean(ks)), 2),
+                  "reached_target": f"{reached}/{n_slices}", "ms_per_slice": round(1e3 * float(np.mean(secs)), 3)}
+    out["learned_over_wavelet"] = round(out["learned"]["slices_per_s"] / out["wavelet"]["slices_per_s"], 2)
+    out["learned_prior"] = f"UNet (kappa {KAPPA_UNET}) with wavelet fallback (rise_tol {RISE_TOL})"
+    return out
+
+
+def unet_rates(pnp, torch):
+    """Forward and training-step throughput of the denoiser (inputs resident)."""
+    import synth
+    layers = pnp.unet_layers()
+    net = pnp.trained_unet()
+    res = {}
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+
+    for B in (1, 24):
+        u = torch.from_numpy(synth.white_complex((B, 320, 320), 3) * 0.5).cuda()
+        sg = torch.full((B,), 0.05, dtype=torch.float32, device="cuda")
+        o = torch.empty_like(u)
+        t = timed(lambda: net.forward(u, sg, out=o), 20 if B == 1 else 5)
+        fl = unet_flops(layers, B, 320, 320)
+        res[f"fwd_320_b{B}"] = {"ms": round(t * 1e3, 3), "gflop": round(fl / 1e9, 2),
+                                "tflops": round(fl / t / 1e12, 1),
+                                "mfma_util": round(fl / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+    trainer = pnp.UNet(net.get("params"))
+    u = torch.from_numpy(synth.white_complex((10, 128, 128), 4) * 0.5).cuda()
+    tg = (u * 0.9).contiguous()
+    sg = torch.full((10,), 0.05, dtype=torch.float32, device="cuda")
+
+    def train_step():
+        trainer.forward(u, sg, train=True)
+        trainer.backward(u, tg)
+        trainer.adam_step(0.0)          # lr 0: the step runs, the weights stay
+    t = timed(train_step, 20)
+    fl = unet_flops(layers, 10, 128, 128, backward=True)
+    res["train_step_b10_128"] = {"ms": round(t * 1e3, 3), "gflop": round(fl / 1e9, 2),
+                                 "tflops": round(fl / t / 1e12, 1),
+                                 "mfma_util": round(fl / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+    res["peak_tflops"] = MFMA_BF16_PEAK_TFLOPS
+    return res
+
+
 def cpu_baseline(w, x, S, dcf, y, b_alg):
     """Oracle (exact NDFT, numpy/OpenBLAS FP64) on one outer HQS iteration of
     the same slice: 1 + n_cg normal operators plus the CG vector work."""
@@ -133,6 +271,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1002)
     ap.add_argument("--reps", type=int, default=200,
                     help="back-to-back repetitions when timing the normal operators alone")
+    ap.add_argument("--psnr-slices", type=int, default=24,
+                    help="held-out phantoms of the learned-vs-wavelet PSNR race (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
@@ -246,6 +386,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    race = psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.psnr_slices) if args.psnr_slices > 0 else None
+    unet = unet_rates(pnp, torch)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, x_true, S, dcf, y.cpu().numpy(), B)
@@ -274,6 +417,8 @@ def main():
         "gridded_normal_op_us": round(gridded_us, 2),
         "gridded_normal_op_GBps": round(B / (gridded_us * 1e-6) / 1e9, 1),
         "roofline": roofline,
+        "psnr_race": race,
+        "unet": unet,
         "kernels": kernel_table,
         "cpu_baseline": cpu,
     }
