@@ -44,6 +44,18 @@ __host__ __device__ inline float2 cfma(float s, float2 a, float2 acc) {
   return make_float2(fmaf(s, a.x, acc.x), fmaf(s, a.y, acc.y));
 }
 
+// ------------------------------------------------------ XCD-aware order
+// The MI355X deals consecutive workgroups of a launch to its 8 XCDs in
+// turn (workgroup b runs on XCD b % 8).  xcd_order(b, nb) renumbers them so
+// that XCD j works through the contiguous range of logical indices
+// [start_j, start_j + count_j): neighbouring logical workgroups then share
+// cache lines (and read-only tables) in one XCD's L2.  Bijective on [0, nb).
+constexpr int kXCDs = 8;
+__device__ __forceinline__ int xcd_order(int b, int nb) {
+  const int j = b % kXCDs, q = nb / kXCDs, r = nb % kXCDs;
+  return j * q + (j < r ? j : r) + b / kXCDs;
+}
+
 // ------------------------------------------------------------ FFT plan
 constexpr int kMaxRadices = 16;
 
@@ -151,12 +163,21 @@ void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, c
 // given) the CG direction p' = r + (*beta) x, which is also stored to pnew;
 // the result is left as op_groups(L) partial images in w.part ([G][N],
 // summed by the consumer).
+// Input of the normal operator: the image x, or (cg.r != nullptr) the
+// Chronopoulos-Gear CG update, formed per pixel by the operator's first pass:
+//   p' = r + beta p,  s' = w + beta s,  u' = u + alpha p',  r' = r - alpha s'
+// reading (r, p, s, u, w) and writing (r2, p2, s2, u2); the operator is then
+// applied to r'.  One workgroup per pixel writes, so the sets must differ.
+struct CGUpdate {
+  const float2 *r, *p, *s, *u, *w;
+  float2 *r2, *p2, *s2, *u2;
+  const double *alpha, *beta;
+};
 struct NormalIn {
   const float2* x;
-  const float2* r;
-  float2* pnew;
-  const double* beta;
+  CGUpdate cg;
 };
+inline NormalIn plain_input(const float2* x) { return NormalIn{x, CGUpdate{}}; }
 int op_groups(int L);
 void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
                      const float* dcf, const OpWorkspace& w, hipStream_t s);

@@ -52,20 +52,32 @@ __device__ __forceinline__ int grid_of_img(int i, int n, int K) {
 // from the device scalars); the workgroups of coil group 0 store p'.
 struct ImgIn {
   const float2* x;
-  const float2* r;      // nullptr: plain image input
-  float2* pnew;
-  const double* beta;
+  CGUpdate cg;   // cg.r == nullptr: plain image input
 };
 
-__device__ __forceinline__ float img_beta(const ImgIn& in) {
-  return in.r ? (float)*in.beta : 0.f;
+struct ImgScal {
+  float alpha, beta;
+};
+__device__ __forceinline__ ImgScal img_scal(const ImgIn& in) {
+  return in.cg.r ? ImgScal{(float)*in.cg.alpha, (float)*in.cg.beta} : ImgScal{0.f, 0.f};
 }
-__device__ __forceinline__ float2 img_at(const ImgIn& in, long long pix, float bt, bool store) {
-  if (!in.r) return in.x[pix];
-  const float2 rv = in.r[pix], pv = in.x[pix];
-  const float2 v = make_float2(fmaf(bt, pv.x, rv.x), fmaf(bt, pv.y, rv.y));
-  if (store) in.pnew[pix] = v;
-  return v;
+__device__ __forceinline__ float2 img_at(const ImgIn& in, long long pix, ImgScal sc, bool store) {
+  if (!in.cg.r) return in.x[pix];
+  // every reader needs r' = r - alpha (w + beta s); the storing workgroup
+  // also forms and writes p', s', u'
+  const CGUpdate& c = in.cg;
+  const float2 rv = c.r[pix], sv = c.s[pix], wv = c.w[pix];
+  const float2 sn = make_float2(fmaf(sc.beta, sv.x, wv.x), fmaf(sc.beta, sv.y, wv.y));
+  const float2 rn = make_float2(fmaf(-sc.alpha, sn.x, rv.x), fmaf(-sc.alpha, sn.y, rv.y));
+  if (store) {
+    const float2 pv = c.p[pix], uv = c.u[pix];
+    const float2 pn = make_float2(fmaf(sc.beta, pv.x, rv.x), fmaf(sc.beta, pv.y, rv.y));
+    c.p2[pix] = pn;
+    c.s2[pix] = sn;
+    c.u2[pix] = make_float2(fmaf(sc.alpha, pn.x, uv.x), fmaf(sc.alpha, pn.y, uv.y));
+    c.r2[pix] = rn;
+  }
+  return rn;
 }
 
 // k-space input of the adjoint column pass: y[l][m], or -- inside the
@@ -166,7 +178,7 @@ k_rows_fwd(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
   float2* a = lds;
   float2* b = lds + kRowCoils * Kx;
   const float sy = day[iy];
-  const float bt = img_beta(in);
+  const ImgScal bt = img_scal(in);
   for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
     const int li = t / Kx;
     const int j = t - li * Kx;
@@ -316,7 +328,7 @@ k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
   if (active && t < K2) {
     float2 v[K1];
     const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
-    const float bt = img_beta(in);
+    const ImgScal bt = img_scal(in);
     const bool store = line == 0 && blockIdx.y == 0;
     const float2* Sl = S + (long long)l * N + (long long)iy * nx;
     const long long row0 = (long long)iy * nx;
@@ -601,8 +613,12 @@ k_cols_toep_fs(float2* __restrict__ mid, int ny, int Kx, const float2* __restric
   __shared__ float2 lds[8 * F::CS];
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;
-  const int c0 = blockIdx.x * tile;
-  const int l = blockIdx.y;
+  // (strip, coil) in XCD order, coil fastest: each XCD sweeps a contiguous
+  // range of strips through all coils, so a strip's slice of T stays in its
+  // L2 across the coils and neighbouring strips share cache lines there
+  const int lin = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int l = lin % gridDim.y;
+  const int c0 = (lin / gridDim.y) * tile;
   const bool colok = c < tile;
   float2* col = mid + (long long)l * ny * Kx + c0 + c;
   if (colok && t < K2) {
@@ -871,7 +887,7 @@ static void adjoint_to_groups(const pnp_plan* p, const KIn& kin, const float2* s
 
 void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y,
                 const OpWorkspace& w, hipStream_t s) {
-  forward_to_partials(p, ImgIn{x, nullptr, nullptr, nullptr}, smaps, L, w, s);
+  forward_to_partials(p, ImgIn{x, CGUpdate{}}, smaps, L, w, s);
   const long long tot = p->M * L;
   const float scale = (float)(1.0 / std::sqrt((double)image_size(p)));
   PNP_LAUNCH(k_gather_entries, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, w.ypart,
@@ -893,7 +909,7 @@ void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, 
 
 void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
                      const float* dcf, const OpWorkspace& w, hipStream_t s) {
-  forward_to_partials(p, ImgIn{in.x, in.r, in.pnew, in.beta}, smaps, L, w, s);
+  forward_to_partials(p, ImgIn{in.x, in.cg}, smaps, L, w, s);
   const float scale = (float)(1.0 / (double)image_size(p));   // both N^{-1/2} factors
   adjoint_to_groups(p, KIn{nullptr, w.ypart, p->sample_ent, (long long)p->M, (long long)p->E}, smaps,
                     L, dcf, scale, w.part, w, s);
@@ -904,7 +920,7 @@ bool toeplitz_supported(const pnp_plan* p) { return p->ndim == 2 && fs_ok(p); }
 void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
                           const OpWorkspace& w, hipStream_t s) {
   const pnp_plan* p = tp->plan;
-  const ImgIn im{in.x, in.r, in.pnew, in.beta};
+  const ImgIn im{in.x, in.cg};
   PNP_FS_DISPATCH(p->ax[0].K, rows_fwd_toep, p, im, smaps, L, w.mid, s);
   PNP_FS_DISPATCH(p->ax[1].K, cols_toep, p, L, tp->T, w.mid, s);
   PNP_FS_DISPATCH(p->ax[0].K, rows_adj_toep, p, L, w.mid, smaps, w.part, s);
@@ -912,7 +928,7 @@ void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const floa
 
 void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps, int L, float2* out,
                     const OpWorkspace& w, hipStream_t s) {
-  op_normal_toep_parts(tp, NormalIn{x, nullptr, nullptr, nullptr}, smaps, L, w, s);
+  op_normal_toep_parts(tp, plain_input(x), smaps, L, w, s);
   const int G = op_groups(L);
   const int64_t N = image_size(tp->plan);
   PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
@@ -921,7 +937,7 @@ void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps
 
 void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,
                float2* out, const OpWorkspace& w, hipStream_t s) {
-  op_normal_parts(p, NormalIn{x, nullptr, nullptr, nullptr}, smaps, L, dcf, w, s);
+  op_normal_parts(p, plain_input(x), smaps, L, dcf, w, s);
   const int G = op_groups(L);
   const int64_t N = image_size(p);
   PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,

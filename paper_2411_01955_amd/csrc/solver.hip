@@ -11,14 +11,20 @@
 // The prox system (Sec. 3.4, read with the density weighting D_w):
 //   M u = b,  M = gamma N + P = c0 I + (gamma - c1 alpha) N,  N = A^H D_w A,
 //   b = P x + gamma b0,  b0 = A^H D_w y,  started at u = x so that
-//   r0 = gamma (b0 - N x).  Each CG step costs one normal operator, whose
-//   first pass also forms the new direction p = r + beta p.
+//   r0 = gamma (b0 - N x).  CG runs in the Chronopoulos-Gear arrangement
+//   (same iterates as the textbook recurrence in exact arithmetic): with
+//   w = M r, both inner products <r,r> and <w,r> of a step are reduced in
+//   one pass, and the vector updates
+//     p = r + beta p, s = w + beta s, u = u + alpha p, r = r - alpha s
+//   are formed inside the next normal operator's first pass, so a step is
+//   one normal operator plus one reduction kernel.
 // The residual rho(x) = ||D_w^{1/2}(A x - y)||^2 = <x,Nx> - 2 Re<x,b0> + ||y||_w^2
 // comes for free from the N x that r0 needs.
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
+#include "cg_scalars.hpp"
 #include "common.hpp"
 #include "trace.hpp"
 
@@ -28,17 +34,6 @@ constexpr int kRedBlocks = 256;
 constexpr int kRedThreads = 256;
 constexpr int kMaxOuter = 1024;
 
-struct DevScalars {
-  double rr;        // <r, r>
-  double pq;        // Re <p, M p>
-  double alpha;     // CG step
-  double beta;      // CG direction update
-  double yw2;       // ||y||^2_w
-  double lam;       // power iteration: Rayleigh quotient
-  double inv;       // power iteration: 1/||w||
-  int bad;          // set when a CG denominator is not positive / finite
-  unsigned cnt;     // last-block ticket (reset by the last block)
-};
 
 namespace {
 
@@ -124,76 +119,61 @@ __global__ void k_copy(long long N, const float2* __restrict__ a, float2* __rest
 }
 
 // Nx = sum of the normal operator's partial images; u = x; r = gamma (b0 - Nx);
-// p = r.  Last block: rr = <r,r>, rho(x) = <x,Nx> - 2 Re<x,b0> + ||y||_w^2.
+// p = s = 0.  Last block: rr = <r,r>, rho(x) = <x,Nx> - 2 Re<x,b0> + ||y||_w^2.
 __global__ void __launch_bounds__(kRedThreads)
 k_cg_init(long long N, int G, const float2* __restrict__ x, const float2* __restrict__ part,
           const float2* __restrict__ b0, float gamma, float2* __restrict__ u, float2* __restrict__ r,
-          float2* __restrict__ p, double* __restrict__ parts, DevScalars* sc, double* rho_out) {
+          float2* __restrict__ p, float2* __restrict__ sv, double* __restrict__ parts, DevScalars* sc,
+          double* rho_out) {
   double acc[3] = {0.0, 0.0, 0.0};
+  const float2 z = make_float2(0.f, 0.f);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     const float2 xv = x[i], nv = sum_groups(part, G, N, i), bv = b0[i];
     const float2 rv = make_float2(gamma * (bv.x - nv.x), gamma * (bv.y - nv.y));
     u[i] = xv;
     r[i] = rv;
-    p[i] = rv;
+    p[i] = z;
+    sv[i] = z;
     acc[0] += re_dot(rv, rv);
     acc[1] += re_dot(xv, nv);
     acc[2] += re_dot(xv, bv);
   }
   double s[3];
-  if (reduce_last<3>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
-    sc->rr = s[0];
-    if (rho_out) *rho_out = s[1] - 2.0 * s[2] + sc->yw2;
-  }
+  if (reduce_last<3>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) cg_finish_init(sc, s[0], s[1], s[2], rho_out);
 }
 
-// q = c0 p + cg N p;  last block: alpha = rr / Re<p, q>
+// w = c0 r + cg N r.  Last block, with g = <r,r>, d = Re<w,r>:
+//   first step:  beta = 0, alpha = g / d
+//   later steps: beta = g / rr, alpha = g / (d - beta g / alpha)
+// then rr = g.  A zero residual gives alpha = beta = 0; a non-positive or
+// non-finite denominator sets `bad` and alpha = beta = 0 (u stops moving).
 __global__ void __launch_bounds__(kRedThreads)
-k_cg_q(long long N, int G, const float2* __restrict__ p, const float2* __restrict__ part, float c0,
-       float cg, float2* __restrict__ q, double* __restrict__ parts, DevScalars* sc) {
-  double acc[1] = {0.0};
+k_cg_dots(long long N, int G, const float2* __restrict__ r, const float2* __restrict__ part, float c0,
+          float cg, int first, float2* __restrict__ w, double* __restrict__ parts, DevScalars* sc) {
+  double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
-    const float2 pv = p[i], nv = sum_groups(part, G, N, i);
-    const float2 qv = make_float2(c0 * pv.x + cg * nv.x, c0 * pv.y + cg * nv.y);
-    q[i] = qv;
-    acc[0] += re_dot(pv, qv);
-  }
-  double s[1];
-  if (reduce_last<1>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
-    sc->pq = s[0];
-    if (sc->rr == 0.0) {
-      sc->alpha = 0.0;
-    } else if (!(s[0] > 0.0) || !isfinite(s[0]) || !isfinite(sc->rr)) {
-      sc->alpha = 0.0;
-      sc->bad = 1;
-    } else {
-      sc->alpha = sc->rr / s[0];
-    }
-  }
-}
-
-// u += alpha p; r -= alpha q;  last block: beta = <r,r>_new / <r,r>, rr updated
-__global__ void __launch_bounds__(kRedThreads)
-k_cg_update(long long N, float2* __restrict__ u, float2* __restrict__ r, const float2* __restrict__ p,
-            const float2* __restrict__ q, double* __restrict__ parts, DevScalars* sc) {
-  const float a = (float)sc->alpha;
-  double acc[1] = {0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
-    const float2 pv = p[i], qv = q[i];
-    float2 uv = u[i], rv = r[i];
-    uv = make_float2(fmaf(a, pv.x, uv.x), fmaf(a, pv.y, uv.y));
-    rv = make_float2(fmaf(-a, qv.x, rv.x), fmaf(-a, qv.y, rv.y));
-    u[i] = uv;
-    r[i] = rv;
+    const float2 rv = r[i], nv = sum_groups(part, G, N, i);
+    const float2 wv = make_float2(c0 * rv.x + cg * nv.x, c0 * rv.y + cg * nv.y);
+    w[i] = wv;
     acc[0] += re_dot(rv, rv);
+    acc[1] += re_dot(wv, rv);
   }
-  double s[1];
-  if (reduce_last<1>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) {
-    sc->beta = sc->rr > 0.0 ? s[0] / sc->rr : 0.0;
-    sc->rr = s[0];
+  double s[2];
+  if (reduce_last<2>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) cg_finish_dots(sc, s[0], s[1], first);
+}
+
+// Last CG step: p = r + beta p, u = u + alpha p (writes u2).
+__global__ void k_cg_final(long long N, const float2* __restrict__ r, const float2* __restrict__ p,
+                           const float2* __restrict__ u, float2* __restrict__ u2,
+                           const DevScalars* __restrict__ sc) {
+  const float a = (float)sc->alpha, b = (float)sc->beta;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 rv = r[i], pv = p[i], uv = u[i];
+    const float2 pn = make_float2(fmaf(b, pv.x, rv.x), fmaf(b, pv.y, rv.y));
+    u2[i] = make_float2(fmaf(a, pn.x, uv.x), fmaf(a, pn.y, uv.y));
   }
 }
 
@@ -277,7 +257,8 @@ unsigned vec_blocks(long long N) {
 // ------------------------------------------------------------ host side
 struct SolverWs {
   OpWorkspace op;
-  float2 *b0, *Nv, *u, *r, *p, *p2, *q;
+  float2 *b0, *Nv, *w;
+  float2 *u[2], *r[2], *p[2], *s[2];   // CG vectors, double-buffered
   double* parts;
   DevScalars* sc;
   double* rho;   // [kMaxOuter + 1]
@@ -286,7 +267,7 @@ struct SolverWs {
 size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
   const int64_t N = image_size(p);
   size_t b = al(op_workspace_bytes(p, L));
-  b += 7 * al(sizeof(float2) * N);
+  b += 11 * al(sizeof(float2) * N);
   b += al(sizeof(double) * 4 * kRedBlocks);
   b += al(sizeof(DevScalars));
   b += al(sizeof(double) * (kMaxOuter + 1));
@@ -299,7 +280,8 @@ static SolverWs solver_ws(const pnp_plan* p, int L, void* ws) {
   char* c = (char*)ws;
   w.op = op_workspace(p, L, c);
   c += al(op_workspace_bytes(p, L));
-  float2** vecs[7] = {&w.b0, &w.Nv, &w.u, &w.r, &w.p, &w.p2, &w.q};
+  float2** vecs[11] = {&w.b0, &w.Nv, &w.w, &w.u[0], &w.u[1], &w.r[0], &w.r[1], &w.p[0], &w.p[1],
+                        &w.s[0], &w.s[1]};
   for (auto v : vecs) {
     *v = (float2*)c;
     c += al(sizeof(float2) * N);
@@ -333,14 +315,14 @@ double power_iteration(const pnp_plan* p, const pnp_toeplitz* tp, const float2* 
   const long long N = image_size(p);
   const int G = op_groups(L);
   const unsigned nb = vec_blocks(N);
-  float2* v = w.u;
+  float2* v = w.u[0];
   PNP_LAUNCH(k_init_scalars, dim3(1), dim3(64), 0, s, w.sc);
   PNP_LAUNCH(k_randn, dim3(nb), dim3(kRedThreads), 0, s, N, seed, w.Nv);
   PNP_LAUNCH(k_pow_dot, dim3(nb), dim3(kRedThreads), 0, s, N, G, (const float2*)nullptr,
              (const float2*)nullptr, w.Nv, w.parts, w.sc);
   PNP_LAUNCH(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, w.sc, v);
   for (int it = 0; it < iters; ++it) {
-    normal_parts(p, tp, NormalIn{v, nullptr, nullptr, nullptr}, smaps, L, dcf, w.op, s);
+    normal_parts(p, tp, plain_input(v), smaps, L, dcf, w.op, s);
     PNP_LAUNCH(k_pow_dot, dim3(nb), dim3(kRedThreads), 0, s, N, G, v, w.op.part, w.Nv, w.parts, w.sc);
     PNP_LAUNCH(k_scale_into, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, w.sc, v);
   }
@@ -410,10 +392,11 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   double rho_prev = 0.0;
   if (fb_host)
     for (int k = 0; k < a.n_out; ++k) fb_host[k] = 0;
+  // N x, then the CG start in set 0: u = x, r = gamma (b0 - N x), p = s = 0
   auto cg_start = [&](double gamma, double* rho_out) {
-    normal_parts(p, a.toep, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
-    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u, w.r,
-               w.p, w.parts, w.sc, rho_out);
+    normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
+    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u[0],
+               w.r[0], w.p[0], w.s[0], w.parts, w.sc, rho_out);
   };
 
   for (int k = 0; k < a.n_out; ++k) {
@@ -422,24 +405,27 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     if (!started) cg_start(gamma, w.rho + k);
     started = false;
     if (guard && k == 0) rho_prev = read_scalar(w.rho, s);
-    float2* pc = w.p;
-    float2* pn = w.p2;
+    // step 0: w = M r0; steps 1..n_cg-1: update (p, s, u, r) inside the
+    // operator's first pass, w = M r; then the last u update
+    int c = 0;
     for (int j = 0; j < a.n_cg; ++j) {
-      if (j == 0) {
-        normal_parts(p, a.toep, NormalIn{pc, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
-      } else {
-        // p <- r + beta p, formed inside the operator's first pass
-        normal_parts(p, a.toep, NormalIn{pc, w.r, pn, &w.sc->beta}, a.smaps, a.L, a.dcf, w.op, s);
-        std::swap(pc, pn);
+      NormalIn in = plain_input(w.r[0]);
+      if (j > 0) {
+        in.x = nullptr;
+        in.cg = CGUpdate{w.r[c], w.p[c], w.s[c], w.u[c], w.w, w.r[1 - c], w.p[1 - c], w.s[1 - c], w.u[1 - c],
+                         &w.sc->alpha, &w.sc->beta};
+        c = 1 - c;
       }
-      PNP_LAUNCH(k_cg_q, dim3(nb), dim3(kRedThreads), 0, s, N, G, pc, w.op.part, (float)c0, cg, w.q,
-                 w.parts, w.sc);
-      PNP_LAUNCH(k_cg_update, dim3(nb), dim3(kRedThreads), 0, s, N, w.u, w.r, pc, w.q, w.parts, w.sc);
+      normal_parts(p, a.toep, in, a.smaps, a.L, a.dcf, w.op, s);
+      PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg,
+                 j == 0 ? 1 : 0, w.w, w.parts, w.sc);
     }
-    prior_apply(a.prior, p->ndim, nd, w.u, x, a.sigmas[k], s);
+    float2* u_res = w.u[1 - c];
+    PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res, w.sc);
+    prior_apply(a.prior, p->ndim, nd, u_res, x, a.sigmas[k], s);
     if (!guard) continue;
     // candidate from the fallback, kept in Nv (free during the solve)
-    prior_apply(a.prior->fallback, p->ndim, nd, w.u, w.Nv, a.sigmas[k], s);
+    prior_apply(a.prior->fallback, p->ndim, nd, u_res, w.Nv, a.sigmas[k], s);
     const double gnext = k + 1 < a.n_out ? a.lambda * a.sigmas[k + 1] : 0.0;
     cg_start(gnext, w.rho + k + 1);
     double rho = read_scalar(w.rho + k + 1, s);
@@ -454,9 +440,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   }
   if (rho_host) {
     // residual of the final image (one extra normal operator)
-    normal_parts(p, a.toep, NormalIn{x, nullptr, nullptr, nullptr}, a.smaps, a.L, a.dcf, w.op, s);
-    PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, 0.0f, w.u, w.r,
-               w.p, w.parts, w.sc, w.rho + a.n_out);
+    cg_start(0.0, w.rho + a.n_out);
     std::vector<double> r(a.n_out + 1);
     DevScalars h;
     PNP_HIP(hipMemcpyAsync(r.data(), w.rho, sizeof(double) * (a.n_out + 1), hipMemcpyDeviceToHost, s));
