@@ -26,6 +26,11 @@ Printed JSON line:
              per slice and method a logged run finds the first outer
              iteration k* that reaches it (30 if none does), and a timed run
              of exactly k* iterations gives seconds per slice;
+* ``batched`` the 24-slice uneven table (n 256/320/384, 8/16/32 coils, AF
+             4/8/16, radial and spiral, Voronoi DCF): the batched Toeplitz
+             normal operator (one persistent launch per stage) against the
+             sum of the slices' B_alg, and batched HQS (30 outer x 5 CG) in
+             slices/s next to the same slices solved one after another;
 * ``unet``   the denoiser's forward (320x320, batch 1 and 24) and training
              step (batch 10 x 128x128, forward + backward + Adam) in TFLOP/s
              and as a fraction of the 2.5 PFLOP/s dense BF16 MFMA peak.
@@ -189,6 +194,63 @@ def psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, n_slices):
     return out
 
 
+def batched_c4(pnp, torch, reps=10):
+    """The 24-slice table through the batched path vs one slice at a time."""
+    import synth
+    w = synth.config_clinical()
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)
+    slices, b_alg = [], 0
+    for sl in synth.batched_slice_table():
+        i, n, L, tr = sl["index"], sl["n"], sl["L"], sl["traj"]
+        M = tr.k.shape[0]
+        x, _ = synth.phantom2d(n, synth.SEED_PHANTOM + i)
+        S = synth.smaps2d(n, L)
+        dcf = synth.voronoi_dcf(tr, n)
+        plan = pnp.Plan(torch.from_numpy(tr.k).cuda(), (n, n))
+        Sd, dd = torch.from_numpy(S).cuda(), torch.from_numpy(dcf).cuda()
+        y = plan.forward(torch.from_numpy(x).cuda(), Sd)
+        y += torch.from_numpy(synth.complex_noise((L, M), synth.noise_variance(x, S), synth.SEED_NOISE + i)).cuda()
+        nrm = plan.opnorm(Sd, dd, iters=60, seed=1)
+        slices.append(dict(plan=plan, toeplitz=pnp.Toeplitz(plan, dd), y=y, smaps=Sd, dcf=dd, opnorm=nrm,
+                           lam=LAM_TIMES_NORM / nrm))
+        b_alg += b_alg_normal(n, L, M)
+    batch = pnp.Batch(slices)
+    xs = [torch.from_numpy(synth.white_complex(d["plan"].shape, 5)).cuda() for d in slices]
+    outs = [torch.empty_like(x) for x in xs]
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n / 1e3
+
+    t_op = timed(lambda: batch.normal(xs, outs), reps)
+    t_op_seq = timed(lambda: [d["toeplitz"].normal(x, d["smaps"], out=o) for d, x, o in zip(slices, xs, outs)], reps)
+    wav = pnp.WaveletPrior(0, KAPPA)
+    t_hqs = timed(lambda: batch.hqs_solve(wav, sig, "f1", w.n_cg), 2)
+    t_seq = timed(lambda: [pnp.hqs_solve(d["plan"], d["y"], d["smaps"], d["dcf"], wav, sig, d["lam"], "f1", w.n_cg,
+                                         opnorm=d["opnorm"], toeplitz=d["toeplitz"], out=o)
+                           for d, o in zip(slices, outs)], 2)
+    lrn = pnp.UNetPrior(pnp.trained_unet(), (320, 320), KAPPA_UNET)
+    k_l = 4
+    t_lrn = timed(lambda: batch.hqs_solve(lrn, sig[:k_l], "f1", w.n_cg), 2)
+    n_ops = w.n_out * (1 + w.n_cg)
+    return {"slices": len(slices), "b_alg_bytes_per_normal_op": b_alg,
+            "normal_op_ms": round(t_op * 1e3, 3), "normal_op_GBps": round(b_alg / t_op / 1e9, 1),
+            "normal_op_frac_of_hbm": round(b_alg / t_op / 1e9 / HBM_PEAK_GBPS, 4),
+            "normal_op_one_by_one_ms": round(t_op_seq * 1e3, 3),
+            "hqs_wavelet_ms": round(t_hqs * 1e3, 2), "hqs_wavelet_slices_per_s": round(len(slices) / t_hqs, 1),
+            "hqs_wavelet_GBps": round(n_ops * b_alg / t_hqs / 1e9, 1),
+            "hqs_wavelet_one_by_one_slices_per_s": round(len(slices) / t_seq, 1),
+            "hqs_learned_outer": k_l, "hqs_learned_ms": round(t_lrn * 1e3, 2),
+            "hqs_learned_slices_per_s": round(len(slices) / t_lrn, 1)}
+
+
 def unet_rates(pnp, torch):
     """Forward and training-step throughput of the denoiser (inputs resident)."""
     import synth
@@ -273,6 +335,7 @@ def main():
                     help="back-to-back repetitions when timing the normal operators alone")
     ap.add_argument("--psnr-slices", type=int, default=24,
                     help="held-out phantoms of the learned-vs-wavelet PSNR race (0: skip)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
@@ -388,6 +451,7 @@ def main():
 
     race = psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.psnr_slices) if args.psnr_slices > 0 else None
     unet = unet_rates(pnp, torch)
+    batched = None if args.no_batched else batched_c4(pnp, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -418,6 +482,7 @@ def main():
         "gridded_normal_op_GBps": round(B / (gridded_us * 1e-6) / 1e9, 1),
         "roofline": roofline,
         "psnr_race": race,
+        "batched": batched,
         "unet": unet,
         "kernels": kernel_table,
         "cpu_baseline": cpu,

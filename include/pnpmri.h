@@ -320,6 +320,53 @@ pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* 
                          int32_t n_out, const pnp_hqs_opts* opts, pnp_c64* x_out,
                          pnp_hqs_report* report, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------- batched slices
+ * Many independent 2D slices (different sizes, coil counts and trajectories)
+ * reconstructed together with the same schedule (Sec. 3.3-3.4 per slice).
+ * Each stage of the Toeplitz normal operator runs as one launch per image
+ * size over the work items of all slices of that size; CG
+ * reductions are per slice (FP64, on the device); the Haar prior is one
+ * launch over all slices and the UNet prior one batched forward per image
+ * size.  Supported: square images with n in {64, 96, 128, 256, 320, 384,
+ * 512} and one Haar depth for all slices. */
+typedef struct {
+  const pnp_plan* plan;          /* the slice's plan (2D, square)              */
+  const pnp_toeplitz* toeplitz;  /* its Toeplitz embedding (built with `dcf`)  */
+  const pnp_c64* y;              /* device [L][M] k-space data                 */
+  const pnp_c64* smaps;          /* device [L][n][n]                           */
+  int32_t L;
+  const float* dcf;              /* device [M] or NULL                         */
+  double opnorm;                 /* ||A^H D_w A|| of the slice (> 0)           */
+  double lambda;                 /* gamma_k = lambda * sigma_k (> 0)           */
+  pnp_c64* x_out;                /* device [n][n] result                       */
+} pnp_slice;
+
+typedef struct pnp_batch pnp_batch;
+
+/* Build the batch (work lists, per-slice tables, workspace; one device
+ * allocation owned by the batch).  Keeps the slices' pointers: the plans,
+ * Toeplitz handles and arrays must outlive the batch.  Waits for `stream`. */
+pnp_status pnp_batch_create(pnp_batch** out, int32_t B, const pnp_slice* slices, hipStream_t stream);
+pnp_status pnp_batch_destroy(pnp_batch* batch);
+
+/* out[i] = A_i^H D_w A_i x[i] for every slice (Toeplitz operator, three
+ * launches per image size plus one coil-group sum).  x, out: host arrays of B
+ * device pointers (each [n_i][n_i]).  Waits for `stream`. */
+pnp_status pnp_batch_normal(pnp_batch* batch, const pnp_c64* const* x, pnp_c64* const* out, hipStream_t stream);
+
+/* Workspace bytes pnp_hqs_solve_batched needs for `prior` (0 for a wavelet prior). */
+pnp_status pnp_batch_workspace_bytes(const pnp_batch* batch, const pnp_prior* prior, size_t* bytes);
+
+/* Annealed PnP-HQS of every slice (pnp_hqs_solve per slice, started at
+ * x0 = A^H D_w y, fallback not available): sigmas host [n_out], precond
+ * PNP_PRECOND_*, n_cg >= 1.  prior: a wavelet prior (its depth must be the
+ * slices' default) or a UNet prior (its network and kappa are used; its
+ * shape is ignored).  rho: host [B][n_out] residuals of x_k, or NULL (the
+ * call then returns without waiting). */
+pnp_status pnp_hqs_solve_batched(pnp_batch* batch, const pnp_prior* prior, const double* sigmas, int32_t n_out,
+                                 int32_t precond, int32_t n_cg, double* rho, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,11 +23,11 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, UNET_BUF, UNetLayer, check, load
+from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, UNET_BUF, Slice, UNetLayer, check, load
 
 __all__ = ["Plan", "Toeplitz", "WaveletPrior", "UNet", "UNetPrior", "hqs_solve", "PnPError", "load",
            "trace_enable", "trace_read", "unet_layers", "pack_unet_params", "unpack_unet_params",
-           "UNET_LAYER_NAMES", "UNET_TENSORS", "trained_unet", "TRAINED_WEIGHTS"]
+           "UNET_LAYER_NAMES", "UNET_TENSORS", "trained_unet", "TRAINED_WEIGHTS", "Batch"]
 
 
 def trace_enable(on: bool = True):
@@ -496,6 +496,83 @@ class UNetPrior:
     def close(self):
         if getattr(self, "_h", None):
             load().pnp_prior_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- batches
+class Batch:
+    """Many 2D slices reconstructed together (one persistent launch per
+    operator stage over all slices).  ``slices``: list of dicts with keys
+    plan, toeplitz, y, smaps, dcf (or None), opnorm, lam and optionally out
+    (the result tensor; allocated when absent)."""
+
+    def __init__(self, slices):
+        torch = _torch()
+        self.slices = []
+        arr = (Slice * len(slices))()
+        for i, d in enumerate(slices):
+            plan, tp = d["plan"], d["toeplitz"]
+            L = plan._L(d["smaps"])
+            _need_c64(d["y"], "y", (L, plan.M))
+            _need_f32(d.get("dcf"), "dcf", (plan.M,))
+            out = d.get("out")
+            if out is None:
+                out = torch.empty(plan.shape, dtype=torch.complex64, device=d["y"].device)
+            _need_c64(out, "out", plan.shape)
+            keep = dict(d, out=out, L=L)
+            self.slices.append(keep)
+            arr[i] = Slice(plan.handle.value, tp.handle.value, d["y"].data_ptr(), d["smaps"].data_ptr(), L,
+                           d["dcf"].data_ptr() if d.get("dcf") is not None else None, float(d["opnorm"]),
+                           float(d["lam"]), out.data_ptr())
+        h = C.c_void_p()
+        check(load().pnp_batch_create(C.byref(h), len(slices), arr, _stream()))
+        self._h = h
+        self._ws = {}
+
+    @property
+    def outputs(self):
+        return [d["out"] for d in self.slices]
+
+    def normal(self, xs, outs=None):
+        """[A_i^H D_w A_i x_i] for every slice (Toeplitz operator)."""
+        torch = _torch()
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for x, o, d in zip(xs, outs, self.slices):
+            _need_c64(x, "x", d["plan"].shape)
+            _need_c64(o, "out", d["plan"].shape)
+        xa = (C.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        oa = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        check(load().pnp_batch_normal(self._h, xa, oa, _stream()))
+        return outs
+
+    def hqs_solve(self, prior, sigmas, precond="f1", n_cg=5, report=False):
+        """Annealed PnP-HQS of every slice; returns (outputs, rho [B][n_out] or None)."""
+        torch = _torch()
+        import numpy as np
+        n_out = len(sigmas)
+        sig = (C.c_double * n_out)(*[float(s) for s in sigmas])
+        nb = C.c_size_t()
+        check(load().pnp_batch_workspace_bytes(self._h, prior.handle, C.byref(nb)))
+        key = nb.value
+        if key not in self._ws:
+            self._ws[key] = torch.empty(max(key, 256), dtype=torch.uint8, device="cuda")
+        ws = self._ws[key]
+        rho = (C.c_double * (len(self.slices) * n_out))() if report else None
+        check(load().pnp_hqs_solve_batched(self._h, prior.handle, sig, n_out, PRECOND[precond.lower()], int(n_cg),
+                                           rho, _ptr(ws), ws.numel(), _stream()))
+        r = np.array(list(rho)).reshape(len(self.slices), n_out) if report else None
+        return self.outputs, r
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pnp_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -56,6 +56,20 @@ class UNetLayer(C.Structure):
 
 UNET_BUF = {"params": 0, "grad": 1, "adam_m": 2, "adam_v": 3}
 
+
+class Slice(C.Structure):
+    _fields_ = [
+        ("plan", C.c_void_p),
+        ("toeplitz", C.c_void_p),
+        ("y", C.c_void_p),
+        ("smaps", C.c_void_p),
+        ("L", C.c_int32),
+        ("dcf", C.c_void_p),
+        ("opnorm", C.c_double),
+        ("lam", C.c_double),
+        ("x_out", C.c_void_p),
+    ]
+
 _vp = C.c_void_p
 _i32 = C.c_int32
 _i64 = C.c_int64
@@ -101,6 +115,12 @@ SIGNATURES = {
     "pnp_unet_adam_step": (_i32, [_vp, _dbl, _dbl, _dbl, _dbl, _vp]),
     "pnp_unet_tensor": (_i32, [_i32, _i32, _i32, _i32, _vp, _i32, C.POINTER(_vp), C.POINTER(_i32)]),
     "pnp_prior_unet": (_i32, [C.POINTER(_vp), _vp, _i32, C.POINTER(_i32), _dbl, _vp]),
+    "pnp_batch_create": (_i32, [C.POINTER(_vp), _i32, C.POINTER(Slice), _vp]),
+    "pnp_batch_destroy": (_i32, [_vp]),
+    "pnp_batch_normal": (_i32, [_vp, C.POINTER(_vp), C.POINTER(_vp), _vp]),
+    "pnp_batch_workspace_bytes": (_i32, [_vp, _vp, C.POINTER(_sz)]),
+    "pnp_hqs_solve_batched": (_i32, [_vp, _vp, C.POINTER(_dbl), _i32, _i32, _i32, C.POINTER(_dbl), _vp, _sz,
+                                     _vp]),
 }
 
 _lib = None

@@ -471,3 +471,53 @@ pnp_status pnp_unet_tensor(int32_t B, int32_t H, int32_t W, int32_t train, void*
     unet_tensor(B, H, W, train != 0, ws, id, ptr, dims);
   });
 }
+
+// --------------------------------------------------------------- batches
+pnp_status pnp_batch_create(pnp_batch** out, int32_t B, const pnp_slice* slices, hipStream_t stream) {
+  return guarded([&] {
+    need(out, "out");
+    need(slices, "slices");
+    *out = batch_create(B, slices, stream);
+  });
+}
+
+pnp_status pnp_batch_destroy(pnp_batch* batch) {
+  return guarded([&] { batch_destroy(batch); });
+}
+
+pnp_status pnp_batch_normal(pnp_batch* batch, const pnp_c64* const* x, pnp_c64* const* out, hipStream_t stream) {
+  return guarded([&] {
+    need(batch, "batch");
+    need(x, "x");
+    need(out, "out");
+    batch_normal(batch, (const float2* const*)x, (float2* const*)out, stream);
+  });
+}
+
+pnp_status pnp_batch_workspace_bytes(const pnp_batch* batch, const pnp_prior* prior, size_t* bytes) {
+  return guarded([&] {
+    need(batch, "batch");
+    need(prior, "prior");
+    need(bytes, "bytes");
+    *bytes = prior->kind == 1 ? batch_unet_ws_bytes(batch) : 0;
+  });
+}
+
+pnp_status pnp_hqs_solve_batched(pnp_batch* batch, const pnp_prior* prior, const double* sigmas, int32_t n_out,
+                                 int32_t precond, int32_t n_cg, double* rho, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  return guarded([&] {
+    need(batch, "batch");
+    need(prior, "prior");
+    need(sigmas, "sigmas");
+    if (n_out < 1) fail(PNP_ERR_SHAPE, "n_out must be >= 1");
+    if (precond < 0 || precond > 2) fail(PNP_ERR_ARG, "unknown preconditioner %d", precond);
+    if (n_cg < 1) fail(PNP_ERR_ARG, "n_cg must be >= 1");
+    for (int k = 0; k < n_out; ++k)
+      if (!(sigmas[k] > 0.0) || !std::isfinite(sigmas[k])) fail(PNP_ERR_ARG, "sigma[%d] must be > 0", k);
+    if (prior->kind == 1) check_ws(ws_bytes, batch_unet_ws_bytes(batch), ws);
+    int bad = 0;
+    batch_hqs_solve(batch, prior, sigmas, n_out, precond, n_cg, ws, rho, rho ? &bad : nullptr, stream);
+    if (bad) fail(PNP_ERR_NUMERIC, "CG breakdown in a batched slice");
+  });
+}

@@ -179,6 +179,29 @@ struct NormalIn {
 };
 inline NormalIn plain_input(const float2* x) { return NormalIn{x, CGUpdate{}}; }
 int op_groups(int L);
+
+// ------------------------------------------------ batched Toeplitz operator
+// One slice of a batched Toeplitz normal operator (device table entry).
+// Supported grids: the register-FFT sizes K = 2n in {128, 192, 256, 512,
+// 640, 768, 1024}.
+struct BatchSlice {
+  int nx, ny, K, L;
+  long long N;
+  const float2* S;      // [L][N] coil maps
+  float2* mid;          // [L][ny][K] half-transformed grid
+  float2* part;         // [G][N] coil-group partial images
+  const float* T;       // [K][K] transfer function
+  const float2* tw;     // K-point twiddles of the slice's plan
+};
+bool batch_grid_supported(int K);
+// Stage launches over the work items int4 {slice, a, b, 0} of all slices
+// with grid size K (one workgroup per item):
+//   rows passes: a = image row, b = coil group;  column pass: a = strip, b = coil.
+// `ins` (device, one per slice) is each slice's operator input.
+void batch_rows_fwd(int K, const BatchSlice* sl, const NormalIn* ins, const int4* items, int n_items,
+                    hipStream_t s);
+void batch_cols_toep(int K, const BatchSlice* sl, const int4* items, int n_items, hipStream_t s);
+void batch_rows_adj(int K, const BatchSlice* sl, const int4* items, int n_items, hipStream_t s);
 void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
                      const float* dcf, const OpWorkspace& w, hipStream_t s);
 
@@ -198,6 +221,16 @@ int64_t image_size(const pnp_plan* p);
 void wavelet_apply(int ndim, const int* n_xyz, int levels, float tau, const float2* in, float2* out,
                    hipStream_t s);
 int wavelet_default_levels(int nmin);
+// Batched 2D Haar prior over slices (device table, ordered by block0; the
+// slices' blocks 0 .. nx*ny/4^J - 1 are numbered from block0 on).
+struct HaarSlice {
+  const float2* in;
+  float2* out;
+  int nx, ny;
+  int block0;
+};
+void wavelet_apply_batched(const HaarSlice* sl, int n_slices, int total_blocks, int levels, float tau,
+                           hipStream_t s);
 
 // UNet (learned prior)
 long long unet_param_count();
@@ -218,6 +251,13 @@ void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, 
                    void* ws, hipStream_t s);
 void unet_adam(pnp_unet* net, double lr, double b1, double b2, double eps, hipStream_t s);
 void unet_tensor(int B, int H, int W, bool train, void* ws, int id, void** ptr, int32_t dims[4]);
+// batched slices
+pnp_batch* batch_create(int B, const pnp_slice* sl, hipStream_t s);
+void batch_destroy(pnp_batch* b);
+void batch_normal(pnp_batch* b, const float2* const* x, float2* const* out, hipStream_t s);
+size_t batch_unet_ws_bytes(const pnp_batch* b);
+void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas, int n_out, int precond, int n_cg,
+                     void* unet_ws, double* rho_host, int* bad_host, hipStream_t s);
 // Apply any prior to an image of the plan's shape (u and x may alias for the wavelet only).
 void prior_apply(const pnp_prior* prior, int ndim, const int* n_xyz, const float2* u, float2* x, double sigma,
                  hipStream_t s);

@@ -311,17 +311,18 @@ __device__ __forceinline__ void fs_twiddle(float2 (&v)[K1], int t, const float2*
   }
 }
 
+// Row pass of the forward operator for image row iy and coil group g
+// (kRowCoils coils, one line of K1 threads each); A: kRowCoils * LA float2
+// of LDS.  Shared by the single-slice and the batched kernels.
 template <int K1, int K2>
-__global__ void __launch_bounds__(kRowCoils * K1)
-k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
-              const float* __restrict__ dax, const float* __restrict__ day,
-              const float2* __restrict__ tw, float2* __restrict__ mid) {
+__device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __restrict__ S, int L, int nx,
+                                              int ny, const float* __restrict__ dax,
+                                              const float* __restrict__ day, const float2* __restrict__ tw,
+                                              float2* __restrict__ mid, int iy, int g, float2* A) {
   using F = FS<K1, K2>;
-  __shared__ float2 A[kRowCoils * F::LA];
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
-  const int iy = blockIdx.x;
-  const int l = blockIdx.y * kRowCoils + line;
+  const int l = g * kRowCoils + line;
   const bool active = l < L;
   const long long N = (long long)nx * ny;
   float2* Al = A + line * F::LA;
@@ -329,7 +330,7 @@ k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
     float2 v[K1];
     const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
     const ImgScal bt = img_scal(in);
-    const bool store = line == 0 && blockIdx.y == 0;
+    const bool store = line == 0 && g == 0;
     const float2* Sl = S + (long long)l * N + (long long)iy * nx;
     const long long row0 = (long long)iy * nx;
 #pragma unroll
@@ -353,6 +354,15 @@ k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
 #pragma unroll
     for (int k2 = 0; k2 < K2; ++k2) dst[t + K1 * k2] = u[k2];
   }
+}
+
+template <int K1, int K2>
+__global__ void __launch_bounds__(kRowCoils * K1)
+k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
+              const float* __restrict__ dax, const float* __restrict__ day,
+              const float2* __restrict__ tw, float2* __restrict__ mid) {
+  __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  rows_fwd_body<K1, K2>(in, S, L, nx, ny, dax, day, tw, mid, blockIdx.x, blockIdx.y, A);
 }
 
 template <int K1, int K2>
@@ -543,17 +553,17 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   }
 }
 
+// Row pass of the adjoint for image row iy and coil group g: inverse row
+// FFT, crop, deapodisation, conj(S_l) and the sum over the group's coils
+// into part[g]; A: kRowCoils * LA float2 of LDS.
 template <int K1, int K2>
-__global__ void __launch_bounds__(kRowCoils * K1)
-k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
-              const float* __restrict__ dax, const float* __restrict__ day,
-              const float2* __restrict__ tw, float2* __restrict__ part) {
+__device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, const float2* __restrict__ S, int L,
+                                              int nx, int ny, const float* __restrict__ dax,
+                                              const float* __restrict__ day, const float2* __restrict__ tw,
+                                              float2* __restrict__ part, int iy, int g, float2* A) {
   using F = FS<K1, K2>;
-  __shared__ float2 A[kRowCoils * F::LA];
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
-  const int iy = blockIdx.x;
-  const int g = blockIdx.y;
   const int l = g * kRowCoils + line;
   const bool active = l < L;
   const long long N = (long long)nx * ny;
@@ -596,6 +606,15 @@ k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int 
   }
 }
 
+template <int K1, int K2>
+__global__ void __launch_bounds__(kRowCoils * K1)
+k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
+              const float* __restrict__ dax, const float* __restrict__ day,
+              const float2* __restrict__ tw, float2* __restrict__ part) {
+  __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  rows_adj_body<K1, K2>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
+}
+
 // Toeplitz column pass: for a strip of grid columns, the zero-padded column
 // FFT, multiplication by the real transfer function T, and the inverse
 // column FFT, all in registers with two LDS transposes:
@@ -604,21 +623,16 @@ k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int 
 //             DFT over k2, twiddle exp(+2 pi i k1 r2 / K), transpose,
 //             thread r2 runs the inverse DFT over k1 -> y[r2 + K2*r1].
 // Only the ny image rows are read and written (in place in mid).
+// Toeplitz column pass for grid columns [c0, c0 + tile) of coil l;
+// lds: 8 * CS float2.
 template <int K1, int K2>
-__global__ void __launch_bounds__(8 * K1)
-k_cols_toep_fs(float2* __restrict__ mid, int ny, int Kx, const float2* __restrict__ tw, int tile,
-               const float* __restrict__ T) {
+__device__ __forceinline__ void cols_toep_body(float2* __restrict__ mid, int ny, int Kx,
+                                               const float2* __restrict__ tw, int tile,
+                                               const float* __restrict__ T, int c0, int l, float2* lds) {
   using F = FS<K1, K2>;
   constexpr int AS2 = K1 + 1;          // row stride of the second transpose
-  __shared__ float2 lds[8 * F::CS];
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;
-  // (strip, coil) in XCD order, coil fastest: each XCD sweeps a contiguous
-  // range of strips through all coils, so a strip's slice of T stays in its
-  // L2 across the coils and neighbouring strips share cache lines there
-  const int lin = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const int l = lin % gridDim.y;
-  const int c0 = (lin / gridDim.y) * tile;
   const bool colok = c < tile;
   float2* col = mid + (long long)l * ny * Kx + c0 + c;
   if (colok && t < K2) {
@@ -669,6 +683,18 @@ k_cols_toep_fs(float2* __restrict__ mid, int ny, int Kx, const float2* __restric
   }
 }
 
+template <int K1, int K2>
+__global__ void __launch_bounds__(8 * K1)
+k_cols_toep_fs(float2* __restrict__ mid, int ny, int Kx, const float2* __restrict__ tw, int tile,
+               const float* __restrict__ T) {
+  __shared__ float2 lds[8 * FS<K1, K2>::CS];
+  // (strip, coil) in XCD order, coil fastest: each XCD sweeps a contiguous
+  // range of strips through all coils, so a strip's slice of T stays in its
+  // L2 across the coils and neighbouring strips share cache lines there
+  const int lin = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  cols_toep_body<K1, K2>(mid, ny, Kx, tw, tile, T, (lin / gridDim.y) * tile, lin % gridDim.y, lds);
+}
+
 // =====================================================================
 // yent[l][e] = scale * w_m * y_l[m] for the sample m of entry e (y given, or
 // the sum of the sample's interpolation partials inside the normal operator)
@@ -716,6 +742,59 @@ void set_lds_limit(const void* fn, size_t bytes) {
   if (bytes > 65536)
     PNP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
+
+// =====================================================================
+// Batched Toeplitz normal operator: for each stage and each grid size, one
+// launch runs the work items of all slices of that size, one workgroup per
+// item: (slice, row, coil group) for the row passes, (slice, strip, coil)
+// for the column pass.  Items are read in XCD order (xcd_order), so each
+// XCD works through a contiguous range of the table, where the items that
+// share data sit together -- the coil groups of one image row, the coils of
+// one strip and its slice of T.  Two alternatives were measured and
+// rejected on gfx950: a switch over sizes inside one kernel, and a
+// persistent loop over items; both raise the register allocation (186-286
+// VGPRs against 113-143 for one item per workgroup) and cost occupancy.
+template <int K1, int K2>
+__global__ void __launch_bounds__(kRowCoils * K1)
+k_batch_rows_fwd(const BatchSlice* __restrict__ sl, const NormalIn* __restrict__ ins,
+                 const int4* __restrict__ items, int n_items) {
+  __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  const int4 w = items[xcd_order(blockIdx.x, n_items)];
+  const BatchSlice& b = sl[w.x];
+  const ImgIn in{ins[w.x].x, ins[w.x].cg};
+  rows_fwd_body<K1, K2>(in, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.mid, w.y, w.z, A);
+}
+
+template <int K1, int K2>
+__global__ void __launch_bounds__(8 * K1)
+k_batch_cols_toep(const BatchSlice* __restrict__ sl, const int4* __restrict__ items, int n_items) {
+  __shared__ float2 lds[8 * FS<K1, K2>::CS];
+  const int4 w = items[xcd_order(blockIdx.x, n_items)];
+  const BatchSlice& b = sl[w.x];
+  cols_toep_body<K1, K2>(b.mid, b.ny, b.K, b.tw, 8, b.T, 8 * w.y, w.z, lds);
+}
+
+template <int K1, int K2>
+__global__ void __launch_bounds__(kRowCoils * K1)
+k_batch_rows_adj(const BatchSlice* __restrict__ sl, const int4* __restrict__ items, int n_items) {
+  __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  const int4 w = items[xcd_order(blockIdx.x, n_items)];
+  const BatchSlice& b = sl[w.x];
+  rows_adj_body<K1, K2>(b.mid, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.part, w.y, w.z, A);
+}
+
+template <int K1, int K2>
+struct BatchLaunch {
+  static void rows_fwd(const BatchSlice* sl, const NormalIn* ins, const int4* items, int n, hipStream_t s) {
+    PNP_LAUNCH((k_batch_rows_fwd<K1, K2>), dim3(n), dim3(kRowCoils * K1), 0, s, sl, ins, items, n);
+  }
+  static void cols_toep(const BatchSlice* sl, const int4* items, int n, hipStream_t s) {
+    PNP_LAUNCH((k_batch_cols_toep<K1, K2>), dim3(n), dim3(8 * K1), 0, s, sl, items, n);
+  }
+  static void rows_adj(const BatchSlice* sl, const int4* items, int n, hipStream_t s) {
+    PNP_LAUNCH((k_batch_rows_adj<K1, K2>), dim3(n), dim3(kRowCoils * K1), 0, s, sl, items, n);
+  }
+};
 
 // ------------------------------------------------- register-path launchers
 template <int K1, int K2>
@@ -916,6 +995,37 @@ void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps,
 }
 
 bool toeplitz_supported(const pnp_plan* p) { return p->ndim == 2 && fs_ok(p); }
+
+bool batch_grid_supported(int K) {
+  return K == 128 || K == 192 || K == 256 || K == 512 || K == 640 || K == 768 || K == 1024;
+}
+
+#define PNP_BATCH_DISPATCH(K, fn, ...)                                   \
+  do {                                                                  \
+    switch (K) {                                                        \
+      case 128: BatchLaunch<16, 8>::fn(__VA_ARGS__); break;             \
+      case 192: BatchLaunch<16, 12>::fn(__VA_ARGS__); break;            \
+      case 256: BatchLaunch<16, 16>::fn(__VA_ARGS__); break;            \
+      case 512: BatchLaunch<32, 16>::fn(__VA_ARGS__); break;            \
+      case 640: BatchLaunch<32, 20>::fn(__VA_ARGS__); break;            \
+      case 768: BatchLaunch<32, 24>::fn(__VA_ARGS__); break;            \
+      case 1024: BatchLaunch<32, 32>::fn(__VA_ARGS__); break;           \
+      default: fail(PNP_ERR_UNSUPPORTED, "batched grid size %d", K);    \
+    }                                                                   \
+  } while (0)
+
+void batch_rows_fwd(int K, const BatchSlice* sl, const NormalIn* ins, const int4* items, int n_items,
+                    hipStream_t s) {
+  if (n_items > 0) PNP_BATCH_DISPATCH(K, rows_fwd, sl, ins, items, n_items, s);
+}
+
+void batch_cols_toep(int K, const BatchSlice* sl, const int4* items, int n_items, hipStream_t s) {
+  if (n_items > 0) PNP_BATCH_DISPATCH(K, cols_toep, sl, items, n_items, s);
+}
+
+void batch_rows_adj(int K, const BatchSlice* sl, const int4* items, int n_items, hipStream_t s) {
+  if (n_items > 0) PNP_BATCH_DISPATCH(K, rows_adj, sl, items, n_items, s);
+}
 
 void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
                           const OpWorkspace& w, hipStream_t s) {

@@ -30,68 +30,10 @@
 
 namespace pnp {
 
-constexpr int kRedBlocks = 256;
-constexpr int kRedThreads = 256;
 constexpr int kMaxOuter = 1024;
 
 
 namespace {
-
-__device__ __forceinline__ double warp_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-
-// Block-reduce Q values into parts[blockIdx.x*Q + q]; the last block to
-// arrive sums all blocks' partials (fixed order) into out[] and returns true
-// (for every thread of that block).
-template <int Q>
-__device__ bool reduce_last(double (&v)[Q], double* __restrict__ parts, unsigned* cnt,
-                            double (&out)[Q]) {
-  __shared__ double sh[Q][kRedThreads / 64];
-  __shared__ double fin[Q][kRedThreads];
-  __shared__ bool last;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const double s = warp_sum(v[q]);
-    if (lane == 0) sh[q][wid] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      double s = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[q][w];
-      parts[blockIdx.x * Q + q] = s;
-    }
-    __threadfence();
-    const unsigned prev = atomicAdd(cnt, 1u);
-    last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  const volatile double* vp = parts;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s += vp[b * Q + q];
-    fin[q][threadIdx.x] = s;
-  }
-  __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) fin[q][threadIdx.x] += fin[q][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) out[q] = fin[q][0];
-  if (threadIdx.x == 0) *cnt = 0u;
-  return true;
-}
 
 __device__ __forceinline__ double re_dot(float2 a, float2 b) {
   return (double)a.x * b.x + (double)a.y * b.y;

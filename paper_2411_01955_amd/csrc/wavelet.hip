@@ -54,15 +54,15 @@ __device__ void haar_step(const float2* __restrict__ src, float2* __restrict__ d
   }
 }
 
-__global__ void k_haar_prior(const float2* __restrict__ in, float2* __restrict__ out, int ndim,
-                             int nx, int ny, int nz, int J, float tau) {
-  extern __shared__ float2 lds[];
+// One 2^J (per axis) block `blk` of the image: analysis, soft threshold
+// of every detail coefficient, synthesis; lds: 2 * 2^(J*ndim) float2.
+__device__ void haar_block(const float2* __restrict__ in, float2* __restrict__ out, int ndim, int nx, int ny,
+                           int J, float tau, int blk, float2* lds) {
   const int B = 1 << J;
   const int total = ndim == 3 ? B * B * B : B * B;
   float2* a = lds;
   float2* b = lds + total;
   const int bx = nx / B, by = ny / B;
-  const int blk = blockIdx.x;
   const int ox = (blk % bx) * B;
   const int oy = ((blk / bx) % by) * B;
   const int oz = ndim == 3 ? (blk / (bx * by)) * B : 0;
@@ -101,6 +101,20 @@ __global__ void k_haar_prior(const float2* __restrict__ in, float2* __restrict__
   }
 }
 
+__global__ void k_haar_prior(const float2* __restrict__ in, float2* __restrict__ out, int ndim,
+                             int nx, int ny, int nz, int J, float tau) {
+  extern __shared__ float2 lds[];
+  haar_block(in, out, ndim, nx, ny, J, tau, blockIdx.x, lds);
+}
+
+// Batched 2D prior: workgroup b belongs to the last slice with block0 <= b.
+__global__ void k_haar_prior_batched(const HaarSlice* __restrict__ sl, int n_slices, int J, float tau) {
+  extern __shared__ float2 lds[];
+  int s = 0;
+  while (s + 1 < n_slices && sl[s + 1].block0 <= (int)blockIdx.x) ++s;
+  haar_block(sl[s].in, sl[s].out, 2, sl[s].nx, sl[s].ny, J, tau, blockIdx.x - sl[s].block0, lds);
+}
+
 }  // namespace
 
 int wavelet_default_levels(int nmin) {
@@ -110,6 +124,13 @@ int wavelet_default_levels(int nmin) {
   if (J > 4) J = 4;
   if (J < 1) J = 1;
   return J;
+}
+
+void wavelet_apply_batched(const HaarSlice* sl, int n_slices, int total_blocks, int levels, float tau,
+                           hipStream_t s) {
+  const int B = 1 << levels;
+  const size_t lds = sizeof(float2) * 2 * B * B;
+  PNP_LAUNCH(k_haar_prior_batched, dim3((unsigned)total_blocks), dim3(256), lds, s, sl, n_slices, levels, tau);
 }
 
 void wavelet_apply(int ndim, const int* n, int levels, float tau, const float2* in, float2* out,
