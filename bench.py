@@ -373,6 +373,7 @@ def main():
     out = torch.empty((n, n), dtype=torch.complex64, device=dev)
     ws, _ = plan.workspace(L, "hqs")
     toep = pnp.Toeplitz(plan, dd)      # transfer function built once per (trajectory, DCF)
+    tuning = plan.autotune(Sd, dd, toeplitz=toep)   # coils per row-pass workgroup, timed on this GPU
 
     def step():
         pnp.hqs_solve(plan, y, Sd, dd, prior, sig, lam, "f1", w.n_cg, opnorm=nrm, out=out, toeplitz=toep)
@@ -481,6 +482,7 @@ def main():
         "gridded_normal_op_us": round(gridded_us, 2),
         "gridded_normal_op_GBps": round(B / (gridded_us * 1e-6) / 1e9, 1),
         "roofline": roofline,
+        "autotune": tuning,
         "psnr_race": race,
         "batched": batched,
         "unet": unet,

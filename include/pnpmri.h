@@ -320,6 +320,29 @@ pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* 
                          int32_t n_out, const pnp_hqs_opts* opts, pnp_c64* x_out,
                          pnp_hqs_report* report, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------ autotuning
+ * The register-FFT row passes of a plan handle 2, 4 or 8 coils per
+ * workgroup (default 4).  pnp_autotune times the normal operator the caller
+ * will run -- Toeplitz when `toeplitz` is given, else the gridded one with
+ * `dcf` -- for each choice on this device, keeps the fastest in the plan and
+ * appends it to the JSON-lines file `cache_path` (NULL: no cache), keyed by
+ * device, image shape, L, M, a hash of the histogram of gridding entries per
+ * column strip, and the operator kind.  A cached key is applied without
+ * timing.  Allocates and frees temporary device memory; waits for `stream`.
+ * Workspaces sized by the query functions fit every choice. */
+typedef struct {
+  uint32_t struct_size;      /* sizeof(pnp_tuning)                            */
+  int32_t row_coils;         /* out: the chosen coils per workgroup           */
+  double time_us[3];         /* out: operator time for 2, 4, 8 (0 if cached)  */
+  int32_t from_cache;        /* out: 1 when the choice came from the cache    */
+} pnp_tuning;
+
+pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const float* dcf,
+                        const pnp_toeplitz* toeplitz, const char* cache_path, pnp_tuning* out,
+                        hipStream_t stream);
+pnp_status pnp_plan_set_row_coils(pnp_plan* plan, int32_t row_coils);
+pnp_status pnp_plan_get_row_coils(const pnp_plan* plan, int32_t* row_coils);
+
 /* ------------------------------------------------------- batched slices
  * Many independent 2D slices (different sizes, coil counts and trajectories)
  * reconstructed together with the same schedule (Sec. 3.3-3.4 per slice).

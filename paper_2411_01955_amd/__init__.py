@@ -23,7 +23,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, UNET_BUF, Slice, UNetLayer, check, load
+from ._lib import HQSOpts, HQSReport, PnPError, PRECOND, UNET_BUF, Slice, Tuning, UNetLayer, check, load
 
 __all__ = ["Plan", "Toeplitz", "WaveletPrior", "UNet", "UNetPrior", "hqs_solve", "PnPError", "load",
            "trace_enable", "trace_read", "unet_layers", "pack_unet_params", "unpack_unet_params",
@@ -170,6 +170,29 @@ class Plan:
         check(load().pnp_normal(self._h, _ptr(x), _ptr(smaps), L, _ptr(dcf), _ptr(o), _ptr(ws), nb,
                                 _stream()))
         return o
+
+    @property
+    def row_coils(self):
+        """Coils per workgroup of the register-FFT row passes (2, 4 or 8)."""
+        v = C.c_int32()
+        check(load().pnp_plan_get_row_coils(self._h, C.byref(v)))
+        return v.value
+
+    @row_coils.setter
+    def row_coils(self, value):
+        check(load().pnp_plan_set_row_coils(self._h, int(value)))
+
+    def autotune(self, smaps, dcf=None, toeplitz=None, cache=None):
+        """Time the normal operator for 2, 4 and 8 coils per row-pass
+        workgroup and keep the fastest; `cache`: JSON-lines file (read and
+        appended).  Returns {row_coils, time_us, from_cache}."""
+        L = self._L(smaps)
+        _need_f32(dcf, "dcf", (self.M,))
+        t = Tuning(C.sizeof(Tuning), 0, (C.c_double * 3)(), 0)
+        check(load().pnp_autotune(self._h, _ptr(smaps), L, _ptr(dcf),
+                                  toeplitz.handle if toeplitz is not None else None,
+                                  cache.encode() if cache else None, C.byref(t), _stream()))
+        return {"row_coils": t.row_coils, "time_us": list(t.time_us), "from_cache": bool(t.from_cache)}
 
     def opnorm(self, smaps, dcf=None, iters=50, seed=0):
         L = self._L(smaps)

@@ -57,6 +57,15 @@ class UNetLayer(C.Structure):
 UNET_BUF = {"params": 0, "grad": 1, "adam_m": 2, "adam_v": 3}
 
 
+class Tuning(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32),
+        ("row_coils", C.c_int32),
+        ("time_us", C.c_double * 3),
+        ("from_cache", C.c_int32),
+    ]
+
+
 class Slice(C.Structure):
     _fields_ = [
         ("plan", C.c_void_p),
@@ -115,6 +124,9 @@ SIGNATURES = {
     "pnp_unet_adam_step": (_i32, [_vp, _dbl, _dbl, _dbl, _dbl, _vp]),
     "pnp_unet_tensor": (_i32, [_i32, _i32, _i32, _i32, _vp, _i32, C.POINTER(_vp), C.POINTER(_i32)]),
     "pnp_prior_unet": (_i32, [C.POINTER(_vp), _vp, _i32, C.POINTER(_i32), _dbl, _vp]),
+    "pnp_autotune": (_i32, [_vp, _vp, _i32, _vp, _vp, C.c_char_p, C.POINTER(Tuning), _vp]),
+    "pnp_plan_set_row_coils": (_i32, [_vp, _i32]),
+    "pnp_plan_get_row_coils": (_i32, [_vp, C.POINTER(_i32)]),
     "pnp_batch_create": (_i32, [C.POINTER(_vp), _i32, C.POINTER(Slice), _vp]),
     "pnp_batch_destroy": (_i32, [_vp]),
     "pnp_batch_normal": (_i32, [_vp, C.POINTER(_vp), C.POINTER(_vp), _vp]),

@@ -222,7 +222,7 @@ pnp_batch* batch_create(int B, const pnp_slice* sl, hipStream_t s) {
       hh.s = x;
       hh.n = p->ax[0].n;
       hh.K = p->ax[0].K;
-      hh.G = op_groups(x.L);
+      hh.G = batch_groups(x.L);
       hh.N = image_size(p);
       const int J = wavelet_default_levels(hh.n);
       if (levels && J != levels) fail(PNP_ERR_UNSUPPORTED, "batched slices need one Haar depth");

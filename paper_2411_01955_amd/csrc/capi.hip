@@ -521,3 +521,32 @@ pnp_status pnp_hqs_solve_batched(pnp_batch* batch, const pnp_prior* prior, const
     if (bad) fail(PNP_ERR_NUMERIC, "CG breakdown in a batched slice");
   });
 }
+
+// ------------------------------------------------------------- autotuning
+pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const float* dcf,
+                        const pnp_toeplitz* toeplitz, const char* cache_path, pnp_tuning* out,
+                        hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(plan, L);
+    need(smaps, "smaps");
+    need(out, "out");
+    if (out->struct_size < sizeof(pnp_tuning)) fail(PNP_ERR_ARG, "out.struct_size too small");
+    if (toeplitz && toeplitz->plan != plan) fail(PNP_ERR_ARG, "toeplitz was built for another plan");
+    autotune(plan, (const float2*)smaps, L, dcf, toeplitz, cache_path, out, stream);
+  });
+}
+
+pnp_status pnp_plan_set_row_coils(pnp_plan* plan, int32_t row_coils) {
+  return guarded([&] {
+    need(plan, "plan");
+    plan_set_row_coils(plan, row_coils);
+  });
+}
+
+pnp_status pnp_plan_get_row_coils(const pnp_plan* plan, int32_t* row_coils) {
+  return guarded([&] {
+    need(plan, "plan");
+    need(row_coils, "row_coils");
+    *row_coils = plan->row_coils;
+  });
+}

@@ -99,6 +99,7 @@ struct pnp_plan {
   int W;                    // kernel width (6)
   double beta;              // Kaiser-Bessel shape
   int tile;                 // tile edge (grid columns) along the tiled axes
+  int row_coils;            // coils per workgroup in the register-FFT row passes (2, 4 or 8)
   int ntx, nty;             // tiles along x and y (nty = 1 in 2D)
   int ntiles;
   int slots;                // max tiles a sample touches (2 in 2D, 4 in 3D)
@@ -161,7 +162,7 @@ void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, c
 
 // Normal operator as used inside the solver: the input is x, or (when r is
 // given) the CG direction p' = r + (*beta) x, which is also stored to pnew;
-// the result is left as op_groups(L) partial images in w.part ([G][N],
+// the result is left as op_groups(p, L) partial images in w.part ([G][N],
 // summed by the consumer).
 // Input of the normal operator: the image x, or (cg.r != nullptr) the
 // Chronopoulos-Gear CG update, formed per pixel by the operator's first pass:
@@ -178,7 +179,13 @@ struct NormalIn {
   CGUpdate cg;
 };
 inline NormalIn plain_input(const float2* x) { return NormalIn{x, CGUpdate{}}; }
-int op_groups(int L);
+// Coil groups of the row passes: partial images left in w.part by the
+// adjoint and normal operators (ceil(L / coils per workgroup)).
+int op_groups(const pnp_plan* p, int L);
+// Largest group count any tuning can produce (workspace sizing).
+int op_groups_max(int L);
+// Coil groups of the batched operator (fixed four coils per workgroup).
+int batch_groups(int L);
 
 // ------------------------------------------------ batched Toeplitz operator
 // One slice of a batched Toeplitz normal operator (device table entry).
@@ -251,6 +258,11 @@ void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, 
                    void* ws, hipStream_t s);
 void unet_adam(pnp_unet* net, double lr, double b1, double b2, double eps, hipStream_t s);
 void unet_tensor(int B, int H, int W, bool train, void* ws, int id, void** ptr, int32_t dims[4]);
+// autotuning
+void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const pnp_toeplitz* tp,
+              const char* cache_path, pnp_tuning* out, hipStream_t s);
+void plan_set_row_coils(pnp_plan* p, int rc);
+
 // batched slices
 pnp_batch* batch_create(int B, const pnp_slice* sl, hipStream_t s);
 void batch_destroy(pnp_batch* b);

@@ -32,7 +32,8 @@ namespace pnp {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowCoils = 4;      // coils per workgroup in the row passes
+constexpr int kRowCoils = 4;      // coils per workgroup in the generic row passes and the batch
+constexpr int kMaxRowCoils = 8;   // register-FFT row passes: 2, 4 or 8 coils (tunable per plan)
 
 __device__ __forceinline__ int img_of_grid(int j, int n, int K) {
   // grid index j -> image index i (or -1 when j is in the zero padding)
@@ -312,17 +313,18 @@ __device__ __forceinline__ void fs_twiddle(float2 (&v)[K1], int t, const float2*
 }
 
 // Row pass of the forward operator for image row iy and coil group g
-// (kRowCoils coils, one line of K1 threads each); A: kRowCoils * LA float2
-// of LDS.  Shared by the single-slice and the batched kernels.
+// (blockDim / K1 coils, one line of K1 threads each); A: one LA block of
+// float2 LDS per coil.  Shared by the single-slice and the batched kernels.
 template <int K1, int K2>
 __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __restrict__ S, int L, int nx,
                                               int ny, const float* __restrict__ dax,
                                               const float* __restrict__ day, const float2* __restrict__ tw,
                                               float2* __restrict__ mid, int iy, int g, float2* A) {
   using F = FS<K1, K2>;
+  const int rc = blockDim.x / K1;
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
-  const int l = g * kRowCoils + line;
+  const int l = g * rc + line;
   const bool active = l < L;
   const long long N = (long long)nx * ny;
   float2* Al = A + line * F::LA;
@@ -357,11 +359,11 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
 }
 
 template <int K1, int K2>
-__global__ void __launch_bounds__(kRowCoils * K1)
+__global__ void __launch_bounds__(kMaxRowCoils * K1)
 k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
               const float* __restrict__ dax, const float* __restrict__ day,
               const float2* __restrict__ tw, float2* __restrict__ mid) {
-  __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  extern __shared__ float2 A[];
   rows_fwd_body<K1, K2>(in, S, L, nx, ny, dax, day, tw, mid, blockIdx.x, blockIdx.y, A);
 }
 
@@ -554,17 +556,18 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
 }
 
 // Row pass of the adjoint for image row iy and coil group g: inverse row
-// FFT, crop, deapodisation, conj(S_l) and the sum over the group's coils
-// into part[g]; A: kRowCoils * LA float2 of LDS.
+// FFT, crop, deapodisation, conj(S_l) and the sum over the group's
+// blockDim / K1 coils into part[g]; A: one LA block of float2 LDS per coil.
 template <int K1, int K2>
 __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, const float2* __restrict__ S, int L,
                                               int nx, int ny, const float* __restrict__ dax,
                                               const float* __restrict__ day, const float2* __restrict__ tw,
                                               float2* __restrict__ part, int iy, int g, float2* A) {
   using F = FS<K1, K2>;
+  const int rc = blockDim.x / K1;
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
-  const int l = g * kRowCoils + line;
+  const int l = g * rc + line;
   const bool active = l < L;
   const long long N = (long long)nx * ny;
   float2* Al = A + line * F::LA;
@@ -597,7 +600,7 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
     }
   }
   __syncthreads();
-  const int nl = min(kRowCoils, L - g * kRowCoils);
+  const int nl = min(rc, L - g * rc);
   const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
   for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
     float2 acc = Z[ix];
@@ -607,11 +610,11 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
 }
 
 template <int K1, int K2>
-__global__ void __launch_bounds__(kRowCoils * K1)
+__global__ void __launch_bounds__(kMaxRowCoils * K1)
 k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
               const float* __restrict__ dax, const float* __restrict__ day,
               const float2* __restrict__ tw, float2* __restrict__ part) {
-  __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  extern __shared__ float2 A[];
   rows_adj_body<K1, K2>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
 }
 
@@ -799,10 +802,16 @@ struct BatchLaunch {
 // ------------------------------------------------- register-path launchers
 template <int K1, int K2>
 struct FSLaunch {
+  static size_t row_lds(const pnp_plan* p) {
+    const size_t b = sizeof(float2) * p->row_coils * FS<K1, K2>::LA;
+    set_lds_limit((const void*)k_rows_fwd_fs<K1, K2>, b);
+    set_lds_limit((const void*)k_rows_adj_fs<K1, K2>, b);
+    return b;
+  }
   static void rows_fwd(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
                        hipStream_t s) {
-    const int G = (L + kRowCoils - 1) / kRowCoils;
-    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, in, S, L,
+    const int rc = p->row_coils, G = (L + rc - 1) / rc;
+    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, in, S, L,
                p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, mid);
   }
   static void cols_fwd(const pnp_plan* p, int L, const float2* mid, float2* ypart, hipStream_t s) {
@@ -817,15 +826,15 @@ struct FSLaunch {
   }
   static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                        hipStream_t s) {
-    const int G = (L + kRowCoils - 1) / kRowCoils;
-    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, mid, S, L,
+    const int rc = p->row_coils, G = (L + rc - 1) / rc;
+    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, mid, S, L,
                p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, part);
   }
   // Toeplitz variants: no deapodisation, column pass = FFT * T * IFFT
   static void rows_fwd_toep(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
                             hipStream_t s) {
-    const int G = (L + kRowCoils - 1) / kRowCoils;
-    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, in, S, L,
+    const int rc = p->row_coils, G = (L + rc - 1) / rc;
+    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, in, S, L,
                p->ax[0].n, p->ax[1].n, (const float*)nullptr, (const float*)nullptr, p->ax[0].fft.tw,
                mid);
   }
@@ -835,8 +844,8 @@ struct FSLaunch {
   }
   static void rows_adj_toep(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                             hipStream_t s) {
-    const int G = (L + kRowCoils - 1) / kRowCoils;
-    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(kRowCoils * K1), 0, s, mid, S, L,
+    const int rc = p->row_coils, G = (L + rc - 1) / rc;
+    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, mid, S, L,
                p->ax[0].n, p->ax[1].n, (const float*)nullptr, (const float*)nullptr, p->ax[0].fft.tw,
                part);
   }
@@ -863,12 +872,17 @@ bool fs_ok(const pnp_plan* p) {
 
 }  // namespace
 
-int op_groups(int L) { return (L + kRowCoils - 1) / kRowCoils; }
+int op_groups(const pnp_plan* p, int L) {
+  const int rc = fs_ok(p) ? p->row_coils : kRowCoils;
+  return (L + rc - 1) / rc;
+}
+int op_groups_max(int L) { return (L + 1) / 2; }
+int batch_groups(int L) { return (L + kRowCoils - 1) / kRowCoils; }
 
 size_t op_workspace_bytes(const pnp_plan* p, int L) {
   const int Kx = p->ax[0].K;
   const int64_t N = image_size(p);
-  const int G = op_groups(L);
+  const int G = std::max(op_groups_max(L), op_groups(p, L));
   size_t b = 0;
   b += al(sizeof(float2) * (size_t)L * p->ax[1].n * Kx);   // mid
   b += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));  // ypart
@@ -882,7 +896,7 @@ OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws) {
   OpWorkspace w;
   const int Kx = p->ax[0].K;
   const int64_t N = image_size(p);
-  const int G = op_groups(L);
+  const int G = std::max(op_groups_max(L), op_groups(p, L));
   char* c = (char*)ws;
   w.mid = (float2*)c;
   c += al(sizeof(float2) * (size_t)L * p->ax[1].n * Kx);
@@ -914,7 +928,7 @@ static void forward_to_partials(const pnp_plan* p, const ImgIn& in, const float2
     PNP_FS_DISPATCH(p->ax[1].K, cols_fwd, p, L, w.mid, w.ypart, s);
     return;
   }
-  const int G = op_groups(L);
+  const int G = op_groups(p, L);
   check_lds(p);
   {
     const size_t lds = rows_lds(Kx);
@@ -936,7 +950,7 @@ static void adjoint_to_groups(const pnp_plan* p, const KIn& kin, const float2* s
                               const float* dcf, float scale, float2* dst, const OpWorkspace& w,
                               hipStream_t s) {
   const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
-  const int G = op_groups(L);
+  const int G = op_groups(p, L);
   // weighted k-space values in entry order (coalesced staging in the spread)
   {
     const long long tot = (long long)L * p->E;
@@ -975,7 +989,7 @@ void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, 
 
 void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf,
                 float2* x, const OpWorkspace& w, hipStream_t s) {
-  const int G = op_groups(L);
+  const int G = op_groups(p, L);
   const int64_t N = image_size(p);
   const float scale = (float)(1.0 / std::sqrt((double)N));
   float2* dst = G == 1 ? x : w.part;
@@ -1039,7 +1053,7 @@ void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const floa
 void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps, int L, float2* out,
                     const OpWorkspace& w, hipStream_t s) {
   op_normal_toep_parts(tp, plain_input(x), smaps, L, w, s);
-  const int G = op_groups(L);
+  const int G = op_groups(tp->plan, L);
   const int64_t N = image_size(tp->plan);
   PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
              (long long)N, out);
@@ -1048,7 +1062,7 @@ void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps
 void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,
                float2* out, const OpWorkspace& w, hipStream_t s) {
   op_normal_parts(p, plain_input(x), smaps, L, dcf, w, s);
-  const int G = op_groups(L);
+  const int G = op_groups(p, L);
   const int64_t N = image_size(p);
   PNP_LAUNCH(k_sum_groups, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, w.part, G,
              (long long)N, out);

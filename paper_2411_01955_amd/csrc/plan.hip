@@ -319,6 +319,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     }
     if (ndim == 3) fail(PNP_ERR_UNSUPPORTED, "3D plans are not available in this build");
     p->tile = choose_tile(p->ax[0].K);
+    p->row_coils = 4;
     if (ndim == 3 && choose_tile(p->ax[1].K) != p->tile)
       fail(PNP_ERR_SHAPE, "3D x and y grids need a common tile size");
     if (p->tile == 0) fail(PNP_ERR_SHAPE, "no tile size divides grid size %d", p->ax[0].K);

@@ -255,7 +255,7 @@ double power_iteration(const pnp_plan* p, const pnp_toeplitz* tp, const float2* 
                        const float* dcf, int iters, uint64_t seed, void* ws, hipStream_t s) {
   SolverWs w = solver_ws(p, L, ws);
   const long long N = image_size(p);
-  const int G = op_groups(L);
+  const int G = op_groups(p, L);
   const unsigned nb = vec_blocks(N);
   float2* v = w.u[0];
   PNP_LAUNCH(k_init_scalars, dim3(1), dim3(64), 0, s, w.sc);
@@ -303,7 +303,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   if (a.n_out > kMaxOuter) fail(PNP_ERR_SHAPE, "n_out %d exceeds %d", a.n_out, kMaxOuter);
   SolverWs w = solver_ws(p, a.L, ws);
   const long long N = image_size(p);
-  const int G = op_groups(a.L);
+  const int G = op_groups(p, a.L);
   const unsigned nb = vec_blocks(N);
   static const double c0s[3] = {1.0, 2.0, 4.0};
   static const double c1s[3] = {0.0, 1.0, 10.0 / 3.0};

@@ -1,0 +1,155 @@
+// Autotuner for a plan's launch shape, with a JSON-lines cache.
+//
+// The tuned parameter is the number of coils a workgroup of the
+// register-FFT row passes handles (2, 4 or 8): it sets the workgroup count,
+// the threads and LDS per workgroup, and how often an image row and its
+// coil maps are read, and the best value depends on the grid size, the coil
+// count and the device.  Each candidate is timed on the normal operator the
+// caller will run (Toeplitz when a handle is given, else gridded), with HIP
+// events over repeated launches after warm-up; the fastest is kept in the
+// plan.  Results are cached by (image shape, coils, samples, a hash of the
+// histogram of gridding entries per column strip, operator kind, device).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pnp {
+
+namespace {
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string tune_key(const pnp_plan* p, int L, bool toeplitz, hipStream_t s) {
+  std::vector<int32_t> off(p->ntiles + 1);
+  PNP_HIP(hipMemcpyAsync(off.data(), p->tile_off, sizeof(int32_t) * off.size(), hipMemcpyDeviceToHost, s));
+  PNP_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> hist(p->ntiles);
+  for (int t = 0; t < p->ntiles; ++t) hist[t] = off[t + 1] - off[t];
+  hipDeviceProp_t prop;
+  int dev = 0;
+  PNP_HIP(hipGetDevice(&dev));
+  PNP_HIP(hipGetDeviceProperties(&prop, dev));
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s|n=%dx%d|L=%d|M=%lld|hist=%016llx|op=%s", prop.gcnArchName, p->ax[1].n,
+           p->ax[0].n, L, (long long)p->M, (unsigned long long)fnv1a(hist.data(), hist.size() * 4),
+           toeplitz ? "toeplitz" : "gridded");
+  return buf;
+}
+
+// the cached row_coils of `key` (0 when absent)
+int cache_lookup(const char* path, const std::string& key) {
+  if (!path) return 0;
+  std::ifstream f(path);
+  std::string line;
+  const std::string want = "\"key\": \"" + key + "\"";
+  int found = 0;
+  while (std::getline(f, line)) {
+    if (line.find(want) == std::string::npos) continue;
+    const size_t at = line.find("\"row_coils\": ");
+    if (at == std::string::npos) continue;
+    const int rc = std::atoi(line.c_str() + at + 13);
+    if (rc == 2 || rc == 4 || rc == 8) found = rc;   // the last entry wins
+  }
+  return found;
+}
+
+void cache_append(const char* path, const std::string& key, int rc, const double* us) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  if (!f) fail(PNP_ERR_ARG, "cannot write the tuning cache %s", path);
+  f << "{\"key\": \"" << key << "\", \"row_coils\": " << rc << ", \"us\": [" << us[0] << ", " << us[1] << ", "
+    << us[2] << "]}\n";
+}
+
+}  // namespace
+
+static const int kCandidates[3] = {2, 4, 8};
+
+void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const pnp_toeplitz* tp,
+              const char* cache_path, pnp_tuning* out, hipStream_t s) {
+  if (p->ndim != 2) fail(PNP_ERR_UNSUPPORTED, "autotuning covers 2D plans");
+  const std::string key = tune_key(p, L, tp != nullptr, s);
+  out->row_coils = 0;
+  for (double& t : out->time_us) t = 0.0;
+  out->from_cache = 0;
+  if (const int rc = cache_lookup(cache_path, key)) {
+    p->row_coils = rc;
+    out->row_coils = rc;
+    out->from_cache = 1;
+    return;
+  }
+  const long long N = image_size(p);
+  void *x = nullptr, *o = nullptr, *ws = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  const int keep = p->row_coils;
+  auto release = [&] {
+    if (x) (void)hipFree(x);
+    if (o) (void)hipFree(o);
+    if (ws) (void)hipFree(ws);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  };
+  try {
+    const size_t wb = op_workspace_bytes(p, L);
+    PNP_HIP(hipMalloc(&x, sizeof(float2) * N));
+    PNP_HIP(hipMalloc(&o, sizeof(float2) * N));
+    PNP_HIP(hipMalloc(&ws, wb));
+    PNP_HIP(hipMemsetAsync(x, 0, sizeof(float2) * N, s));
+    PNP_HIP(hipEventCreate(&a));
+    PNP_HIP(hipEventCreate(&b));
+    const OpWorkspace w = op_workspace(p, L, ws);
+    auto run = [&] {
+      if (tp)
+        op_normal_toep(tp, (const float2*)x, smaps, L, (float2*)o, w, s);
+      else
+        op_normal(p, (const float2*)x, smaps, L, dcf, (float2*)o, w, s);
+    };
+    double best = 0.0;
+    int best_rc = keep;
+    for (int c = 0; c < 3; ++c) {
+      p->row_coils = kCandidates[c];
+      for (int r = 0; r < 3; ++r) run();
+      const int reps = 20;
+      PNP_HIP(hipEventRecord(a, s));
+      for (int r = 0; r < reps; ++r) run();
+      PNP_HIP(hipEventRecord(b, s));
+      PNP_HIP(hipEventSynchronize(b));
+      float ms = 0.f;
+      PNP_HIP(hipEventElapsedTime(&ms, a, b));
+      out->time_us[c] = 1e3 * ms / reps;
+      if (c == 0 || out->time_us[c] < best) {
+        best = out->time_us[c];
+        best_rc = kCandidates[c];
+      }
+    }
+    p->row_coils = best_rc;
+    out->row_coils = best_rc;
+    release();
+  } catch (...) {
+    p->row_coils = keep;
+    release();
+    throw;
+  }
+  cache_append(cache_path, key, out->row_coils, out->time_us);
+}
+
+void plan_set_row_coils(pnp_plan* p, int rc) {
+  if (rc != 2 && rc != 4 && rc != 8) fail(PNP_ERR_ARG, "row_coils must be 2, 4 or 8");
+  p->row_coils = rc;
+}
+
+}  // namespace pnp

@@ -1,0 +1,90 @@
+"""Autotuned launch shape: the operators agree with the oracle for every
+coils-per-workgroup choice (2, 4, 8), and the tuner picks one, records it in
+its JSON-lines cache and reapplies it from there without timing."""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ndft
+from tests.gpu_util import rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pnp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_01955_amd as pnp
+    pnp.load()
+    return pnp
+
+
+@pytest.mark.parametrize("rc", [2, 4, 8])
+def test_operators_match_oracle_for_every_row_coils(pnp, rc):
+    w = synth.config_tiny()
+    x, _ = synth.phantom2d(w.n, 5)
+    S = synth.smaps2d(w.n, 6)                # 6 coils: a ragged last group for 4 and 8
+    k = w.traj.k
+    dcf = np.random.default_rng(7).uniform(0.5, 1.5, k.shape[0]).astype(np.float32)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    plan.row_coils = rc
+    assert plan.row_coils == rc
+    xd, Sd, dd = to_dev(x), to_dev(S), to_dev(dcf)
+    ref = ndft.normal(x, S, k, dcf)
+    e_g = rel_l2(to_np(plan.normal(xd, Sd, dd)), ref)
+    e_t = rel_l2(to_np(pnp.Toeplitz(plan, dd).normal(xd, Sd)), ref)
+    y = synth.white_complex((6, k.shape[0]), 8)
+    e_a = rel_l2(to_np(plan.adjoint(to_dev(y), Sd, dd)), ndft.adjoint(y, S, k, dcf))
+    say(f"[tune] row_coils={rc}: gridded {e_g:.2e} toeplitz {e_t:.2e} adjoint {e_a:.2e}")
+    assert max(e_g, e_a) < 2e-5 and e_t < 2e-6
+
+
+def test_autotune_and_cache(pnp, tmp_path):
+    w = synth.config_clinical()
+    S = to_dev(synth.smaps2d(w.n, w.L))
+    dcf = to_dev(synth.voronoi_dcf(w.traj, w.n))
+    cache = str(tmp_path / "tune.jsonl")
+    plan = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    tp = pnp.Toeplitz(plan, dcf)
+    r1 = plan.autotune(S, dcf, toeplitz=tp, cache=cache)
+    say(f"[tune] clinical Toeplitz: {r1}")
+    assert r1["row_coils"] in (2, 4, 8) and not r1["from_cache"]
+    assert all(t > 0 for t in r1["time_us"])
+    assert plan.row_coils == r1["row_coils"]
+    assert r1["time_us"][(2, 4, 8).index(r1["row_coils"])] == min(r1["time_us"])
+    lines = [json.loads(l) for l in open(cache)]
+    assert len(lines) == 1 and lines[0]["row_coils"] == r1["row_coils"]
+    # a second plan on the same trajectory takes the cached choice
+    plan2 = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    plan2.row_coils = 2 if r1["row_coils"] != 2 else 8
+    r2 = plan2.autotune(S, dcf, toeplitz=pnp.Toeplitz(plan2, dcf), cache=cache)
+    assert r2["from_cache"] and r2["row_coils"] == r1["row_coils"] == plan2.row_coils
+    # the gridded operator is a different key
+    r3 = plan2.autotune(S, dcf, cache=cache)
+    assert not r3["from_cache"]
+    assert len(open(cache).readlines()) == 2
+
+
+def test_tuned_plan_gives_the_same_hqs(pnp):
+    w = synth.config_clinical()
+    x, _ = synth.phantom2d(w.n, 9)
+    S = synth.smaps2d(w.n, w.L)
+    dcf = synth.voronoi_dcf(w.traj, w.n)
+    plan = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    Sd, dd = to_dev(S), to_dev(dcf)
+    y = plan.forward(to_dev(x), Sd)
+    tp = pnp.Toeplitz(plan, dd)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)[:3]
+    outs = {}
+    for rc in (2, 4, 8):
+        plan.row_coils = rc
+        xr, _ = pnp.hqs_solve(plan, y, Sd, dd, pnp.WaveletPrior(0, 0.75), sig, 1e4 / 17.45, "f1", 5,
+                              opnorm=17.45, toeplitz=tp)
+        outs[rc] = to_np(xr)
+    e = max(rel_l2(outs[2], outs[4]), rel_l2(outs[8], outs[4]))
+    say(f"[tune] HQS with 2/4/8 coils per workgroup: max rel difference {e:.2e}")
+    assert e < 1e-5
