@@ -31,6 +31,9 @@ Printed JSON line:
              normal operator (one persistent launch per stage) against the
              sum of the slices' B_alg, and batched HQS (30 outer x 5 CG) in
              slices/s next to the same slices solved one after another;
+* ``volume_3d`` the 128^3 / 32-coil / 4,096 x 256 kooshball volume: the 3D
+             Toeplitz normal operator against B_alg, and HQS (20 outer x 5 CG)
+             with the wavelet prior and with the UNet applied slice by slice;
 * ``unet``   the denoiser's forward (320x320, batch 1 and 24) and training
              step (batch 10 x 128x128, forward + backward + Adam) in TFLOP/s
              and as a fraction of the 2.5 PFLOP/s dense BF16 MFMA peak.
@@ -251,6 +254,58 @@ def batched_c4(pnp, torch, reps=10):
             "hqs_learned_slices_per_s": round(len(slices) / t_lrn, 1)}
 
 
+def volume_3d(pnp, torch, n_out=None):
+    """The 128^3 / 32-coil / 4,096 x 256 kooshball workload: Toeplitz normal
+    operator against its B_alg, and one annealed HQS volume (wavelet prior,
+    and the UNet applied slice by slice) -- data from the GPU forward operator."""
+    import synth
+    w = synth.config_3d()
+    n, L = w.n, w.L
+    k = w.traj.k
+    M = k.shape[0]
+    x, _ = synth.phantom3d(n, synth.SEED_PHANTOM)
+    S = synth.smaps3d(n, L)
+    dcf = synth.radial3d_dcf(w.traj, n)
+    plan = pnp.Plan(torch.from_numpy(k).cuda(), (n, n, n))
+    Sd, dd = torch.from_numpy(S).cuda(), torch.from_numpy(dcf).cuda()
+    xd = torch.from_numpy(x).cuda()
+    y = plan.forward(xd, Sd)
+    y += torch.from_numpy(synth.complex_noise((L, M), synth.noise_variance(x, S), synth.SEED_NOISE)).cuda()
+    toep = pnp.Toeplitz(plan, dd)
+    nrm = plan.opnorm(Sd, dd, iters=30, seed=1)
+    out = torch.empty_like(xd)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+
+    B = b_alg_normal(n, L, M, d=3)
+    t_op = timed(lambda: toep.normal(xd, Sd, out=out), 5)
+    n_out = n_out or w.n_out
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)[:n_out]
+    lam = LAM_TIMES_NORM / nrm
+    wav = pnp.WaveletPrior(0, KAPPA)
+    t_hqs = timed(lambda: pnp.hqs_solve(plan, y, Sd, dd, wav, sig, lam, "f1", w.n_cg, opnorm=nrm, out=out,
+                                        toeplitz=toep), 1)
+    lrn = pnp.UNetPrior(pnp.trained_unet(), (n, n, n), KAPPA_UNET, fallback=wav)
+    t_lrn = timed(lambda: pnp.hqs_solve(plan, y, Sd, dd, lrn, sig, lam, "f1", w.n_cg, opnorm=nrm, out=out,
+                                        toeplitz=toep, rise_tol=RISE_TOL), 1)
+    n_ops = n_out * (1 + w.n_cg)
+    return {"workload": w.name, "b_alg_bytes_per_normal_op": B, "toeplitz_normal_op_ms": round(t_op * 1e3, 3),
+            "toeplitz_normal_op_GBps": round(B / t_op / 1e9, 1),
+            "toeplitz_normal_op_frac_of_hbm": round(B / t_op / 1e9 / HBM_PEAK_GBPS, 4),
+            "hqs_outer": n_out, "hqs_wavelet_s_per_volume": round(t_hqs, 3),
+            "hqs_wavelet_GBps": round(n_ops * B / t_hqs / 1e9, 1),
+            "hqs_learned_slicewise_s_per_volume": round(t_lrn, 3)}
+
+
 def unet_rates(pnp, torch):
     """Forward and training-step throughput of the denoiser (inputs resident)."""
     import synth
@@ -336,6 +391,7 @@ def main():
     ap.add_argument("--psnr-slices", type=int, default=24,
                     help="held-out phantoms of the learned-vs-wavelet PSNR race (0: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
@@ -453,6 +509,7 @@ def main():
     race = psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.psnr_slices) if args.psnr_slices > 0 else None
     unet = unet_rates(pnp, torch)
     batched = None if args.no_batched else batched_c4(pnp, torch)
+    vol3d = None if args.no_3d else volume_3d(pnp, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -485,6 +542,7 @@ def main():
         "autotune": tuning,
         "psnr_race": race,
         "batched": batched,
+        "volume_3d": vol3d,
         "unet": unet,
         "kernels": kernel_table,
         "cpu_baseline": cpu,

@@ -324,7 +324,9 @@ pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* 
  * The register-FFT row passes of a plan handle 2, 4 or 8 coils per
  * workgroup (default 4).  pnp_autotune times the normal operator the caller
  * will run -- Toeplitz when `toeplitz` is given, else the gridded one with
- * `dcf` -- for each choice on this device, keeps the fastest in the plan and
+ * `dcf` -- for each choice on this device (after a warm-up, in interleaved
+ * rounds), keeps the fastest in the plan (the default 4 unless another is
+ * more than 2% faster) and
  * appends it to the JSON-lines file `cache_path` (NULL: no cache), keyed by
  * device, image shape, L, M, a hash of the histogram of gridding entries per
  * column strip, and the operator kind.  A cached key is applied without

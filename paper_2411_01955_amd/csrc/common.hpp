@@ -109,6 +109,7 @@ struct pnp_plan {
   // device arrays (inside one allocation `block`)
   int4* j0;                 // [M] wrapped first tap index per axis (x, y, z)
   float* wts;               // [M][ndim][W] kernel weights phi(g - j) / I0(beta)
+  float* deapod_yz;         // 3D: [nz][ny] deapodisation of the (z, y) image rows
   int32_t* tile_off;        // [ntiles + 1]
   int32_t* row_start;       // [ntiles][K_last + 1] first entry per first-tap row
   int32_t* ent_sample;      // [E] sample of each entry, grouped by tile
@@ -148,6 +149,8 @@ struct OpWorkspace {
   float2* ytmp;    // [L][M]         k-space scratch for the normal operator
   float2* yent;    // [L][E]         weighted k-space values in entry order
   float2* part;    // [G][N]         per-coil-group partial images
+  float2* g2;      // 3D: [L][nz][Ky][Kx] after the y pass
+  float2* grid;    // 3D: [L][Kz][Ky][Kx] full oversampled grid
   size_t bytes;
 };
 size_t op_workspace_bytes(const pnp_plan* p, int L);
@@ -258,6 +261,21 @@ void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, 
                    void* ws, hipStream_t s);
 void unet_adam(pnp_unet* net, double lr, double b1, double b2, double eps, hipStream_t s);
 void unet_tensor(int B, int H, int W, bool train, void* ws, int id, void** ptr, int32_t dims[4]);
+// 3D operator (register-FFT grid sizes on every axis)
+bool plan3_supported(const pnp_plan* p);
+int op3_groups(int L);
+size_t op3_workspace_bytes(const pnp_plan* p, int L);
+OpWorkspace op3_workspace(const pnp_plan* p, int L, void* ws);
+void op3_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y, const OpWorkspace& w,
+                 hipStream_t s);
+void op3_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf, float2* x,
+                 const OpWorkspace& w, hipStream_t s);
+void op3_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L, const float* dcf,
+                      const OpWorkspace& w, hipStream_t s);
+void op3_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
+                           const OpWorkspace& w, hipStream_t s);
+pnp_toeplitz* toeplitz3_create(const pnp_plan* p, const float* dcf, hipStream_t s);
+
 // autotuning
 void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const pnp_toeplitz* tp,
               const char* cache_path, pnp_tuning* out, hipStream_t s);

@@ -25,6 +25,7 @@
 #include "common.hpp"
 #include "fft_lds.hpp"
 #include "fft_reg.hpp"
+#include "fs_bodies.hpp"
 #include "trace.hpp"
 
 namespace pnp {
@@ -33,53 +34,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRowCoils = 4;      // coils per workgroup in the generic row passes and the batch
-constexpr int kMaxRowCoils = 8;   // register-FFT row passes: 2, 4 or 8 coils (tunable per plan)
-
-__device__ __forceinline__ int img_of_grid(int j, int n, int K) {
-  // grid index j -> image index i (or -1 when j is in the zero padding)
-  const int h = n >> 1;
-  if (j < h) return j + h;
-  if (j >= K - h) return j - (K - h);
-  return -1;
-}
-
-__device__ __forceinline__ int grid_of_img(int i, int n, int K) {
-  const int r = i - (n >> 1);
-  return r < 0 ? r + K : r;
-}
-
-// Image input of the forward row pass: the image x, or -- inside CG -- the
-// direction update p' = r + beta p computed on the fly (x = p, beta read
-// from the device scalars); the workgroups of coil group 0 store p'.
-struct ImgIn {
-  const float2* x;
-  CGUpdate cg;   // cg.r == nullptr: plain image input
-};
-
-struct ImgScal {
-  float alpha, beta;
-};
-__device__ __forceinline__ ImgScal img_scal(const ImgIn& in) {
-  return in.cg.r ? ImgScal{(float)*in.cg.alpha, (float)*in.cg.beta} : ImgScal{0.f, 0.f};
-}
-__device__ __forceinline__ float2 img_at(const ImgIn& in, long long pix, ImgScal sc, bool store) {
-  if (!in.cg.r) return in.x[pix];
-  // every reader needs r' = r - alpha (w + beta s); the storing workgroup
-  // also forms and writes p', s', u'
-  const CGUpdate& c = in.cg;
-  const float2 rv = c.r[pix], sv = c.s[pix], wv = c.w[pix];
-  const float2 sn = make_float2(fmaf(sc.beta, sv.x, wv.x), fmaf(sc.beta, sv.y, wv.y));
-  const float2 rn = make_float2(fmaf(-sc.alpha, sn.x, rv.x), fmaf(-sc.alpha, sn.y, rv.y));
-  if (store) {
-    const float2 pv = c.p[pix], uv = c.u[pix];
-    const float2 pn = make_float2(fmaf(sc.beta, pv.x, rv.x), fmaf(sc.beta, pv.y, rv.y));
-    c.p2[pix] = pn;
-    c.s2[pix] = sn;
-    c.u2[pix] = make_float2(fmaf(sc.alpha, pn.x, uv.x), fmaf(sc.alpha, pn.y, uv.y));
-    c.r2[pix] = rn;
-  }
-  return rn;
-}
 
 // k-space input of the adjoint column pass: y[l][m], or -- inside the
 // normal operator -- the sum of the sample's interpolation partials.
@@ -292,79 +246,19 @@ k_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L, 
 // =====================================================================
 // Register path: four-step transforms, K = K1*K2
 // =====================================================================
+// RC coils per workgroup (static LDS; RC = 8 only where it fits in 64 KB)
 template <int K1, int K2>
-struct FS {
-  static constexpr int K = K1 * K2;
-  static constexpr int AS = K2 + 1;                 // LDS row stride of the transpose
-  static constexpr int LA = K1 * AS;                // one line's transpose block
-  static constexpr int CS = ((LA + 13) / 16) * 16 + 2;   // column stride, = 2 mod 16
-  static constexpr int GS = ((K + 13) / 16) * 16 + 2;    // grid column stride, = 2 mod 16
-  static constexpr int CSTR = CS > GS ? CS : GS;         // strip LDS per column
-};
-
-template <int K1, int K2, bool INV>
-__device__ __forceinline__ void fs_twiddle(float2 (&v)[K1], int t, const float2* __restrict__ tw) {
-#pragma unroll
-  for (int k1 = 1; k1 < K1; ++k1) {
-    float2 w = tw[t * k1];
-    if (INV) w.y = -w.y;
-    v[k1] = cmul(v[k1], w);
-  }
+constexpr int fit_rc(int rc) {
+  return (size_t)rc * FS<K1, K2>::LA * sizeof(float2) <= 65536 ? rc : 4;
 }
 
-// Row pass of the forward operator for image row iy and coil group g
-// (blockDim / K1 coils, one line of K1 threads each); A: one LA block of
-// float2 LDS per coil.  Shared by the single-slice and the batched kernels.
-template <int K1, int K2>
-__device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __restrict__ S, int L, int nx,
-                                              int ny, const float* __restrict__ dax,
-                                              const float* __restrict__ day, const float2* __restrict__ tw,
-                                              float2* __restrict__ mid, int iy, int g, float2* A) {
-  using F = FS<K1, K2>;
-  const int rc = blockDim.x / K1;
-  const int line = threadIdx.x / K1;
-  const int t = threadIdx.x % K1;
-  const int l = g * rc + line;
-  const bool active = l < L;
-  const long long N = (long long)nx * ny;
-  float2* Al = A + line * F::LA;
-  if (active && t < K2) {
-    float2 v[K1];
-    const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
-    const ImgScal bt = img_scal(in);
-    const bool store = line == 0 && g == 0;
-    const float2* Sl = S + (long long)l * N + (long long)iy * nx;
-    const long long row0 = (long long)iy * nx;
-#pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) {
-      const int ix = img_of_grid(n1 * K2 + t, nx, F::K);
-      v[n1] = ix >= 0 ? cscale(cmul(Sl[ix], img_at(in, row0 + ix, bt, store)), (dax ? dax[ix] : 1.f) * sy)
-                      : make_float2(0.f, 0.f);
-    }
-    reg::dft<K1, false>(v);
-    fs_twiddle<K1, K2, false>(v, t, tw);
-#pragma unroll
-    for (int k1 = 0; k1 < K1; ++k1) Al[k1 * F::AS + t] = v[k1];
-  }
-  __syncthreads();
-  if (active) {
-    float2 u[K2];
-#pragma unroll
-    for (int n2 = 0; n2 < K2; ++n2) u[n2] = Al[t * F::AS + n2];
-    reg::dft<K2, false>(u);
-    float2* dst = mid + ((long long)l * ny + iy) * F::K;
-#pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) dst[t + K1 * k2] = u[k2];
-  }
-}
-
-template <int K1, int K2>
-__global__ void __launch_bounds__(kMaxRowCoils * K1)
+template <int K1, int K2, int RC>
+__global__ void __launch_bounds__(RC * K1)
 k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
               const float* __restrict__ dax, const float* __restrict__ day,
               const float2* __restrict__ tw, float2* __restrict__ mid) {
-  extern __shared__ float2 A[];
-  rows_fwd_body<K1, K2>(in, S, L, nx, ny, dax, day, tw, mid, blockIdx.x, blockIdx.y, A);
+  __shared__ float2 A[RC * FS<K1, K2>::LA];
+  rows_fwd_body<K1, K2, RC>(in, S, L, nx, ny, dax, day, tw, mid, blockIdx.x, blockIdx.y, A);
 }
 
 template <int K1, int K2>
@@ -555,135 +449,13 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   }
 }
 
-// Row pass of the adjoint for image row iy and coil group g: inverse row
-// FFT, crop, deapodisation, conj(S_l) and the sum over the group's
-// blockDim / K1 coils into part[g]; A: one LA block of float2 LDS per coil.
-template <int K1, int K2>
-__device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, const float2* __restrict__ S, int L,
-                                              int nx, int ny, const float* __restrict__ dax,
-                                              const float* __restrict__ day, const float2* __restrict__ tw,
-                                              float2* __restrict__ part, int iy, int g, float2* A) {
-  using F = FS<K1, K2>;
-  const int rc = blockDim.x / K1;
-  const int line = threadIdx.x / K1;
-  const int t = threadIdx.x % K1;
-  const int l = g * rc + line;
-  const bool active = l < L;
-  const long long N = (long long)nx * ny;
-  float2* Al = A + line * F::LA;
-  if (active && t < K2) {
-    float2 v[K1];
-    const float2* src = mid + ((long long)l * ny + iy) * F::K;
-#pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) v[n1] = src[n1 * K2 + t];
-    reg::dft<K1, true>(v);
-    fs_twiddle<K1, K2, true>(v, t, tw);
-#pragma unroll
-    for (int k1 = 0; k1 < K1; ++k1) Al[k1 * F::AS + t] = v[k1];
-  }
-  __syncthreads();
-  float2 u[K2];
-  if (active) {
-#pragma unroll
-    for (int n2 = 0; n2 < K2; ++n2) u[n2] = Al[t * F::AS + n2];
-    reg::dft<K2, true>(u);
-  }
-  __syncthreads();
-  // per-coil contributions conj(S_l) * crop(row) into LDS (reusing A), then coil sum
-  float2* Z = A;
-  if (active) {
-    const float2* Sl = S + (long long)l * N + (long long)iy * nx;
-#pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) {
-      const int ix = img_of_grid(t + K1 * k2, nx, F::K);
-      if (ix >= 0) Z[line * nx + ix] = cmulc(Sl[ix], u[k2]);
-    }
-  }
-  __syncthreads();
-  const int nl = min(rc, L - g * rc);
-  const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
-  for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
-    float2 acc = Z[ix];
-    for (int li = 1; li < nl; ++li) acc = cadd(acc, Z[li * nx + ix]);
-    part[(long long)g * N + (long long)iy * nx + ix] = cscale(acc, (dax ? dax[ix] : 1.f) * sy);
-  }
-}
-
-template <int K1, int K2>
-__global__ void __launch_bounds__(kMaxRowCoils * K1)
+template <int K1, int K2, int RC>
+__global__ void __launch_bounds__(RC * K1)
 k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
               const float* __restrict__ dax, const float* __restrict__ day,
               const float2* __restrict__ tw, float2* __restrict__ part) {
-  extern __shared__ float2 A[];
-  rows_adj_body<K1, K2>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
-}
-
-// Toeplitz column pass: for a strip of grid columns, the zero-padded column
-// FFT, multiplication by the real transfer function T, and the inverse
-// column FFT, all in registers with two LDS transposes:
-//   forward   n = n1*K2 + n2, k = k1 + K1*k2   (as in the other kernels)
-//   inverse   k = k1 + K1*k2, r = r2 + K2*r1:  thread k1 runs the inverse
-//             DFT over k2, twiddle exp(+2 pi i k1 r2 / K), transpose,
-//             thread r2 runs the inverse DFT over k1 -> y[r2 + K2*r1].
-// Only the ny image rows are read and written (in place in mid).
-// Toeplitz column pass for grid columns [c0, c0 + tile) of coil l;
-// lds: 8 * CS float2.
-template <int K1, int K2>
-__device__ __forceinline__ void cols_toep_body(float2* __restrict__ mid, int ny, int Kx,
-                                               const float2* __restrict__ tw, int tile,
-                                               const float* __restrict__ T, int c0, int l, float2* lds) {
-  using F = FS<K1, K2>;
-  constexpr int AS2 = K1 + 1;          // row stride of the second transpose
-  const int c = threadIdx.x % 8;
-  const int t = threadIdx.x / 8;
-  const bool colok = c < tile;
-  float2* col = mid + (long long)l * ny * Kx + c0 + c;
-  if (colok && t < K2) {
-    float2 v[K1];
-#pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) {
-      const int iy = img_of_grid(n1 * K2 + t, ny, F::K);
-      v[n1] = iy >= 0 ? col[(long long)iy * Kx] : make_float2(0.f, 0.f);
-    }
-    reg::dft<K1, false>(v);
-    fs_twiddle<K1, K2, false>(v, t, tw);
-#pragma unroll
-    for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];
-  }
-  __syncthreads();
-  float2 u[K2];
-  if (colok) {
-#pragma unroll
-    for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
-    reg::dft<K2, false>(u);                         // u[k2] = X[t + K1*k2]
-    const float* Tc = T + c0 + c;
-#pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], Tc[(long long)(t + K1 * k2) * Kx]);
-    reg::dft<K2, true>(u);                          // u[r2] = sum_k2 Y exp(+...)
-#pragma unroll
-    for (int r2 = 1; r2 < K2; ++r2) {
-      float2 w = tw[t * r2];
-      w.y = -w.y;
-      u[r2] = cmul(u[r2], w);
-    }
-  }
-  __syncthreads();
-  if (colok) {
-#pragma unroll
-    for (int r2 = 0; r2 < K2; ++r2) lds[c * F::CS + r2 * AS2 + t] = u[r2];
-  }
-  __syncthreads();
-  if (colok && t < K2) {
-    float2 z[K1];
-#pragma unroll
-    for (int k1 = 0; k1 < K1; ++k1) z[k1] = lds[c * F::CS + t * AS2 + k1];
-    reg::dft<K1, true>(z);                          // z[r1] = y[t + K2*r1]
-#pragma unroll
-    for (int r1 = 0; r1 < K1; ++r1) {
-      const int iy = img_of_grid(t + K2 * r1, ny, F::K);
-      if (iy >= 0) col[(long long)iy * Kx] = z[r1];
-    }
-  }
+  __shared__ float2 A[RC * FS<K1, K2>::LA];
+  rows_adj_body<K1, K2, RC>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
 }
 
 template <int K1, int K2>
@@ -802,18 +574,43 @@ struct BatchLaunch {
 // ------------------------------------------------- register-path launchers
 template <int K1, int K2>
 struct FSLaunch {
-  static size_t row_lds(const pnp_plan* p) {
-    const size_t b = sizeof(float2) * p->row_coils * FS<K1, K2>::LA;
-    set_lds_limit((const void*)k_rows_fwd_fs<K1, K2>, b);
-    set_lds_limit((const void*)k_rows_adj_fs<K1, K2>, b);
-    return b;
+  // the plan's coils per workgroup, as instantiated for this grid size
+  static int rc_of(const pnp_plan* p) {
+    return p->row_coils == 2 ? 2 : (p->row_coils == 8 ? fit_rc<K1, K2>(8) : 4);
+  }
+  template <int RC>
+  static void rows_fwd_rc(const pnp_plan* p, const ImgIn& in, const float2* S, int L, const float* dax,
+                          const float* day, float2* mid, hipStream_t s) {
+    PNP_LAUNCH((k_rows_fwd_fs<K1, K2, RC>), dim3(p->ax[1].n, (L + RC - 1) / RC), dim3(RC * K1), 0, s, in, S, L,
+               p->ax[0].n, p->ax[1].n, dax, day, p->ax[0].fft.tw, mid);
+  }
+  template <int RC>
+  static void rows_adj_rc(const pnp_plan* p, int L, const float2* mid, const float2* S, const float* dax,
+                          const float* day, float2* part, hipStream_t s) {
+    PNP_LAUNCH((k_rows_adj_fs<K1, K2, RC>), dim3(p->ax[1].n, (L + RC - 1) / RC), dim3(RC * K1), 0, s, mid, S, L,
+               p->ax[0].n, p->ax[1].n, dax, day, p->ax[0].fft.tw, part);
+  }
+  static void rows_fwd_any(const pnp_plan* p, const ImgIn& in, const float2* S, int L, const float* dax,
+                           const float* day, float2* mid, hipStream_t s) {
+    switch (rc_of(p)) {
+      case 2: rows_fwd_rc<2>(p, in, S, L, dax, day, mid, s); break;
+      case 8: rows_fwd_rc<fit_rc<K1, K2>(8)>(p, in, S, L, dax, day, mid, s); break;
+      default: rows_fwd_rc<4>(p, in, S, L, dax, day, mid, s); break;
+    }
+  }
+  static void rows_adj_any(const pnp_plan* p, int L, const float2* mid, const float2* S, const float* dax,
+                           const float* day, float2* part, hipStream_t s) {
+    switch (rc_of(p)) {
+      case 2: rows_adj_rc<2>(p, L, mid, S, dax, day, part, s); break;
+      case 8: rows_adj_rc<fit_rc<K1, K2>(8)>(p, L, mid, S, dax, day, part, s); break;
+      default: rows_adj_rc<4>(p, L, mid, S, dax, day, part, s); break;
+    }
   }
   static void rows_fwd(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
                        hipStream_t s) {
-    const int rc = p->row_coils, G = (L + rc - 1) / rc;
-    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, in, S, L,
-               p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, mid);
+    rows_fwd_any(p, in, S, L, p->ax[0].deapod, p->ax[1].deapod, mid, s);
   }
+  static void rows_coils(const pnp_plan* p, int* rc) { *rc = rc_of(p); }
   static void cols_fwd(const pnp_plan* p, int L, const float2* mid, float2* ypart, hipStream_t s) {
     PNP_LAUNCH((k_cols_fwd_fs<K1, K2>), dim3(p->ntx, L), dim3(8 * K1), 0, s, mid, p->ax[0].n,
                p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off, p->rec,
@@ -826,17 +623,12 @@ struct FSLaunch {
   }
   static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                        hipStream_t s) {
-    const int rc = p->row_coils, G = (L + rc - 1) / rc;
-    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, mid, S, L,
-               p->ax[0].n, p->ax[1].n, p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft.tw, part);
+    rows_adj_any(p, L, mid, S, p->ax[0].deapod, p->ax[1].deapod, part, s);
   }
   // Toeplitz variants: no deapodisation, column pass = FFT * T * IFFT
   static void rows_fwd_toep(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
                             hipStream_t s) {
-    const int rc = p->row_coils, G = (L + rc - 1) / rc;
-    PNP_LAUNCH((k_rows_fwd_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, in, S, L,
-               p->ax[0].n, p->ax[1].n, (const float*)nullptr, (const float*)nullptr, p->ax[0].fft.tw,
-               mid);
+    rows_fwd_any(p, in, S, L, nullptr, nullptr, mid, s);
   }
   static void cols_toep(const pnp_plan* p, int L, const float* T, float2* mid, hipStream_t s) {
     PNP_LAUNCH((k_cols_toep_fs<K1, K2>), dim3(p->ntx, L), dim3(8 * K1), 0, s, mid, p->ax[1].n, p->ax[0].K,
@@ -844,10 +636,7 @@ struct FSLaunch {
   }
   static void rows_adj_toep(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                             hipStream_t s) {
-    const int rc = p->row_coils, G = (L + rc - 1) / rc;
-    PNP_LAUNCH((k_rows_adj_fs<K1, K2>), dim3(p->ax[1].n, G), dim3(rc * K1), row_lds(p), s, mid, S, L,
-               p->ax[0].n, p->ax[1].n, (const float*)nullptr, (const float*)nullptr, p->ax[0].fft.tw,
-               part);
+    rows_adj_any(p, L, mid, S, nullptr, nullptr, part, s);
   }
 };
 
@@ -873,13 +662,19 @@ bool fs_ok(const pnp_plan* p) {
 }  // namespace
 
 int op_groups(const pnp_plan* p, int L) {
-  const int rc = fs_ok(p) ? p->row_coils : kRowCoils;
+  if (p->ndim == 3) return op3_groups(L);
+  int rc = kRowCoils;
+  if (fs_ok(p)) {
+    rc = 4;
+    PNP_FS_DISPATCH(p->ax[0].K, rows_coils, p, &rc);
+  }
   return (L + rc - 1) / rc;
 }
 int op_groups_max(int L) { return (L + 1) / 2; }
 int batch_groups(int L) { return (L + kRowCoils - 1) / kRowCoils; }
 
 size_t op_workspace_bytes(const pnp_plan* p, int L) {
+  if (p->ndim == 3) return op3_workspace_bytes(p, L);
   const int Kx = p->ax[0].K;
   const int64_t N = image_size(p);
   const int G = std::max(op_groups_max(L), op_groups(p, L));
@@ -893,7 +688,8 @@ size_t op_workspace_bytes(const pnp_plan* p, int L) {
 }
 
 OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws) {
-  OpWorkspace w;
+  if (p->ndim == 3) return op3_workspace(p, L, ws);
+  OpWorkspace w{};
   const int Kx = p->ax[0].K;
   const int64_t N = image_size(p);
   const int G = std::max(op_groups_max(L), op_groups(p, L));
@@ -980,6 +776,7 @@ static void adjoint_to_groups(const pnp_plan* p, const KIn& kin, const float2* s
 
 void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y,
                 const OpWorkspace& w, hipStream_t s) {
+  if (p->ndim == 3) return op3_forward(p, x, smaps, L, y, w, s);
   forward_to_partials(p, ImgIn{x, CGUpdate{}}, smaps, L, w, s);
   const long long tot = p->M * L;
   const float scale = (float)(1.0 / std::sqrt((double)image_size(p)));
@@ -989,6 +786,7 @@ void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, 
 
 void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf,
                 float2* x, const OpWorkspace& w, hipStream_t s) {
+  if (p->ndim == 3) return op3_adjoint(p, y, smaps, L, dcf, x, w, s);
   const int G = op_groups(p, L);
   const int64_t N = image_size(p);
   const float scale = (float)(1.0 / std::sqrt((double)N));
@@ -1002,13 +800,14 @@ void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, 
 
 void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
                      const float* dcf, const OpWorkspace& w, hipStream_t s) {
+  if (p->ndim == 3) return op3_normal_parts(p, in, smaps, L, dcf, w, s);
   forward_to_partials(p, ImgIn{in.x, in.cg}, smaps, L, w, s);
   const float scale = (float)(1.0 / (double)image_size(p));   // both N^{-1/2} factors
   adjoint_to_groups(p, KIn{nullptr, w.ypart, p->sample_ent, (long long)p->M, (long long)p->E}, smaps,
                     L, dcf, scale, w.part, w, s);
 }
 
-bool toeplitz_supported(const pnp_plan* p) { return p->ndim == 2 && fs_ok(p); }
+bool toeplitz_supported(const pnp_plan* p) { return p->ndim == 3 ? plan3_supported(p) : fs_ok(p); }
 
 bool batch_grid_supported(int K) {
   return K == 128 || K == 192 || K == 256 || K == 512 || K == 640 || K == 768 || K == 1024;
@@ -1044,6 +843,7 @@ void batch_rows_adj(int K, const BatchSlice* sl, const int4* items, int n_items,
 void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
                           const OpWorkspace& w, hipStream_t s) {
   const pnp_plan* p = tp->plan;
+  if (p->ndim == 3) return op3_normal_toep_parts(tp, in, smaps, L, w, s);
   const ImgIn im{in.x, in.cg};
   PNP_FS_DISPATCH(p->ax[0].K, rows_fwd_toep, p, im, smaps, L, w.mid, s);
   PNP_FS_DISPATCH(p->ax[1].K, cols_toep, p, L, tp->T, w.mid, s);

@@ -94,6 +94,7 @@ __global__ void k_plan_samples(const float* __restrict__ traj, long long M, int 
     jj[a] = wrapi((long long)f, Kd[a]);
   }
   j0[m] = make_int4(jj[0], jj[1], jj[2], 0);
+  if (!tile_count) return;   // no strip tables (3D plans)
   // tiles along x (and y in 3D) touched by taps j0 .. j0 + W - 1 (mod K)
   int tx[2], ty[2];
   int nxs = 0, nys = 0;
@@ -288,6 +289,90 @@ static int choose_tile(int K) {
   return 0;
 }
 
+__global__ void k_deapod_yz(const float* __restrict__ dy, const float* __restrict__ dz, int ny, int nz,
+                            float* __restrict__ dyz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ny * nz) dyz[i] = dy[i % ny] * dz[i / ny];
+}
+
+// 3D plan: twiddles and deapodisation per axis, the combined y-z
+// deapodisation of the (z, y) image rows, and per sample the wrapped first
+// taps and kernel weights (the 3D operator spreads and interpolates from
+// the full oversampled grid; no strip tables).
+static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
+  const int64_t M = p->M;
+  p->tile = 8;                  // strip width of the column passes
+  p->row_coils = 4;
+  p->ntx = p->ax[0].K / 8;
+  p->nty = 1;
+  p->ntiles = 0;
+  p->slots = 0;
+  p->E = 0;
+  p->max_tile_entries = 0;
+  PNP_HIP(hipGetDevice(&p->device));
+  {
+    int* bad = nullptr;
+    PNP_HIP(hipMalloc((void**)&bad, sizeof(int)));
+    PNP_HIP(hipMemsetAsync(bad, 0, sizeof(int), stream));
+    const long long nv = M * 3;
+    k_check_finite<<<(unsigned)((nv + 255) / 256), 256, 0, stream>>>(traj, nv, bad);
+    PNP_CHECK_LAUNCH();
+    int hbad = 0;
+    PNP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    PNP_HIP(hipStreamSynchronize(stream));
+    PNP_HIP(hipFree(bad));
+    if (hbad) fail(PNP_ERR_NUMERIC, "trajectory holds non-finite coordinates");
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  size_t o_tw[3], o_dp[3];
+  for (int a = 0; a < 3; ++a) {
+    o_tw[a] = take(sizeof(float2) * p->ax[a].K);
+    o_dp[a] = take(sizeof(float) * p->ax[a].n);
+  }
+  const size_t o_yz = take(sizeof(float) * p->ax[1].n * p->ax[2].n);
+  const size_t o_j0 = take(sizeof(int4) * M);
+  const size_t o_w = take(sizeof(float) * M * 3 * p->W);
+  const size_t o_traj = take(sizeof(float) * M * 3);
+  PNP_HIP(hipMalloc(&p->block, off));
+  p->block_bytes = off;
+  char* base = (char*)p->block;
+  for (int a = 0; a < 3; ++a) {
+    p->ax[a].fft.tw = (const float2*)(base + o_tw[a]);
+    p->ax[a].deapod = (float*)(base + o_dp[a]);
+  }
+  p->deapod_yz = (float*)(base + o_yz);
+  p->j0 = (int4*)(base + o_j0);
+  p->wts = (float*)(base + o_w);
+  p->traj = (float*)(base + o_traj);
+  p->tile_off = nullptr;
+  p->row_start = nullptr;
+  p->ent_sample = nullptr;
+  p->sample_ent = nullptr;
+  p->rec = nullptr;
+  PNP_HIP(hipMemcpyAsync(p->traj, traj, sizeof(float) * M * 3, hipMemcpyDeviceToDevice, stream));
+  for (int a = 0; a < 3; ++a) {
+    const int K = p->ax[a].K, n = p->ax[a].n;
+    k_twiddles<<<(K + 255) / 256, 256, 0, stream>>>((float2*)p->ax[a].fft.tw, K);
+    PNP_CHECK_LAUNCH();
+    k_deapod<<<(n + 255) / 256, 256, 0, stream>>>(p->ax[a].deapod, n, K, p->W, p->beta);
+    PNP_CHECK_LAUNCH();
+  }
+  const int nyz = p->ax[1].n * p->ax[2].n;
+  k_deapod_yz<<<(nyz + 255) / 256, 256, 0, stream>>>(p->ax[1].deapod, p->ax[2].deapod, p->ax[1].n, p->ax[2].n,
+                                                     p->deapod_yz);
+  PNP_CHECK_LAUNCH();
+  k_plan_samples<<<(unsigned)((M + 255) / 256), 256, 0, stream>>>(traj, M, 3, p->ax[0].K, p->ax[1].K, p->ax[2].K,
+                                                                   p->W, p->beta, 8, 1, 1, p->j0, p->wts, nullptr,
+                                                                   nullptr, 0);
+  PNP_CHECK_LAUNCH();
+  PNP_HIP(hipStreamSynchronize(stream));
+}
+
 pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* traj,
                       hipStream_t stream) {
   if (ndim != 2 && ndim != 3) fail(PNP_ERR_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
@@ -317,7 +402,10 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
       if (!fft_factor(2 * n, &p->ax[a].fft))
         fail(PNP_ERR_SHAPE, "grid size %d must have only prime factors 2, 3, 5", 2 * n);
     }
-    if (ndim == 3) fail(PNP_ERR_UNSUPPORTED, "3D plans are not available in this build");
+    if (ndim == 3) {
+      plan_create_3d(p, traj, stream);
+      return p;
+    }
     p->tile = choose_tile(p->ax[0].K);
     p->row_coils = 4;
     if (ndim == 3 && choose_tile(p->ax[1].K) != p->tile)

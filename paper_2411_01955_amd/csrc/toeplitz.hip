@@ -86,8 +86,9 @@ k_psf_gemm(const double* __restrict__ Dy, const double* __restrict__ Dx, const f
 
 pnp_toeplitz* toeplitz_create(const pnp_plan* p, const float* traj, const float* dcf, hipStream_t s) {
   if (!toeplitz_supported(p))
-    fail(PNP_ERR_UNSUPPORTED, "the Toeplitz normal operator needs a 2D plan with grid sides in "
+    fail(PNP_ERR_UNSUPPORTED, "the Toeplitz normal operator needs grid sides in "
                               "{128, 192, 256, 512, 640, 768, 1024}");
+  if (p->ndim == 3) return toeplitz3_create(p, dcf, s);
   pnp_toeplitz* tp = new pnp_toeplitz();
   tp->plan = p;
   tp->T = nullptr;

@@ -55,7 +55,8 @@ def test_autotune_and_cache(pnp, tmp_path):
     assert r1["row_coils"] in (2, 4, 8) and not r1["from_cache"]
     assert all(t > 0 for t in r1["time_us"])
     assert plan.row_coils == r1["row_coils"]
-    assert r1["time_us"][(2, 4, 8).index(r1["row_coils"])] == min(r1["time_us"])
+    t = dict(zip((2, 4, 8), r1["time_us"]))
+    assert t[r1["row_coils"]] <= t[4]                 # never slower than the default
     lines = [json.loads(l) for l in open(cache)]
     assert len(lines) == 1 and lines[0]["row_coils"] == r1["row_coils"]
     # a second plan on the same trajectory takes the cached choice
