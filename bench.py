@@ -63,9 +63,11 @@ KAPPA = 0.75
 KAPPA_UNET = 1.0       # UNet conditioning level = kappa * sigma_k
 RISE_TOL = 0.5         # wavelet fallback when the residual rises by more than 50%
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical.json")
-KERNEL_SOURCES = ["paper_2411_01955_amd/csrc/nufft2d.hip", "paper_2411_01955_amd/csrc/fft_lds.hpp",
-                  "paper_2411_01955_amd/csrc/fft_reg.hpp", "paper_2411_01955_amd/csrc/plan.hip",
-                  "paper_2411_01955_amd/csrc/toeplitz.hip", "paper_2411_01955_amd/csrc/solver.hip"]
+KERNEL_SOURCES = ["paper_2411_01955_amd/csrc/nufft2d.hip", "paper_2411_01955_amd/csrc/fs_bodies.hpp",
+                  "paper_2411_01955_amd/csrc/fft_lds.hpp", "paper_2411_01955_amd/csrc/fft_reg.hpp",
+                  "paper_2411_01955_amd/csrc/common.hpp", "paper_2411_01955_amd/csrc/cg_scalars.hpp",
+                  "paper_2411_01955_amd/csrc/plan.hip", "paper_2411_01955_amd/csrc/toeplitz.hip",
+                  "paper_2411_01955_amd/csrc/solver.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -107,6 +109,11 @@ def kernel_bytes(n, L, M, E, groups):
     out["k_entry_values"] = 64 * E + 8 * L * E * 2 + 8 * M * 2 + 8 * L * E
     # Toeplitz column pass: mid in and out (image rows only) + the real transfer function once
     out["k_cols_toep_fs"] = 2 * mid + 4 * (2 * n) ** 2
+    # CG vector kernels: w = c0 r + cg sum_g part_g (r, G partials in; w out),
+    # the first step's (u, r, p, s) from (x, partials, b0), the last u update
+    out["k_cg_dots"] = 8 * N * (2 + groups)
+    out["k_cg_init"] = 8 * N * (2 + groups + 4)
+    out["k_cg_final"] = 8 * N * 4
     return out
 
 
@@ -480,7 +487,7 @@ def main():
         c0, t0 = tr.get(_kname(kname), (0, 0.0))
         tr[_kname(kname)] = (c0 + c, t0 + t)
     pnp.trace_enable(False)
-    groups = (L + 3) // 4
+    groups = -(-L // plan.row_coils)
     kb = kernel_bytes(n, L, M, info["entries"], groups)
     dom = max((kname for kname in tr if kname in kb), key=lambda kname: tr[kname][1])
     launches, tot_ms = tr[dom]

@@ -1,7 +1,9 @@
 // Per-kernel duration tracing with HIP events.
 //
 // When enabled, every launch site brackets its kernel with two events
-// recorded on the kernel's own stream; pnp_trace_read() waits for the
+// recorded on the kernel's own stream (without the system-scope release
+// fence a default event performs, so an interval holds the kernel and its
+// dispatch only); pnp_trace_read() waits for the
 // recorded events and reports, per kernel name, the launch count and the
 // summed duration.  Disabled (the default), a launch site costs one branch.
 #include <cstdio>
@@ -41,8 +43,11 @@ hipEvent_t take_event(TraceState& s) {
     s.pool.pop_back();
     return e;
   }
+  // no system-scope fence when the event completes: the events only time,
+  // and the fence's cache writeback and invalidation would be counted in
+  // the kernel's interval and slow the kernel after it
   hipEvent_t e;
-  PNP_HIP(hipEventCreate(&e));
+  PNP_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 
