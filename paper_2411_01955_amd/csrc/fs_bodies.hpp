@@ -23,9 +23,31 @@ __device__ __forceinline__ int grid_of_img(int i, int n, int K) {
   return r < 0 ? r + K : r;
 }
 
+// Zero padding of the 2x-oversampled transforms (HALF: image side n = K/2).
+// K1 and K2 are multiples of 4, so with Q = K1/4 a grid index j = n1*K2 + t
+// (t < K2) is padding exactly for Q <= n1 < 3Q, holds image index
+// (n1 + Q)*K2 + t for n1 < Q and (n1 - 3Q)*K2 + t for n1 >= 3Q; likewise
+// j = t + K1*k2 (t < K1) with P = K2/4: padding for P <= k2 < 3P, image
+// index t + K1*(k2 + P) or t + K1*(k2 - 3P).  The patterns are known at
+// compile time: no per-element index tests.  Without HALF (a transform of
+// a full grid-sized array) img_of_grid decides at run time.
+//
+// Addresses are a workgroup-uniform base plus a per-thread byte offset of
+// type OFF (32-bit where every offset of the launch fits, 64-bit else).
+template <typename OFF, typename T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, OFF byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename OFF, typename T>
+__device__ __forceinline__ void st_off(T* __restrict__ base, OFF byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // Image input of the forward row pass: the image x, or -- inside CG -- the
-// direction update p' = r + beta p computed on the fly (x = p, beta read
-// from the device scalars); the workgroups of coil group 0 store p'.
+// next residual r' = r - alpha (w + beta s) formed on the fly from the
+// previous CG vectors (alpha, beta read from the device scalars); the
+// workgroups of coil group 0 also store r', s' = w + beta s, p' = r + beta p
+// and u' = u + alpha p'.
 struct ImgIn {
   const float2* x;
   CGUpdate cg;   // cg.r == nullptr: plain image input
@@ -37,21 +59,21 @@ struct ImgScal {
 __device__ __forceinline__ ImgScal img_scal(const ImgIn& in) {
   return in.cg.r ? ImgScal{(float)*in.cg.alpha, (float)*in.cg.beta} : ImgScal{0.f, 0.f};
 }
-__device__ __forceinline__ float2 img_at(const ImgIn& in, long long pix, ImgScal sc, bool store) {
-  if (!in.cg.r) return in.x[pix];
-  // every reader needs r' = r - alpha (w + beta s); the storing workgroup
-  // also forms and writes p', s', u'
+// element ix of the image row starting at pixel row0
+__device__ __forceinline__ float2 img_at(const ImgIn& in, long long row0, int ix, ImgScal sc, bool store) {
+  const unsigned b = (unsigned)ix * 8u;
+  if (!in.cg.r) return ld_off(in.x + row0, b);
   const CGUpdate& c = in.cg;
-  const float2 rv = c.r[pix], sv = c.s[pix], wv = c.w[pix];
+  const float2 rv = ld_off(c.r + row0, b), sv = ld_off(c.s + row0, b), wv = ld_off(c.w + row0, b);
   const float2 sn = make_float2(fmaf(sc.beta, sv.x, wv.x), fmaf(sc.beta, sv.y, wv.y));
   const float2 rn = make_float2(fmaf(-sc.alpha, sn.x, rv.x), fmaf(-sc.alpha, sn.y, rv.y));
   if (store) {
-    const float2 pv = c.p[pix], uv = c.u[pix];
+    const float2 pv = ld_off(c.p + row0, b), uv = ld_off(c.u + row0, b);
     const float2 pn = make_float2(fmaf(sc.beta, pv.x, rv.x), fmaf(sc.beta, pv.y, rv.y));
-    c.p2[pix] = pn;
-    c.s2[pix] = sn;
-    c.u2[pix] = make_float2(fmaf(sc.alpha, pn.x, uv.x), fmaf(sc.alpha, pn.y, uv.y));
-    c.r2[pix] = rn;
+    st_off(c.p2 + row0, b, pn);
+    st_off(c.s2 + row0, b, sn);
+    st_off(c.u2 + row0, b, make_float2(fmaf(sc.alpha, pn.x, uv.x), fmaf(sc.alpha, pn.y, uv.y)));
+    st_off(c.r2 + row0, b, rn);
   }
   return rn;
 }
@@ -64,48 +86,68 @@ struct FS {
   static constexpr int CS = ((LA + 13) / 16) * 16 + 2;   // column stride, = 2 mod 16
   static constexpr int GS = ((K + 13) / 16) * 16 + 2;    // grid column stride, = 2 mod 16
   static constexpr int CSTR = CS > GS ? CS : GS;         // strip LDS per column
+  static_assert(K1 % 4 == 0 && K2 % 4 == 0, "padding patterns need factors divisible by 4");
 };
 
 template <int K1, int K2, bool INV>
 __device__ __forceinline__ void fs_twiddle(float2 (&v)[K1], int t, const float2* __restrict__ tw) {
+  const unsigned tb = (unsigned)t * 8u;
 #pragma unroll
   for (int k1 = 1; k1 < K1; ++k1) {
-    float2 w = tw[t * k1];
+    float2 w = ld_off(tw, tb * (unsigned)k1);
     if (INV) w.y = -w.y;
     v[k1] = cmul(v[k1], w);
   }
 }
 
 // Row pass of the forward operator for image row iy and coil group g
-// (RC coils, one line of K1 threads each: blockDim = RC * K1); A: RC LA
-// blocks of float2 LDS.  Shared by the single-slice, batched and 3D kernels.
-template <int K1, int K2, int RC = 4>
+// (RC coils, one line of K1 threads each: blockDim = RC * K1).  The
+// workgroup first forms the row's input (image or CG residual, times the
+// deapodisation) once into X, then each line multiplies by its coil map,
+// zero-pads and transforms.  A: RC LA blocks of float2 LDS; X: nx float2.
+// Shared by the single-slice, batched and 3D kernels.
+template <int K1, int K2, int RC, bool HALF, typename OFF>
 __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __restrict__ S, int L, int nx,
                                               int ny, const float* __restrict__ dax,
                                               const float* __restrict__ day, const float2* __restrict__ tw,
-                                              float2* __restrict__ mid, int iy, int g, float2* A) {
+                                              float2* __restrict__ mid, int iy, int g, float2* A, float2* X) {
   using F = FS<K1, K2>;
-  constexpr int rc = RC;
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
-  const int l = g * rc + line;
-  const bool active = l < L;
+  const int l0 = g * RC;
+  const bool active = l0 + line < L;
   const long long N = (long long)nx * ny;
+  const long long row0 = (long long)iy * nx;
+  {
+    const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
+    const ImgScal bt = img_scal(in);
+    const bool store = g == 0;
+    for (int ix = threadIdx.x; ix < nx; ix += RC * K1)
+      X[ix] = cscale(img_at(in, row0, ix, bt, store), (dax ? dax[ix] : 1.f) * sy);
+  }
+  __syncthreads();
   float2* Al = A + line * F::LA;
   if (active && t < K2) {
     float2 v[K1];
-    const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
-    const ImgScal bt = img_scal(in);
-    const bool store = line == 0 && g == 0;
-    const float2* Sl = S ? S + (long long)l * N + (long long)iy * nx : nullptr;
-    const long long row0 = (long long)iy * nx;
+    const float2* Sg = S ? S + (long long)l0 * N + row0 : nullptr;
+    const OFF sb = (OFF)line * (OFF)N * 8u;
+    auto at = [&](int ix) {
+      return S ? cmul(ld_off(Sg, sb + (OFF)ix * 8u), X[ix]) : X[ix];
+    };
+    if constexpr (HALF) {
+      constexpr int Q = K1 / 4;
 #pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) {
-      const int ix = img_of_grid(n1 * K2 + t, nx, F::K);
-      v[n1] = ix >= 0 ? cscale(S ? cmul(Sl[ix], img_at(in, row0 + ix, bt, store))
-                                  : img_at(in, row0 + ix, bt, store),
-                                (dax ? dax[ix] : 1.f) * sy)
-                      : make_float2(0.f, 0.f);
+      for (int n1 = 0; n1 < K1; ++n1) {
+        if (n1 < Q) v[n1] = at((n1 + Q) * K2 + t);
+        else if (n1 >= 3 * Q) v[n1] = at((n1 - 3 * Q) * K2 + t);
+        else v[n1] = make_float2(0.f, 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int n1 = 0; n1 < K1; ++n1) {
+        const int ix = img_of_grid(n1 * K2 + t, nx, F::K);
+        v[n1] = ix >= 0 ? at(ix) : make_float2(0.f, 0.f);
+      }
     }
     reg::dft<K1, false>(v);
     fs_twiddle<K1, K2, false>(v, t, tw);
@@ -118,33 +160,34 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
 #pragma unroll
     for (int n2 = 0; n2 < K2; ++n2) u[n2] = Al[t * F::AS + n2];
     reg::dft<K2, false>(u);
-    float2* dst = mid + ((long long)l * ny + iy) * F::K;
+    float2* dst = mid + ((long long)l0 * ny + iy) * F::K;
+    const OFF db = ((OFF)line * (OFF)ny * (OFF)F::K + (OFF)t) * 8u;
 #pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) dst[t + K1 * k2] = u[k2];
+    for (int k2 = 0; k2 < K2; ++k2) st_off(dst, db + (OFF)(K1 * k2 * 8), u[k2]);
   }
 }
 
 // Row pass of the adjoint for image row iy and coil group g: inverse row
 // FFT, crop, deapodisation, conj(S_l) and the sum over the group's RC coils
 // into part[g]; A: RC LA blocks of float2 LDS.
-template <int K1, int K2, int RC = 4>
+template <int K1, int K2, int RC, bool HALF, typename OFF>
 __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, const float2* __restrict__ S, int L,
                                               int nx, int ny, const float* __restrict__ dax,
                                               const float* __restrict__ day, const float2* __restrict__ tw,
                                               float2* __restrict__ part, int iy, int g, float2* A) {
   using F = FS<K1, K2>;
-  constexpr int rc = RC;
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
-  const int l = g * rc + line;
-  const bool active = l < L;
+  const int l0 = g * RC;
+  const bool active = l0 + line < L;
   const long long N = (long long)nx * ny;
   float2* Al = A + line * F::LA;
   if (active && t < K2) {
     float2 v[K1];
-    const float2* src = mid + ((long long)l * ny + iy) * F::K;
+    const float2* src = mid + ((long long)l0 * ny + iy) * F::K;
+    const OFF sb = ((OFF)line * (OFF)ny * (OFF)F::K + (OFF)t) * 8u;
 #pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) v[n1] = src[n1 * K2 + t];
+    for (int n1 = 0; n1 < K1; ++n1) v[n1] = ld_off(src, sb + (OFF)(n1 * K2 * 8));
     reg::dft<K1, true>(v);
     fs_twiddle<K1, K2, true>(v, t, tw);
 #pragma unroll
@@ -161,29 +204,41 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   // per-coil contributions conj(S_l) * crop(row) into LDS (reusing A), then coil sum
   float2* Z = A;
   if (active) {
-    const float2* Sl = S ? S + (long long)l * N + (long long)iy * nx : nullptr;
+    const float2* Sg = S ? S + (long long)l0 * N + (long long)iy * nx : nullptr;
+    const OFF sb = (OFF)line * (OFF)N * 8u;
+    auto put = [&](int ix, float2 v) { Z[line * nx + ix] = S ? cmulc(ld_off(Sg, sb + (OFF)ix * 8u), v) : v; };
+    if constexpr (HALF) {
+      constexpr int P = K2 / 4;
 #pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) {
-      const int ix = img_of_grid(t + K1 * k2, nx, F::K);
-      if (ix >= 0) Z[line * nx + ix] = S ? cmulc(Sl[ix], u[k2]) : u[k2];
+      for (int k2 = 0; k2 < K2; ++k2) {
+        if (k2 < P) put(t + K1 * (k2 + P), u[k2]);
+        else if (k2 >= 3 * P) put(t + K1 * (k2 - 3 * P), u[k2]);
+      }
+    } else {
+#pragma unroll
+      for (int k2 = 0; k2 < K2; ++k2) {
+        const int ix = img_of_grid(t + K1 * k2, nx, F::K);
+        if (ix >= 0) put(ix, u[k2]);
+      }
     }
   }
   __syncthreads();
-  const int nl = min(rc, L - g * rc);
+  const int nl = min(RC, L - l0);
   const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
+  float2* pg = part + (long long)g * N + (long long)iy * nx;
   for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
     float2 acc = Z[ix];
     for (int li = 1; li < nl; ++li) acc = cadd(acc, Z[li * nx + ix]);
-    part[(long long)g * N + (long long)iy * nx + ix] = cscale(acc, (dax ? dax[ix] : 1.f) * sy);
+    pg[ix] = cscale(acc, (dax ? dax[ix] : 1.f) * sy);
   }
 }
 
 // Column passes over a strip of 8 grid columns (one thread column c per
 // grid column, threads t < K1 along the column), in registers with LDS
-// transposes; `col` points at the strip's column c, grid row j sits at
-// col[j * rs].  The column is the zero-padded image of `nimg` rows
-// (img_of_grid placement) on the input side of the forward transform and
-// on the output side of the inverse one.
+// transposes.  `strip` is the workgroup's column 0; column c, grid row j
+// sits at strip[c + j * rs].  The column is the zero-padded image of
+// `nimg` rows (img_of_grid placement) on the input side of the forward
+// transform and on the output side of the inverse one.
 //   forward   n = n1*K2 + n2, k = k1 + K1*k2: thread n2 runs the DFT over n1,
 //             twiddle, transpose, thread k1 runs the DFT over n2
 //             -> u[k2] = X[t + K1*k2]
@@ -191,18 +246,30 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
 //             over k2, twiddle exp(+2 pi i k1 r2 / K), transpose, thread r2
 //             runs the inverse DFT over k1 -> y[r2 + K2*r1]
 // lds: 8 * CS float2.  Every thread of the workgroup must call these.
-template <int K1, int K2>
-__device__ __forceinline__ void col_fwd(const float2* __restrict__ col, long long rs, int nimg, bool colok,
+template <int K1, int K2, bool HALF, typename OFF>
+__device__ __forceinline__ void col_fwd(const float2* __restrict__ strip, OFF rs, int nimg, bool colok,
                                         const float2* __restrict__ tw, float2* lds, float2 (&u)[K2]) {
   using F = FS<K1, K2>;
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;
   if (colok && t < K2) {
     float2 v[K1];
+    const OFF rb = rs * 8u;
+    const OFF cb = (OFF)c * 8u + (OFF)t * rb;
+    if constexpr (HALF) {
+      constexpr int Q = K1 / 4;
 #pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) {
-      const int iy = img_of_grid(n1 * K2 + t, nimg, F::K);
-      v[n1] = iy >= 0 ? col[(long long)iy * rs] : make_float2(0.f, 0.f);
+      for (int n1 = 0; n1 < K1; ++n1) {
+        if (n1 < Q) v[n1] = ld_off(strip, cb + (OFF)((n1 + Q) * K2) * rb);
+        else if (n1 >= 3 * Q) v[n1] = ld_off(strip, cb + (OFF)((n1 - 3 * Q) * K2) * rb);
+        else v[n1] = make_float2(0.f, 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int n1 = 0; n1 < K1; ++n1) {
+        const int iy = img_of_grid(n1 * K2 + t, nimg, F::K);
+        v[n1] = iy >= 0 ? ld_off(strip, (OFF)c * 8u + (OFF)iy * rb) : make_float2(0.f, 0.f);
+      }
     }
     reg::dft<K1, false>(v);
     fs_twiddle<K1, K2, false>(v, t, tw);
@@ -218,8 +285,8 @@ __device__ __forceinline__ void col_fwd(const float2* __restrict__ col, long lon
   __syncthreads();
 }
 
-template <int K1, int K2>
-__device__ __forceinline__ void col_inv(float2* __restrict__ col, long long rs, int nimg, bool colok,
+template <int K1, int K2, bool HALF, typename OFF>
+__device__ __forceinline__ void col_inv(float2* __restrict__ strip, OFF rs, int nimg, bool colok,
                                         const float2* __restrict__ tw, float2* lds, float2 (&u)[K2]) {
   using F = FS<K1, K2>;
   constexpr int AS2 = K1 + 1;          // row stride of the second transpose
@@ -227,9 +294,10 @@ __device__ __forceinline__ void col_inv(float2* __restrict__ col, long long rs, 
   const int t = threadIdx.x / 8;
   if (colok) {
     reg::dft<K2, true>(u);
+    const unsigned tb = (unsigned)t * 8u;
 #pragma unroll
     for (int r2 = 1; r2 < K2; ++r2) {
-      float2 w = tw[t * r2];
+      float2 w = ld_off(tw, tb * (unsigned)r2);
       w.y = -w.y;
       u[r2] = cmul(u[r2], w);
     }
@@ -242,10 +310,21 @@ __device__ __forceinline__ void col_inv(float2* __restrict__ col, long long rs, 
 #pragma unroll
     for (int k1 = 0; k1 < K1; ++k1) z[k1] = lds[c * F::CS + t * AS2 + k1];
     reg::dft<K1, true>(z);
+    const OFF rb = rs * 8u;
+    const OFF cb = (OFF)c * 8u + (OFF)t * rb;
+    if constexpr (HALF) {
+      constexpr int Q = K1 / 4;
 #pragma unroll
-    for (int r1 = 0; r1 < K1; ++r1) {
-      const int iy = img_of_grid(t + K2 * r1, nimg, F::K);
-      if (iy >= 0) col[(long long)iy * rs] = z[r1];
+      for (int r1 = 0; r1 < K1; ++r1) {
+        if (r1 < Q) st_off(strip, cb + (OFF)(K2 * (r1 + Q)) * rb, z[r1]);
+        else if (r1 >= 3 * Q) st_off(strip, cb + (OFF)(K2 * (r1 - 3 * Q)) * rb, z[r1]);
+      }
+    } else {
+#pragma unroll
+      for (int r1 = 0; r1 < K1; ++r1) {
+        const int iy = img_of_grid(t + K2 * r1, nimg, F::K);
+        if (iy >= 0) st_off(strip, (OFF)c * 8u + (OFF)iy * rb, z[r1]);
+      }
     }
   }
   __syncthreads();
@@ -253,7 +332,8 @@ __device__ __forceinline__ void col_inv(float2* __restrict__ col, long long rs, 
 
 // Toeplitz column pass (2D): zero-padded column FFT, multiplication by the
 // real transfer function T, inverse FFT, for grid columns [c0, c0 + tile) of
-// coil l; only the ny image rows of mid are read and written (in place).
+// coil l; only the ny = K/2 image rows of mid are read and written (in
+// place).  Every offset within one coil's mid fits 32 bits.
 template <int K1, int K2>
 __device__ __forceinline__ void cols_toep_body(float2* __restrict__ mid, int ny, int Kx,
                                                const float2* __restrict__ tw, int tile,
@@ -261,15 +341,16 @@ __device__ __forceinline__ void cols_toep_body(float2* __restrict__ mid, int ny,
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;
   const bool colok = c < tile;
-  float2* col = mid + (long long)l * ny * Kx + c0 + c;
+  float2* strip = mid + (long long)l * ny * Kx + c0;
   float2 u[K2];
-  col_fwd<K1, K2>(col, Kx, ny, colok, tw, lds, u);
+  col_fwd<K1, K2, true, unsigned>(strip, (unsigned)Kx, ny, colok, tw, lds, u);
   if (colok) {
-    const float* Tc = T + c0 + c;
+    const float* Ts = T + c0;
+    const unsigned tb = ((unsigned)c + (unsigned)t * (unsigned)Kx) * 4u;
 #pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], Tc[(long long)(t + K1 * k2) * Kx]);
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, tb + (unsigned)(K1 * k2) * (unsigned)Kx * 4u));
   }
-  col_inv<K1, K2>(col, Kx, ny, colok, tw, lds, u);
+  col_inv<K1, K2, true, unsigned>(strip, (unsigned)Kx, ny, colok, tw, lds, u);
 }
 
 }  // namespace pnp

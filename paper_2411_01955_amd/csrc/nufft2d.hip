@@ -141,7 +141,7 @@ k_rows_fwd(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
     float2 v = make_float2(0.f, 0.f);
     if (ix >= 0) {
       const long long pix = (long long)iy * nx + ix;
-      const float2 xv = img_at(in, pix, bt, li == 0 && blockIdx.y == 0);
+      const float2 xv = img_at(in, (long long)iy * nx, ix, bt, li == 0 && blockIdx.y == 0);
       v = cscale(cmul(S[(long long)(l0 + li) * N + pix], xv), dax[ix] * sy);
     }
     a[li * Kx + j] = v;
@@ -246,10 +246,13 @@ k_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L, 
 // =====================================================================
 // Register path: four-step transforms, K = K1*K2
 // =====================================================================
-// RC coils per workgroup (static LDS; RC = 8 only where it fits in 64 KB)
+// RC coils per workgroup (static LDS: RC transpose blocks and one image
+// row; RC = 8 only where it fits in 64 KB).  The 2D row kernels run on
+// images of side K/2 (HALF), with 32-bit offsets (one coil group's mid and
+// maps stay far below 4 GB).
 template <int K1, int K2>
 constexpr int fit_rc(int rc) {
-  return (size_t)rc * FS<K1, K2>::LA * sizeof(float2) <= 65536 ? rc : 4;
+  return ((size_t)rc * FS<K1, K2>::LA + FS<K1, K2>::K / 2) * sizeof(float2) <= 65536 ? rc : 4;
 }
 
 template <int K1, int K2, int RC>
@@ -258,7 +261,8 @@ k_rows_fwd_fs(ImgIn in, const float2* __restrict__ S, int L, int nx, int ny,
               const float* __restrict__ dax, const float* __restrict__ day,
               const float2* __restrict__ tw, float2* __restrict__ mid) {
   __shared__ float2 A[RC * FS<K1, K2>::LA];
-  rows_fwd_body<K1, K2, RC>(in, S, L, nx, ny, dax, day, tw, mid, blockIdx.x, blockIdx.y, A);
+  __shared__ float2 X[FS<K1, K2>::K / 2];
+  rows_fwd_body<K1, K2, RC, true, unsigned>(in, S, L, nx, ny, dax, day, tw, mid, blockIdx.x, blockIdx.y, A, X);
 }
 
 template <int K1, int K2>
@@ -455,7 +459,7 @@ k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int 
               const float* __restrict__ dax, const float* __restrict__ day,
               const float2* __restrict__ tw, float2* __restrict__ part) {
   __shared__ float2 A[RC * FS<K1, K2>::LA];
-  rows_adj_body<K1, K2, RC>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
+  rows_adj_body<K1, K2, RC, true, unsigned>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
 }
 
 template <int K1, int K2>
@@ -534,10 +538,12 @@ __global__ void __launch_bounds__(kRowCoils * K1)
 k_batch_rows_fwd(const BatchSlice* __restrict__ sl, const NormalIn* __restrict__ ins,
                  const int4* __restrict__ items, int n_items) {
   __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
+  __shared__ float2 X[FS<K1, K2>::K / 2];
   const int4 w = items[xcd_order(blockIdx.x, n_items)];
   const BatchSlice& b = sl[w.x];
   const ImgIn in{ins[w.x].x, ins[w.x].cg};
-  rows_fwd_body<K1, K2>(in, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.mid, w.y, w.z, A);
+  rows_fwd_body<K1, K2, kRowCoils, true, unsigned>(in, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.mid, w.y, w.z,
+                                                   A, X);
 }
 
 template <int K1, int K2>
@@ -555,7 +561,8 @@ k_batch_rows_adj(const BatchSlice* __restrict__ sl, const int4* __restrict__ ite
   __shared__ float2 A[kRowCoils * FS<K1, K2>::LA];
   const int4 w = items[xcd_order(blockIdx.x, n_items)];
   const BatchSlice& b = sl[w.x];
-  rows_adj_body<K1, K2>(b.mid, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.part, w.y, w.z, A);
+  rows_adj_body<K1, K2, kRowCoils, true, unsigned>(b.mid, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.part, w.y,
+                                                   w.z, A);
 }
 
 template <int K1, int K2>

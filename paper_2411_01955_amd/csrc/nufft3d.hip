@@ -34,22 +34,30 @@ namespace {
 
 constexpr int kRowCoils3 = 4;
 
+// Offsets in the 3D passes are 64-bit (a coil group's mid exceeds 4 GB at
+// 384^3).  HALF: the axis is zero-padded from n = K/2 (every operator pass);
+// without it the pass transforms a full grid-sized array (the transfer
+// function's DFT).
+using Off3 = unsigned long long;
+
 // x pass (forward): rows are the nz*ny image lines
-template <int K1, int K2>
+template <int K1, int K2, bool HALF>
 __global__ void __launch_bounds__(kRowCoils3 * K1)
 k3_rows_fwd(ImgIn in, const float2* __restrict__ S, int L, int nx, int nrows, const float* __restrict__ dax,
             const float* __restrict__ dyz, const float2* __restrict__ tw, float2* __restrict__ mid) {
   __shared__ float2 A[kRowCoils3 * FS<K1, K2>::LA];
-  rows_fwd_body<K1, K2>(in, S, L, nx, nrows, dax, dyz, tw, mid, blockIdx.x, blockIdx.y, A);
+  __shared__ float2 X[FS<K1, K2>::K];
+  rows_fwd_body<K1, K2, kRowCoils3, HALF, Off3>(in, S, L, nx, nrows, dax, dyz, tw, mid, blockIdx.x, blockIdx.y, A,
+                                                X);
 }
 
-template <int K1, int K2>
+template <int K1, int K2, bool HALF>
 __global__ void __launch_bounds__(kRowCoils3 * K1)
 k3_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int nrows,
             const float* __restrict__ dax, const float* __restrict__ dyz, const float2* __restrict__ tw,
             float2* __restrict__ part) {
   __shared__ float2 A[kRowCoils3 * FS<K1, K2>::LA];
-  rows_adj_body<K1, K2>(mid, S, L, nx, nrows, dax, dyz, tw, part, blockIdx.x, blockIdx.y, A);
+  rows_adj_body<K1, K2, kRowCoils3, HALF, Off3>(mid, S, L, nx, nrows, dax, dyz, tw, part, blockIdx.x, blockIdx.y, A);
 }
 
 // A set of columns: workgroup (strip, set) works on columns c0 .. c0+7 of
@@ -61,7 +69,7 @@ struct ColSets {
 };
 
 // forward: zero-padded image rows (nimg) -> all K rows
-template <int K1, int K2>
+template <int K1, int K2, bool HALF>
 __global__ void __launch_bounds__(8 * K1)
 k3_cols_fwd(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs, int nimg,
             const float2* __restrict__ tw) {
@@ -69,16 +77,17 @@ k3_cols_fwd(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
   const int c = threadIdx.x % 8, t = threadIdx.x / 8;
   const int a = blockIdx.y / cs.nb, b = blockIdx.y % cs.nb;
   const int c0 = blockIdx.x * 8;
-  const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0 + c;
-  float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0 + c;
+  const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0;
+  float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
-  col_fwd<K1, K2>(src, cs.rs_in, nimg, true, tw, lds, u);
+  col_fwd<K1, K2, HALF, Off3>(src, (Off3)cs.rs_in, nimg, true, tw, lds, u);
+  const Off3 rb = (Off3)cs.rs_out * 8u, cb = (Off3)c * 8u + (Off3)t * rb;
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) dst[(long long)(t + K1 * k2) * cs.rs_out] = u[k2];
+  for (int k2 = 0; k2 < K2; ++k2) st_off(dst, cb + (Off3)(K1 * k2) * rb, u[k2]);
 }
 
 // inverse: all K rows -> image rows (nimg), cropped
-template <int K1, int K2>
+template <int K1, int K2, bool HALF>
 __global__ void __launch_bounds__(8 * K1)
 k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs, int nimg,
             const float2* __restrict__ tw) {
@@ -86,12 +95,13 @@ k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
   const int c = threadIdx.x % 8, t = threadIdx.x / 8;
   const int a = blockIdx.y / cs.nb, b = blockIdx.y % cs.nb;
   const int c0 = blockIdx.x * 8;
-  const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0 + c;
-  float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0 + c;
+  const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0;
+  float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
+  const Off3 rb = (Off3)cs.rs_in * 8u, cb = (Off3)c * 8u + (Off3)t * rb;
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) u[k2] = src[(long long)(t + K1 * k2) * cs.rs_in];
-  col_inv<K1, K2>(dst, cs.rs_out, nimg, true, tw, lds, u);
+  for (int k2 = 0; k2 < K2; ++k2) u[k2] = ld_off(src, cb + (Off3)(K1 * k2) * rb);
+  col_inv<K1, K2, HALF, Off3>(dst, (Off3)cs.rs_out, nimg, true, tw, lds, u);
 }
 
 // z pass of the Toeplitz operator, in place on g2: sets (coil l, row ky),
@@ -108,13 +118,14 @@ k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float
   const int rest = lin / L;                 // = ky * nstrips + strip
   const int ky = rest / nstrips, c0 = (rest % nstrips) * 8;
   const long long plane = (long long)Ky * Kx;
-  float2* col = g2 + (long long)l * nz * plane + (long long)ky * Kx + c0 + c;
+  float2* strip = g2 + (long long)l * nz * plane + (long long)ky * Kx + c0;
   float2 u[K2];
-  col_fwd<K1, K2>(col, plane, nz, true, tw, lds, u);
-  const float* Tc = T + (long long)ky * Kx + c0 + c;
+  col_fwd<K1, K2, true, Off3>(strip, (Off3)plane, nz, true, tw, lds, u);
+  const float* Ts = T + (long long)ky * Kx + c0;
+  const Off3 tb = (Off3)plane * 4u, cb = (Off3)c * 4u + (Off3)t * tb;
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], Tc[(long long)(t + K1 * k2) * plane]);
-  col_inv<K1, K2>(col, plane, nz, true, tw, lds, u);
+  for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, cb + (Off3)(K1 * k2) * tb));
+  col_inv<K1, K2, true, Off3>(strip, (Off3)plane, nz, true, tw, lds, u);
 }
 
 // type-2 interpolation: y[l][m] = scale * sum of the 6^3 taps of grid[l]
@@ -220,27 +231,43 @@ __global__ void k3_psf_prepare(float2* __restrict__ a, int Nx, int Ny, int Nz, f
 // ------------------------------------------------------------- launchers
 template <int K1, int K2>
 struct F3 {
+  static constexpr int K = K1 * K2;
   static void rows_fwd(const ImgIn& in, const float2* S, int L, int nx, int nrows, const float* dax,
                        const float* dyz, const float2* tw, float2* mid, hipStream_t s) {
     const int G = (L + kRowCoils3 - 1) / kRowCoils3;
-    PNP_LAUNCH((k3_rows_fwd<K1, K2>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, in, S, L, nx, nrows, dax, dyz,
-               tw, mid);
+    if (2 * nx == K)
+      PNP_LAUNCH((k3_rows_fwd<K1, K2, true>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, in, S, L, nx, nrows, dax,
+                 dyz, tw, mid);
+    else
+      PNP_LAUNCH((k3_rows_fwd<K1, K2, false>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, in, S, L, nx, nrows, dax,
+                 dyz, tw, mid);
   }
   static void rows_adj(const float2* mid, const float2* S, int L, int nx, int nrows, const float* dax,
                        const float* dyz, const float2* tw, float2* part, hipStream_t s) {
     const int G = (L + kRowCoils3 - 1) / kRowCoils3;
-    PNP_LAUNCH((k3_rows_adj<K1, K2>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, mid, S, L, nx, nrows, dax, dyz,
-               tw, part);
+    if (2 * nx == K)
+      PNP_LAUNCH((k3_rows_adj<K1, K2, true>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, mid, S, L, nx, nrows, dax,
+                 dyz, tw, part);
+    else
+      PNP_LAUNCH((k3_rows_adj<K1, K2, false>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, mid, S, L, nx, nrows,
+                 dax, dyz, tw, part);
   }
   static void cols_fwd(const float2* in, float2* out, const ColSets& cs, int nsets, int Kc, int nimg,
                        const float2* tw, hipStream_t s) {
-    PNP_LAUNCH((k3_cols_fwd<K1, K2>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
+    if (2 * nimg == K)
+      PNP_LAUNCH((k3_cols_fwd<K1, K2, true>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
+    else
+      PNP_LAUNCH((k3_cols_fwd<K1, K2, false>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
   }
   static void cols_inv(const float2* in, float2* out, const ColSets& cs, int nsets, int Kc, int nimg,
                        const float2* tw, hipStream_t s) {
-    PNP_LAUNCH((k3_cols_inv<K1, K2>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
+    if (2 * nimg == K)
+      PNP_LAUNCH((k3_cols_inv<K1, K2, true>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
+    else
+      PNP_LAUNCH((k3_cols_inv<K1, K2, false>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
   }
   static void cols_toep(float2* g2, int L, int nz, int Ky, int Kx, const float2* tw, const float* T, hipStream_t s) {
+    if (2 * nz != K) fail(PNP_ERR_SHAPE, "3D Toeplitz pass needs a grid twice the image along z");
     PNP_LAUNCH((k3_cols_toep<K1, K2>), dim3(L * Ky * (Kx / 8)), dim3(8 * K1), 0, s, g2, L, nz, Ky, Kx, tw, T);
   }
 };
