@@ -204,6 +204,59 @@ def psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, n_slices):
     return out
 
 
+def pgd_fista(pnp, torch, plan, toep, Sd, dd, w, S, nrm, seed, b_alg):
+    """PnP-PGD (Id, F-1; wavelet prior on the annealed sigma schedule) and
+    FISTA-Wavelet on the clinical slice, 30 iterations each, gamma = 1/||N||:
+    time per solve, normal operators per second and final PSNR.  The FISTA
+    weight is picked once on a training phantom (seed 0) from a small grid."""
+    import synth
+    n, L = w.n, w.L
+    M = w.traj.k.shape[0]
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)
+    gamma = 1.0 / nrm
+    wav = pnp.WaveletPrior(0, KAPPA)
+
+    def data(sd):
+        x, roi = synth.phantom2d(n, sd)
+        y = plan.forward(torch.from_numpy(x).cuda(), Sd)
+        y += torch.from_numpy(synth.complex_noise((L, M), synth.noise_variance(x, S), synth.SEED_NOISE + sd)).cuda()
+        return x, roi, y
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) / reps
+
+    xt, rt, yt = data(0)
+    scale = float(plan.adjoint(yt, Sd, dd).abs().max())
+    best = None
+    for rel in (1e-3, 3e-3, 1e-2, 3e-2):
+        lam = rel * scale * nrm
+        xr = pnp.fista_wavelet(plan, yt, Sd, dd, lam, gamma, w.n_out, toeplitz=toep)
+        p = psnr_roi(xr.cpu().numpy(), xt, rt)
+        if best is None or p > best[1]:
+            best = (rel, p)
+    x, roi, y = data(seed)
+    out = {"iterations": w.n_out, "gamma_times_norm": 1.0}
+    runs = {
+        "pgd_id": (lambda: pnp.pgd_solve(plan, y, Sd, dd, wav, sig, gamma, "id", opnorm=nrm, toeplitz=toep), 1),
+        "pgd_f1": (lambda: pnp.pgd_solve(plan, y, Sd, dd, wav, sig, gamma, "f1", opnorm=nrm, toeplitz=toep), 2),
+        "fista_wavelet": (lambda: pnp.fista_wavelet(plan, y, Sd, dd, best[0] * scale * nrm, gamma, w.n_out,
+                                                    toeplitz=toep), 1),
+    }
+    for name, (fn, ops) in runs.items():
+        xr, sec = timed(fn)
+        n_ops = ops * w.n_out
+        out[name] = {"ms_per_solve": round(sec * 1e3, 3), "normal_ops": n_ops,
+                     "GBps": round(n_ops * b_alg / sec / 1e9, 1), "psnr_db": round(psnr_roi(xr.cpu().numpy(), x, roi), 2)}
+    out["fista_wavelet"]["lam_rel_to_max_b0"] = best[0]
+    return out
+
+
 def batched_c4(pnp, torch, reps=10):
     """The 24-slice table through the batched path vs one slice at a time."""
     import synth
@@ -399,6 +452,7 @@ def main():
                     help="held-out phantoms of the learned-vs-wavelet PSNR race (0: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
+    ap.add_argument("--no-pgd", action="store_true", help="skip the PnP-PGD / FISTA-Wavelet measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
@@ -514,6 +568,7 @@ def main():
         torch.cuda.synchronize()
 
     race = psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.psnr_slices) if args.psnr_slices > 0 else None
+    others = None if args.no_pgd else pgd_fista(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.seed, B)
     unet = unet_rates(pnp, torch)
     batched = None if args.no_batched else batched_c4(pnp, torch)
     vol3d = None if args.no_3d else volume_3d(pnp, torch)
@@ -548,6 +603,7 @@ def main():
         "roofline": roofline,
         "autotune": tuning,
         "psnr_race": race,
+        "pgd_fista": others,
         "batched": batched,
         "volume_3d": vol3d,
         "unet": unet,

@@ -320,6 +320,36 @@ pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* 
                          int32_t n_out, const pnp_hqs_opts* opts, pnp_c64* x_out,
                          pnp_hqs_report* report, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* PnP-PGD (Sec. 3.3, the preconditioned plug-and-play proximal gradient
+ * scheme), one noise level per iteration:
+ *   b0 = A^H D_w y;  x = x0 (or b0)
+ *   for k = 0..n_iter-1:  u = x - gamma P (A^H D_w A x - b0);  x = D_{sigma[k]}(u)
+ * with P = c0 - c1 alpha A^H D_w A as in pnp_hqs_solve (alpha = 1/opnorm,
+ * opnorm > 0 required unless precond is PNP_PRECOND_ID).  One normal
+ * operator per iteration with P = Id, two otherwise.  A UNet prior is
+ * applied without its fallback.
+ *   y, smaps, dcf, x0, x_out as in pnp_hqs_solve;  sigmas host double [n_iter]
+ *   toeplitz  NULL: gridded normal operator; else the Toeplitz one
+ *   ws        the pnp_hqs_workspace_bytes workspace.  Asynchronous on `stream`. */
+pnp_status pnp_pgd_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                         const float* dcf, const pnp_prior* prior, const double* sigmas, int32_t n_iter,
+                         double gamma, int32_t precond, double opnorm, const pnp_toeplitz* toeplitz,
+                         const pnp_c64* x0, pnp_c64* x_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* FISTA-Wavelet (the wavelet baseline of Table 1): FISTA (Beck and Teboulle
+ * 2009) on f(x) + lam ||detail(Psi x)||_1, Psi the orthonormal Haar
+ * transform with `levels` levels (0: the default rule), only detail bands
+ * penalised:
+ *   z = x = x0 (or b0), t = 1
+ *   for k: x' = soft_{gamma lam}(z - gamma (A^H D_w A z - b0))
+ *          t' = (1 + sqrt(1 + 4 t^2)) / 2;  z = x' + ((t - 1)/t') (x' - x);  x = x', t = t'
+ * gamma > 0 is the step (convergent for gamma <= 1/||A^H D_w A||), lam >= 0.
+ * Arguments and workspace as in pnp_pgd_solve; x_out receives x_{n_iter}. */
+pnp_status pnp_fista_wavelet(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                             const float* dcf, int32_t levels, double lam, double gamma, int32_t n_iter,
+                             const pnp_toeplitz* toeplitz, const pnp_c64* x0, pnp_c64* x_out, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------ autotuning
  * The register-FFT row passes of a plan handle 2, 4 or 8 coils per
  * workgroup (default 4).  pnp_autotune times the normal operator the caller

@@ -21,6 +21,9 @@ Paper passages followed:
   P = 4 - (10/3) A^H A (read with the same alpha normalisation);
   identity P = Id.  alpha = 1/||A^H D_w A||.
 * PnP-PGD (Sec. 3.3):  u_k = x_k - gamma P grad f(x_k),  x_{k+1} = D_sigma(u_k)
+* FISTA with the wavelet l1 prior (the FISTA-Wavelet baseline of Table 1):
+  the accelerated proximal gradient method of Beck and Teboulle (2009) on
+  f(x) + lam ||detail(Psi x)||_1.
 """
 from __future__ import annotations
 
@@ -193,3 +196,37 @@ def pgd(b0, normal, x0, gamma: float, n_iter: int, prior, sigma: float, precond:
         Pg = c0 * g - c1a * normal(g) if c1 != 0.0 else c0 * g
         x = np.asarray(prior(x - gamma * Pg, sigma), dtype=np.complex128)
     return x
+
+
+def pgd_schedule(b0, normal, x0, gamma: float, sigmas, prior, precond: str = "id", opnorm_value: float = 1.0):
+    """PnP-PGD with one noise level per iteration (sigma_k of ``sigmas``),
+    each step the PnP-PGD step of Sec. 3.3 at fixed gamma."""
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for sigma in sigmas:
+        x = pgd(b0, normal, x, gamma, 1, prior, float(sigma), precond, opnorm_value)
+    return x
+
+
+def fista(b0, normal, x0, gamma: float, n_iter: int, prox):
+    """FISTA (Beck and Teboulle 2009) for f + g, f the data term with
+    gradient N x - b0 and ``prox(v)`` = prox_{gamma g}(v):
+        x_k     = prox(z_k - gamma (N z_k - b0))
+        t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+        z_{k+1} = x_k + ((t_k - 1) / t_{k+1}) (x_k - x_{k-1})
+    from z_1 = x_0 and t_1 = 1.  Returns x_{n_iter}."""
+    x_prev = np.array(x0, dtype=np.complex128, copy=True)
+    z = x_prev.copy()
+    t = 1.0
+    for _ in range(n_iter):
+        x = np.asarray(prox(z - gamma * (normal(z) - b0)), dtype=np.complex128)
+        t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        z = x + ((t - 1.0) / t_next) * (x - x_prev)
+        x_prev, t = x, t_next
+    return x_prev
+
+
+def fista_wavelet(b0, normal, x0, gamma: float, lam: float, n_iter: int, levels: int | None = None):
+    """FISTA on f(x) + lam ||detail(Psi x)||_1 (orthonormal Haar, detail bands
+    only): the prox is the wavelet soft threshold at tau = gamma * lam."""
+    from . import wavelet
+    return fista(b0, normal, x0, gamma, n_iter, lambda v: wavelet.wavelet_denoise(v, gamma * lam, levels))

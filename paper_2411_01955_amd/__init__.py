@@ -307,6 +307,49 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
     return x, None
 
 
+def pgd_solve(plan: Plan, y, smaps, dcf, prior, sigmas, gamma: float, precond: str = "id", opnorm: float = 0.0,
+              x0=None, out=None, toeplitz: "Toeplitz" = None):
+    """PnP-PGD with one noise level per iteration (sigmas); returns x."""
+    torch = _torch()
+    L = plan._L(smaps)
+    _need_c64(y, "y", (L, plan.M))
+    _need_f32(dcf, "dcf", (plan.M,))
+    if x0 is not None:
+        _need_c64(x0, "x0", plan.shape)
+    if toeplitz is not None and toeplitz.plan is not plan:
+        raise ValueError("toeplitz was built for another plan")
+    n = len(sigmas)
+    sig = (C.c_double * n)(*[float(s) for s in sigmas])
+    x = out if out is not None else torch.empty(plan.shape, dtype=torch.complex64, device=y.device)
+    _need_c64(x, "out", plan.shape)
+    ws, nb = plan.workspace(L, "hqs")
+    check(load().pnp_pgd_solve(plan.handle, _ptr(y), _ptr(smaps), L, _ptr(dcf), prior.handle, sig, n, float(gamma),
+                               PRECOND[precond.lower()], float(opnorm),
+                               toeplitz.handle.value if toeplitz is not None else None,
+                               x0.data_ptr() if x0 is not None else None, _ptr(x), _ptr(ws), nb, _stream()))
+    return x
+
+
+def fista_wavelet(plan: Plan, y, smaps, dcf, lam: float, gamma: float, n_iter: int, levels: int = 0, x0=None,
+                  out=None, toeplitz: "Toeplitz" = None):
+    """FISTA on f + lam ||detail(Haar x)||_1; returns x."""
+    torch = _torch()
+    L = plan._L(smaps)
+    _need_c64(y, "y", (L, plan.M))
+    _need_f32(dcf, "dcf", (plan.M,))
+    if x0 is not None:
+        _need_c64(x0, "x0", plan.shape)
+    if toeplitz is not None and toeplitz.plan is not plan:
+        raise ValueError("toeplitz was built for another plan")
+    x = out if out is not None else torch.empty(plan.shape, dtype=torch.complex64, device=y.device)
+    _need_c64(x, "out", plan.shape)
+    ws, nb = plan.workspace(L, "hqs")
+    check(load().pnp_fista_wavelet(plan.handle, _ptr(y), _ptr(smaps), L, _ptr(dcf), int(levels), float(lam),
+                                   float(gamma), int(n_iter), toeplitz.handle.value if toeplitz is not None else None,
+                                   x0.data_ptr() if x0 is not None else None, _ptr(x), _ptr(ws), nb, _stream()))
+    return x
+
+
 # ------------------------------------------------------------------ UNet
 # Parameters trained by train_unet.py (2,000 seeded 320 x 320 phantoms, 100
 # epochs, batch 10, 128 x 128 patches, sigma ~ U(0.001, 0.1), Adam 1e-4).

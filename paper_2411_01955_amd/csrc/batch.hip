@@ -49,8 +49,7 @@ __device__ __forceinline__ float2 sum_groups(const float2* __restrict__ part, in
 
 // chunk items: {slice, first element, chunk index within the slice, chunks of the slice}
 __global__ void __launch_bounds__(kRedThreads)
-k_bcg_init(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef co, double* __restrict__ parts,
-           DevScalars* __restrict__ sc, double* __restrict__ rho, int k) {
+k_bcg_init(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef co, double* __restrict__ parts) {
   const int4 c = ch[blockIdx.x];
   const BVec& v = vec[c.x];
   const long long e = std::min<long long>((long long)c.y + kChunk, v.N);
@@ -68,15 +67,23 @@ k_bcg_init(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef 
     acc[1] += re_dot(xv, nv);
     acc[2] += re_dot(xv, bv);
   }
+  block_parts<3>(acc, parts + (long long)c.x * kRedBlocks * 3, c.z);
+}
+
+// one workgroup per slice: the slice's chunk sums -> rr and rho
+__global__ void __launch_bounds__(kRedThreads)
+k_bcg_init_fin(const BVec* __restrict__ vec, const double* __restrict__ parts, DevScalars* __restrict__ sc,
+               double* __restrict__ rho, int k) {
+  const int i = blockIdx.x;
+  const int nch = (int)((vec[i].N + kChunk - 1) / kChunk);
   double s[3];
-  if (reduce_last_of<3>(acc, parts + (long long)c.x * kRedBlocks * 3, &sc[c.x].cnt, c.w, c.z, s) &&
-      threadIdx.x == 0)
-    cg_finish_init(&sc[c.x], s[0], s[1], s[2], rho + (long long)c.x * (kBatchMaxOuter + 1) + k);
+  sum_parts<3>(parts + (long long)i * kRedBlocks * 3, nch, s);
+  if (threadIdx.x == 0) cg_finish_init(&sc[i], s[0], s[1], s[2], rho + (long long)i * (kBatchMaxOuter + 1) + k);
 }
 
 __global__ void __launch_bounds__(kRedThreads)
-k_bcg_dots(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef co, float c0, int cur, int first,
-           double* __restrict__ parts, DevScalars* __restrict__ sc) {
+k_bcg_dots(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef co, float c0, int cur,
+           double* __restrict__ parts) {
   const int4 c = ch[blockIdx.x];
   const BVec& v = vec[c.x];
   const long long e = std::min<long long>((long long)c.y + kChunk, v.N);
@@ -90,10 +97,18 @@ k_bcg_dots(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef 
     acc[0] += re_dot(rv, rv);
     acc[1] += re_dot(wv, rv);
   }
+  block_parts<2>(acc, parts + (long long)c.x * kRedBlocks * 3, c.z);
+}
+
+// one workgroup per slice: the slice's chunk sums -> alpha, beta, rr
+__global__ void __launch_bounds__(kRedThreads)
+k_bcg_dots_fin(const BVec* __restrict__ vec, const double* __restrict__ parts, int first,
+               DevScalars* __restrict__ sc) {
+  const int i = blockIdx.x;
+  const int nch = (int)((vec[i].N + kChunk - 1) / kChunk);
   double s[2];
-  if (reduce_last_of<2>(acc, parts + (long long)c.x * kRedBlocks * 3, &sc[c.x].cnt, c.w, c.z, s) &&
-      threadIdx.x == 0)
-    cg_finish_dots(&sc[c.x], s[0], s[1], first);
+  sum_parts<2>(parts + (long long)i * kRedBlocks * 3, nch, s);
+  if (threadIdx.x == 0) cg_finish_dots(&sc[i], s[0], s[1], first);
 }
 
 // u[1-cur] = u[cur] + alpha (r[cur] + beta p[cur])
@@ -436,7 +451,8 @@ void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas,
       co.cg[i] = (float)(gamma - c1s[precond] / b->h[i].s.opnorm);
     }
     launch_stages(b, b->d_in[0], s);   // N x
-    PNP_LAUNCH(k_bcg_init, gch, bch, 0, s, b->d_chunks, b->d_vec, co, b->d_parts, b->d_sc, b->d_rho, k);
+    PNP_LAUNCH(k_bcg_init, gch, bch, 0, s, b->d_chunks, b->d_vec, co, b->d_parts);
+    PNP_LAUNCH(k_bcg_init_fin, dim3(B), bch, 0, s, b->d_vec, b->d_parts, b->d_sc, b->d_rho, k);
     int c = 0;
     for (int j = 0; j < n_cg; ++j) {
       const NormalIn* ins = b->d_in[1];
@@ -445,8 +461,8 @@ void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas,
         c = 1 - c;
       }
       launch_stages(b, ins, s);
-      PNP_LAUNCH(k_bcg_dots, gch, bch, 0, s, b->d_chunks, b->d_vec, co, (float)c0, c, j == 0 ? 1 : 0,
-                 b->d_parts, b->d_sc);
+      PNP_LAUNCH(k_bcg_dots, gch, bch, 0, s, b->d_chunks, b->d_vec, co, (float)c0, c, b->d_parts);
+      PNP_LAUNCH(k_bcg_dots_fin, dim3(B), bch, 0, s, b->d_vec, b->d_parts, j == 0 ? 1 : 0, b->d_sc);
     }
     PNP_LAUNCH(k_bcg_final, gch, bch, 0, s, b->d_chunks, b->d_vec, c, (const DevScalars*)b->d_sc);
     const int cur = 1 - c;               // the prox result u lives in set cur
@@ -461,7 +477,8 @@ void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas,
   if (rho_host) {
     SliceCoef zero{};
     launch_stages(b, b->d_in[0], s);
-    PNP_LAUNCH(k_bcg_init, gch, bch, 0, s, b->d_chunks, b->d_vec, zero, b->d_parts, b->d_sc, b->d_rho, n_out);
+    PNP_LAUNCH(k_bcg_init, gch, bch, 0, s, b->d_chunks, b->d_vec, zero, b->d_parts);
+    PNP_LAUNCH(k_bcg_init_fin, dim3(B), bch, 0, s, b->d_vec, b->d_parts, b->d_sc, b->d_rho, n_out);
   }
   PNP_LAUNCH(k_bcopy, gch, bch, 0, s, b->d_chunks, b->d_vec, 1, (float2* const*)nullptr);
   if (rho_host || bad_host) {

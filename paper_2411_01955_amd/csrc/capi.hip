@@ -522,6 +522,81 @@ pnp_status pnp_hqs_solve_batched(pnp_batch* batch, const pnp_prior* prior, const
   });
 }
 
+pnp_status pnp_pgd_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* smaps, int32_t L, const float* dcf,
+                         const pnp_prior* prior, const double* sigmas, int32_t n_iter, double gamma,
+                         int32_t precond, double opnorm, const pnp_toeplitz* toeplitz, const pnp_c64* x0,
+                         pnp_c64* x_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(y, "y");
+    need(smaps, "smaps");
+    need(prior, "prior");
+    need(sigmas, "sigmas");
+    need(x_out, "x_out");
+    need(ws, "ws");
+    if (n_iter < 1) fail(PNP_ERR_SHAPE, "n_iter must be >= 1");
+    if (precond < 0 || precond > 2) fail(PNP_ERR_ARG, "unknown preconditioner %d", precond);
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) fail(PNP_ERR_ARG, "gamma must be > 0");
+    if (precond != 0 && (!(opnorm > 0.0) || !std::isfinite(opnorm)))
+      fail(PNP_ERR_ARG, "a preconditioned PGD needs opnorm > 0");
+    for (int k = 0; k < n_iter; ++k)
+      if (!(sigmas[k] > 0.0) || !std::isfinite(sigmas[k])) fail(PNP_ERR_ARG, "sigma[%d] must be > 0", k);
+    if ((const void*)x_out == (const void*)y || (const void*)x_out == (const void*)smaps)
+      fail(PNP_ERR_ARG, "x_out must not alias y or smaps");
+    if (toeplitz && toeplitz->plan != p) fail(PNP_ERR_ARG, "toeplitz was built for another plan");
+    check_ws(ws_bytes, hqs_workspace_bytes(p, L), ws);
+    PGDArgs a;
+    a.y = (const float2*)y;
+    a.smaps = (const float2*)smaps;
+    a.L = L;
+    a.dcf = dcf;
+    a.prior = prior;
+    a.sigmas = sigmas;
+    a.n_iter = n_iter;
+    a.precond = precond;
+    a.gamma = gamma;
+    a.opnorm = precond != 0 ? opnorm : 1.0;
+    a.x0 = (const float2*)x0;
+    a.x_out = (float2*)x_out;
+    a.toep = toeplitz;
+    pgd_solve(p, a, ws, stream);
+  });
+}
+
+pnp_status pnp_fista_wavelet(const pnp_plan* p, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
+                             const float* dcf, int32_t levels, double lam, double gamma, int32_t n_iter,
+                             const pnp_toeplitz* toeplitz, const pnp_c64* x0, pnp_c64* x_out, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(y, "y");
+    need(smaps, "smaps");
+    need(x_out, "x_out");
+    need(ws, "ws");
+    if (n_iter < 1) fail(PNP_ERR_SHAPE, "n_iter must be >= 1");
+    if (levels < 0) fail(PNP_ERR_ARG, "levels must be >= 0");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) fail(PNP_ERR_ARG, "gamma must be > 0");
+    if (!(lam >= 0.0) || !std::isfinite(lam)) fail(PNP_ERR_ARG, "lam must be >= 0");
+    if ((const void*)x_out == (const void*)y || (const void*)x_out == (const void*)smaps)
+      fail(PNP_ERR_ARG, "x_out must not alias y or smaps");
+    if (toeplitz && toeplitz->plan != p) fail(PNP_ERR_ARG, "toeplitz was built for another plan");
+    check_ws(ws_bytes, hqs_workspace_bytes(p, L), ws);
+    FISTAArgs a;
+    a.y = (const float2*)y;
+    a.smaps = (const float2*)smaps;
+    a.L = L;
+    a.dcf = dcf;
+    a.levels = levels;
+    a.lam = lam;
+    a.gamma = gamma;
+    a.n_iter = n_iter;
+    a.x0 = (const float2*)x0;
+    a.x_out = (float2*)x_out;
+    a.toep = toeplitz;
+    fista_wavelet(p, a, ws, stream);
+  });
+}
+
 // ------------------------------------------------------------- autotuning
 pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const float* dcf,
                         const pnp_toeplitz* toeplitz, const char* cache_path, pnp_tuning* out,

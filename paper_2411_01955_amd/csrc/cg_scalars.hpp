@@ -71,6 +71,52 @@ __device__ bool reduce_last(double (&v)[Q], double* __restrict__ parts, unsigned
   return reduce_last_of<Q>(v, parts, cnt, (int)gridDim.x, (int)blockIdx.x, out);
 }
 
+// Two-kernel form of the same reduction, for the reductions on the CG
+// path: every block writes its Q block sums to parts[bidx*Q + q] with
+// plain stores (block_parts), and a following one-workgroup kernel sums
+// the partial sets in the same fixed order (sum_parts).  The kernel
+// boundary orders the stores, so no block pays a device-scope fence and an
+// atomic ticket; the results are bitwise those of reduce_last_of.
+template <int Q>
+__device__ void block_parts(double (&v)[Q], double* __restrict__ parts, int bidx) {
+  __shared__ double sh[Q][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const double s = warp_sum(v[q]);
+    if (lane == 0) sh[q][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < Q) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[threadIdx.x][w];
+    parts[bidx * Q + threadIdx.x] = s;
+  }
+}
+
+// Sum of `nblocks` partial sets (one workgroup of kRedThreads threads);
+// every thread receives the sums.
+template <int Q>
+__device__ void sum_parts(const double* __restrict__ parts, int nblocks, double (&out)[Q]) {
+  __shared__ double fin[Q][kRedThreads];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += parts[b * Q + q];
+    fin[q][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) fin[q][threadIdx.x] += fin[q][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) out[q] = fin[q][0];
+}
+
 
 struct DevScalars {
   double rr;        // <r, r>

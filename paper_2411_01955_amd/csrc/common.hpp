@@ -324,4 +324,38 @@ struct HQSArgs {
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
                int* bad_host, int* fb_host);
 
+// PnP-PGD (Sec. 3.3): u = x - gamma P (N x - b0), x = D_{sigma_k}(u)
+struct PGDArgs {
+  const float2* y;
+  const float2* smaps;
+  int L;
+  const float* dcf;
+  const pnp_prior* prior;
+  const double* sigmas;   // host [n_iter]
+  int n_iter;
+  int precond;
+  double gamma;
+  double opnorm;
+  const float2* x0;
+  float2* x_out;
+  const pnp_toeplitz* toep;
+};
+void pgd_solve(const pnp_plan* p, const PGDArgs& a, void* ws, hipStream_t s);
+
+// FISTA on f + lam ||detail(Psi x)||_1 (orthonormal Haar)
+struct FISTAArgs {
+  const float2* y;
+  const float2* smaps;
+  int L;
+  const float* dcf;
+  int levels;       // 0: the default rule
+  double lam;
+  double gamma;
+  int n_iter;
+  const float2* x0;
+  float2* x_out;
+  const pnp_toeplitz* toep;
+};
+void fista_wavelet(const pnp_plan* p, const FISTAArgs& a, void* ws, hipStream_t s);
+
 }  // namespace pnp

@@ -61,12 +61,12 @@ __global__ void k_copy(long long N, const float2* __restrict__ a, float2* __rest
 }
 
 // Nx = sum of the normal operator's partial images; u = x; r = gamma (b0 - Nx);
-// p = s = 0.  Last block: rr = <r,r>, rho(x) = <x,Nx> - 2 Re<x,b0> + ||y||_w^2.
+// p = s = 0; block sums of <r,r>, <x,Nx>, Re<x,b0> (k_cg_init_fin: rr = <r,r>,
+// rho(x) = <x,Nx> - 2 Re<x,b0> + ||y||_w^2).
 __global__ void __launch_bounds__(kRedThreads)
 k_cg_init(long long N, int G, const float2* __restrict__ x, const float2* __restrict__ part,
           const float2* __restrict__ b0, float gamma, float2* __restrict__ u, float2* __restrict__ r,
-          float2* __restrict__ p, float2* __restrict__ sv, double* __restrict__ parts, DevScalars* sc,
-          double* rho_out) {
+          float2* __restrict__ p, float2* __restrict__ sv, double* __restrict__ parts) {
   double acc[3] = {0.0, 0.0, 0.0};
   const float2 z = make_float2(0.f, 0.f);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
@@ -81,18 +81,26 @@ k_cg_init(long long N, int G, const float2* __restrict__ x, const float2* __rest
     acc[1] += re_dot(xv, nv);
     acc[2] += re_dot(xv, bv);
   }
-  double s[3];
-  if (reduce_last<3>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) cg_finish_init(sc, s[0], s[1], s[2], rho_out);
+  block_parts<3>(acc, parts, blockIdx.x);
 }
 
-// w = c0 r + cg N r.  Last block, with g = <r,r>, d = Re<w,r>:
+// one workgroup: the three sums of k_cg_init -> rr and rho
+__global__ void __launch_bounds__(kRedThreads)
+k_cg_init_fin(const double* __restrict__ parts, int nblocks, DevScalars* sc, double* rho_out) {
+  double s[3];
+  sum_parts<3>(parts, nblocks, s);
+  if (threadIdx.x == 0) cg_finish_init(sc, s[0], s[1], s[2], rho_out);
+}
+
+// w = c0 r + cg N r, block sums of g = <r,r> and d = Re<w,r>; then
+// k_cg_dots_fin:
 //   first step:  beta = 0, alpha = g / d
 //   later steps: beta = g / rr, alpha = g / (d - beta g / alpha)
 // then rr = g.  A zero residual gives alpha = beta = 0; a non-positive or
 // non-finite denominator sets `bad` and alpha = beta = 0 (u stops moving).
 __global__ void __launch_bounds__(kRedThreads)
 k_cg_dots(long long N, int G, const float2* __restrict__ r, const float2* __restrict__ part, float c0,
-          float cg, int first, float2* __restrict__ w, double* __restrict__ parts, DevScalars* sc) {
+          float cg, float2* __restrict__ w, double* __restrict__ parts) {
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
@@ -102,8 +110,15 @@ k_cg_dots(long long N, int G, const float2* __restrict__ r, const float2* __rest
     acc[0] += re_dot(rv, rv);
     acc[1] += re_dot(wv, rv);
   }
+  block_parts<2>(acc, parts, blockIdx.x);
+}
+
+// one workgroup: the two sums of k_cg_dots -> alpha, beta, rr
+__global__ void __launch_bounds__(kRedThreads)
+k_cg_dots_fin(const double* __restrict__ parts, int nblocks, int first, DevScalars* sc) {
   double s[2];
-  if (reduce_last<2>(acc, parts, &sc->cnt, s) && threadIdx.x == 0) cg_finish_dots(sc, s[0], s[1], first);
+  sum_parts<2>(parts, nblocks, s);
+  if (threadIdx.x == 0) cg_finish_dots(sc, s[0], s[1], first);
 }
 
 // Last CG step: p = r + beta p, u = u + alpha p (writes u2).
@@ -185,6 +200,49 @@ __global__ void k_scale_into(long long N, const float2* __restrict__ w, const De
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x)
     v[i] = cscale(w[i], s);
+}
+
+// ---- PnP-PGD and FISTA vector steps
+// PnP-PGD with P = Id: u = x - gc0 (N x - b0), N x the sum of the partials
+__global__ void k_pgd_id(long long N, int G, const float2* __restrict__ x, const float2* __restrict__ part,
+                         const float2* __restrict__ b0, float gc0, float2* __restrict__ u) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 xv = x[i], nv = sum_groups(part, G, N, i), bv = b0[i];
+    u[i] = make_float2(xv.x - gc0 * (nv.x - bv.x), xv.y - gc0 * (nv.y - bv.y));
+  }
+}
+
+// g = N x - b0 (the data-term gradient)
+__global__ void k_grad(long long N, int G, const float2* __restrict__ part, const float2* __restrict__ b0,
+                       float2* __restrict__ g) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 nv = sum_groups(part, G, N, i), bv = b0[i];
+    g[i] = make_float2(nv.x - bv.x, nv.y - bv.y);
+  }
+}
+
+// preconditioned step: u = x - gamma P g = x - gc0 g + gc1a N g
+__global__ void k_pgd_step(long long N, int G, const float2* __restrict__ x, const float2* __restrict__ g,
+                           const float2* __restrict__ part, float gc0, float gc1a, float2* __restrict__ u) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 xv = x[i], gv = g[i], nv = sum_groups(part, G, N, i);
+    u[i] = make_float2(xv.x - gc0 * gv.x + gc1a * nv.x, xv.y - gc0 * gv.y + gc1a * nv.y);
+  }
+}
+
+// FISTA: z_k, x_{k-1} -> x_k (v = z - gamma (N z - b0) first, then the
+// wavelet prox) -> z_{k+1} = x_k + beta (x_k - x_{k-1}); x_{k-1} <- x_k
+__global__ void k_fista_mom(long long N, const float2* __restrict__ x, float2* __restrict__ xp, float beta,
+                            float2* __restrict__ z) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 xv = x[i], pv = xp[i];
+    z[i] = make_float2(fmaf(beta, xv.x - pv.x, xv.x), fmaf(beta, xv.y - pv.y, xv.y));
+    xp[i] = xv;
+  }
 }
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -338,7 +396,8 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   auto cg_start = [&](double gamma, double* rho_out) {
     normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u[0],
-               w.r[0], w.p[0], w.s[0], w.parts, w.sc, rho_out);
+               w.r[0], w.p[0], w.s[0], w.parts);
+    PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc, rho_out);
   };
 
   for (int k = 0; k < a.n_out; ++k) {
@@ -359,8 +418,9 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
         c = 1 - c;
       }
       normal_parts(p, a.toep, in, a.smaps, a.L, a.dcf, w.op, s);
-      PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg,
-                 j == 0 ? 1 : 0, w.w, w.parts, w.sc);
+      PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg, w.w,
+                 w.parts);
+      PNP_LAUNCH(k_cg_dots_fin, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, j == 0 ? 1 : 0, w.sc);
     }
     float2* u_res = w.u[1 - c];
     PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res, w.sc);
@@ -390,6 +450,69 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     PNP_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < a.n_out; ++k) rho_host[k] = r[k + 1];
     if (bad_host) *bad_host = h.bad;
+  }
+}
+
+// b0 = A^H D_w y into w.b0, x = x0 (or b0) into x
+static void start_from_data(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf,
+                            const float2* x0, float2* x, const SolverWs& w, hipStream_t s) {
+  const long long N = image_size(p);
+  op_adjoint(p, y, smaps, L, dcf, w.b0, w.op, s);
+  PNP_LAUNCH(k_copy, dim3(vec_blocks(N)), dim3(kRedThreads), 0, s, N, x0 ? x0 : w.b0, x);
+}
+
+void pgd_solve(const pnp_plan* p, const PGDArgs& a, void* ws, hipStream_t s) {
+  SolverWs w = solver_ws(p, a.L, ws);
+  const long long N = image_size(p);
+  const int G = op_groups(p, a.L);
+  const unsigned nb = vec_blocks(N);
+  static const double c0s[3] = {1.0, 2.0, 4.0};
+  static const double c1s[3] = {0.0, 1.0, 10.0 / 3.0};
+  const float gc0 = (float)(a.gamma * c0s[a.precond]);
+  const float gc1a = (float)(a.gamma * c1s[a.precond] / a.opnorm);
+  float2* x = a.x_out;
+  start_from_data(p, a.y, a.smaps, a.L, a.dcf, a.x0, x, w, s);
+  const int nd[3] = {p->ax[0].n, p->ax[1].n, p->ax[2].n};
+  float2* u = w.u[0];
+  float2* g = w.r[0];
+  for (int k = 0; k < a.n_iter; ++k) {
+    normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
+    if (a.precond == 0) {
+      PNP_LAUNCH(k_pgd_id, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, gc0, u);
+    } else {
+      PNP_LAUNCH(k_grad, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.op.part, w.b0, g);
+      normal_parts(p, a.toep, plain_input(g), a.smaps, a.L, a.dcf, w.op, s);
+      PNP_LAUNCH(k_pgd_step, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, g, w.op.part, gc0, gc1a, u);
+    }
+    prior_apply(a.prior, p->ndim, nd, u, x, a.sigmas[k], s);
+  }
+}
+
+void fista_wavelet(const pnp_plan* p, const FISTAArgs& a, void* ws, hipStream_t s) {
+  SolverWs w = solver_ws(p, a.L, ws);
+  const long long N = image_size(p);
+  const int G = op_groups(p, a.L);
+  const unsigned nb = vec_blocks(N);
+  float2* x = a.x_out;
+  start_from_data(p, a.y, a.smaps, a.L, a.dcf, a.x0, x, w, s);
+  float2* xp = w.u[1];
+  float2* z = w.p[0];
+  float2* v = w.r[0];
+  PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, x, xp);
+  PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, x, z);
+  const int nd[3] = {p->ax[0].n, p->ax[1].n, p->ax[2].n};
+  int nmin = nd[0];
+  for (int d = 1; d < p->ndim; ++d) nmin = std::min(nmin, nd[d]);
+  const int J = a.levels > 0 ? a.levels : wavelet_default_levels(nmin);
+  const float tau = (float)(a.gamma * a.lam);
+  double t = 1.0;
+  for (int k = 0; k < a.n_iter; ++k) {
+    normal_parts(p, a.toep, plain_input(z), a.smaps, a.L, a.dcf, w.op, s);
+    PNP_LAUNCH(k_pgd_id, dim3(nb), dim3(kRedThreads), 0, s, N, G, z, w.op.part, w.b0, (float)a.gamma, v);
+    wavelet_apply(p->ndim, nd, J, tau, v, x, s);
+    const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    PNP_LAUNCH(k_fista_mom, dim3(nb), dim3(kRedThreads), 0, s, N, x, xp, (float)((t - 1.0) / t_next), z);
+    t = t_next;
   }
 }
 

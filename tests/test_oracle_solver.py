@@ -225,6 +225,72 @@ def test_proposition1_fixed_points():
     assert np.linalg.norm(prox_g(u, 1.0) - x) > 1e-6 * np.linalg.norm(x)
 
 
+def test_fista_scalar_hand_iterates():
+    """Three FISTA steps on the scalar problem a/2 x^2 - b x + tau |x| (a = 0.5,
+    b = 2, tau = 0.1, gamma = 1, x0 = 0), iterates worked by hand:
+    x1 = soft(2) = 1.9, z2 = 1.9 (t1 = 1); x2 = soft(2.95) = 2.85,
+    t2 = (1 + sqrt 5)/2, z3 = 2.85 + (t2 - 1)/t3 * 0.95 = 3.117665849;
+    x3 = soft(3.558832924) = 3.458832924.  The limit is (b - tau)/a = 3.8."""
+    a, b, tau = 0.5, 2.0, 0.1
+    normal = lambda v: a * v
+    b0 = np.array([b], dtype=np.complex128)
+    soft = lambda v: np.sign(v) * np.maximum(np.abs(v) - tau, 0.0)
+    got = [solver.fista(b0, normal, np.zeros(1), 1.0, k, soft)[0].real for k in (1, 2, 3)]
+    assert np.allclose(got, [1.9, 2.85, 3.4588329244345273], rtol=0, atol=1e-12)
+    assert abs(solver.fista(b0, normal, np.zeros(1), 1.0, 400, soft)[0] - 3.8) < 1e-9
+
+
+def test_fista_wavelet_identity_normal_closed_form():
+    """A^H D_w A = Id: the minimiser of 1/2 ||x - b0||^2 + lam ||detail(Psi x)||_1 is
+    the wavelet soft threshold of b0 at lam (orthonormal Psi); FISTA with
+    gamma = 1 reaches it in one step, with gamma = 0.4 in the limit."""
+    b0 = synth.white_complex((16, 16), 61).astype(np.complex128)
+    lam = 0.3
+    ref = wavelet.wavelet_denoise(b0, lam, 2)
+    one = solver.fista_wavelet(b0, lambda v: v, np.zeros_like(b0), 1.0, lam, 1, 2)
+    assert np.abs(one - ref).max() < 1e-14
+    lim = solver.fista_wavelet(b0, lambda v: v, np.zeros_like(b0), 0.4, lam, 300, 2)
+    assert np.abs(lim - ref).max() < 1e-10
+
+
+def test_fista_wavelet_reaches_the_pgd_minimiser():
+    """On a strongly convex NUFFT problem, FISTA-Wavelet and plain proximal
+    gradient (the PGD loop with D = prox) converge to the same minimiser of
+    f + lam ||detail(Psi x)||_1 (unique), which satisfies the fixed-point
+    condition x = prox(x - gamma grad f(x))."""
+    n = 8
+    rng = np.random.default_rng(62)
+    M = 200
+    k = rng.uniform(-math.pi, math.pi, (M, 2))
+    S = synth.smaps2d(n, 2)
+    normal = lambda v: ndft.normal(v, S, k)
+    xt, _ = synth.phantom2d(n, 7)
+    y = ndft.forward(xt, S, k) + synth.complex_noise((2, M), 1e-4, 8)
+    b0 = ndft.adjoint(y, S, k)
+    Ln, _ = solver.opnorm(normal, (n, n), tol=1e-12)
+    gamma, lam = 1.0 / Ln, 0.05
+    xf = solver.fista_wavelet(b0, normal, b0, gamma, lam, 400, 2)
+    prox = lambda v, s: wavelet.wavelet_denoise(v, gamma * lam, 2)
+    xp = solver.pgd(b0, normal, b0, gamma, 3000, prox, 1.0)
+    assert np.linalg.norm(xf - xp) < 1e-9 * np.linalg.norm(xp)
+    fp = prox(xf - gamma * (normal(xf) - b0), 1.0)
+    assert np.linalg.norm(fp - xf) < 1e-9 * np.linalg.norm(xf)
+    # acceleration: after 30 steps FISTA is closer to the minimiser than proximal gradient
+    e_f = np.linalg.norm(solver.fista_wavelet(b0, normal, b0, gamma, lam, 30, 2) - xp)
+    e_p = np.linalg.norm(solver.pgd(b0, normal, b0, gamma, 30, prox, 1.0) - xp)
+    assert e_f < e_p
+
+
+def test_pgd_schedule_constant_equals_pgd():
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    b0 = synth.white_complex((8, 8), 63).astype(np.complex128)
+    prior = lambda u, s: wavelet.wavelet_denoise(u, 0.1 * s, 2)
+    Ln = np.linalg.eigvalsh(Nmat)[-1]
+    a = solver.pgd(b0, normal, b0, 0.5 / Ln, 7, prior, 0.3, "f1", Ln)
+    b = solver.pgd_schedule(b0, normal, b0, 0.5 / Ln, [0.3] * 7, prior, "f1", Ln)
+    assert np.abs(a - b).max() < 1e-15
+
+
 def test_hqs_fallback_on_bad_prior():
     """A prior that returns garbage raises the residual; the fallback
     (wavelet) takes over and the final result equals the all-wavelet run."""
