@@ -569,6 +569,14 @@ def main():
 
     race = psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.psnr_slices) if args.psnr_slices > 0 else None
     others = None if args.no_pgd else pgd_fista(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.seed, B)
+    # coil sensitivity estimate from the k-space centre of the same data (20 x 20 Hamming window)
+    pnp.estimate_smaps(plan, y, dd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        pnp.estimate_smaps(plan, y, dd)
+    torch.cuda.synchronize()
+    smaps_ms = (time.perf_counter() - t0) * 1e2
     unet = unet_rates(pnp, torch)
     batched = None if args.no_batched else batched_c4(pnp, torch)
     vol3d = None if args.no_3d else volume_3d(pnp, torch)
@@ -604,6 +612,7 @@ def main():
         "autotune": tuning,
         "psnr_race": race,
         "pgd_fista": others,
+        "smaps_estimate_ms": round(smaps_ms, 3),
         "batched": batched,
         "volume_3d": vol3d,
         "unet": unet,

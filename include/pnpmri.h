@@ -320,6 +320,23 @@ pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* 
                          int32_t n_out, const pnp_hqs_opts* opts, pnp_c64* x_out,
                          pnp_hqs_report* report, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Coil sensitivity maps estimated from the centre of k-space (Sec. 4.1: a
+ * 20 x 20 Hamming window on the k-space centre, brought to the image domain
+ * and masked).  Each sample m is weighted by dcf[m] * prod_axis h(kappa_a),
+ * kappa_a = k_a n_a / (2 pi) its frequency in grid units and
+ * h(kappa) = 0.54 + 0.46 cos(pi kappa / c) for |kappa| <= c = width/2, else
+ * 0; z_l = the adjoint of coil l's weighted data with a unit map;
+ * s = sqrt(sum_l |z_l|^2); smaps_out[l] = z_l / s where s > threshold * max s,
+ * 0 elsewhere.
+ *   y          device pnp_c64 [L][M];  dcf device float [M] or NULL
+ *   width      window width in grid units (> 0; 20 for the paper's window)
+ *   threshold  mask level as a fraction of max s, in [0, 1) (0: no mask)
+ *   smaps_out  device pnp_c64 [L][N] (written, also used as scratch)
+ *   ws         pnp_smaps_workspace_bytes bytes.  Asynchronous on `stream`. */
+pnp_status pnp_smaps_workspace_bytes(const pnp_plan* plan, size_t* bytes);
+pnp_status pnp_smaps_estimate(const pnp_plan* plan, const pnp_c64* y, int32_t L, const float* dcf, double width,
+                              double threshold, pnp_c64* smaps_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* PnP-PGD (Sec. 3.3, the preconditioned plug-and-play proximal gradient
  * scheme), one noise level per iteration:
  *   b0 = A^H D_w y;  x = x0 (or b0)

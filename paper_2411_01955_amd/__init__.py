@@ -307,6 +307,26 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
     return x, None
 
 
+def estimate_smaps(plan: Plan, y, dcf=None, width: float = 20.0, threshold: float = 0.05, out=None):
+    """Coil sensitivity maps [L][shape] from the k-space centre of y [L][M]
+    (Hamming window of `width` grid units, root-sum-of-squares, mask at
+    `threshold` of the largest root sum of squares)."""
+    torch = _torch()
+    if not (isinstance(y, torch.Tensor) and y.dim() == 2):
+        raise ValueError("y must be a [L][M] tensor")
+    L = int(y.shape[0])
+    _need_c64(y, "y", (L, plan.M))
+    _need_f32(dcf, "dcf", (plan.M,))
+    S = out if out is not None else torch.empty((L,) + tuple(plan.shape), dtype=torch.complex64, device=y.device)
+    _need_c64(S, "out", (L,) + tuple(plan.shape))
+    nb = C.c_size_t()
+    check(load().pnp_smaps_workspace_bytes(plan.handle, C.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=y.device)
+    check(load().pnp_smaps_estimate(plan.handle, _ptr(y), L, _ptr(dcf), float(width), float(threshold), _ptr(S),
+                                    _ptr(ws), ws.numel(), _stream()))
+    return S
+
+
 def pgd_solve(plan: Plan, y, smaps, dcf, prior, sigmas, gamma: float, precond: str = "id", opnorm: float = 0.0,
               x0=None, out=None, toeplitz: "Toeplitz" = None):
     """PnP-PGD with one noise level per iteration (sigmas); returns x."""

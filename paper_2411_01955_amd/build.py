@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpnpmri.so")
 
-SOURCES = ["plan.hip", "nufft2d.hip", "nufft3d.hip", "toeplitz.hip", "wavelet.hip", "solver.hip", "batch.hip", "unet.hip", "tune.hip", "trace.hip",
+SOURCES = ["plan.hip", "nufft2d.hip", "nufft3d.hip", "toeplitz.hip", "wavelet.hip", "solver.hip", "batch.hip", "unet.hip", "tune.hip", "smaps.hip", "trace.hip",
            "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

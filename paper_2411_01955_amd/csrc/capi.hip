@@ -522,6 +522,29 @@ pnp_status pnp_hqs_solve_batched(pnp_batch* batch, const pnp_prior* prior, const
   });
 }
 
+pnp_status pnp_smaps_workspace_bytes(const pnp_plan* p, size_t* bytes) {
+  return guarded([&] {
+    need(p, "plan");
+    need(bytes, "bytes");
+    *bytes = smaps_workspace_bytes(p);
+  });
+}
+
+pnp_status pnp_smaps_estimate(const pnp_plan* p, const pnp_c64* y, int32_t L, const float* dcf, double width,
+                              double threshold, pnp_c64* smaps_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    check_plan_L(p, L);
+    need(y, "y");
+    need(smaps_out, "smaps_out");
+    need(ws, "ws");
+    if (!(width > 0.0) || !std::isfinite(width)) fail(PNP_ERR_ARG, "width must be > 0");
+    if (!(threshold >= 0.0 && threshold < 1.0)) fail(PNP_ERR_ARG, "threshold must be in [0, 1)");
+    if ((const void*)smaps_out == (const void*)y) fail(PNP_ERR_ARG, "smaps_out must not alias y");
+    check_ws(ws_bytes, smaps_workspace_bytes(p), ws);
+    smaps_estimate(p, (const float2*)y, L, dcf, width, threshold, (float2*)smaps_out, ws, stream);
+  });
+}
+
 pnp_status pnp_pgd_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* smaps, int32_t L, const float* dcf,
                          const pnp_prior* prior, const double* sigmas, int32_t n_iter, double gamma,
                          int32_t precond, double opnorm, const pnp_toeplitz* toeplitz, const pnp_c64* x0,

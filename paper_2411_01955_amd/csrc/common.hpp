@@ -324,6 +324,11 @@ struct HQSArgs {
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
                int* bad_host, int* fb_host);
 
+// coil sensitivity maps from the k-space centre
+size_t smaps_workspace_bytes(const pnp_plan* p);
+void smaps_estimate(const pnp_plan* p, const float2* y, int L, const float* dcf, double width, double threshold,
+                    float2* out, void* ws, hipStream_t s);
+
 // PnP-PGD (Sec. 3.3): u = x - gamma P (N x - b0), x = D_{sigma_k}(u)
 struct PGDArgs {
   const float2* y;
