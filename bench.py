@@ -407,6 +407,18 @@ def unet_rates(pnp, torch):
     res["train_step_b10_128"] = {"ms": round(t * 1e3, 3), "gflop": round(fl / 1e9, 2),
                                  "tflops": round(fl / t / 1e12, 1),
                                  "mfma_util": round(fl / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+    # Neighbor2Neighbor step: f(x) on the full patches, f(g1(x)) forward and
+    # backward on the half-size sub-images, Adam
+    codes = torch.randint(0, 8, (10, 64, 64), dtype=torch.uint8, device="cuda")
+
+    def n2n_step():
+        trainer.n2n_backward(u, codes, 2.0)
+        trainer.adam_step(0.0)
+    t = timed(n2n_step, 20)
+    fl = unet_flops(layers, 10, 128, 128) + unet_flops(layers, 10, 64, 64, backward=True)
+    res["n2n_step_b10_128"] = {"ms": round(t * 1e3, 3), "gflop": round(fl / 1e9, 2),
+                               "tflops": round(fl / t / 1e12, 1),
+                               "mfma_util": round(fl / t / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
     res["peak_tflops"] = MFMA_BF16_PEAK_TFLOPS
     return res
 

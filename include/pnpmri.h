@@ -252,6 +252,23 @@ pnp_status pnp_unet_forward(const pnp_unet* net, const pnp_c64* u, const float* 
 pnp_status pnp_unet_backward(pnp_unet* net, const pnp_c64* u, const pnp_c64* target, int32_t B, int32_t H,
                              int32_t W, double* loss, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Neighbor2Neighbor training of the network as a restoration model f
+ * without noise conditioning (Sec. 3.1; the conditioning channel is 0).
+ * For noisy images x [B][H][W] (H, W divisible by 16) and one pair code per
+ * 2 x 2 cell (codes device uint8 [B][H/2][W/2], values 0..7, drawn by the
+ * caller) the sub-images take, in cell (i, j), the ordered pair of
+ * 4-adjacent pixels (offsets (dy, dx) in the cell)
+ *   0 (0,0)(0,1)  1 (0,0)(1,0)  2 (0,1)(0,0)  3 (0,1)(1,1)
+ *   4 (1,0)(0,0)  5 (1,0)(1,1)  6 (1,1)(0,1)  7 (1,1)(1,0)
+ * the first into g1(x), the second into g2(x).  loss (device double) =
+ * mean over the 2B(H/2)(W/2) real values of d^2 + eta (d - e)^2 with
+ * d = f(g1(x)) - g2(x), e = g1(f(x)) - g2(f(x)), f(x) held constant (no
+ * gradient through it); its gradient replaces the network's gradient array
+ * (then pnp_unet_adam_step).  ws: pnp_n2n_workspace_bytes. */
+pnp_status pnp_n2n_workspace_bytes(int32_t B, int32_t H, int32_t W, size_t* bytes);
+pnp_status pnp_n2n_backward(pnp_unet* net, const pnp_c64* x, const uint8_t* codes, double eta, int32_t B,
+                            int32_t H, int32_t W, double* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* One Adam step on the FP32 master weights with the current gradients
  * (bias-corrected moments: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * w -= lr/(1-b1^t) * m / (sqrt(v/(1-b2^t)) + eps)), then the BF16 copies

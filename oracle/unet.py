@@ -325,3 +325,53 @@ class Adam:
                 new.append(w - self.lr * mh / (np.sqrt(vh) + self.eps))
             out[n] = tuple(new)
         return out
+
+
+# ------------------------------------------------- Neighbor2Neighbor (Sec. 3.1)
+# Ordered pairs of 4-adjacent pixels of a 2 x 2 cell, (dy1, dx1, dy2, dx2):
+# the first goes to the sub-image g1, the second to g2.
+N2N_PAIRS = ((0, 0, 0, 1), (0, 0, 1, 0), (0, 1, 0, 0), (0, 1, 1, 1),
+             (1, 0, 0, 0), (1, 0, 1, 1), (1, 1, 0, 1), (1, 1, 1, 0))
+
+
+def n2n_subsample(x, codes):
+    """(g1, g2) [B, H/2, W/2]: in cell (i, j) of image b, pair N2N_PAIRS[codes[b, i, j]]."""
+    x = np.asarray(x)
+    codes = np.asarray(codes)
+    B, h, w = codes.shape
+    pairs = np.asarray(N2N_PAIRS)[codes]            # [B, h, w, 4]
+    bi = np.arange(B)[:, None, None]
+    ii = 2 * np.arange(h)[None, :, None]
+    jj = 2 * np.arange(w)[None, None, :]
+    g1 = x[bi, ii + pairs[..., 0], jj + pairs[..., 1]]
+    g2 = x[bi, ii + pairs[..., 2], jj + pairs[..., 3]]
+    return g1, g2
+
+
+def n2n_loss(D1, g2, f1, f2, eta: float):
+    """mean over the 2P real values of |d|^2 + eta |d - e|^2 (per real
+    component), d = D1 - g2 = f(g1(x)) - g2(x), e = f1 - f2 = g1(f(x)) - g2(f(x))."""
+    d = np.asarray(D1) - np.asarray(g2)
+    r = d - (np.asarray(f1) - np.asarray(f2))
+    n = 2 * d.size
+    return float((np.sum(np.abs(d) ** 2) + eta * np.sum(np.abs(r) ** 2)) / n)
+
+
+def n2n_loss_grad(params, x, codes, eta: float, bf16_mode=True):
+    """Loss and parameter gradients of the Neighbor2Neighbor objective for the
+    network without noise conditioning (sigma input 0), f(x) held constant:
+    d loss / d f(g1(x)) = 2 (d + eta (d - e)) / (2P)."""
+    x = np.asarray(x, dtype=np.complex128)
+    B = x.shape[0]
+    zeros = np.zeros(B)
+    Dx, _ = forward(params, x, zeros, bf16_mode)
+    g1, g2 = n2n_subsample(x, codes)
+    f1, f2 = n2n_subsample(Dx, codes)
+    D1, a = forward(params, g1, zeros, bf16_mode)
+    loss = n2n_loss(D1, g2, f1, f2, eta)
+    d = D1 - g2
+    r = d - (f1 - f2)
+    gc = 2.0 * (d + eta * r) / (2 * d.size)
+    gout = np.stack([gc.real, gc.imag], axis=-1)
+    grads, _ = backward(params, a, gout, bf16_mode)
+    return loss, grads

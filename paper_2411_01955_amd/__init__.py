@@ -502,6 +502,27 @@ class UNet:
                                        _stream()))
         return self._loss
 
+    def n2n_backward(self, x, codes, eta=2.0):
+        """Neighbor2Neighbor loss of the noisy images x [B][H][W] with the pair
+        codes [B][H/2][W/2] (uint8, 0..7); fills the gradients.  Returns the
+        loss as a CUDA float64 tensor [1]."""
+        torch = _torch()
+        _need_c64(x, "x")
+        x3 = x if x.dim() == 3 else x.reshape((1,) + tuple(x.shape))
+        B, H, W = (int(s) for s in x3.shape)
+        if not (isinstance(codes, torch.Tensor) and codes.is_cuda and codes.dtype == torch.uint8
+                and codes.is_contiguous() and tuple(codes.shape) == (B, H // 2, W // 2)):
+            raise TypeError("codes must be a contiguous CUDA uint8 tensor [B][H/2][W/2]")
+        key = ("n2n", B, H, W)
+        if key not in self._ws:
+            n = C.c_size_t()
+            check(load().pnp_n2n_workspace_bytes(B, H, W, C.byref(n)))
+            self._ws[key] = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        ws = self._ws[key]
+        check(load().pnp_n2n_backward(self._h, _ptr(x3), _ptr(codes), float(eta), B, H, W, _ptr(self._loss),
+                                      _ptr(ws), ws.numel(), _stream()))
+        return self._loss
+
     def adam_step(self, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8):
         check(load().pnp_unet_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream()))
 

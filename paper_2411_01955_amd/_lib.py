@@ -109,6 +109,8 @@ SIGNATURES = {
     "pnp_hqs_workspace_bytes": (_i32, [_vp, _i32, C.POINTER(_sz)]),
     "pnp_hqs_solve": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, C.POINTER(_dbl), _i32,
                              C.POINTER(HQSOpts), _vp, C.POINTER(HQSReport), _vp, _sz, _vp]),
+    "pnp_n2n_workspace_bytes": (_i32, [_i32, _i32, _i32, C.POINTER(_sz)]),
+    "pnp_n2n_backward": (_i32, [_vp, _vp, _vp, _dbl, _i32, _i32, _i32, _vp, _vp, _sz, _vp]),
     "pnp_smaps_workspace_bytes": (_i32, [_vp, C.POINTER(_sz)]),
     "pnp_smaps_estimate": (_i32, [_vp, _vp, _i32, _vp, _dbl, _dbl, _vp, _vp, _sz, _vp]),
     "pnp_pgd_solve": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, C.POINTER(_dbl), _i32, _dbl, _i32, _dbl, _vp, _vp,

@@ -451,6 +451,26 @@ pnp_status pnp_unet_backward(pnp_unet* net, const pnp_c64* u, const pnp_c64* tar
   });
 }
 
+pnp_status pnp_n2n_workspace_bytes(int32_t B, int32_t H, int32_t W, size_t* bytes) {
+  return guarded([&] {
+    need(bytes, "bytes");
+    *bytes = unet_n2n_ws_bytes(B, H, W);
+  });
+}
+
+pnp_status pnp_n2n_backward(pnp_unet* net, const pnp_c64* x, const uint8_t* codes, double eta, int32_t B,
+                            int32_t H, int32_t W, double* loss, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&] {
+    need(net, "net");
+    need(x, "x");
+    need(codes, "codes");
+    need(loss, "loss");
+    if (!(eta >= 0.0) || !std::isfinite(eta)) fail(PNP_ERR_ARG, "eta must be finite and >= 0");
+    check_ws(ws_bytes, unet_n2n_ws_bytes(B, H, W), ws);
+    unet_n2n_backward(net, (const float2*)x, codes, eta, B, H, W, loss, ws, stream);
+  });
+}
+
 pnp_status pnp_unet_adam_step(pnp_unet* net, double lr, double beta1, double beta2, double eps,
                               hipStream_t stream) {
   return guarded([&] {

@@ -260,6 +260,9 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
 void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, int H, int W, double* loss,
                    void* ws, hipStream_t s);
 void unet_adam(pnp_unet* net, double lr, double b1, double b2, double eps, hipStream_t s);
+size_t unet_n2n_ws_bytes(int B, int H, int W);
+void unet_n2n_backward(pnp_unet* net, const float2* x, const uint8_t* codes, double eta, int B, int H, int W,
+                       double* loss, void* ws, hipStream_t s);
 void unet_tensor(int B, int H, int W, bool train, void* ws, int id, void** ptr, int32_t dims[4]);
 // 3D operator (register-FFT grid sizes on every axis)
 bool plan3_supported(const pnp_plan* p);

@@ -206,6 +206,75 @@ __global__ void __launch_bounds__(kThreads) k_unet_l1(const float2* __restrict__
   if (threadIdx.x == 0) atomicAdd(loss, red[0] * (double)scale);
 }
 
+// Neighbor2Neighbor sub-samplers: in every 2 x 2 cell (i, j) of image b,
+// code c picks an ordered pair of 4-adjacent pixels, the first to g1 and
+// the second to g2 (offsets (dy, dx) within the cell):
+//   0 (0,0)(0,1)  1 (0,0)(1,0)  2 (0,1)(0,0)  3 (0,1)(1,1)
+//   4 (1,0)(0,0)  5 (1,0)(1,1)  6 (1,1)(0,1)  7 (1,1)(1,0)
+__constant__ int8_t kN2NPair[8][4] = {{0, 0, 0, 1}, {0, 0, 1, 0}, {0, 1, 0, 0}, {0, 1, 1, 1},
+                                      {1, 0, 0, 0}, {1, 0, 1, 1}, {1, 1, 0, 1}, {1, 1, 1, 0}};
+__device__ __forceinline__ void n2n_pair(int code, int& a1, int& b1, int& a2, int& b2) {
+  const int c = code & 7;
+  a1 = kN2NPair[c][0];
+  b1 = kN2NPair[c][1];
+  a2 = kN2NPair[c][2];
+  b2 = kN2NPair[c][3];
+}
+
+__global__ void __launch_bounds__(kThreads) k_n2n_sub(const float2* __restrict__ x, const uint8_t* __restrict__ codes,
+                                                      int h, int w, long long P, float2* __restrict__ g1,
+                                                      float2* __restrict__ g2) {
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < P;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long b = q / ((long long)h * w);
+    const int i = (int)((q / w) % h), j = (int)(q % w);
+    int a1, b1, a2, b2;
+    n2n_pair(codes[q], a1, b1, a2, b2);
+    const long long row = b * 2 * h;
+    g1[q] = x[(row + 2 * i + a1) * 2 * w + 2 * j + b1];
+    g2[q] = x[(row + 2 * i + a2) * 2 * w + 2 * j + b2];
+  }
+}
+
+// Loss of Sec. 3.1 as a mean over the 2P real values of
+//   d^2 + eta (d - e)^2,  d = f(g1) - g2,  e = g1(f(x)) - g2(f(x))
+// (f(x) held fixed); its gradient with respect to f(g1) into gout.
+__global__ void __launch_bounds__(kThreads) k_n2n_loss(const float2* __restrict__ D, const float2* __restrict__ g2,
+                                                       const float2* __restrict__ fx,
+                                                       const uint8_t* __restrict__ codes, int h, int w, long long P,
+                                                       float eta, float scale, uint16_t* __restrict__ gout,
+                                                       double* __restrict__ loss) {
+  __shared__ double red[kThreads];
+  double acc = 0.0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < P;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long b = q / ((long long)h * w);
+    const int i = (int)((q / w) % h), j = (int)(q % w);
+    int a1, b1, a2, b2;
+    n2n_pair(codes[q], a1, b1, a2, b2);
+    const long long row = b * 2 * h;
+    const float2 f1 = fx[(row + 2 * i + a1) * 2 * w + 2 * j + b1];
+    const float2 f2 = fx[(row + 2 * i + a2) * 2 * w + 2 * j + b2];
+    const float2 Dv = D[q], tv = g2[q];
+    const float dx = Dv.x - tv.x, dy = Dv.y - tv.y;
+    const float rx = dx - (f1.x - f2.x), ry = dy - (f1.y - f2.y);
+    acc += (double)dx * dx + (double)dy * dy + (double)eta * ((double)rx * rx + (double)ry * ry);
+    uint4 g;
+    g.x = (uint32_t)f2bf(scale * 2.f * (dx + eta * rx)) | ((uint32_t)f2bf(scale * 2.f * (dy + eta * ry)) << 16);
+    g.y = 0u;
+    g.z = 0u;
+    g.w = 0u;
+    *reinterpret_cast<uint4*>(gout + q * 8) = g;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int hh = kThreads / 2; hh > 0; hh >>= 1) {
+    if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, red[0] * (double)scale);
+}
+
 // Adam (bias-corrected moments), FP32 master weights, refreshed BF16 copy
 __global__ void k_unet_adam(long long n, float* __restrict__ w, const float* __restrict__ g,
                             float* __restrict__ m, float* __restrict__ v, uint16_t* __restrict__ wbf, float b1,
@@ -478,7 +547,11 @@ pnp_unet* unet_create(const float* params, hipStream_t s) {
   net->wt = reinterpret_cast<uint16_t*>(take((size_t)lay.n_wt * 2));
   try {
     PNP_HIP(hipMemcpyAsync(net->master, params, nb * 4, hipMemcpyDeviceToDevice, s));
-    PNP_HIP(hipMemsetAsync(net->grad, 0, nb * 4 * 3, s));
+    // gradient and Adam moments start at zero (each buffer on its own: the
+    // 256-byte alignment of the blocks leaves gaps between them)
+    PNP_HIP(hipMemsetAsync(net->grad, 0, nb * 4, s));
+    PNP_HIP(hipMemsetAsync(net->m, 0, nb * 4, s));
+    PNP_HIP(hipMemsetAsync(net->v, 0, nb * 4, s));
     PNP_LAUNCH(k_unet_cast, dim3(blocks_for(lay.n_params)), dim3(kThreads), 0, s, lay.n_params, net->master,
                net->wbf);
     refresh_weights(net, s);
@@ -559,19 +632,10 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
                reinterpret_cast<const float2*>(w.out), P0, out);
 }
 
-void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, int H, int W, double* loss,
-                   void* ws, hipStream_t s) {
-  check_dims(B, H, W);
-  const UWs w = unet_ws(B, H, W, true, ws);
+// Parameter gradients from the output gradient w.gout of a train-sized
+// workspace holding the activations of the preceding forward pass.
+static void unet_backprop(pnp_unet* net, const UWs& w, int B, int H, int W, hipStream_t s) {
   const Geo g0{B, H, W}, g1{B, H / 2, W / 2}, g2{B, H / 4, W / 4}, g3{B, H / 8, W / 8};
-  const long long P0 = (long long)B * H * W;
-  PNP_HIP(hipMemsetAsync(net->grad, 0, (size_t)layout().n_params * 4, s));
-  PNP_HIP(hipMemsetAsync(loss, 0, sizeof(double), s));
-  {
-    const unsigned nb = std::min<unsigned>(blocks_for(P0), 1024);
-    PNP_LAUNCH(k_unet_l1, dim3(nb), dim3(kThreads), 0, s, u, reinterpret_cast<const float2*>(w.out), target, P0,
-               (float)(0.5 / (double)P0), w.gout, loss);
-  }
   // output layer and the last decoder stage
   launch_conv_dw(net, 17, A(w.gout, 8, 0, 2), A(w.d1b, 32, 0, 32), g0, s);
   launch_conv_dx(net, 17, A(w.gout, 8, 0, 8), A(w.gd1b, 32, 0, 32), relu_mask(w.d1b, 32, 0, 32), g0, s);
@@ -613,6 +677,59 @@ void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, 
   launch_conv_dw(net, 1, A(w.gc1, 64, 0, 32), A(w.e1a, 32, 0, 32), g0, s);
   launch_conv_dx(net, 1, A(w.gc1, 64, 0, 32), A(w.ge1a, 32, 0, 32), relu_mask(w.e1a, 32, 0, 32), g0, s);
   launch_conv_dw(net, 0, A(w.ge1a, 32, 0, 32), A(w.x0, 8, 0, 8), g0, s);
+}
+
+void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, int H, int W, double* loss,
+                   void* ws, hipStream_t s) {
+  check_dims(B, H, W);
+  const UWs w = unet_ws(B, H, W, true, ws);
+  const long long P0 = (long long)B * H * W;
+  PNP_HIP(hipMemsetAsync(net->grad, 0, (size_t)layout().n_params * 4, s));
+  PNP_HIP(hipMemsetAsync(loss, 0, sizeof(double), s));
+  {
+    const unsigned nb = std::min<unsigned>(blocks_for(P0), 1024);
+    PNP_LAUNCH(k_unet_l1, dim3(nb), dim3(kThreads), 0, s, u, reinterpret_cast<const float2*>(w.out), target, P0,
+               (float)(0.5 / (double)P0), w.gout, loss);
+  }
+  unet_backprop(net, w, B, H, W, s);
+}
+
+// ---- Neighbor2Neighbor training (Sec. 3.1): sub-samplers and loss
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t unet_n2n_ws_bytes(int B, int H, int W) {
+  if (H % 16 || W % 16) fail(PNP_ERR_SHAPE, "Neighbor2Neighbor needs H and W divisible by 16 (%d x %d)", H, W);
+  const long long P = (long long)B * H * W, p = P / 4;
+  return al256(unet_ws_bytes(B, H, W, false)) + al256(unet_ws_bytes(B, H / 2, W / 2, true)) +
+         al256(sizeof(float2) * P) + 3 * al256(sizeof(float2) * p);
+}
+
+void unet_n2n_backward(pnp_unet* net, const float2* x, const uint8_t* codes, double eta, int B, int H, int W,
+                       double* loss, void* ws, hipStream_t s) {
+  const int h = H / 2, wd = W / 2;
+  const long long P = (long long)B * H * W, p = P / 4;
+  char* c = (char*)ws;
+  void* ws_full = c;
+  c += al256(unet_ws_bytes(B, H, W, false));
+  void* ws_sub = c;
+  c += al256(unet_ws_bytes(B, h, wd, true));
+  float2* fx = (float2*)c;
+  c += al256(sizeof(float2) * P);
+  float2* g1 = (float2*)c;
+  c += al256(sizeof(float2) * p);
+  float2* g2 = (float2*)c;
+  c += al256(sizeof(float2) * p);
+  float2* dsub = (float2*)c;
+  const unsigned nb = std::min<unsigned>(blocks_for(p), 1024);
+  PNP_LAUNCH(k_n2n_sub, dim3(nb), dim3(kThreads), 0, s, x, codes, h, wd, p, g1, g2);
+  unet_forward(net, x, nullptr, 0.f, B, H, W, fx, ws_full, s);        // f(x), no gradient
+  unet_forward(net, g1, nullptr, 0.f, B, h, wd, dsub, ws_sub, s);    // f(g1(x)), activations kept
+  const UWs w = unet_ws(B, h, wd, true, ws_sub);
+  PNP_HIP(hipMemsetAsync(net->grad, 0, (size_t)layout().n_params * 4, s));
+  PNP_HIP(hipMemsetAsync(loss, 0, sizeof(double), s));
+  PNP_LAUNCH(k_n2n_loss, dim3(nb), dim3(kThreads), 0, s, dsub, g2, fx, codes, h, wd, p, (float)eta,
+             (float)(0.5 / (double)p), w.gout, loss);
+  unet_backprop(net, w, B, h, wd, s);
 }
 
 void unet_adam(pnp_unet* net, double lr, double b1, double b2, double eps, hipStream_t s) {

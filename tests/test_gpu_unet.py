@@ -308,3 +308,22 @@ def test_training_reduces_the_loss(pnp):
     say(f"[unet train] loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.7 * losses[0]
+
+
+def test_new_network_starts_with_zero_adam_moments(pnp):
+    """Moments of a network created where a trained one was freed are zero
+    (every buffer is cleared on its own; the aligned blocks have gaps)."""
+    import gc
+    B, H, W = 1, 16, 16
+    params, net, u, sigma = _setup(pnp, B, H, W, seed=10)
+    ud = _dev(u)
+    for _ in range(3):
+        net.forward(ud, _dev(sigma), train=True)
+        net.backward(ud, _dev((0.5 * u).astype(np.complex64)))
+        net.adam_step(1e-3)
+    net.close()
+    del net
+    gc.collect()
+    fresh = pnp.UNet(params)
+    for which in ("grad", "adam_m", "adam_v"):
+        assert not fresh.get(which).cpu().numpy().any(), which

@@ -289,3 +289,76 @@ def test_adam_first_step_is_lr_times_sign():
     out = ad.step(p, {"a": (np.array([2.0, -0.5, 0.0]), np.array([1e-3]))})
     np.testing.assert_allclose(out["a"][0], [-0.01, 0.01, 0.0], rtol=1e-7)
     np.testing.assert_allclose(out["a"][1], [-0.01], rtol=1e-4)
+
+
+# ------------------------------------------------------- Neighbor2Neighbor
+def test_n2n_subsample_hand_values():
+    """4 x 4 image x[r, c] = 10 r + c, codes [[0, 3], [5, 6]]:
+    cell (0,0) code 0 (0,0)->(0,1): 0, 1;   cell (0,1) code 3 (0,1)->(1,1): 3, 13;
+    cell (1,0) code 5 (1,0)->(1,1): 30, 31; cell (1,1) code 6 (1,1)->(0,1): 33, 23."""
+    x = (10 * np.arange(4)[:, None] + np.arange(4)[None, :]).astype(np.complex128)[None]
+    g1, g2 = U.n2n_subsample(x, np.array([[[0, 3], [5, 6]]]))
+    np.testing.assert_array_equal(g1[0].real, [[0, 3], [30, 33]])
+    np.testing.assert_array_equal(g2[0].real, [[1, 13], [31, 23]])
+    # every code is an ordered pair of distinct 4-adjacent pixels of the cell
+    pairs = set()
+    for a1, b1, a2, b2 in U.N2N_PAIRS:
+        assert abs(a1 - a2) + abs(b1 - b2) == 1
+        pairs.add((a1, b1, a2, b2))
+    assert len(pairs) == 8
+
+
+def test_n2n_identity_network_has_no_regulariser():
+    """With a zero output layer f(u) = u, so e = g1(x) - g2(x) = d and the
+    loss is the mean squared difference of the two sub-images, for any eta."""
+    params = _params(TINY, 31)
+    params["out"] = (np.zeros_like(params["out"][0]), np.zeros_like(params["out"][1]))
+    x = synth.white_complex((2, 16, 16), 32).astype(np.complex128)
+    codes = np.random.default_rng(33).integers(0, 8, (2, 8, 8))
+    g1, g2 = U.n2n_subsample(x, codes)
+    ref = float(np.mean(np.concatenate([(g1 - g2).real.ravel(), (g1 - g2).imag.ravel()]) ** 2))
+    for eta in (0.0, 2.0):
+        loss, _ = U.n2n_loss_grad(params, x, codes, eta, bf16_mode=False)
+        assert abs(loss - ref) < 1e-12 * ref
+
+
+def test_n2n_gradients_match_torch_autograd():
+    """The same objective written with torch ops, f(x) detached."""
+    params = _params(TINY, 34, bias=0.05)
+    x = synth.white_complex((2, 16, 16), 35).astype(np.complex128) * 0.5
+    codes = np.random.default_rng(36).integers(0, 8, (2, 8, 8))
+    eta = 2.0
+    loss, grads = U.n2n_loss_grad(params, x, codes, eta, bf16_mode=False)
+    zeros = np.zeros(2)
+    out_full, _ = _torch_net(params, x, zeros)
+    f_full = _t(x.real) + out_full.detach()[:, 0], _t(x.imag) + out_full.detach()[:, 1]
+    # sub-sampling written directly with the cell offsets of each code
+    table = {0: ((0, 0), (0, 1)), 1: ((0, 0), (1, 0)), 2: ((0, 1), (0, 0)), 3: ((0, 1), (1, 1)),
+             4: ((1, 0), (0, 0)), 5: ((1, 0), (1, 1)), 6: ((1, 1), (0, 1)), 7: ((1, 1), (1, 0))}
+    B, h, w = codes.shape
+    i1 = np.zeros((B, h, w, 2), dtype=int)
+    i2 = np.zeros((B, h, w, 2), dtype=int)
+    for b in range(B):
+        for i in range(h):
+            for j in range(w):
+                (a1, c1), (a2, c2) = table[int(codes[b, i, j])]
+                i1[b, i, j] = (2 * i + a1, 2 * j + c1)
+                i2[b, i, j] = (2 * i + a2, 2 * j + c2)
+    bb = np.arange(B)[:, None, None]
+    sub = lambda a, ix: a[bb, ix[..., 0], ix[..., 1]]
+    g1 = sub(x, i1)
+    g2 = sub(x, i2)
+    out_sub, tp = _torch_net(params, g1, zeros)
+    D1r, D1i = _t(g1.real) + out_sub[:, 0], _t(g1.imag) + out_sub[:, 1]
+    f1r, f1i = f_full[0][bb, i1[..., 0], i1[..., 1]], f_full[1][bb, i1[..., 0], i1[..., 1]]
+    f2r, f2i = f_full[0][bb, i2[..., 0], i2[..., 1]], f_full[1][bb, i2[..., 0], i2[..., 1]]
+    dr, di = D1r - _t(g2.real), D1i - _t(g2.imag)
+    rr, ri = dr - (f1r - f2r), di - (f1i - f2i)
+    L = (dr ** 2 + di ** 2 + eta * (rr ** 2 + ri ** 2)).sum() / (2 * dr.numel())
+    L.backward()
+    assert abs(L.item() - loss) < 1e-12 * loss
+    for n, (W, b) in params.items():
+        Wg = tp[n][0].grad.numpy()
+        Wg = Wg.transpose(1, 2, 3, 0).reshape(W.shape) if W.shape[1] == 4 else Wg.transpose(0, 2, 3, 1).reshape(W.shape)
+        np.testing.assert_allclose(grads[n][0], Wg, rtol=1e-9, atol=1e-13, err_msg=n)
+        np.testing.assert_allclose(grads[n][1], tp[n][1].grad.numpy(), rtol=1e-9, atol=1e-13, err_msg=n)
