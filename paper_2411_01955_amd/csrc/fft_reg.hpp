@@ -210,9 +210,38 @@ struct DFT {
     }
   }
 
-  template <int S>
+  // HZ: inputs a = 1, 2 of every first-level column (the middle half of
+  // the sequence) are zero -- a forward transform of a zero-padded line.
+  // The size-4 column DFTs of (x0, 0, 0, x3) reduce to x0 +- x3 and
+  // x0 -+ i x3 (the general form cannot drop the zero terms itself: x + 0
+  // is not x for x = -0 in IEEE arithmetic).
+  template <int b, int S>
+  __host__ __device__ __forceinline__ static void col_hz(float2* v) {
+    float2* c = v + b * S;
+    const float2 x0 = c[0], x3 = c[3 * B * S];
+    const float2 m = mul_mi<INV>(x3);
+    c[0] = cadd(x0, x3);
+    c[2 * B * S] = csub(x0, x3);
+    c[B * S] = csub(x0, m);
+    c[3 * B * S] = cadd(x0, m);
+    tw_row<b, 0, S>(v);
+  }
+  template <int b, int S>
+  __host__ __device__ __forceinline__ static void cols_hz(float2* v) {
+    if constexpr (b < B) {
+      col_hz<b, S>(v);
+      cols_hz<b + 1, S>(v);
+    }
+  }
+
+  template <int S, bool HZ = false>
   __host__ __device__ __forceinline__ static void run(float2* v) {
-    cols<0, S>(v);
+    if constexpr (HZ) {
+      static_assert(A == 4, "zero-padded first level needs a radix-4 split");
+      cols_hz<0, S>(v);
+    } else {
+      cols<0, S>(v);
+    }
     rows<0, S>(v);
     // now v[(ka*B + kb) S] holds X[ka + A*kb]; reorder to natural order
     float2 t[N];
@@ -228,6 +257,12 @@ struct DFT {
 template <int N, bool INV>
 __host__ __device__ __forceinline__ void dft(float2* v) {
   DFT<N, INV>::template run<1>(v);
+}
+
+// dft of a line whose middle half (indices N/4 .. 3N/4-1) is zero
+template <int N, bool INV>
+__host__ __device__ __forceinline__ void dft_halfzero(float2* v) {
+  DFT<N, INV>::template run<1, true>(v);
 }
 
 }  // namespace reg

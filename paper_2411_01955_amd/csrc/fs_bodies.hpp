@@ -118,6 +118,21 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
   const bool active = l0 + line < L;
   const long long N = (long long)nx * ny;
   const long long row0 = (long long)iy * nx;
+  const float2* Sg = S ? S + (long long)l0 * N + row0 : nullptr;
+  const OFF sb = (OFF)line * (OFF)N * 8u;
+  // HALF: the map values of the line's K1/2 image pixels are loaded first,
+  // so that their latency overlaps the row staging below
+  constexpr int Q = K1 / 4;
+  float2 sp[HALF ? 2 * Q : 1];
+  if constexpr (HALF) {
+    if (active && t < K2 && S) {
+#pragma unroll
+      for (int m = 0; m < 2 * Q; ++m) {
+        const int ix = m < Q ? (m + Q) * K2 + t : (m - Q) * K2 + t;
+        sp[m] = ld_off(Sg, sb + (OFF)ix * 8u);
+      }
+    }
+  }
   {
     const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
     const ImgScal bt = img_scal(in);
@@ -129,18 +144,21 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
   float2* Al = A + line * F::LA;
   if (active && t < K2) {
     float2 v[K1];
-    const float2* Sg = S ? S + (long long)l0 * N + row0 : nullptr;
-    const OFF sb = (OFF)line * (OFF)N * 8u;
     auto at = [&](int ix) {
       return S ? cmul(ld_off(Sg, sb + (OFF)ix * 8u), X[ix]) : X[ix];
     };
     if constexpr (HALF) {
-      constexpr int Q = K1 / 4;
 #pragma unroll
       for (int n1 = 0; n1 < K1; ++n1) {
-        if (n1 < Q) v[n1] = at((n1 + Q) * K2 + t);
-        else if (n1 >= 3 * Q) v[n1] = at((n1 - 3 * Q) * K2 + t);
-        else v[n1] = make_float2(0.f, 0.f);
+        if (n1 < Q) {
+          const int ix = (n1 + Q) * K2 + t;
+          v[n1] = S ? cmul(sp[n1], X[ix]) : X[ix];
+        } else if (n1 >= 3 * Q) {
+          const int ix = (n1 - 3 * Q) * K2 + t;
+          v[n1] = S ? cmul(sp[n1 - 2 * Q], X[ix]) : X[ix];
+        } else {
+          v[n1] = make_float2(0.f, 0.f);
+        }
       }
     } else {
 #pragma unroll
@@ -149,7 +167,8 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
         v[n1] = ix >= 0 ? at(ix) : make_float2(0.f, 0.f);
       }
     }
-    reg::dft<K1, false>(v);
+    if constexpr (HALF) reg::dft_halfzero<K1, false>(v);
+    else reg::dft<K1, false>(v);
     fs_twiddle<K1, K2, false>(v, t, tw);
 #pragma unroll
     for (int k1 = 0; k1 < K1; ++k1) Al[k1 * F::AS + t] = v[k1];
@@ -182,6 +201,21 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   const bool active = l0 + line < L;
   const long long N = (long long)nx * ny;
   float2* Al = A + line * F::LA;
+  const float2* Sg = S ? S + (long long)l0 * N + (long long)iy * nx : nullptr;
+  const OFF sbm = (OFF)line * (OFF)N * 8u;
+  // HALF: the map values of the line's K2/2 kept pixels are loaded with the
+  // grid row, ahead of the transforms that produce the values they multiply
+  constexpr int P = K2 / 4;
+  float2 sp[HALF ? 2 * P : 1];
+  if constexpr (HALF) {
+    if (active && S) {
+#pragma unroll
+      for (int m = 0; m < 2 * P; ++m) {
+        const int ix = m < P ? t + K1 * (m + P) : t + K1 * (m - P);
+        sp[m] = ld_off(Sg, sbm + (OFF)ix * 8u);
+      }
+    }
+  }
   if (active && t < K2) {
     float2 v[K1];
     const float2* src = mid + ((long long)l0 * ny + iy) * F::K;
@@ -204,15 +238,17 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   // per-coil contributions conj(S_l) * crop(row) into LDS (reusing A), then coil sum
   float2* Z = A;
   if (active) {
-    const float2* Sg = S ? S + (long long)l0 * N + (long long)iy * nx : nullptr;
-    const OFF sb = (OFF)line * (OFF)N * 8u;
-    auto put = [&](int ix, float2 v) { Z[line * nx + ix] = S ? cmulc(ld_off(Sg, sb + (OFF)ix * 8u), v) : v; };
+    auto put = [&](int ix, float2 v) { Z[line * nx + ix] = S ? cmulc(ld_off(Sg, sbm + (OFF)ix * 8u), v) : v; };
     if constexpr (HALF) {
-      constexpr int P = K2 / 4;
 #pragma unroll
       for (int k2 = 0; k2 < K2; ++k2) {
-        if (k2 < P) put(t + K1 * (k2 + P), u[k2]);
-        else if (k2 >= 3 * P) put(t + K1 * (k2 - 3 * P), u[k2]);
+        if (k2 < P) {
+          const int ix = t + K1 * (k2 + P);
+          Z[line * nx + ix] = S ? cmulc(sp[k2], u[k2]) : u[k2];
+        } else if (k2 >= 3 * P) {
+          const int ix = t + K1 * (k2 - 3 * P);
+          Z[line * nx + ix] = S ? cmulc(sp[k2 - 2 * P], u[k2]) : u[k2];
+        }
       }
     } else {
 #pragma unroll
@@ -271,7 +307,8 @@ __device__ __forceinline__ void col_fwd(const float2* __restrict__ strip, OFF rs
         v[n1] = iy >= 0 ? ld_off(strip, (OFF)c * 8u + (OFF)iy * rb) : make_float2(0.f, 0.f);
       }
     }
-    reg::dft<K1, false>(v);
+    if constexpr (HALF) reg::dft_halfzero<K1, false>(v);
+    else reg::dft<K1, false>(v);
     fs_twiddle<K1, K2, false>(v, t, tw);
 #pragma unroll
     for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];

@@ -34,30 +34,31 @@ namespace {
 
 constexpr int kRowCoils3 = 4;
 
-// Offsets in the 3D passes are 64-bit (a coil group's mid exceeds 4 GB at
-// 384^3).  HALF: the axis is zero-padded from n = K/2 (every operator pass);
-// without it the pass transforms a full grid-sized array (the transfer
-// function's DFT).
+// Per-thread byte offsets in the 3D passes are 32-bit where every offset of
+// the launch fits (up to 256^3 grids), else 64-bit (a coil group's mid
+// exceeds 4 GB at 384^3).  HALF: the axis is zero-padded from n = K/2
+// (every operator pass); without it the pass transforms a full grid-sized
+// array (the transfer function's DFT).
 using Off3 = unsigned long long;
+inline bool fits32(double max_bytes) { return max_bytes < 4294967296.0 - 1024.0; }
 
 // x pass (forward): rows are the nz*ny image lines
-template <int K1, int K2, bool HALF>
+template <int K1, int K2, bool HALF, typename OFF>
 __global__ void __launch_bounds__(kRowCoils3 * K1)
 k3_rows_fwd(ImgIn in, const float2* __restrict__ S, int L, int nx, int nrows, const float* __restrict__ dax,
             const float* __restrict__ dyz, const float2* __restrict__ tw, float2* __restrict__ mid) {
   __shared__ float2 A[kRowCoils3 * FS<K1, K2>::LA];
   __shared__ float2 X[FS<K1, K2>::K];
-  rows_fwd_body<K1, K2, kRowCoils3, HALF, Off3>(in, S, L, nx, nrows, dax, dyz, tw, mid, blockIdx.x, blockIdx.y, A,
-                                                X);
+  rows_fwd_body<K1, K2, kRowCoils3, HALF, OFF>(in, S, L, nx, nrows, dax, dyz, tw, mid, blockIdx.x, blockIdx.y, A, X);
 }
 
-template <int K1, int K2, bool HALF>
+template <int K1, int K2, bool HALF, typename OFF>
 __global__ void __launch_bounds__(kRowCoils3 * K1)
 k3_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int nrows,
             const float* __restrict__ dax, const float* __restrict__ dyz, const float2* __restrict__ tw,
             float2* __restrict__ part) {
   __shared__ float2 A[kRowCoils3 * FS<K1, K2>::LA];
-  rows_adj_body<K1, K2, kRowCoils3, HALF, Off3>(mid, S, L, nx, nrows, dax, dyz, tw, part, blockIdx.x, blockIdx.y, A);
+  rows_adj_body<K1, K2, kRowCoils3, HALF, OFF>(mid, S, L, nx, nrows, dax, dyz, tw, part, blockIdx.x, blockIdx.y, A);
 }
 
 // A set of columns: workgroup (strip, set) works on columns c0 .. c0+7 of
@@ -69,7 +70,7 @@ struct ColSets {
 };
 
 // forward: zero-padded image rows (nimg) -> all K rows
-template <int K1, int K2, bool HALF>
+template <int K1, int K2, bool HALF, typename OFF>
 __global__ void __launch_bounds__(8 * K1)
 k3_cols_fwd(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs, int nimg,
             const float2* __restrict__ tw) {
@@ -80,14 +81,14 @@ k3_cols_fwd(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
   const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0;
   float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
-  col_fwd<K1, K2, HALF, Off3>(src, (Off3)cs.rs_in, nimg, true, tw, lds, u);
-  const Off3 rb = (Off3)cs.rs_out * 8u, cb = (Off3)c * 8u + (Off3)t * rb;
+  col_fwd<K1, K2, HALF, OFF>(src, (OFF)cs.rs_in, nimg, true, tw, lds, u);
+  const OFF rb = (OFF)cs.rs_out * 8u, cb = (OFF)c * 8u + (OFF)t * rb;
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) st_off(dst, cb + (Off3)(K1 * k2) * rb, u[k2]);
+  for (int k2 = 0; k2 < K2; ++k2) st_off(dst, cb + (OFF)(K1 * k2) * rb, u[k2]);
 }
 
 // inverse: all K rows -> image rows (nimg), cropped
-template <int K1, int K2, bool HALF>
+template <int K1, int K2, bool HALF, typename OFF>
 __global__ void __launch_bounds__(8 * K1)
 k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs, int nimg,
             const float2* __restrict__ tw) {
@@ -98,15 +99,15 @@ k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
   const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0;
   float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
-  const Off3 rb = (Off3)cs.rs_in * 8u, cb = (Off3)c * 8u + (Off3)t * rb;
+  const OFF rb = (OFF)cs.rs_in * 8u, cb = (OFF)c * 8u + (OFF)t * rb;
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) u[k2] = ld_off(src, cb + (Off3)(K1 * k2) * rb);
-  col_inv<K1, K2, HALF, Off3>(dst, (Off3)cs.rs_out, nimg, true, tw, lds, u);
+  for (int k2 = 0; k2 < K2; ++k2) u[k2] = ld_off(src, cb + (OFF)(K1 * k2) * rb);
+  col_inv<K1, K2, HALF, OFF>(dst, (OFF)cs.rs_out, nimg, true, tw, lds, u);
 }
 
 // z pass of the Toeplitz operator, in place on g2: sets (coil l, row ky),
 // visited in XCD order with the coil fastest (T slices shared in L2)
-template <int K1, int K2>
+template <int K1, int K2, typename OFF>
 __global__ void __launch_bounds__(8 * K1)
 k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float2* __restrict__ tw,
              const float* __restrict__ T) {
@@ -120,12 +121,12 @@ k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float
   const long long plane = (long long)Ky * Kx;
   float2* strip = g2 + (long long)l * nz * plane + (long long)ky * Kx + c0;
   float2 u[K2];
-  col_fwd<K1, K2, true, Off3>(strip, (Off3)plane, nz, true, tw, lds, u);
+  col_fwd<K1, K2, true, OFF>(strip, (OFF)plane, nz, true, tw, lds, u);
   const float* Ts = T + (long long)ky * Kx + c0;
-  const Off3 tb = (Off3)plane * 4u, cb = (Off3)c * 4u + (Off3)t * tb;
+  const OFF tb = (OFF)plane * 4u, cb = (OFF)c * 4u + (OFF)t * tb;
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, cb + (Off3)(K1 * k2) * tb));
-  col_inv<K1, K2, true, Off3>(strip, (Off3)plane, nz, true, tw, lds, u);
+  for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, cb + (OFF)(K1 * k2) * tb));
+  col_inv<K1, K2, true, OFF>(strip, (OFF)plane, nz, true, tw, lds, u);
 }
 
 // type-2 interpolation: y[l][m] = scale * sum of the 6^3 taps of grid[l]
@@ -232,43 +233,68 @@ __global__ void k3_psf_prepare(float2* __restrict__ a, int Nx, int Ny, int Nz, f
 template <int K1, int K2>
 struct F3 {
   static constexpr int K = K1 * K2;
+  // largest per-thread byte offsets: a coil group's rows of mid or maps, a
+  // column of K rows at the row stride
+  static bool rows32(int nx, int nrows) {
+    return fits32(8.0 * kRowCoils3 * std::max((double)nx * nrows, (double)nrows * K));
+  }
+  static bool cols32(long long rs_a, long long rs_b) { return fits32(8.0 * K * (double)std::max(rs_a, rs_b) + 64.0); }
+
+  template <bool HALF, typename OFF>
+  static void rows_fwd_t(const ImgIn& in, const float2* S, int L, int nx, int nrows, const float* dax,
+                         const float* dyz, const float2* tw, float2* mid, hipStream_t s) {
+    const int G = (L + kRowCoils3 - 1) / kRowCoils3;
+    PNP_LAUNCH((k3_rows_fwd<K1, K2, HALF, OFF>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, in, S, L, nx, nrows,
+               dax, dyz, tw, mid);
+  }
+  template <bool HALF, typename OFF>
+  static void rows_adj_t(const float2* mid, const float2* S, int L, int nx, int nrows, const float* dax,
+                         const float* dyz, const float2* tw, float2* part, hipStream_t s) {
+    const int G = (L + kRowCoils3 - 1) / kRowCoils3;
+    PNP_LAUNCH((k3_rows_adj<K1, K2, HALF, OFF>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, mid, S, L, nx, nrows,
+               dax, dyz, tw, part);
+  }
   static void rows_fwd(const ImgIn& in, const float2* S, int L, int nx, int nrows, const float* dax,
                        const float* dyz, const float2* tw, float2* mid, hipStream_t s) {
-    const int G = (L + kRowCoils3 - 1) / kRowCoils3;
-    if (2 * nx == K)
-      PNP_LAUNCH((k3_rows_fwd<K1, K2, true>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, in, S, L, nx, nrows, dax,
-                 dyz, tw, mid);
-    else
-      PNP_LAUNCH((k3_rows_fwd<K1, K2, false>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, in, S, L, nx, nrows, dax,
-                 dyz, tw, mid);
+    const bool half = 2 * nx == K, n32 = rows32(nx, nrows);
+    if (half && n32) rows_fwd_t<true, unsigned>(in, S, L, nx, nrows, dax, dyz, tw, mid, s);
+    else if (half) rows_fwd_t<true, Off3>(in, S, L, nx, nrows, dax, dyz, tw, mid, s);
+    else if (n32) rows_fwd_t<false, unsigned>(in, S, L, nx, nrows, dax, dyz, tw, mid, s);
+    else rows_fwd_t<false, Off3>(in, S, L, nx, nrows, dax, dyz, tw, mid, s);
   }
   static void rows_adj(const float2* mid, const float2* S, int L, int nx, int nrows, const float* dax,
                        const float* dyz, const float2* tw, float2* part, hipStream_t s) {
-    const int G = (L + kRowCoils3 - 1) / kRowCoils3;
-    if (2 * nx == K)
-      PNP_LAUNCH((k3_rows_adj<K1, K2, true>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, mid, S, L, nx, nrows, dax,
-                 dyz, tw, part);
-    else
-      PNP_LAUNCH((k3_rows_adj<K1, K2, false>), dim3(nrows, G), dim3(kRowCoils3 * K1), 0, s, mid, S, L, nx, nrows,
-                 dax, dyz, tw, part);
+    const bool half = 2 * nx == K, n32 = rows32(nx, nrows);
+    if (half && n32) rows_adj_t<true, unsigned>(mid, S, L, nx, nrows, dax, dyz, tw, part, s);
+    else if (half) rows_adj_t<true, Off3>(mid, S, L, nx, nrows, dax, dyz, tw, part, s);
+    else if (n32) rows_adj_t<false, unsigned>(mid, S, L, nx, nrows, dax, dyz, tw, part, s);
+    else rows_adj_t<false, Off3>(mid, S, L, nx, nrows, dax, dyz, tw, part, s);
   }
   static void cols_fwd(const float2* in, float2* out, const ColSets& cs, int nsets, int Kc, int nimg,
                        const float2* tw, hipStream_t s) {
-    if (2 * nimg == K)
-      PNP_LAUNCH((k3_cols_fwd<K1, K2, true>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
-    else
-      PNP_LAUNCH((k3_cols_fwd<K1, K2, false>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
+    const bool half = 2 * nimg == K, n32 = cols32(cs.rs_in, cs.rs_out);
+    const dim3 g(Kc / 8, nsets), b(8 * K1);
+    if (half && n32) PNP_LAUNCH((k3_cols_fwd<K1, K2, true, unsigned>), g, b, 0, s, in, out, cs, nimg, tw);
+    else if (half) PNP_LAUNCH((k3_cols_fwd<K1, K2, true, Off3>), g, b, 0, s, in, out, cs, nimg, tw);
+    else if (n32) PNP_LAUNCH((k3_cols_fwd<K1, K2, false, unsigned>), g, b, 0, s, in, out, cs, nimg, tw);
+    else PNP_LAUNCH((k3_cols_fwd<K1, K2, false, Off3>), g, b, 0, s, in, out, cs, nimg, tw);
   }
   static void cols_inv(const float2* in, float2* out, const ColSets& cs, int nsets, int Kc, int nimg,
                        const float2* tw, hipStream_t s) {
-    if (2 * nimg == K)
-      PNP_LAUNCH((k3_cols_inv<K1, K2, true>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
-    else
-      PNP_LAUNCH((k3_cols_inv<K1, K2, false>), dim3(Kc / 8, nsets), dim3(8 * K1), 0, s, in, out, cs, nimg, tw);
+    const bool half = 2 * nimg == K, n32 = cols32(cs.rs_in, cs.rs_out);
+    const dim3 g(Kc / 8, nsets), b(8 * K1);
+    if (half && n32) PNP_LAUNCH((k3_cols_inv<K1, K2, true, unsigned>), g, b, 0, s, in, out, cs, nimg, tw);
+    else if (half) PNP_LAUNCH((k3_cols_inv<K1, K2, true, Off3>), g, b, 0, s, in, out, cs, nimg, tw);
+    else if (n32) PNP_LAUNCH((k3_cols_inv<K1, K2, false, unsigned>), g, b, 0, s, in, out, cs, nimg, tw);
+    else PNP_LAUNCH((k3_cols_inv<K1, K2, false, Off3>), g, b, 0, s, in, out, cs, nimg, tw);
   }
   static void cols_toep(float2* g2, int L, int nz, int Ky, int Kx, const float2* tw, const float* T, hipStream_t s) {
     if (2 * nz != K) fail(PNP_ERR_SHAPE, "3D Toeplitz pass needs a grid twice the image along z");
-    PNP_LAUNCH((k3_cols_toep<K1, K2>), dim3(L * Ky * (Kx / 8)), dim3(8 * K1), 0, s, g2, L, nz, Ky, Kx, tw, T);
+    const dim3 g(L * Ky * (Kx / 8)), b(8 * K1);
+    if (cols32((long long)Ky * Kx, 0))
+      PNP_LAUNCH((k3_cols_toep<K1, K2, unsigned>), g, b, 0, s, g2, L, nz, Ky, Kx, tw, T);
+    else
+      PNP_LAUNCH((k3_cols_toep<K1, K2, Off3>), g, b, 0, s, g2, L, nz, Ky, Kx, tw, T);
   }
 };
 

@@ -26,6 +26,21 @@ static void one() {
   printf("\n");
 }
 
+// dft of a line whose middle half is zero (the zero-padded forward lines)
+template <int N>
+static void halfzero() {
+  float2 v[N], in[N];
+  for (int i = 0; i < N; ++i) {
+    const bool pad = i >= N / 4 && i < 3 * N / 4;
+    in[i] = v[i] = pad ? make_float2(0.f, 0.f) : make_float2(rnd(), rnd());
+  }
+  reg::dft_halfzero<N, false>(v);
+  printf("hz %d 0", N);
+  for (int i = 0; i < N; ++i) printf(" %.9g %.9g", in[i].x, in[i].y);
+  for (int i = 0; i < N; ++i) printf(" %.9g %.9g", v[i].x, v[i].y);
+  printf("\n");
+}
+
 // four-step with a double-tabulated twiddle table, emulating the kernels:
 // thread n2 < K2 runs step 1, thread k1 < K1 runs step 2
 template <int K1, int K2, bool INV>
@@ -113,5 +128,6 @@ int main() {
   four<16, 8, false>(); four<16, 12, false>(); four<16, 16, false>(); four<32, 16, false>();
   four<32, 20, false>(); four<32, 24, false>(); four<32, 32, false>();
   four<16, 8, true>(); four<32, 20, true>(); four<32, 24, true>();
+  halfzero<16>(); halfzero<32>();
   return 0;
 }

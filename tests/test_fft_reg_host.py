@@ -59,3 +59,5 @@ def test_register_dfts_match_numpy(rows):
         assert ("dft", n) in seen
     for K in (128, 192, 256, 512, 640, 768, 1024):
         assert ("four", K) in seen
+    for n in (16, 32):                     # middle half zero: the padded forward lines
+        assert ("hz", n) in seen
