@@ -116,6 +116,12 @@ struct pnp_plan {
   int32_t* sample_ent;      // [M][slots] entry indices of a sample (-1: none)
   pnp::EntryRec* rec;       // [E] packed taps and weights, grouped by tile (2D)
   float* traj;              // [M][ndim] copy of the trajectory (radians)
+  // 3D: samples sorted by the grid cell of their first tap (stable), for
+  // the gather form of the spread
+  int32_t* sorted_m;        // [M] sample index in sorted order
+  int32_t* sorted_jx;       // [M] first x tap of each sorted sample
+  float* sorted_w;          // [M][3][W] weights in sorted order
+  int32_t* cell_off;        // [Kz*Ky*Kx + 1] first sorted index of each cell
   void* block;
   size_t block_bytes;
 };
@@ -151,6 +157,7 @@ struct OpWorkspace {
   float2* part;    // [G][N]         per-coil-group partial images
   float2* g2;      // 3D: [L][nz][Ky][Kx] after the y pass
   float2* grid;    // 3D: [L][Kz][Ky][Kx] full oversampled grid
+  float2* ysort;   // 3D: [M][L] k-space values in the plan's sorted sample order
   size_t bytes;
 };
 size_t op_workspace_bytes(const pnp_plan* p, int L);

@@ -167,39 +167,69 @@ k3_interp(const float2* __restrict__ grid, int Kx, int Ky, int Kz, long long M, 
   y[(long long)l * M + m] = cscale(acc, scale);
 }
 
-// type-1 spread: grid[l] += scale * w_m * y[l][m] * taps (FP32 atomics)
+// k-space values in the plan's sorted sample order, coils contiguous:
+// ys[i][l] = scale * w_m * y[l][m] for m = sorted_m[i]
+__global__ void k3_sort_y(long long M, int L, const float2* __restrict__ y, const float* __restrict__ dcf,
+                          const int32_t* __restrict__ sorted_m, float scale, float2* __restrict__ ys) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * L) return;
+  const long long i = idx / L;
+  const int l = (int)(idx - i * L);
+  const int32_t m = sorted_m[i];
+  ys[idx] = cscale(y[(long long)l * M + m], scale * (dcf ? dcf[m] : 1.f));
+}
+
+// type-1 spread as a gather: grid point g receives from every sample whose
+// 6^3 window covers it, i.e. whose first tap lies in [g - 5, g] (mod K) on
+// every axis.  The samples are sorted by first-tap cell, so for each of the
+// 36 (z, y) tap rows the candidates form one contiguous range of the sorted
+// order (two across the x wrap).  Workgroup: 8 consecutive grid points
+// along x, 32 coil lanes each (coils >= L idle; blockIdx.y picks the chunk
+// of 32 coils).  Every grid point is written once: no atomics, no clearing,
+// and a summation order fixed by the plan.
 __global__ void __launch_bounds__(256)
-k3_spread(const float2* __restrict__ y, const float* __restrict__ dcf, int Kx, int Ky, int Kz, long long M,
-          const int4* __restrict__ j0, const float* __restrict__ wts, float scale, float2* __restrict__ grid) {
-  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  const int l = blockIdx.y;
-  const int4 j = j0[m];
-  float w[3][6];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int t = 0; t < 6; ++t) w[a][t] = wts[(m * 3 + a) * 6 + t];
-  const float2 v = cscale(y[(long long)l * M + m], scale * (dcf ? dcf[m] : 1.f));
-  float* g = reinterpret_cast<float*>(grid + (long long)l * Kz * Ky * Kx);
+k3_gather(const float2* __restrict__ ys, int L, const int32_t* __restrict__ cell_off,
+          const int32_t* __restrict__ jx, const float* __restrict__ sw, int Kx, int Ky, int Kz, long long nblocks,
+          float2* __restrict__ grid) {
+  // workgroups are numbered over x and z of the launch (a 512^3 grid needs
+  // more than fit along x); the surplus of the last z row exits at once
+  const long long b = (long long)blockIdx.z * gridDim.x + blockIdx.x;
+  if (b >= nblocks) return;
+  const int lane = threadIdx.x & 31;
+  const long long g = b * 8 + (threadIdx.x >> 5);
+  const int l = blockIdx.y * 32 + lane;
+  const bool lok = l < L;
+  const int gx = (int)(g % Kx);
+  const int gy = (int)((g / Kx) % Ky);
+  const int gz = (int)(g / ((long long)Kx * Ky));
+  float ax = 0.f, ay = 0.f;
   for (int tz = 0; tz < 6; ++tz) {
-    int z = j.z + tz;
-    if (z >= Kz) z -= Kz;
+    int cz = gz - tz;
+    if (cz < 0) cz += Kz;
     for (int ty = 0; ty < 6; ++ty) {
-      int yy = j.y + ty;
-      if (yy >= Ky) yy -= Ky;
-      const float wzy = w[2][tz] * w[1][ty];
-      const long long row = ((long long)z * Ky + yy) * Kx;
-#pragma unroll
-      for (int tx = 0; tx < 6; ++tx) {
-        int x = j.x + tx;
-        if (x >= Kx) x -= Kx;
-        const float f = wzy * w[0][tx];
-        atomicAdd(g + 2 * (row + x), f * v.x);
-        atomicAdd(g + 2 * (row + x) + 1, f * v.y);
+      int cy = gy - ty;
+      if (cy < 0) cy += Ky;
+      const long long row = ((long long)cz * Ky + cy) * Kx;
+      const int nseg = gx >= 5 ? 1 : 2;
+      for (int seg = 0; seg < nseg; ++seg) {
+        const int x0 = gx >= 5 ? gx - 5 : (seg == 0 ? 0 : Kx + gx - 5);
+        const int x1 = gx >= 5 ? gx : (seg == 0 ? gx : Kx - 1);
+        const int s0 = cell_off[row + x0], s1 = cell_off[row + x1 + 1];
+        for (int i = s0; i < s1; ++i) {
+          int tx = gx - jx[i];
+          if (tx < 0) tx += Kx;
+          const float* w = sw + (long long)i * 18;
+          const float f = w[tx] * w[6 + ty] * w[12 + tz];
+          if (lok) {
+            const float2 v = ys[(long long)i * L + l];
+            ax = fmaf(f, v.x, ax);
+            ay = fmaf(f, v.y, ay);
+          }
+        }
       }
     }
   }
+  if (lok) grid[(long long)l * Kx * Ky * Kz + g] = make_float2(ax, ay);
 }
 
 __global__ void k3_fill_ones(float2* __restrict__ y, long long n) {
@@ -387,6 +417,7 @@ size_t op3_workspace_bytes(const pnp_plan* p, int L) {
   b += al3(sizeof(float2) * (size_t)L * d.Kz * d.Ky * d.Kx);   // grid
   b += al3(sizeof(float2) * (size_t)L * p->M);                 // ytmp
   b += al3(sizeof(float2) * (size_t)op3_groups(L) * d.N);      // part
+  b += al3(sizeof(float2) * (size_t)L * p->M);                 // ysort
   return b;
 }
 
@@ -403,6 +434,8 @@ OpWorkspace op3_workspace(const pnp_plan* p, int L, void* ws) {
   w.ytmp = (float2*)c;
   c += al3(sizeof(float2) * (size_t)L * p->M);
   w.part = (float2*)c;
+  c += al3(sizeof(float2) * (size_t)op3_groups(L) * d.N);
+  w.ysort = (float2*)c;
   w.bytes = op3_workspace_bytes(p, L);
   return w;
 }
@@ -420,9 +453,15 @@ void op3_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L,
 static void adjoint_parts3(const pnp_plan* p, const float2* y, const float2* smaps, int L, const float* dcf,
                            float scale, float2* dst, const OpWorkspace& w, hipStream_t s) {
   const Dims d = dims_of(p);
-  PNP_HIP(hipMemsetAsync(w.grid, 0, sizeof(float2) * (size_t)L * d.Kz * d.Ky * d.Kx, s));
-  PNP_LAUNCH(k3_spread, dim3((unsigned)((p->M + 255) / 256), L), dim3(256), 0, s, y, dcf, d.Kx, d.Ky, d.Kz,
-             (long long)p->M, p->j0, p->wts, scale, w.grid);
+  const long long ML = p->M * L;
+  PNP_LAUNCH(k3_sort_y, dim3((unsigned)((ML + 255) / 256)), dim3(256), 0, s, (long long)p->M, L, y, dcf,
+             p->sorted_m, scale, w.ysort);
+  const long long G = (long long)d.Kx * d.Ky * d.Kz;
+  const long long nblocks = G / 8;
+  const unsigned bx = (unsigned)std::min<long long>(nblocks, 65536);
+  const unsigned bz = (unsigned)((nblocks + bx - 1) / bx);
+  PNP_LAUNCH(k3_gather, dim3(bx, (unsigned)((L + 31) / 32), bz), dim3(256), 0, s, w.ysort, L, p->cell_off,
+             p->sorted_jx, p->sorted_w, d.Kx, d.Ky, d.Kz, nblocks, w.grid);
   passes_adj(p, d, smaps, L, p->ax[0].deapod, p->deapod_yz, w.grid, w.g2, w.mid, dst, s);
 }
 

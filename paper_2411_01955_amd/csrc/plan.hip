@@ -20,6 +20,9 @@
 #include <cstdio>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+#include <hipcub/device/device_radix_sort.hpp>
+
 #include "common.hpp"
 
 namespace pnp {
@@ -299,6 +302,77 @@ __global__ void k_deapod_yz(const float* __restrict__ dy, const float* __restric
 // deapodisation of the (z, y) image rows, and per sample the wrapped first
 // taps and kernel weights (the 3D operator spreads and interpolates from
 // the full oversampled grid; no strip tables).
+// 3D sort by first-tap cell: keys, cell bounds, tables in sorted order
+__global__ void k3_cell_keys(long long M, const int4* __restrict__ j0, int Kx, int Ky, uint32_t* __restrict__ keys,
+                             int32_t* __restrict__ vals) {
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int4 j = j0[m];
+  keys[m] = ((uint32_t)j.z * (uint32_t)Ky + (uint32_t)j.y) * (uint32_t)Kx + (uint32_t)j.x;
+  vals[m] = (int32_t)m;
+}
+
+// off[c] = first sorted index whose key is >= c, for c = 0..ncells
+__global__ void k3_cell_bounds(long long ncells, const uint32_t* __restrict__ keys, long long M,
+                               int32_t* __restrict__ off) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncells) return;
+  long long lo = 0, hi = M;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if ((long long)keys[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  off[c] = (int32_t)lo;
+}
+
+__global__ void k3_sorted_tables(long long M, int W, const int32_t* __restrict__ sm, const int4* __restrict__ j0,
+                                 const float* __restrict__ wts, int32_t* __restrict__ jx, float* __restrict__ sw) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int32_t m = sm[i];
+  jx[i] = j0[m].x;
+  for (int k = 0; k < 3 * W; ++k) sw[i * 3 * W + k] = wts[(long long)m * 3 * W + k];
+}
+
+static void sort_by_cell(pnp_plan* p, hipStream_t stream) {
+  const long long M = p->M;
+  const int Kx = p->ax[0].K, Ky = p->ax[1].K, Kz = p->ax[2].K;
+  const long long ncells = (long long)Kx * Ky * Kz;
+  if (M >= (1ll << 31) || ncells >= (1ll << 31)) fail(PNP_ERR_SHAPE, "3D plan too large for the sample sort");
+  int bits = 1;
+  while ((1ll << bits) < ncells) ++bits;
+  void* blk = nullptr;
+  auto release = [&] {
+    if (blk) (void)hipFree(blk);
+  };
+  try {
+    size_t tb = 0;
+    PNP_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                               (const int32_t*)nullptr, (int32_t*)nullptr, (int)M, 0, bits, stream));
+    const size_t kb = align256(sizeof(uint32_t) * M);
+    PNP_HIP(hipMalloc(&blk, 3 * kb + align256(tb)));
+    char* c = (char*)blk;
+    uint32_t* keys = (uint32_t*)c;
+    uint32_t* keys_s = (uint32_t*)(c + kb);
+    int32_t* vals = (int32_t*)(c + 2 * kb);
+    void* tmp = c + 3 * kb;
+    const unsigned nb = (unsigned)((M + 255) / 256);
+    k3_cell_keys<<<nb, 256, 0, stream>>>(M, p->j0, Kx, Ky, keys, vals);
+    PNP_CHECK_LAUNCH();
+    PNP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys, keys_s, vals, p->sorted_m, (int)M, 0, bits, stream));
+    k3_cell_bounds<<<(unsigned)((ncells + 1 + 255) / 256), 256, 0, stream>>>(ncells, keys_s, M, p->cell_off);
+    PNP_CHECK_LAUNCH();
+    k3_sorted_tables<<<nb, 256, 0, stream>>>(M, p->W, p->sorted_m, p->j0, p->wts, p->sorted_jx, p->sorted_w);
+    PNP_CHECK_LAUNCH();
+    PNP_HIP(hipStreamSynchronize(stream));
+  } catch (...) {
+    release();
+    throw;
+  }
+  release();
+}
+
 static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   const int64_t M = p->M;
   p->tile = 8;                  // strip width of the column passes
@@ -338,6 +412,11 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   const size_t o_j0 = take(sizeof(int4) * M);
   const size_t o_w = take(sizeof(float) * M * 3 * p->W);
   const size_t o_traj = take(sizeof(float) * M * 3);
+  const long long ncells = (long long)p->ax[0].K * p->ax[1].K * p->ax[2].K;
+  const size_t o_sm = take(sizeof(int32_t) * M);
+  const size_t o_jx = take(sizeof(int32_t) * M);
+  const size_t o_sw = take(sizeof(float) * M * 3 * p->W);
+  const size_t o_co = take(sizeof(int32_t) * (ncells + 1));
   PNP_HIP(hipMalloc(&p->block, off));
   p->block_bytes = off;
   char* base = (char*)p->block;
@@ -349,6 +428,10 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   p->j0 = (int4*)(base + o_j0);
   p->wts = (float*)(base + o_w);
   p->traj = (float*)(base + o_traj);
+  p->sorted_m = (int32_t*)(base + o_sm);
+  p->sorted_jx = (int32_t*)(base + o_jx);
+  p->sorted_w = (float*)(base + o_sw);
+  p->cell_off = (int32_t*)(base + o_co);
   p->tile_off = nullptr;
   p->row_start = nullptr;
   p->ent_sample = nullptr;
@@ -370,7 +453,7 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
                                                                    p->W, p->beta, 8, 1, 1, p->j0, p->wts, nullptr,
                                                                    nullptr, 0);
   PNP_CHECK_LAUNCH();
-  PNP_HIP(hipStreamSynchronize(stream));
+  sort_by_cell(p, stream);
 }
 
 pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* traj,
