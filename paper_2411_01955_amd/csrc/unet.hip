@@ -409,8 +409,17 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
   unet::ConvFwd v{in, net->wbf + l.w_off, net->master + l.b_off, out, out32, g, l.taps, l.cp, l.cout,
                   relu ? 1 : 0};
   const long long P = (long long)g.B * g.H * g.W;
-  PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 1), dim3(256),
-             0, s, v);
+  // larger tiles where the input channels come in 32-wide chunks and the
+  // launch still has a workgroup per compute unit; else 64 x 64
+  if (l.cp % 32 == 0 && l.cout == 32 && P / 256 >= 256) {
+    PNP_LAUNCH((unet::k_conv_fwd_tiled<256, 32, 4>), dim3(blocks_for(P, 256), 1, 1), dim3(256), 0, s, v);
+  } else if (l.cp % 32 == 0 && l.cout % 64 == 0 && (P / 128) * (l.cout / 64) >= 256) {
+    PNP_LAUNCH((unet::k_conv_fwd_tiled<128, 64, 2>), dim3(blocks_for(P, 128), l.cout / 64, 1), dim3(256), 0, s,
+               v);
+  } else {
+    PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 1), dim3(256),
+               0, s, v);
+  }
 }
 
 void launch_up_fwd(const pnp_unet* net, int li, Act in, Act out, Geo g, hipStream_t s) {

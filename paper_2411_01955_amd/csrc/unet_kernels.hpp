@@ -185,6 +185,94 @@ struct ConvFwd {
   }
 };
 
+// Forward convolution with larger output tiles (inference and training
+// forward passes): a TM x TN tile per 256-thread workgroup, the four waves
+// arranged WM x (4/WM), each wave a 64 x 32 block of 4 x 2 MFMA tiles (8
+// MFMAs per 32-wide K step against 6 LDS reads), LDS stages double-buffered
+// (one barrier per step).  The K loop walks the taps and 32-channel chunks
+// of the input (Cp a multiple of 32), so a step's tap offset is uniform and
+// each thread's pixel coordinates are computed once.  TN = 32 serves the
+// 32-channel layers without the half-empty tiles of the 64 x 64 kernel.
+template <int TM, int TN, int WM>
+__global__ void __launch_bounds__(256) k_conv_fwd_tiled(ConvFwd v) {
+  constexpr int WN = 4 / WM;
+  constexpr int BI = TM / WM / 16, BJ = TN / WN / 16;
+  static_assert(BI == 4 && BJ == 2, "64 x 32 per wave");
+  constexpr int RA = TM / 64;                  // A rows per thread
+  constexpr int NB = TN / 8;                   // B loaders: TN rows x 4 chunks = TN*4 threads
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][TM][40];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN][40];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+  const int wm = (wave / WN) * (TM / WM), wn = (wave % WN) * (TN / WN);
+  const int rr = tid >> 2, kq = (tid & 3) * 8;
+  const int P = v.g.P();
+  // pixel coordinates of this thread's A rows
+  int px[RA], py[RA], pb[RA];
+#pragma unroll
+  for (int i = 0; i < RA; ++i) {
+    const int m = m0 + rr + 64 * i;
+    pb[i] = m < P ? m / (v.g.W * v.g.H) : -1;
+    py[i] = (m / v.g.W) % v.g.H;
+    px[i] = m % v.g.W;
+  }
+  const int chunks = v.Cp / 32;
+  const int nsteps = v.taps * chunks;
+  const bool bload = tid < TN * 4;
+  const int bn = n0 + (tid >> 2);
+  auto fetch = [&](int step, uint4 (&a)[RA], uint4& b) {
+    const int t = step / chunks, cc = (step - t * chunks) * 32;
+    const int dy = tap_dy(v.taps, t), dx = tap_dx(v.taps, t);
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      const int y = py[i] + dy, x = px[i] + dx;
+      if (pb[i] >= 0 && (unsigned)y < (unsigned)v.g.H && (unsigned)x < (unsigned)v.g.W) {
+        const long long pix = ((long long)pb[i] * v.g.H + y) * v.g.W + x;
+        a[i] = ld16(v.in.p + pix * v.in.cs + v.in.co + cc + kq);
+      } else {
+        a[i] = zero4();
+      }
+    }
+    b = (bload && bn < v.Cout) ? ld16(v.W + (long long)bn * v.taps * v.Cp + t * v.Cp + cc + kq) : zero4();
+  };
+  f32x4 acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 na[RA], nb;
+  fetch(0, na, nb);
+  for (int step = 0; step < nsteps; ++step) {
+    const int buf = step & 1;
+#pragma unroll
+    for (int i = 0; i < RA; ++i) *reinterpret_cast<uint4*>(&As[buf][rr + 64 * i][kq]) = na[i];
+    if (bload) *reinterpret_cast<uint4*>(&Bs[buf][tid >> 2][kq]) = nb;
+    __syncthreads();
+    if (step + 1 < nsteps) fetch(step + 1, na, nb);
+    bf16x8 a[BI], b[BJ];
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  (void)NB;
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
+}
+
 // Convolution, gradient of the input:
 //   dIn[q][c] = sum_{t, o} dZ[q - off(t)][o] W[o][t][c]
 //   m = pixel q, k = t*Coutp + o, n = c; B read from WT[Cin][taps][Coutp].

@@ -238,6 +238,23 @@ def test_whole_network_forward_128(pnp):
     assert e < 1e-2
 
 
+def test_whole_network_forward_large_tiles(pnp):
+    """4 x 128 x 128 (65,536 pixels at full resolution, 16,384 at the second
+    scale): the 32-channel full-resolution convolutions run on the 256 x 32
+    tiles and the 64-channel second-scale ones on the 128 x 64 tiles."""
+    B, H, W = 4, 128, 128
+    params = _params(12)
+    net = pnp.UNet(params)
+    u = np.stack([(synth.phantom2d(128, 60 + i)[0] + 0.03 * synth.white_complex((H, W), 70 + i))
+                  for i in range(B)]).astype(np.complex64)
+    sigma = np.linspace(0.05, 0.01, B).astype(np.float32)
+    D = net.forward(_dev(u), _dev(sigma))
+    D_ref, _ = U.forward(params, u, sigma)
+    e = rel_l2(D.cpu().numpy() - u, D_ref - u)
+    say(f"[unet whole] 4x128x128 (large tiles) output rel {e:.2e}")
+    assert e < 1e-2
+
+
 def test_adam_step_matches_oracle(pnp):
     B, H, W = 1, 16, 16
     params, net, u, sigma = _setup(pnp, B, H, W, seed=9)
