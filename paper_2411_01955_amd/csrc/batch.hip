@@ -71,7 +71,7 @@ k_bcg_init(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef 
 }
 
 // one workgroup per slice: the slice's chunk sums -> rr and rho
-__global__ void __launch_bounds__(kRedThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_bcg_init_fin(const BVec* __restrict__ vec, const double* __restrict__ parts, DevScalars* __restrict__ sc,
                double* __restrict__ rho, int k) {
   const int i = blockIdx.x;
@@ -101,7 +101,7 @@ k_bcg_dots(const int4* __restrict__ ch, const BVec* __restrict__ vec, SliceCoef 
 }
 
 // one workgroup per slice: the slice's chunk sums -> alpha, beta, rr
-__global__ void __launch_bounds__(kRedThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_bcg_dots_fin(const BVec* __restrict__ vec, const double* __restrict__ parts, int first,
                DevScalars* __restrict__ sc) {
   const int i = blockIdx.x;
@@ -452,7 +452,7 @@ void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas,
     }
     launch_stages(b, b->d_in[0], s);   // N x
     PNP_LAUNCH(k_bcg_init, gch, bch, 0, s, b->d_chunks, b->d_vec, co, b->d_parts);
-    PNP_LAUNCH(k_bcg_init_fin, dim3(B), bch, 0, s, b->d_vec, b->d_parts, b->d_sc, b->d_rho, k);
+    PNP_LAUNCH(k_bcg_init_fin, dim3(B), dim3(kFinThreads), 0, s, b->d_vec, b->d_parts, b->d_sc, b->d_rho, k);
     int c = 0;
     for (int j = 0; j < n_cg; ++j) {
       const NormalIn* ins = b->d_in[1];
@@ -462,7 +462,7 @@ void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas,
       }
       launch_stages(b, ins, s);
       PNP_LAUNCH(k_bcg_dots, gch, bch, 0, s, b->d_chunks, b->d_vec, co, (float)c0, c, b->d_parts);
-      PNP_LAUNCH(k_bcg_dots_fin, dim3(B), bch, 0, s, b->d_vec, b->d_parts, j == 0 ? 1 : 0, b->d_sc);
+      PNP_LAUNCH(k_bcg_dots_fin, dim3(B), dim3(kFinThreads), 0, s, b->d_vec, b->d_parts, j == 0 ? 1 : 0, b->d_sc);
     }
     PNP_LAUNCH(k_bcg_final, gch, bch, 0, s, b->d_chunks, b->d_vec, c, (const DevScalars*)b->d_sc);
     const int cur = 1 - c;               // the prox result u lives in set cur
@@ -478,7 +478,7 @@ void batch_hqs_solve(pnp_batch* b, const pnp_prior* prior, const double* sigmas,
     SliceCoef zero{};
     launch_stages(b, b->d_in[0], s);
     PNP_LAUNCH(k_bcg_init, gch, bch, 0, s, b->d_chunks, b->d_vec, zero, b->d_parts);
-    PNP_LAUNCH(k_bcg_init_fin, dim3(B), bch, 0, s, b->d_vec, b->d_parts, b->d_sc, b->d_rho, n_out);
+    PNP_LAUNCH(k_bcg_init_fin, dim3(B), dim3(kFinThreads), 0, s, b->d_vec, b->d_parts, b->d_sc, b->d_rho, n_out);
   }
   PNP_LAUNCH(k_bcopy, gch, bch, 0, s, b->d_chunks, b->d_vec, 1, (float2* const*)nullptr);
   if (rho_host || bad_host) {

@@ -76,7 +76,7 @@ __device__ bool reduce_last(double (&v)[Q], double* __restrict__ parts, unsigned
 // plain stores (block_parts), and a following one-workgroup kernel sums
 // the partial sets in the same fixed order (sum_parts).  The kernel
 // boundary orders the stores, so no block pays a device-scope fence and an
-// atomic ticket; the results are bitwise those of reduce_last_of.
+// atomic ticket.
 template <int Q>
 __device__ void block_parts(double (&v)[Q], double* __restrict__ parts, int bidx) {
   __shared__ double sh[Q][kRedThreads / 64];
@@ -94,29 +94,22 @@ __device__ void block_parts(double (&v)[Q], double* __restrict__ parts, int bidx
   }
 }
 
-// Sum of `nblocks` partial sets (one workgroup of kRedThreads threads);
-// every thread receives the sums.
+// Sum of `nblocks` partial sets by one wave (launch with kFinThreads = 64
+// threads): lane j adds sets j, j + 64, ... in order, then a shuffle tree
+// combines the lanes -- no barriers; a fixed order, so deterministic.
+// Every lane receives the sums.
+constexpr int kFinThreads = 64;
 template <int Q>
 __device__ void sum_parts(const double* __restrict__ parts, int nblocks, double (&out)[Q]) {
-  __shared__ double fin[Q][kRedThreads];
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += parts[b * Q + q];
-    fin[q][threadIdx.x] = s;
+    for (int b = lane; b < nblocks; b += 64) s += parts[b * Q + q];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    out[q] = s;
   }
-  __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) fin[q][threadIdx.x] += fin[q][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) out[q] = fin[q][0];
 }
-
 
 struct DevScalars {
   double rr;        // <r, r>

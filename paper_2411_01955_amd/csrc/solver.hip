@@ -85,7 +85,7 @@ k_cg_init(long long N, int G, const float2* __restrict__ x, const float2* __rest
 }
 
 // one workgroup: the three sums of k_cg_init -> rr and rho
-__global__ void __launch_bounds__(kRedThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_cg_init_fin(const double* __restrict__ parts, int nblocks, DevScalars* sc, double* rho_out) {
   double s[3];
   sum_parts<3>(parts, nblocks, s);
@@ -114,7 +114,7 @@ k_cg_dots(long long N, int G, const float2* __restrict__ r, const float2* __rest
 }
 
 // one workgroup: the two sums of k_cg_dots -> alpha, beta, rr
-__global__ void __launch_bounds__(kRedThreads)
+__global__ void __launch_bounds__(kFinThreads)
 k_cg_dots_fin(const double* __restrict__ parts, int nblocks, int first, DevScalars* sc) {
   double s[2];
   sum_parts<2>(parts, nblocks, s);
@@ -397,7 +397,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u[0],
                w.r[0], w.p[0], w.s[0], w.parts);
-    PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, w.sc, rho_out);
+    PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, w.sc, rho_out);
   };
 
   for (int k = 0; k < a.n_out; ++k) {
@@ -420,7 +420,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
       normal_parts(p, a.toep, in, a.smaps, a.L, a.dcf, w.op, s);
       PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg, w.w,
                  w.parts);
-      PNP_LAUNCH(k_cg_dots_fin, dim3(1), dim3(kRedThreads), 0, s, w.parts, (int)nb, j == 0 ? 1 : 0, w.sc);
+      PNP_LAUNCH(k_cg_dots_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, j == 0 ? 1 : 0, w.sc);
     }
     float2* u_res = w.u[1 - c];
     PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res, w.sc);
