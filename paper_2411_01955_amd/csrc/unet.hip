@@ -403,20 +403,50 @@ namespace {
 
 const LayerInfo& layer(int i) { return layout().L[i]; }
 
+// K chunks of a forward convolution on the tiled kernels: fixed by the layer
+// and the image size, never by the batch, so every image of a batch gets
+// the arithmetic it gets alone.  Layers whose single-image launch has fewer
+// than 256 64 x 64 tiles split K in 2 or 4 (chunks of a multiple of 3 steps).
+int conv_chunks(const LayerInfo& l, int H, int W) {
+  if (l.cp % 32 != 0 || l.cout % 64 != 0) return 1;
+  const long long tiles = ((long long)H * W + 63) / 64 * (l.cout / 64);
+  const int nsteps = l.taps * (l.cp / 32);
+  int c = 1;
+  while (c < 4 && tiles * c < 256 && nsteps % (6 * c) == 0) c *= 2;
+  return c;
+}
+
 void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32, Geo g, bool relu,
                      hipStream_t s) {
   const LayerInfo& l = layer(li);
+  const int chunks = conv_chunks(l, g.H, g.W);
   unet::ConvFwd v{in, net->wbf + l.w_off, net->master + l.b_off, out, out32, g, l.taps, l.cp, l.cout,
-                  relu ? 1 : 0};
+                  relu ? 1 : 0, chunks};
   const long long P = (long long)g.B * g.H * g.W;
+  const int nsteps = l.taps * (l.cp / 32);     // K steps of the tiled kernels
   // larger tiles where the input channels come in 32-wide chunks and the
-  // launch still has a workgroup per compute unit; else 64 x 64
+  // launch still has a workgroup per compute unit (K chunks in sequence);
+  // else 64 x 64 tiles with one wave group per K chunk and a deeper load
+  // pipeline; the generic kernel for the rest (3-channel input, 1 x 1
+  // output), whose layers have a single chunk
   if (l.cp % 32 == 0 && l.cout == 32 && P / 256 >= 256) {
-    PNP_LAUNCH((unet::k_conv_fwd_tiled<256, 32, 4>), dim3(blocks_for(P, 256), 1, 1), dim3(256), 0, s, v);
+    PNP_LAUNCH((unet::k_conv_fwd_tiled<256, 32, 4, 1, 1, false>), dim3(blocks_for(P, 256), 1, 1), dim3(256), 0, s, v);
   } else if (l.cp % 32 == 0 && l.cout % 64 == 0 && (P / 128) * (l.cout / 64) >= 256) {
-    PNP_LAUNCH((unet::k_conv_fwd_tiled<128, 64, 2>), dim3(blocks_for(P, 128), l.cout / 64, 1), dim3(256), 0, s,
-               v);
+    const dim3 grid(blocks_for(P, 128), l.cout / 64, 1);
+    if (chunks > 1)
+      PNP_LAUNCH((unet::k_conv_fwd_tiled<128, 64, 2, 1, 1, true>), grid, dim3(256), 0, s, v);
+    else
+      PNP_LAUNCH((unet::k_conv_fwd_tiled<128, 64, 2, 1, 1, false>), grid, dim3(256), 0, s, v);
+  } else if (l.cp % 32 == 0 && l.cout % 64 == 0 && (nsteps / chunks) % 3 == 0) {
+    const dim3 grid(blocks_for(P, 64), l.cout / 64, 1);
+    if (chunks == 4)
+      PNP_LAUNCH((unet::k_conv_fwd_tiled<64, 64, 2, 3, 4, true>), grid, dim3(1024), 0, s, v);
+    else if (chunks == 2)
+      PNP_LAUNCH((unet::k_conv_fwd_tiled<64, 64, 2, 3, 2, true>), grid, dim3(512), 0, s, v);
+    else
+      PNP_LAUNCH((unet::k_conv_fwd_tiled<64, 64, 2, 3, 1, false>), grid, dim3(256), 0, s, v);
   } else {
+    if (chunks != 1) fail(PNP_ERR_UNSUPPORTED, "layer %d: K chunks on the generic convolution kernel", li);
     PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 1), dim3(256),
                0, s, v);
   }

@@ -60,6 +60,17 @@ struct Geo {
 };
 
 __device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+// 16 zero bytes: the load address of lanes whose operand element is outside
+// the tensor (a zero padding tap, a row past the end)
+static __device__ __attribute__((aligned(16))) const uint32_t kZeroRow[4] = {0u, 0u, 0u, 0u};
+// 16-byte load through the global address space (a pointer chosen between
+// a tensor and kZeroRow would otherwise become a flat load, which the
+// hardware counts together with the LDS accesses)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld16g(const uint16_t* p) {
+  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)(p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 
 // ------------------------------------------------------------ the GEMM
@@ -160,6 +171,7 @@ struct ConvFwd {
   float* out_f32;         // [P][Cout] FP32 output, or nullptr
   Geo g;
   int taps, Cp, Cout, relu;
+  int chunks;             // K chunks summed in order (k_conv_fwd_tiled; 1 elsewhere)
   __device__ int k_lo(int) const { return 0; }
   __device__ int k_hi(int) const { return taps * Cp; }
   __device__ uint4 loadA(int m, int k) const {
@@ -186,91 +198,185 @@ struct ConvFwd {
 };
 
 // Forward convolution with larger output tiles (inference and training
-// forward passes): a TM x TN tile per 256-thread workgroup, the four waves
-// arranged WM x (4/WM), each wave a 64 x 32 block of 4 x 2 MFMA tiles (8
-// MFMAs per 32-wide K step against 6 LDS reads), LDS stages double-buffered
-// (one barrier per step).  The K loop walks the taps and 32-channel chunks
-// of the input (Cp a multiple of 32), so a step's tap offset is uniform and
-// each thread's pixel coordinates are computed once.  TN = 32 serves the
-// 32-channel layers without the half-empty tiles of the 64 x 64 kernel.
-template <int TM, int TN, int WM>
-__global__ void __launch_bounds__(256) k_conv_fwd_tiled(ConvFwd v) {
+// forward passes): a TM x TN tile per group of four waves, the waves
+// arranged WM x (4/WM), each a (16 BI) x 32 block of BI x 2 MFMA tiles, LDS
+// stages double-buffered (one barrier per step).  The K loop walks the taps
+// and 32-channel chunks of the input (Cp a multiple of 32) in the order of
+// k_mfma_gemm.  The layer's K steps form v.chunks equal chunks: each chunk
+// is accumulated from zero and the chunk sums are added in order, so the
+// result depends on the layer and the image size only; G = 1 runs the
+// chunks one after the other, G = v.chunks runs them on G wave groups of
+// one workgroup (256 G threads) combined in order through LDS -- the deep
+// layers of one image launch a few tens of tiles, whose long K loops would
+// otherwise run one wave per SIMD with nothing to hide their latency.
+// CH = false instantiations serve single-chunk layers only (one set of
+// accumulators).  A step's tap and chunk are tracked by counters (no
+// division), each thread's pixel offset is formed once, and the global
+// loads run D steps ahead of the MFMAs in a register ring.  TN = 32 serves
+// the 32-channel layers without the half-empty tiles of the 64 x 64 kernel.
+template <int TM, int TN, int WM, int D, int G, bool CH>
+__global__ void __launch_bounds__(256 * G) k_conv_fwd_tiled(ConvFwd v) {
   constexpr int WN = 4 / WM;
   constexpr int BI = TM / WM / 16, BJ = TN / WN / 16;
-  static_assert(BI == 4 && BJ == 2, "64 x 32 per wave");
+  static_assert((BI == 4 || BI == 2) && BJ == 2, "(16 BI) x 32 per wave");
+  static_assert(D >= 1 && D <= 6, "prefetch depth");
+  static_assert(CH || G == 1, "wave groups need chunk sums");
   constexpr int RA = TM / 64;                  // A rows per thread
-  constexpr int NB = TN / 8;                   // B loaders: TN rows x 4 chunks = TN*4 threads
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][TM][40];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN][40];
-  const int tid = threadIdx.x;
+  constexpr int STAGE = 2 * (TM + TN) * 40;    // BF16 elements of one group's A and B stages
+  static_assert(G == 1 || (G - 1) * TM * TN * 2 <= G * STAGE, "LDS reduction fits in the stages");
+  __shared__ __attribute__((aligned(16))) uint16_t lds[G * STAGE];
+  const int grp = G == 1 ? 0 : (int)(threadIdx.x >> 8);
+  const int tid = threadIdx.x & 255;
+  uint16_t (*As)[TM][40] = reinterpret_cast<uint16_t (*)[TM][40]>(lds + grp * STAGE);
+  uint16_t (*Bs)[TN][40] = reinterpret_cast<uint16_t (*)[TN][40]>(lds + grp * STAGE + 2 * TM * 40);
   const int lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
   const int wm = (wave / WN) * (TM / WM), wn = (wave % WN) * (TN / WN);
   const int rr = tid >> 2, kq = (tid & 3) * 8;
+  const int H = v.g.H, W = v.g.W;
   const int P = v.g.P();
-  // pixel coordinates of this thread's A rows
-  int px[RA], py[RA], pb[RA];
+  // this thread's A rows: pixel coordinates and element offset of the
+  // centre tap (channel kq of the slice)
+  int px[RA], py[RA];
+  long long pa[RA];
 #pragma unroll
   for (int i = 0; i < RA; ++i) {
     const int m = m0 + rr + 64 * i;
-    pb[i] = m < P ? m / (v.g.W * v.g.H) : -1;
-    py[i] = (m / v.g.W) % v.g.H;
-    px[i] = m % v.g.W;
+    px[i] = m % W;
+    py[i] = m < P ? (m / W) % H : -(1 << 20);     // out-of-range rows fail the bounds test
+    pa[i] = (long long)m * v.in.cs + v.in.co + kq;
   }
-  const int chunks = v.Cp / 32;
-  const int nsteps = v.taps * chunks;
+  // steps of this group and of one chunk (multiples of D, checked by the
+  // launcher)
+  const int cpc = v.Cp / 32;
+  const int nsteps = v.taps * cpc;
+  const int csteps = nsteps / v.chunks;
+  const int sbeg = grp * (nsteps / G), send = sbeg + nsteps / G;
   const bool bload = tid < TN * 4;
   const int bn = n0 + (tid >> 2);
+  const bool bok = bload && bn < v.Cout;
+  // every load is issued unconditionally: out-of-range lanes read a row of
+  // zeros in device memory, so no value needs a select after its load and
+  // the loads stay in flight across the steps
+  const uint16_t* const zrow = reinterpret_cast<const uint16_t*>(kZeroRow);
+  const uint16_t* bp = bok ? v.W + (long long)bn * v.taps * v.Cp + kq : zrow;
+  const int bstep = bok ? 32 : 0;
+  // tap and channel offset of the next fetch, and of the group's last step
+  int ft = sbeg / cpc, fc = (sbeg - ft * cpc) * 32;
+  const int lt = (send - 1) / cpc, lc = (send - 1 - lt * cpc) * 32;
   auto fetch = [&](int step, uint4 (&a)[RA], uint4& b) {
-    const int t = step / chunks, cc = (step - t * chunks) * 32;
-    const int dy = tap_dy(v.taps, t), dx = tap_dx(v.taps, t);
+    const int dy = tap_dy(v.taps, ft), dx = tap_dx(v.taps, ft);
+    const long long toff = (long long)(dy * W + dx) * v.in.cs + fc;
 #pragma unroll
     for (int i = 0; i < RA; ++i) {
       const int y = py[i] + dy, x = px[i] + dx;
-      if (pb[i] >= 0 && (unsigned)y < (unsigned)v.g.H && (unsigned)x < (unsigned)v.g.W) {
-        const long long pix = ((long long)pb[i] * v.g.H + y) * v.g.W + x;
-        a[i] = ld16(v.in.p + pix * v.in.cs + v.in.co + cc + kq);
-      } else {
-        a[i] = zero4();
-      }
+      const bool ok = (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
+      a[i] = ld16g(ok ? v.in.p + pa[i] + toff : zrow);
     }
-    b = (bload && bn < v.Cout) ? ld16(v.W + (long long)bn * v.taps * v.Cp + t * v.Cp + cc + kq) : zero4();
+    b = ld16g(bp + (long long)step * bstep);
   };
-  f32x4 acc[BI][BJ];
+  auto advance = [&]() {
+    fc += 32;
+    if (fc == v.Cp) {
+      fc = 0;
+      ++ft;
+    }
+  };
+  f32x4 acc[BI][BJ], tot[BI][BJ];
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < BJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 na[RA], nb;
-  fetch(0, na, nb);
-  for (int step = 0; step < nsteps; ++step) {
-    const int buf = step & 1;
+    for (int j = 0; j < BJ; ++j) acc[i][j] = tot[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 na[D][RA], nb[D];
 #pragma unroll
-    for (int i = 0; i < RA; ++i) *reinterpret_cast<uint4*>(&As[buf][rr + 64 * i][kq]) = na[i];
-    if (bload) *reinterpret_cast<uint4*>(&Bs[buf][tid >> 2][kq]) = nb;
-    __syncthreads();
-    if (step + 1 < nsteps) fetch(step + 1, na, nb);
-    bf16x8 a[BI], b[BJ];
+  for (int d = 0; d < D; ++d) {
+    fetch(sbeg + d, na[d], nb[d]);
+    advance();
+  }
+  int left = csteps;                           // steps left in the current chunk
+  for (int s0 = sbeg; s0 < send; s0 += D) {
 #pragma unroll
-    for (int i = 0; i < BI; ++i)
-      a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+    for (int d = 0; d < D; ++d) {
+      const int step = s0 + d;
+      const int buf = step & 1;
 #pragma unroll
-    for (int j = 0; j < BJ; ++j)
-      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+      for (int i = 0; i < RA; ++i) *reinterpret_cast<uint4*>(&As[buf][rr + 64 * i][kq]) = na[d][i];
+      if (bload) *reinterpret_cast<uint4*>(&Bs[buf][tid >> 2][kq]) = nb[d];
+      __syncthreads();
+      // the last D steps fetch the group's final step again (a valid
+      // address; the values are never used)
+      const bool more = step + D < send;
+      if (!more) {
+        ft = lt;
+        fc = lc;
+      }
+      fetch(more ? step + D : send - 1, na[d], nb[d]);
+      if (more) advance();
+      bf16x8 a[BI], b[BJ];
 #pragma unroll
-    for (int i = 0; i < BI; ++i)
+      for (int i = 0; i < BI; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + 16 * i + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
       for (int j = 0; j < BJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + 16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if constexpr (CH) left -= D;
+    if (CH && left == 0) {                     // end of a chunk: add its sum in order
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) {
+          tot[i][j] += acc[i][j];
+          acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      left = csteps;
+    }
   }
-  (void)NB;
+  if constexpr (!CH) {
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) tot[i][j] = acc[i][j];
+  }
+  if constexpr (G > 1) {
+    // groups 1..G-1 hand their chunk sums to group 0, which adds them in
+    // chunk order (the stages are free once every group has left the loop)
+    float* red = reinterpret_cast<float*>(lds);
+    __syncthreads();
+    if (grp > 0) {
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            red[((grp - 1) * TM + wm + 16 * i + 4 * (lane >> 4) + q) * TN + wn + 16 * j + (lane & 15)] =
+                tot[i][j][q];
+    }
+    __syncthreads();
+    if (grp > 0) return;
+#pragma unroll
+    for (int g = 1; g < G; ++g)
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            tot[i][j][q] += red[((g - 1) * TM + wm + 16 * i + 4 * (lane >> 4) + q) * TN + wn + 16 * j + (lane & 15)];
+  }
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
+        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), tot[i][j][q]);
 }
 
 // Convolution, gradient of the input:

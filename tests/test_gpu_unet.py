@@ -255,6 +255,27 @@ def test_whole_network_forward_large_tiles(pnp):
     assert e < 1e-2
 
 
+def test_forward_batch_equals_single_images(pnp):
+    """Six 320 x 320 images in one call give bit-identical outputs to six
+    single-image calls.  The deep layers sum their K range in fixed chunks
+    (2 or 4, set by the image size); a single image runs the chunks on
+    parallel wave groups combined in order, the batch runs them in sequence
+    on the 128 x 64 tiles, so the two must agree exactly."""
+    B, H, W = 6, 320, 320
+    params = _params(13)
+    net = pnp.UNet(params)
+    u = np.stack([(synth.phantom2d(H, 80 + i)[0] + 0.03 * synth.white_complex((H, W), 90 + i))
+                  for i in range(B)]).astype(np.complex64)
+    sigma = np.linspace(0.06, 0.01, B).astype(np.float32)
+    Db = net.forward(_dev(u), _dev(sigma)).cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        Di = net.forward(_dev(u[i:i + 1]), _dev(sigma[i:i + 1])).cpu().numpy()
+        worst = max(worst, float(np.abs(Di[0] - Db[i]).max()))
+    say(f"[unet batch] 6x320x320 vs single images: max |difference| {worst:.1e}")
+    assert worst == 0.0
+
+
 def test_adam_step_matches_oracle(pnp):
     B, H, W = 1, 16, 16
     params, net, u, sigma = _setup(pnp, B, H, W, seed=9)
