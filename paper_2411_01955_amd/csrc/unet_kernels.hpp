@@ -13,7 +13,11 @@
 //                  true:  loadA(k, m) / loadB(k, n) return 8 consecutive-m / -n
 //                  values at one k (operand contiguous in m / n)
 //   k_lo(z), k_hi(z)  the K range handled by grid slice z (split-K)
-//   store(m, n, v) the epilogue (bias, ReLU, ReLU-derivative mask, BF16 or
+//   pre(m, n)      the epilogue's operand of element (m, n) read from memory
+//                  (bias, ReLU-derivative mask as 1/0; 0 where none): the
+//                  kernels read all of them before the first store, so the
+//                  loads are not serialised behind stores that might alias
+//   store(m, n, v, e) the epilogue (bias, ReLU, ReLU-derivative mask, BF16 or
 //                  FP32 output, FP32 atomics for split-K weight gradients)
 // Activations are NHWC BF16 with a per-tensor channel stride and offset, so
 // the concatenated skip connections are channel slices, never copies.
@@ -72,6 +76,11 @@ __device__ __forceinline__ uint4 ld16g(const uint16_t* p) {
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// Waits once for every outstanding vector-memory load (vmcnt 0, the other
+// counters left at their maximum): the epilogue operands have arrived, and
+// the per-element stores that follow need no wait of their own.
+__device__ __forceinline__ void epilogue_operands_ready() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // ------------------------------------------------------------ the GEMM
 template <class View>
@@ -134,13 +143,22 @@ __global__ void __launch_bounds__(256) k_mfma_gemm(View v) {
     __syncthreads();
   }
   // output block layout: lane holds rows 4*(lane/16) + q (q < 4) of column lane%16
+  float e[2][2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
+        e[i][j][q] = v.pre(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15));
+  epilogue_operands_ready();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), acc[i][j][q], e[i][j][q]);
 }
 
 // Offsets of the 3x3 taps (t = 3*(dy+1) + (dx+1)); a 1x1 convolution has one
@@ -155,6 +173,15 @@ struct Mask {
   int cs, co, mc;
   __device__ bool keep(int m, int n) const {
     return !p || n >= mc || bf_pos(p[(long long)m * cs + co + n]);
+  }
+  // keep() of element (m, n) when it lies in [0, P) x [0, nmax), else false;
+  // the load is issued for every lane (clamped to element (0, 0))
+  __device__ float keep_or_zero(int m, int n, int P, int nmax) const {
+    const bool in = m < P && n < nmax;
+    const bool chk = p && in && n < mc;
+    const uint16_t* q = p ? p : reinterpret_cast<const uint16_t*>(kZeroRow);
+    const uint16_t h = q[chk ? (long long)m * cs + co + n : 0ll];
+    return in && (!chk || bf_pos(h)) ? 1.f : 0.f;
   }
 };
 
@@ -186,9 +213,13 @@ struct ConvFwd {
     if (n >= Cout || k >= taps * Cp) return zero4();
     return ld16(W + (long long)n * taps * Cp + k);
   }
-  __device__ void store(int m, int n, float val) const {
+  __device__ float pre(int, int n) const {     // unconditional load (a clamped index)
+    const float b = bias[n < Cout ? n : 0];
+    return n < Cout ? b : 0.f;
+  }
+  __device__ void store(int m, int n, float val, float b) const {
     if (m >= g.P() || n >= Cout) return;
-    val += bias[n];
+    val += b;
     if (relu) val = fmaxf(val, 0.f);
     if (out_f32)
       out_f32[(long long)m * Cout + n] = val;
@@ -370,13 +401,17 @@ __global__ void __launch_bounds__(256 * G) k_conv_fwd_tiled(ConvFwd v) {
           for (int q = 0; q < 4; ++q)
             tot[i][j][q] += red[((g - 1) * TM + wm + 16 * i + 4 * (lane >> 4) + q) * TN + wn + 16 * j + (lane & 15)];
   }
+  float e[BJ];                                   // the bias of this lane's columns
+#pragma unroll
+  for (int j = 0; j < BJ; ++j) e[j] = v.pre(0, n0 + wn + 16 * j + (lane & 15));
+  epilogue_operands_ready();
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), tot[i][j][q]);
+        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), tot[i][j][q], e[j]);
 }
 
 // Convolution, gradient of the input:
@@ -404,9 +439,10 @@ struct ConvDX {
     if (n >= Cin || k >= taps * Coutp) return zero4();
     return ld16(WT + (long long)n * taps * Coutp + k);
   }
-  __device__ void store(int m, int n, float val) const {
+  __device__ float pre(int m, int n) const { return mask.keep_or_zero(m, n, g.P(), Cin); }
+  __device__ void store(int m, int n, float val, float keep) const {
     if (m >= g.P() || n >= Cin) return;
-    if (!mask.keep(m, n)) val = 0.f;
+    if (keep == 0.f) val = 0.f;
     dx.p[(long long)m * dx.cs + dx.co + n] = f2bf(val);
   }
 };
@@ -435,7 +471,8 @@ struct ConvDW {
     const long long pix = ((long long)(k / (g.W * g.H)) * g.H + y) * g.W + x;
     return ld16(in.p + pix * in.cs + in.co + c);
   }
-  __device__ void store(int m, int n, float val) const {
+  __device__ float pre(int, int) const { return 0.f; }
+  __device__ void store(int m, int n, float val, float) const {
     if (m >= Cout || n > taps * Cin) return;
     if (n == taps * Cin)
       atomicAdd(&dW[(long long)Cout * taps * Cin + m], val);
@@ -472,9 +509,13 @@ struct UpFwd {
     if (n >= Cout || k >= Cin) return zero4();
     return ld16(W + ((long long)n * 4 + blockIdx.z) * Cin + k);
   }
-  __device__ void store(int m, int n, float val) const {
+  __device__ float pre(int, int n) const {
+    const float b = bias[n < Cout ? n : 0];
+    return n < Cout ? b : 0.f;
+  }
+  __device__ void store(int m, int n, float val, float b) const {
     if (m >= g.P() || n >= Cout) return;
-    out.p[up_pix(g, m, blockIdx.z) * out.cs + out.co + n] = f2bf(val + bias[n]);
+    out.p[up_pix(g, m, blockIdx.z) * out.cs + out.co + n] = f2bf(val + b);
   }
 };
 
@@ -500,9 +541,10 @@ struct UpDX {
     if (n >= Cin || k >= 4 * Cout) return zero4();
     return ld16(WT + (long long)n * 4 * Cout + k);
   }
-  __device__ void store(int m, int n, float val) const {
+  __device__ float pre(int m, int n) const { return mask.keep_or_zero(m, n, g.P(), Cin); }
+  __device__ void store(int m, int n, float val, float keep) const {
     if (m >= g.P() || n >= Cin) return;
-    if (!mask.keep(m, n)) val = 0.f;
+    if (keep == 0.f) val = 0.f;
     dx.p[(long long)m * dx.cs + dx.co + n] = f2bf(val);
   }
 };
@@ -528,7 +570,8 @@ struct UpDW {
     if (n == Cin) return make_uint4(0x3f80u, 0u, 0u, 0u);
     return ld16(in.p + (long long)k * in.cs + in.co + n);
   }
-  __device__ void store(int m, int n, float val) const {
+  __device__ float pre(int, int) const { return 0.f; }
+  __device__ void store(int m, int n, float val, float) const {
     if (m >= Cout || n > Cin) return;
     if (n == Cin)
       atomicAdd(&dW[(long long)Cout * 4 * Cin + m], val);

@@ -193,3 +193,55 @@ def test_toeplitz_rejects_unsupported_size(pnp):
     with pytest.raises(pnp.PnPError) as ei:
         pnp.Toeplitz(plan)
     assert ei.value.status == -3
+
+
+# ------------------------------------------------- maximum sizes, rejections
+@pytest.mark.parametrize("n,L,M,toeplitz", [(1024, 2, 40000, False), (512, 4, 40000, True)])
+def test_maximum_sizes_sampled(pnp, n, L, M, toeplitz):
+    """The largest image of the plan (1024^2, general path) and of the fused
+    Toeplitz path (512^2): forward at sampled samples and adjoint at sampled
+    pixels against the NDFT, the normal operator by its self-adjointness and,
+    for 512^2, Toeplitz against gridded (both within the operator bar)."""
+    rng = np.random.default_rng(n + L)
+    k = rng.uniform(-math.pi, math.pi, (M, 2)).astype(np.float32)
+    k[:2] = [[-math.pi, -math.pi], [0.0, 0.0]]
+    dcf = rng.uniform(0.2, 2.0, M).astype(np.float32)
+    x, _ = synth.phantom2d(n, 31)
+    S = synth.smaps2d(n, L)
+    plan = pnp.Plan(to_dev(k), (n, n))
+    xd, Sd, dd = to_dev(x), to_dev(S), to_dev(dcf)
+    idx = rng.choice(M, 48, replace=False)
+    e_f = rel_l2(to_np(plan.forward(xd, Sd))[:, idx], ndft.forward_at(x, S, k, idx))
+    yv = synth.white_complex((L, M), 32)
+    pix = rng.choice(n * n, 48, replace=False)
+    xa = to_np(plan.adjoint(to_dev(yv), Sd, dd))
+    e_a = rel_l2(xa.reshape(-1)[pix], ndft.adjoint_at(yv, S, k, dcf, pix))
+    normal = (lambda v: pnp.Toeplitz(plan, dd).normal(v, Sd)) if toeplitz else (lambda v: plan.normal(v, Sd, dd))
+    x2 = synth.white_complex((n, n), 33)
+    N1 = to_np(normal(xd)).astype(np.complex128)
+    N2 = to_np(normal(to_dev(x2))).astype(np.complex128)
+    lhs, rhs = np.vdot(x2.astype(np.complex128), N1), np.vdot(N2, x.astype(np.complex128))
+    e_sa = abs(lhs - rhs) / abs(lhs)
+    e_tg = rel_l2(N1, to_np(plan.normal(xd, Sd, dd)).astype(np.complex128)) if toeplitz else 0.0
+    say(f"[ops] max size {n}x{n} L{L} M{M}: forward@48 {e_f:.2e} adjoint@48 {e_a:.2e} "
+        f"self-adjoint {e_sa:.1e} Toeplitz vs gridded {e_tg:.2e}")
+    assert max(e_f, e_a, e_tg) < TOL
+    assert e_sa < 1e-5
+
+
+def test_plan_rejects_bad_sizes(pnp):
+    """Odd, too small or too large sides, grids with a prime factor above 5,
+    four dimensions and an empty trajectory are refused before any launch."""
+    import ctypes as C
+    import torch
+    from paper_2411_01955_amd import _lib
+    k2 = torch.zeros((16, 2), dtype=torch.float32, device="cuda")
+    for shape in [(15, 16), (16, 2), (2048, 16), (14, 16)]:
+        with pytest.raises(pnp.PnPError) as ei:
+            pnp.Plan(k2, shape)
+        assert ei.value.status == -2, shape
+    h = C.c_void_p()
+    for ndim, M in [(4, 16), (2, 0), (2, -3)]:
+        shp = (C.c_int32 * 4)(16, 16, 16, 16)
+        st = _lib.load().pnp_plan_create(C.byref(h), ndim, shp, M, C.c_void_p(k2.data_ptr()), None)
+        assert st == -2, (ndim, M)
