@@ -96,7 +96,11 @@ typedef struct pnp_plan pnp_plan;
  *   out      host: receives the new handle
  *   ndim     2 or 3
  *   shape    host int32[ndim], slowest first; every size even, 4..1024, and
- *            2*size may only have prime factors 2, 3 and 5
+ *            2*size may only have prime factors 2, 3 and 5 (PNP_ERR_SHAPE
+ *            otherwise); 2D grids outside the register-FFT sizes also need
+ *            their column strips in LDS, 16 * tile * (2*ny + 1) bytes <= 160 KB
+ *            with tile = 8 where it divides 2*nx (sides up to 600 at 8-column
+ *            tiles; PNP_ERR_UNSUPPORTED otherwise)
  *   M        number of samples (>= 1)
  *   traj     device float32 [M][ndim], (kx, ky[, kz]) radians per pixel,
  *            all finite (checked; PNP_ERR_NUMERIC otherwise)

@@ -162,6 +162,9 @@ struct OpWorkspace {
 };
 size_t op_workspace_bytes(const pnp_plan* p, int L);
 OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws);
+// PNP_ERR_UNSUPPORTED when the 2D passes of plan p need more LDS than a
+// workgroup has (checked when the plan is created)
+void nufft2d_check_plan(const pnp_plan* p);
 
 void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y,
                 const OpWorkspace& w, hipStream_t s);

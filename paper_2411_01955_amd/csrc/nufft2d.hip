@@ -715,12 +715,17 @@ OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws) {
   return w;
 }
 
-static void check_lds(const pnp_plan* p) {
+// A 2D plan whose grid is served by the general passes must fit their LDS
+// (the register-FFT sizes always do).
+void nufft2d_check_plan(const pnp_plan* p) {
+  if (fs_ok(p)) return;
   const size_t need = std::max(rows_lds(p->ax[0].K), cols_lds(p));
   if (need > 160 * 1024)
-    fail(PNP_ERR_UNSUPPORTED, "grid %dx%d needs %zu bytes of LDS per workgroup", p->ax[1].K,
+    fail(PNP_ERR_UNSUPPORTED, "grid %dx%d needs %zu bytes of LDS per workgroup (160 KB available)", p->ax[1].K,
          p->ax[0].K, need);
 }
+
+static void check_lds(const pnp_plan* p) { nufft2d_check_plan(p); }
 
 // image -> per-entry interpolation partials in w.ypart
 static void forward_to_partials(const pnp_plan* p, const ImgIn& in, const float2* smaps, int L,

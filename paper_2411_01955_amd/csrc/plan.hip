@@ -498,6 +498,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     p->nty = ndim == 3 ? p->ax[1].K / p->tile : 1;
     p->ntiles = p->ntx * p->nty;
     p->slots = ndim == 3 ? 4 : 2;
+    nufft2d_check_plan(p);
 
     PNP_HIP(hipGetDevice(&p->device));
 

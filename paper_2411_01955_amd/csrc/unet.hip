@@ -166,13 +166,35 @@ __global__ void k_unet_pool_bwd(Act fin, Act gout, Act gin, Geo go, int C) {
   *dst = f2bf(bf2f(*dst) + bf2f(gout.p[p * gout.cs + gout.co + c]));
 }
 
-// dst = u + out (FP32 residual output of the denoiser)
-__global__ void k_unet_residual(const float2* __restrict__ u, const float2* __restrict__ o, long long P,
-                                float2* __restrict__ dst) {
+// Output layer (1 x 1 convolution, 32 -> 2 channels) and residual, one
+// thread per pixel: o[p] = b + W d[p] in FP32 (the network output, kept for
+// the loss) and, when dst is set, dst[p] = u[p] + o[p].  d: BF16 [P][32];
+// W: BF16 [2][32]; b: FP32 [2].
+__global__ void __launch_bounds__(kThreads) k_unet_head(const uint16_t* __restrict__ d,
+                                                        const uint16_t* __restrict__ W,
+                                                        const float* __restrict__ b,
+                                                        const float2* __restrict__ u, long long P,
+                                                        float2* __restrict__ o, float2* __restrict__ dst) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  const float2 a = u[p], b = o[p];
-  dst[p] = make_float2(a.x + b.x, a.y + b.y);
+  float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+  for (int c8 = 0; c8 < 4; ++c8) {
+    const uint4 q = *reinterpret_cast<const uint4*>(d + p * 32 + 8 * c8);
+    const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float f = unet::bf2f((uint16_t)(w4[e >> 1] >> (16 * (e & 1))));
+      a0 = fmaf(f, unet::bf2f(W[8 * c8 + e]), a0);
+      a1 = fmaf(f, unet::bf2f(W[32 + 8 * c8 + e]), a1);
+    }
+  }
+  const float2 r = make_float2(a0 + b[0], a1 + b[1]);
+  o[p] = r;
+  if (dst) {
+    const float2 x = u[p];
+    dst[p] = make_float2(x.x + r.x, x.y + r.y);
+  }
 }
 
 __device__ __forceinline__ float sgnf(float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); }
@@ -429,22 +451,24 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
   // else 64 x 64 tiles with one wave group per K chunk and a deeper load
   // pipeline; the generic kernel for the rest (3-channel input, 1 x 1
   // output), whose layers have a single chunk
-  if (l.cp % 32 == 0 && l.cout == 32 && P / 256 >= 256) {
-    PNP_LAUNCH((unet::k_conv_fwd_tiled<256, 32, 4, 1, 1, false>), dim3(blocks_for(P, 256), 1, 1), dim3(256), 0, s, v);
+  if (l.cp % 32 == 0 && l.cout == 32 && P / 256 >= 512) {
+    PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 256, 32, 4, 1, 1, false>), dim3(blocks_for(P, 256), 1, 1), dim3(256), 0, s, v);
+  } else if (l.cp % 32 == 0 && l.cout == 32 && P / 128 >= 256) {
+    PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 128, 32, 4, 1, 1, false>), dim3(blocks_for(P, 128), 1, 1), dim3(256), 0, s, v);
   } else if (l.cp % 32 == 0 && l.cout % 64 == 0 && (P / 128) * (l.cout / 64) >= 256) {
     const dim3 grid(blocks_for(P, 128), l.cout / 64, 1);
     if (chunks > 1)
-      PNP_LAUNCH((unet::k_conv_fwd_tiled<128, 64, 2, 1, 1, true>), grid, dim3(256), 0, s, v);
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 128, 64, 2, 1, 1, true>), grid, dim3(256), 0, s, v);
     else
-      PNP_LAUNCH((unet::k_conv_fwd_tiled<128, 64, 2, 1, 1, false>), grid, dim3(256), 0, s, v);
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 128, 64, 2, 1, 1, false>), grid, dim3(256), 0, s, v);
   } else if (l.cp % 32 == 0 && l.cout % 64 == 0 && (nsteps / chunks) % 3 == 0) {
     const dim3 grid(blocks_for(P, 64), l.cout / 64, 1);
     if (chunks == 4)
-      PNP_LAUNCH((unet::k_conv_fwd_tiled<64, 64, 2, 3, 4, true>), grid, dim3(1024), 0, s, v);
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 64, 64, 2, 3, 4, true>), grid, dim3(1024), 0, s, v);
     else if (chunks == 2)
-      PNP_LAUNCH((unet::k_conv_fwd_tiled<64, 64, 2, 3, 2, true>), grid, dim3(512), 0, s, v);
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 64, 64, 2, 3, 2, true>), grid, dim3(512), 0, s, v);
     else
-      PNP_LAUNCH((unet::k_conv_fwd_tiled<64, 64, 2, 3, 1, false>), grid, dim3(256), 0, s, v);
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvFwd, 64, 64, 2, 3, 1, false>), grid, dim3(256), 0, s, v);
   } else {
     if (chunks != 1) fail(PNP_ERR_UNSUPPORTED, "layer %d: K chunks on the generic convolution kernel", li);
     PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 1), dim3(256),
@@ -454,10 +478,20 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
 
 void launch_up_fwd(const pnp_unet* net, int li, Act in, Act out, Geo g, hipStream_t s) {
   const LayerInfo& l = layer(li);
-  unet::UpFwd v{in, net->wbf + l.w_off, net->master + l.b_off, out, g, l.cin, l.cout};
+  unet::UpFwd v{in, net->wbf + l.w_off, net->master + l.b_off, out, g, l.cin, l.cout, 1, l.cin, 1};
   const long long P = (long long)g.B * g.H * g.W;
-  PNP_LAUNCH(unet::k_mfma_gemm<unet::UpFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 4), dim3(256), 0,
-             s, v);
+  // the tiled kernels (K = Cin in 32-wide steps) where the channels allow,
+  // one grid slice per output sub-pixel
+  if (l.cin % 64 == 0 && l.cout % 64 == 0) {
+    PNP_LAUNCH((unet::k_gemm_tiled<unet::UpFwd, 64, 64, 2, 2, 1, false>), dim3(blocks_for(P, 64), l.cout / 64, 4),
+               dim3(256), 0, s, v);
+  } else if (l.cin % 32 == 0 && l.cout == 32) {
+    PNP_LAUNCH((unet::k_gemm_tiled<unet::UpFwd, 128, 32, 4, 1, 1, false>), dim3(blocks_for(P, 128), 1, 4),
+               dim3(256), 0, s, v);
+  } else {
+    PNP_LAUNCH(unet::k_mfma_gemm<unet::UpFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 4), dim3(256), 0,
+               s, v);
+  }
 }
 
 void launch_pool(Act in, Act out, Geo go, int C, hipStream_t s) {
@@ -665,10 +699,11 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
   launch_up_fwd(net, 14, A(w.d2b, 64, 0, 64), A(w.c1, 64, 32, 32), g1, s);
   launch_conv_fwd(net, 15, A(w.c1, 64, 0, 64), A(w.d1a, 32, 0, 32), nullptr, g0, true, s);
   launch_conv_fwd(net, 16, A(w.d1a, 32, 0, 32), A(w.d1b, 32, 0, 32), nullptr, g0, true, s);
-  launch_conv_fwd(net, 17, A(w.d1b, 32, 0, 32), Act{nullptr, 0, 0, 0}, w.out, g0, false, s);
-  if (out)
-    PNP_LAUNCH(k_unet_residual, dim3(blocks_for(P0)), dim3(kThreads), 0, s, u,
-               reinterpret_cast<const float2*>(w.out), P0, out);
+  {
+    const LayerInfo& l = layer(17);
+    PNP_LAUNCH(k_unet_head, dim3(blocks_for(P0)), dim3(kThreads), 0, s, w.d1b, net->wbf + l.w_off,
+               net->master + l.b_off, u, P0, reinterpret_cast<float2*>(w.out), out);
+  }
 }
 
 // Parameter gradients from the output gradient w.gout of a train-sized

@@ -34,13 +34,14 @@ namespace unet {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-// FP32 -> BF16, round to nearest even (NaN stays NaN)
+// FP32 -> BF16, round to nearest even (NaN stays NaN, quieted); written as
+// a select so that epilogues do not branch per element
 __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u;
   memcpy(&u, &f, 4);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const uint32_t quiet = (u >> 16) | 0x40u;
+  return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? quiet : rounded);
 }
 __host__ __device__ __forceinline__ float bf2f(uint16_t h) {
   const uint32_t u = (uint32_t)h << 16;
@@ -198,9 +199,11 @@ struct ConvFwd {
   float* out_f32;         // [P][Cout] FP32 output, or nullptr
   Geo g;
   int taps, Cp, Cout, relu;
-  int chunks;             // K chunks summed in order (k_conv_fwd_tiled; 1 elsewhere)
+  int chunks;             // K chunks summed in order (k_gemm_tiled; 1 elsewhere)
   __device__ int k_lo(int) const { return 0; }
   __device__ int k_hi(int) const { return taps * Cp; }
+  // start of output channel n's weights (k_gemm_tiled)
+  __device__ const uint16_t* wrow(int n) const { return W + (long long)n * taps * Cp; }
   __device__ uint4 loadA(int m, int k) const {
     if (m >= g.P() || k >= taps * Cp) return zero4();
     const int t = k / Cp, c = k - t * Cp;
@@ -217,19 +220,26 @@ struct ConvFwd {
     const float b = bias[n < Cout ? n : 0];
     return n < Cout ? b : 0.f;
   }
-  __device__ void store(int m, int n, float val, float b) const {
+  // output pixels of rows m .. m+3 (k_gemm_tiled)
+  __device__ void pix4(int m, long long (&o)[4]) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = m + q;
+  }
+  __device__ void store_px(int m, long long px, int n, float val, float b) const {
     if (m >= g.P() || n >= Cout) return;
     val += b;
     if (relu) val = fmaxf(val, 0.f);
     if (out_f32)
-      out_f32[(long long)m * Cout + n] = val;
+      out_f32[px * Cout + n] = val;
     else
-      out.p[(long long)m * out.cs + out.co + n] = f2bf(val);
+      out.p[px * out.cs + out.co + n] = f2bf(val);
   }
+  __device__ void store(int m, int n, float val, float b) const { store_px(m, m, n, val, b); }
 };
 
-// Forward convolution with larger output tiles (inference and training
-// forward passes): a TM x TN tile per group of four waves, the waves
+// Forward convolution (view ConvFwd) and transposed convolution (UpFwd, one
+// tap, grid z = the output sub-pixel) with larger output tiles (inference
+// and training forward passes): a TM x TN tile per group of four waves, the waves
 // arranged WM x (4/WM), each a (16 BI) x 32 block of BI x 2 MFMA tiles, LDS
 // stages double-buffered (one barrier per step).  The K loop walks the taps
 // and 32-channel chunks of the input (Cp a multiple of 32) in the order of
@@ -245,8 +255,8 @@ struct ConvFwd {
 // division), each thread's pixel offset is formed once, and the global
 // loads run D steps ahead of the MFMAs in a register ring.  TN = 32 serves
 // the 32-channel layers without the half-empty tiles of the 64 x 64 kernel.
-template <int TM, int TN, int WM, int D, int G, bool CH>
-__global__ void __launch_bounds__(256 * G) k_conv_fwd_tiled(ConvFwd v) {
+template <class V, int TM, int TN, int WM, int D, int G, bool CH>
+__global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
   constexpr int WN = 4 / WM;
   constexpr int BI = TM / WM / 16, BJ = TN / WN / 16;
   static_assert((BI == 4 || BI == 2) && BJ == 2, "(16 BI) x 32 per wave");
@@ -290,7 +300,7 @@ __global__ void __launch_bounds__(256 * G) k_conv_fwd_tiled(ConvFwd v) {
   // zeros in device memory, so no value needs a select after its load and
   // the loads stay in flight across the steps
   const uint16_t* const zrow = reinterpret_cast<const uint16_t*>(kZeroRow);
-  const uint16_t* bp = bok ? v.W + (long long)bn * v.taps * v.Cp + kq : zrow;
+  const uint16_t* bp = bok ? v.wrow(bn) + kq : zrow;
   const int bstep = bok ? 32 : 0;
   // tap and channel offset of the next fetch, and of the group's last step
   int ft = sbeg / cpc, fc = (sbeg - ft * cpc) * 32;
@@ -406,12 +416,15 @@ __global__ void __launch_bounds__(256 * G) k_conv_fwd_tiled(ConvFwd v) {
   for (int j = 0; j < BJ; ++j) e[j] = v.pre(0, n0 + wn + 16 * j + (lane & 15));
   epilogue_operands_ready();
 #pragma unroll
-  for (int i = 0; i < BI; ++i)
+  for (int i = 0; i < BI; ++i) {
+    const int mr = m0 + wm + 16 * i + 4 * (lane >> 4);
+    long long px[4];
+    v.pix4(mr, px);
 #pragma unroll
     for (int j = 0; j < BJ; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        v.store(m0 + wm + 16 * i + 4 * (lane >> 4) + q, n0 + wn + 16 * j + (lane & 15), tot[i][j][q], e[j]);
+      for (int q = 0; q < 4; ++q) v.store_px(mr + q, px[q], n0 + wn + 16 * j + (lane & 15), tot[i][j][q], e[j]);
+  }
 }
 
 // Convolution, gradient of the input:
@@ -499,8 +512,10 @@ struct UpFwd {
   Act out;                // BF16 slice at twice the resolution
   Geo g;                  // input geometry
   int Cin, Cout;
+  int taps, Cp, chunks;   // k_gemm_tiled: 1 tap, Cp = Cin, 1 chunk
   __device__ int k_lo(int) const { return 0; }
   __device__ int k_hi(int) const { return Cin; }
+  __device__ const uint16_t* wrow(int n) const { return W + ((long long)n * 4 + blockIdx.z) * Cin; }
   __device__ uint4 loadA(int m, int k) const {
     if (m >= g.P() || k >= Cin) return zero4();
     return ld16(in.p + (long long)m * in.cs + in.co + k);
@@ -513,10 +528,36 @@ struct UpFwd {
     const float b = bias[n < Cout ? n : 0];
     return n < Cout ? b : 0.f;
   }
-  __device__ void store(int m, int n, float val, float b) const {
-    if (m >= g.P() || n >= Cout) return;
-    out.p[up_pix(g, m, blockIdx.z) * out.cs + out.co + n] = f2bf(val + b);
+  // output pixels of input rows m .. m+3 for this grid slice's sub-pixel,
+  // one division pair for the four (k_gemm_tiled)
+  __device__ void pix4(int m, long long (&o)[4]) const {
+    const int t = blockIdx.z;
+    if (g.W >= 4) {
+      int r = m / g.W;
+      int j = m - r * g.W;
+      int b = r / g.H;
+      int i = r - b * g.H;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        o[q] = ((long long)b * 2 * g.H + 2 * i + (t >> 1)) * (2 * g.W) + 2 * j + (t & 1);
+        if (++j == g.W) {
+          j = 0;
+          if (++i == g.H) {
+            i = 0;
+            ++b;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = up_pix(g, m + q, t);
+    }
   }
+  __device__ void store_px(int m, long long px, int n, float val, float b) const {
+    if (m >= g.P() || n >= Cout) return;
+    out.p[px * out.cs + out.co + n] = f2bf(val + b);
+  }
+  __device__ void store(int m, int n, float val, float b) const { store_px(m, up_pix(g, m, blockIdx.z), n, val, b); }
 };
 
 // Transposed convolution, gradient of the input:

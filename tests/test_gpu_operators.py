@@ -196,10 +196,11 @@ def test_toeplitz_rejects_unsupported_size(pnp):
 
 
 # ------------------------------------------------- maximum sizes, rejections
-@pytest.mark.parametrize("n,L,M,toeplitz", [(1024, 2, 40000, False), (512, 4, 40000, True)])
+@pytest.mark.parametrize("n,L,M,toeplitz", [(600, 2, 40000, False), (512, 4, 40000, True)])
 def test_maximum_sizes_sampled(pnp, n, L, M, toeplitz):
-    """The largest image of the plan (1024^2, general path) and of the fused
-    Toeplitz path (512^2): forward at sampled samples and adjoint at sampled
+    """The largest 2D image of the general passes (600^2: the 8-column strip
+    of a 1200-point column fills 154 KB of LDS) and of the fused register-FFT
+    and Toeplitz path (512^2): forward at sampled samples and adjoint at sampled
     pixels against the NDFT, the normal operator by its self-adjointness and,
     for 512^2, Toeplitz against gridded (both within the operator bar)."""
     rng = np.random.default_rng(n + L)
@@ -231,7 +232,9 @@ def test_maximum_sizes_sampled(pnp, n, L, M, toeplitz):
 
 def test_plan_rejects_bad_sizes(pnp):
     """Odd, too small or too large sides, grids with a prime factor above 5,
-    four dimensions and an empty trajectory are refused before any launch."""
+    four dimensions and an empty trajectory are refused (PNP_ERR_SHAPE), and
+    a 2D grid too large for the LDS of its passes (PNP_ERR_UNSUPPORTED), when
+    the plan is created."""
     import ctypes as C
     import torch
     from paper_2411_01955_amd import _lib
@@ -240,6 +243,10 @@ def test_plan_rejects_bad_sizes(pnp):
         with pytest.raises(pnp.PnPError) as ei:
             pnp.Plan(k2, shape)
         assert ei.value.status == -2, shape
+    # a valid size whose column strip does not fit in LDS (2048-point columns)
+    with pytest.raises(pnp.PnPError) as ei:
+        pnp.Plan(k2, (1024, 1024))
+    assert ei.value.status == -3
     h = C.c_void_p()
     for ndim, M in [(4, 16), (2, 0), (2, -3)]:
         shp = (C.c_int32 * 4)(16, 16, 16, 16)
