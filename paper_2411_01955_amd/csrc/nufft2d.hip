@@ -314,14 +314,22 @@ constexpr int kSpreadChunk = 256;   // entries staged in LDS at a time
 constexpr int kAdjThreads = 512;    // spread uses all waves, the FFT the first 8*K1 threads
 constexpr int kAdjWaves = kAdjThreads / 64;
 constexpr int kSpreadIlp = 8;       // entries in flight per lane in the gather loop
+constexpr int kMaxDense = 4;        // dense row blocks per strip shared by all waves
+constexpr int kDenseMin = 256;      // entries in a row block's window that make it dense
+static_assert(kMaxDense * kAdjWaves * 64 * sizeof(float2) <= kSpreadChunk * sizeof(EntryRec),
+              "dense-block partial sums fit in the entry staging buffer");
 
 // Type-1 spread by gathering: wave w owns the 8x8 grid-point blocks
 // (rows 8*rb .. 8*rb+7 of the strip's 8 columns) with rb = w, w + 8, ...;
 // lane (row lr = lane/8, column lc = lane%8) accumulates in registers every
 // entry whose first row tap lies within 5 rows above its block (entries are
 // sorted by first row tap, row_start indexes them), reading the entry's taps,
-// weights and weighted k-space value from LDS as broadcasts.  Each grid
-// point is written once: no atomics, deterministic summation order.
+// weights and weighted k-space value from LDS as broadcasts.  Up to
+// kMaxDense blocks whose window holds kDenseMin or more entries (the densely
+// sampled k-space centre) are shared by all waves instead: each wave takes a
+// fixed slice of every staged chunk of the block's entries, and the eight
+// partial sums are added in wave order.  Each grid point is written once: no
+// atomics, deterministic summation order.
 template <int K1, int K2>
 __global__ void __launch_bounds__(kAdjThreads)
 k_cols_adj_fs(const float2* __restrict__ yent, long long E,
@@ -335,6 +343,7 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   __shared__ EntryRec srec[kSpreadChunk];
   __shared__ float2 sval[kSpreadChunk];
   __shared__ int srs[F::K + 1];
+  __shared__ int sdense[kMaxDense + 1];                          // count, then row blocks
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;           // FFT threads: t < K1
   const int s = blockIdx.x;
@@ -347,84 +356,134 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   int gc = c0 + lc;
   if (gc >= Kx) gc -= Kx;
   for (int i = threadIdx.x; i <= F::K; i += blockDim.x) srs[i] = row_start[(long long)s * (F::K + 1) + i];
-  float2 acc[RBW];
+  __syncthreads();
+  // entry range(s) of the window of row block rb: rows [8 rb - 5, 8 rb + 8), wrapped
+  auto window = [&](int rb, int& ra0, int& rb0, int& ra1, int& rb1) {
+    const int lo = rb * 8 - 5, hi = rb * 8 + 8;
+    if (lo >= 0) {
+      ra0 = srs[lo]; rb0 = srs[hi]; ra1 = 0; rb1 = 0;
+    } else {
+      ra0 = srs[F::K + lo]; rb0 = srs[F::K]; ra1 = srs[0]; rb1 = srs[hi];
+    }
+  };
+  if (threadIdx.x == 0) {
+    int nd = 0;
+    for (int rb = 0; rb < NRB && nd < kMaxDense; ++rb) {
+      int ra0, rb0, ra1, rb1;
+      window(rb, ra0, rb0, ra1, rb1);
+      if ((rb0 - ra0) + (rb1 - ra1) >= kDenseMin) sdense[1 + nd++] = rb;
+    }
+    sdense[0] = nd;
+  }
+  float2 acc[RBW], accd[kMaxDense];
 #pragma unroll
   for (int k = 0; k < RBW; ++k) acc[k] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int d = 0; d < kMaxDense; ++d) accd[d] = make_float2(0.f, 0.f);
   const int e0 = tile_off[s], e1 = tile_off[s + 1];
   const float* srec_f = reinterpret_cast<const float*>(srec);
-  for (int cb = e0; cb < e1; cb += kSpreadChunk) {
+  int cb = e0;
+  // entries [ea, eb) of the staged chunk starting at cb into grid point
+  // (row, gc): kSpreadIlp independent entries per step, all LDS reads of a
+  // step issued before any is consumed; out-of-range entries are clamped to a
+  // valid index and masked to zero weight
+  auto gather = [&](int ea, int eb, int row, float2& a) {
+    for (int e = ea; e < eb; e += kSpreadIlp) {
+      int ii[kSpreadIlp], dxc[kSpreadIlp], dyc[kSpreadIlp];
+      bool ok[kSpreadIlp];
+      int4 idx[kSpreadIlp];
+#pragma unroll
+      for (int u = 0; u < kSpreadIlp; ++u) {
+        ii[u] = min(e + u, eb - 1) - cb;
+        idx[u] = srec[ii[u]].idx;
+      }
+#pragma unroll
+      for (int u = 0; u < kSpreadIlp; ++u) {
+        int dx = gc - idx[u].x;
+        dx += dx < 0 ? Kx : 0;
+        int dy = row - idx[u].y;
+        dy += dy < 0 ? F::K : 0;
+        ok[u] = dx < 6 && dy < 6 && e + u < eb;
+        dxc[u] = ok[u] ? dx : 0;
+        dyc[u] = ok[u] ? dy : 0;
+      }
+      float wx[kSpreadIlp], wy[kSpreadIlp];
+      float2 sv[kSpreadIlp];
+#pragma unroll
+      for (int u = 0; u < kSpreadIlp; ++u) {
+        wx[u] = srec_f[16 * ii[u] + 4 + dxc[u]];
+        wy[u] = srec_f[16 * ii[u] + 10 + dyc[u]];
+        sv[u] = sval[ii[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kSpreadIlp; ++u) {
+        const float wgt = ok[u] ? wx[u] * wy[u] : 0.f;
+        a = make_float2(fmaf(wgt, sv[u].x, a.x), fmaf(wgt, sv[u].y, a.y));
+      }
+    }
+  };
+  for (; cb < e1; cb += kSpreadChunk) {
     const int n = min(kSpreadChunk, e1 - cb);
-    __syncthreads();  // previous chunk consumed (and srs staged)
+    __syncthreads();  // previous chunk consumed (and the dense list written)
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       srec[i] = rec[cb + i];
       sval[i] = yent[(long long)l * E + cb + i];
     }
     __syncthreads();
     const int ce = cb + n;
+    const int nd = sdense[0];
 #pragma unroll
     for (int k = 0; k < RBW; ++k) {
       const int rb = wave + k * kAdjWaves;
-      if (rb < NRB) {
-        const int r0 = rb * 8;
-        const int row = r0 + lr;
-        const int lo = r0 - 5, hi = r0 + 8;
+      bool shared = false;
+#pragma unroll
+      for (int d = 0; d < kMaxDense; ++d) shared |= d < nd && sdense[1 + d] == rb;
+      if (rb < NRB && !shared) {
         int ra0, rb0, ra1, rb1;
-        if (lo >= 0) {
-          ra0 = srs[lo]; rb0 = srs[hi]; ra1 = 0; rb1 = 0;
-        } else {
-          ra0 = srs[F::K + lo]; rb0 = srs[F::K]; ra1 = srs[0]; rb1 = srs[hi];
-        }
+        window(rb, ra0, rb0, ra1, rb1);
+        gather(max(ra0, cb), min(rb0, ce), rb * 8 + lr, acc[k]);
+        gather(max(ra1, cb), min(rb1, ce), rb * 8 + lr, acc[k]);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < kMaxDense; ++d) {
+      if (d < nd) {
+        const int rb = sdense[1 + d];
+        int ra[2], rz[2];
+        window(rb, ra[0], rz[0], ra[1], rz[1]);
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
-          const int ea = max(part ? ra1 : ra0, cb);
-          const int eb = min(part ? rb1 : rb0, ce);
-          // kSpreadIlp independent entries per step: all LDS reads of a step
-          // are issued before any is consumed; out-of-range entries are
-          // clamped to a valid index and masked to zero weight
-          for (int e = ea; e < eb; e += kSpreadIlp) {
-            int ii[kSpreadIlp], dxc[kSpreadIlp], dyc[kSpreadIlp];
-            bool ok[kSpreadIlp];
-            int4 idx[kSpreadIlp];
-#pragma unroll
-            for (int u = 0; u < kSpreadIlp; ++u) {
-              ii[u] = min(e + u, eb - 1) - cb;
-              idx[u] = srec[ii[u]].idx;
-            }
-#pragma unroll
-            for (int u = 0; u < kSpreadIlp; ++u) {
-              int dx = gc - idx[u].x;
-              dx += dx < 0 ? Kx : 0;
-              int dy = row - idx[u].y;
-              dy += dy < 0 ? F::K : 0;
-              ok[u] = dx < 6 && dy < 6 && e + u < eb;
-              dxc[u] = ok[u] ? dx : 0;
-              dyc[u] = ok[u] ? dy : 0;
-            }
-            float wx[kSpreadIlp], wy[kSpreadIlp];
-            float2 sv[kSpreadIlp];
-#pragma unroll
-            for (int u = 0; u < kSpreadIlp; ++u) {
-              wx[u] = srec_f[16 * ii[u] + 4 + dxc[u]];
-              wy[u] = srec_f[16 * ii[u] + 10 + dyc[u]];
-              sv[u] = sval[ii[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kSpreadIlp; ++u) {
-              const float wgt = ok[u] ? wx[u] * wy[u] : 0.f;
-              acc[k] = make_float2(fmaf(wgt, sv[u].x, acc[k].x), fmaf(wgt, sv[u].y, acc[k].y));
-            }
+          const int ea = max(ra[part], cb), eb = min(rz[part], ce);
+          if (ea < eb) {
+            const long long len = eb - ea;
+            gather(ea + (int)(len * wave / kAdjWaves), ea + (int)(len * (wave + 1) / kAdjWaves), rb * 8 + lr,
+                   accd[d]);
           }
         }
       }
     }
   }
   __syncthreads();
+  const int nd = sdense[0];
+  float2* dpart = reinterpret_cast<float2*>(srec);               // staging buffer is free now
   if (lc < tile) {
 #pragma unroll
     for (int k = 0; k < RBW; ++k) {
       const int rb = wave + k * kAdjWaves;
       if (rb < NRB) lds[lc * F::GS + rb * 8 + lr] = acc[k];
     }
+  }
+#pragma unroll
+  for (int d = 0; d < kMaxDense; ++d)
+    if (d < nd) dpart[(d * kAdjWaves + wave) * 64 + lane] = accd[d];
+  __syncthreads();
+  if (wave < nd) {                         // wave d adds dense block d's partial sums in wave order
+    float2 sum = make_float2(0.f, 0.f);
+    for (int w = 0; w < kAdjWaves; ++w) {
+      const float2 v = dpart[(wave * kAdjWaves + w) * 64 + lane];
+      sum = make_float2(sum.x + v.x, sum.y + v.y);
+    }
+    if (lc < tile) lds[lc * F::GS + sdense[1 + wave] * 8 + lr] = sum;
   }
   __syncthreads();
   float2 v[K1];
