@@ -111,6 +111,28 @@ __device__ void sum_parts(const double* __restrict__ parts, int nblocks, double 
   }
 }
 
+// sum_parts for a workgroup of 32 lanes or of whole waves: with 32 lanes,
+// lane j also adds the sets of lane j + 32 of the 64-lane order and the
+// first level of the tree becomes that addition, so the result equals
+// sum_parts' bit for bit.
+template <int Q>
+__device__ void sum_parts_any(const double* __restrict__ parts, int nblocks, double (&out)[Q]) {
+  if (blockDim.x >= 64) {
+    sum_parts<Q>(parts, nblocks, out);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double a = 0.0, b = 0.0;
+    for (int k = lane; k < nblocks; k += 64) a += parts[k * Q + q];
+    for (int k = lane + 32; k < nblocks; k += 64) b += parts[k * Q + q];
+    double s = a + b;
+    for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    out[q] = s;
+  }
+}
+
 struct DevScalars {
   double rr;        // <r, r>
   double pq;        // Re <w, r> of the last step (w = M r)
@@ -128,25 +150,52 @@ struct DevScalars {
 //   later steps: beta = g / rr, alpha = g / (d - beta g / alpha)
 // then rr = g.  A zero residual gives alpha = beta = 0; a non-positive or
 // non-finite denominator sets `bad` and alpha = beta = 0 (u stops moving).
-__device__ inline void cg_finish_dots(DevScalars* sc, double g, double d, int first) {
-  double alpha = 0.0, beta = 0.0;
+struct CgStep {
+  double alpha, beta, rr;
+  int bad;
+};
+__device__ inline CgStep cg_step(double g, double d, int first, double rr_prev, double alpha_prev) {
+  CgStep st{0.0, 0.0, g, 0};
   if (g > 0.0 && isfinite(g)) {
-    const bool restart = first || !(sc->alpha != 0.0) || !(sc->rr > 0.0);
-    beta = restart ? 0.0 : g / sc->rr;
-    const double den = restart ? d : d - beta * g / sc->alpha;
+    const bool restart = first || !(alpha_prev != 0.0) || !(rr_prev > 0.0);
+    st.beta = restart ? 0.0 : g / rr_prev;
+    const double den = restart ? d : d - st.beta * g / alpha_prev;
     if (den > 0.0 && isfinite(den)) {
-      alpha = g / den;
+      st.alpha = g / den;
     } else {
-      beta = 0.0;
-      sc->bad = 1;
+      st.beta = 0.0;
+      st.bad = 1;
     }
   } else if (!isfinite(g)) {
-    sc->bad = 1;
+    st.bad = 1;
   }
+  return st;
+}
+__device__ inline void cg_finish_dots(DevScalars* sc, double g, double d, int first) {
+  const CgStep st = cg_step(g, d, first, sc->rr, sc->alpha);
+  if (st.bad) sc->bad = 1;
   sc->pq = d;
-  sc->alpha = alpha;
-  sc->beta = beta;
-  sc->rr = g;
+  sc->alpha = st.alpha;
+  sc->beta = st.beta;
+  sc->rr = st.rr;
+}
+// The finisher of CGFinish f run by every wave of a consuming pass (all
+// lanes active; workgroups of 32 lanes or of whole waves); workgroup 0
+// stores the state.
+__device__ inline CgStep cg_finish_deferred(const CGFinish& f) {
+  double s[2];
+  sum_parts_any<2>(f.parts, f.nparts, s);
+  const double rr_prev = f.first ? 0.0 : f.prev->rr;
+  const double alpha_prev = f.first ? 0.0 : f.prev->alpha;
+  const CgStep st = cg_step(s[0], s[1], f.first, rr_prev, alpha_prev);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+    f.next->pq = s[1];
+    f.next->alpha = st.alpha;
+    f.next->beta = st.beta;
+    f.next->rr = st.rr;
+    if (st.bad) *f.bad = 1;
+  }
+  return st;
 }
 
 // CG start: rr = <r0,r0>; rho(x) = <x,Nx> - 2 Re<x,b0> + ||y||_w^2.

@@ -182,10 +182,25 @@ void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, c
 //   p' = r + beta p,  s' = w + beta s,  u' = u + alpha p',  r' = r - alpha s'
 // reading (r, p, s, u, w) and writing (r2, p2, s2, u2); the operator is then
 // applied to r'.  One workgroup per pixel writes, so the sets must differ.
+struct DevScalars;
+// The step sizes of the preceding CG step formed by the pass that consumes
+// them, from that step's block sums, instead of by a kernel of their own:
+// every wave of the consumer adds the sums in the same order and applies
+// the same step rule, so all of them (and the separate finisher) obtain the
+// same values; workgroup 0 stores the new state.  parts == nullptr: alpha
+// and beta are read from CGUpdate::alpha / beta.
+struct CGFinish {
+  const double* parts;     // [nparts][2]: block sums of <r, r> and Re<w, r>
+  int nparts, first;       // first: the step restarts (beta = 0)
+  const DevScalars* prev;  // rr and alpha of the step before (unused when first)
+  DevScalars* next;        // receives alpha, beta, rr, pq of this step
+  int* bad;                // set to 1 on a non-positive or non-finite denominator
+};
 struct CGUpdate {
   const float2 *r, *p, *s, *u, *w;
   float2 *r2, *p2, *s2, *u2;
   const double *alpha, *beta;
+  CGFinish fin;
 };
 struct NormalIn {
   const float2* x;

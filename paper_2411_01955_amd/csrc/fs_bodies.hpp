@@ -5,6 +5,7 @@
 // grid index r mod K; grid index j is frequency j (mod K).
 #pragma once
 
+#include "cg_scalars.hpp"
 #include "common.hpp"
 #include "fft_reg.hpp"
 
@@ -56,8 +57,14 @@ struct ImgIn {
 struct ImgScal {
   float alpha, beta;
 };
+// (called by every thread of the workgroup, outside any branch)
 __device__ __forceinline__ ImgScal img_scal(const ImgIn& in) {
-  return in.cg.r ? ImgScal{(float)*in.cg.alpha, (float)*in.cg.beta} : ImgScal{0.f, 0.f};
+  if (!in.cg.r) return ImgScal{0.f, 0.f};
+  if (in.cg.fin.parts) {
+    const CgStep st = cg_finish_deferred(in.cg.fin);
+    return ImgScal{(float)st.alpha, (float)st.beta};
+  }
+  return ImgScal{(float)*in.cg.alpha, (float)*in.cg.beta};
 }
 // element ix of the image row starting at pixel row0
 __device__ __forceinline__ float2 img_at(const ImgIn& in, long long row0, int ix, ImgScal sc, bool store) {

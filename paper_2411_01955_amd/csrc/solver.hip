@@ -92,12 +92,8 @@ k_cg_init_fin(const double* __restrict__ parts, int nblocks, DevScalars* sc, dou
   if (threadIdx.x == 0) cg_finish_init(sc, s[0], s[1], s[2], rho_out);
 }
 
-// w = c0 r + cg N r, block sums of g = <r,r> and d = Re<w,r>; then
-// k_cg_dots_fin:
-//   first step:  beta = 0, alpha = g / d
-//   later steps: beta = g / rr, alpha = g / (d - beta g / alpha)
-// then rr = g.  A zero residual gives alpha = beta = 0; a non-positive or
-// non-finite denominator sets `bad` and alpha = beta = 0 (u stops moving).
+// w = c0 r + cg N r, block sums of g = <r,r> and d = Re<w,r> (turned into
+// the step sizes by the pass that uses them: cg_finish_deferred)
 __global__ void __launch_bounds__(kRedThreads)
 k_cg_dots(long long N, int G, const float2* __restrict__ r, const float2* __restrict__ part, float c0,
           float cg, float2* __restrict__ w, double* __restrict__ parts) {
@@ -113,19 +109,12 @@ k_cg_dots(long long N, int G, const float2* __restrict__ r, const float2* __rest
   block_parts<2>(acc, parts, blockIdx.x);
 }
 
-// one workgroup: the two sums of k_cg_dots -> alpha, beta, rr
-__global__ void __launch_bounds__(kFinThreads)
-k_cg_dots_fin(const double* __restrict__ parts, int nblocks, int first, DevScalars* sc) {
-  double s[2];
-  sum_parts<2>(parts, nblocks, s);
-  if (threadIdx.x == 0) cg_finish_dots(sc, s[0], s[1], first);
-}
-
-// Last CG step: p = r + beta p, u = u + alpha p (writes u2).
+// Last CG step: p = r + beta p, u = u + alpha p (writes u2), with alpha and
+// beta of the last step formed here from its block sums.
 __global__ void k_cg_final(long long N, const float2* __restrict__ r, const float2* __restrict__ p,
-                           const float2* __restrict__ u, float2* __restrict__ u2,
-                           const DevScalars* __restrict__ sc) {
-  const float a = (float)sc->alpha, b = (float)sc->beta;
+                           const float2* __restrict__ u, float2* __restrict__ u2, CGFinish fin) {
+  const CgStep st = cg_finish_deferred(fin);
+  const float a = (float)st.alpha, b = (float)st.beta;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     const float2 rv = r[i], pv = p[i], uv = u[i];
@@ -261,6 +250,7 @@ struct SolverWs {
   float2 *u[2], *r[2], *p[2], *s[2];   // CG vectors, double-buffered
   double* parts;
   DevScalars* sc;
+  DevScalars* cgs;   // [2] CG step state, alternating between steps
   double* rho;   // [kMaxOuter + 1]
 };
 
@@ -269,7 +259,7 @@ size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
   size_t b = al(op_workspace_bytes(p, L));
   b += 11 * al(sizeof(float2) * N);
   b += al(sizeof(double) * 4 * kRedBlocks);
-  b += al(sizeof(DevScalars));
+  b += al(sizeof(DevScalars) * 3);
   b += al(sizeof(double) * (kMaxOuter + 1));
   return b;
 }
@@ -289,7 +279,8 @@ static SolverWs solver_ws(const pnp_plan* p, int L, void* ws) {
   w.parts = (double*)c;
   c += al(sizeof(double) * 4 * kRedBlocks);
   w.sc = (DevScalars*)c;
-  c += al(sizeof(DevScalars));
+  w.cgs = w.sc + 1;
+  c += al(sizeof(DevScalars) * 3);
   w.rho = (double*)c;
   return w;
 }
@@ -407,23 +398,29 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     started = false;
     if (guard && k == 0) rho_prev = read_scalar(w.rho, s);
     // step 0: w = M r0; steps 1..n_cg-1: update (p, s, u, r) inside the
-    // operator's first pass, w = M r; then the last u update
+    // operator's first pass, w = M r; then the last u update.  The step
+    // sizes of step j are formed by the pass that uses them (the first pass
+    // of step j + 1, or the last update) from step j's block sums; step j's
+    // state goes to cgs[j % 2], the previous step's is read from the other.
+    auto fin_of = [&](int j) {
+      return CGFinish{w.parts, (int)nb, j == 0 ? 1 : 0, w.cgs + ((j + 1) & 1), w.cgs + (j & 1), &w.sc->bad};
+    };
     int c = 0;
     for (int j = 0; j < a.n_cg; ++j) {
       NormalIn in = plain_input(w.r[0]);
       if (j > 0) {
         in.x = nullptr;
         in.cg = CGUpdate{w.r[c], w.p[c], w.s[c], w.u[c], w.w, w.r[1 - c], w.p[1 - c], w.s[1 - c], w.u[1 - c],
-                         &w.sc->alpha, &w.sc->beta};
+                         nullptr, nullptr, fin_of(j - 1)};
         c = 1 - c;
       }
       normal_parts(p, a.toep, in, a.smaps, a.L, a.dcf, w.op, s);
       PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg, w.w,
                  w.parts);
-      PNP_LAUNCH(k_cg_dots_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, j == 0 ? 1 : 0, w.sc);
     }
     float2* u_res = w.u[1 - c];
-    PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res, w.sc);
+    PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res,
+               fin_of(a.n_cg - 1));
     prior_apply(a.prior, p->ndim, nd, u_res, x, a.sigmas[k], s);
     if (!guard) continue;
     // candidate from the fallback, kept in Nv (free during the solve)
