@@ -467,8 +467,9 @@ def main():
     ap.add_argument("--no-pgd", action="store_true", help="skip the PnP-PGD / FISTA-Wavelet measurement")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the slices and coils "
-              "of this workload would shard across GPUs as described in DESIGN.md, but no multi-GPU "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): slices are independent "
+              "and a slice's coils only meet in the image sum, so the workload would shard across GPUs by "
+              "slice or by coil group with one image all-reduce per normal operator, but no multi-GPU "
               "path is built or measured.", file=sys.stderr)
         sys.exit(2)
 
