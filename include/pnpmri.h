@@ -59,7 +59,7 @@ typedef int32_t pnp_status;
 #define PNP_OK                 0
 #define PNP_ERR_ARG           -1   /* NULL pointer or invalid scalar argument  */
 #define PNP_ERR_SHAPE         -2   /* unsupported or inconsistent sizes        */
-#define PNP_ERR_UNSUPPORTED   -3   /* valid request this build cannot serve    */
+#define PNP_ERR_UNSUPPORTED   -3   /* valid request the library does not serve */
 #define PNP_ERR_DEVICE        -4   /* HIP runtime error (text in last_error)   */
 #define PNP_ERR_WORKSPACE     -5   /* workspace smaller than required          */
 #define PNP_ERR_NUMERIC       -6   /* non-finite input or CG/norm breakdown    */
