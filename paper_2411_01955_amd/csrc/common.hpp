@@ -112,6 +112,7 @@ struct pnp_plan {
   float* deapod_yz;         // 3D: [nz][ny] deapodisation of the (z, y) image rows
   int32_t* tile_off;        // [ntiles + 1]
   int32_t* row_start;       // [ntiles][K_last + 1] first entry per first-tap row
+  int32_t* tile_order;      // 2D: [ntiles] tiles by descending entry count (spread dispatch order)
   int32_t* ent_sample;      // [E] sample of each entry, grouped by tile
   int32_t* sample_ent;      // [M][slots] entry indices of a sample (-1: none)
   pnp::EntryRec* rec;       // [E] packed taps and weights, grouped by tile (2D)

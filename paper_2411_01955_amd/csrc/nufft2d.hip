@@ -335,7 +335,8 @@ __global__ void __launch_bounds__(kAdjThreads)
 k_cols_adj_fs(const float2* __restrict__ yent, long long E,
               int nx, int ny, int Kx, const float2* __restrict__ tw, int tile,
               const int* __restrict__ tile_off, const int* __restrict__ row_start,
-              const EntryRec* __restrict__ rec, float2* __restrict__ mid) {
+              const int* __restrict__ tile_order, const EntryRec* __restrict__ rec,
+              float2* __restrict__ mid) {
   using F = FS<K1, K2>;
   constexpr int NRB = F::K / 8;                                  // row blocks per strip
   constexpr int RBW = (NRB + kAdjWaves - 1) / kAdjWaves;         // row blocks per wave
@@ -346,8 +347,8 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   __shared__ int sdense[kMaxDense + 1];                          // count, then row blocks
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;           // FFT threads: t < K1
-  const int s = blockIdx.x;
-  const int l = blockIdx.y;
+  const int s = tile_order[blockIdx.y];    // strips by descending entry count; coils of a strip adjacent
+  const int l = blockIdx.x;
   const int c0 = s * tile;
   const bool colok = c < tile && t < K1;
   const int lane = threadIdx.x & 63;
@@ -683,9 +684,9 @@ struct FSLaunch {
                (long long)p->E, ypart);
   }
   static void cols_adj(const pnp_plan* p, int L, const float2* yent, float2* mid, hipStream_t s) {
-    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(p->ntx, L), dim3(kAdjThreads), 0, s, yent, (long long)p->E,
+    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(L, p->ntx), dim3(kAdjThreads), 0, s, yent, (long long)p->E,
                p->ax[0].n, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off,
-               p->row_start, p->rec, mid);
+               p->row_start, p->tile_order, p->rec, mid);
   }
   static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                        hipStream_t s) {

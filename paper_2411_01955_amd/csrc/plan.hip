@@ -434,6 +434,7 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   p->cell_off = (int32_t*)(base + o_co);
   p->tile_off = nullptr;
   p->row_start = nullptr;
+  p->tile_order = nullptr;
   p->ent_sample = nullptr;
   p->sample_ent = nullptr;
   p->rec = nullptr;
@@ -540,6 +541,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     const size_t o_se = take(sizeof(int) * M * p->slots);
     const size_t o_rec = take(sizeof(EntryRec) * (ndim == 2 ? Emax : 1));
     const size_t o_traj = take(sizeof(float) * M * ndim);
+    const size_t o_ord = take(sizeof(int) * p->ntiles);
     // set-up scratch (freed below)
     size_t soff = 0;
     const size_t s_cnt = soff; soff += align256(sizeof(int) * p->ntiles);
@@ -565,6 +567,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     p->sample_ent = (int32_t*)(base + o_se);
     p->rec = (EntryRec*)(base + o_rec);
     p->traj = (float*)(base + o_traj);
+    p->tile_order = (int32_t*)(base + o_ord);
     PNP_HIP(hipMemcpyAsync(p->traj, traj, sizeof(float) * M * ndim, hipMemcpyDeviceToDevice, stream));
 
     struct Scratch {
@@ -629,6 +632,19 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
         k_build_records<<<gE, 256, 0, stream>>>(p->E, p->ent_sample, p->j0, p->wts, p->rec);
         PNP_CHECK_LAUNCH();
       }
+    }
+    // dispatch order of the 2D spread: the tiles with the most entries (the
+    // k-space centre) first, so their long workgroups start at once
+    {
+      std::vector<int32_t> off(p->ntiles + 1), ord(p->ntiles);
+      PNP_HIP(hipMemcpyAsync(off.data(), p->tile_off, sizeof(int32_t) * (p->ntiles + 1), hipMemcpyDeviceToHost,
+                             stream));
+      PNP_HIP(hipStreamSynchronize(stream));
+      for (int t = 0; t < p->ntiles; ++t) ord[t] = t;
+      std::stable_sort(ord.begin(), ord.end(),
+                       [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+      PNP_HIP(hipMemcpyAsync(p->tile_order, ord.data(), sizeof(int32_t) * p->ntiles, hipMemcpyHostToDevice,
+                             stream));
     }
     PNP_HIP(hipStreamSynchronize(stream));
   } catch (...) {
