@@ -173,6 +173,11 @@ void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, 
                 float2* x, const OpWorkspace& w, hipStream_t s);
 void op_normal(const pnp_plan* p, const float2* x, const float2* smaps, int L, const float* dcf,
                float2* out, const OpWorkspace& w, hipStream_t s);
+// Per-coil adjoint images with unit maps: out[l] = A_1^H D_w y_l for l < L
+// (ones: the unit map [N]); 2D runs the column pass once for all L coils.
+// Workspace: op_workspace(p, L).
+void op_adjoint_coils(const pnp_plan* p, const float2* y, int L, const float* dcf, const float2* ones,
+                      float2* out, const OpWorkspace& w, hipStream_t s);
 
 // Normal operator as used inside the solver: the input is x, or (when r is
 // given) the CG direction p' = r + (*beta) x, which is also stored to pnew;

@@ -870,6 +870,39 @@ void op_adjoint(const pnp_plan* p, const float2* y, const float2* smaps, int L, 
                (long long)N, x);
 }
 
+void op_adjoint_coils(const pnp_plan* p, const float2* y, int L, const float* dcf, const float2* ones,
+                      float2* out, const OpWorkspace& w, hipStream_t s) {
+  const int64_t N = image_size(p);
+  if (p->ndim == 3) {
+    for (int l = 0; l < L; ++l) op3_adjoint(p, y + (long long)l * p->M, ones, 1, dcf, out + l * N, w, s);
+    return;
+  }
+  const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
+  const float scale = (float)(1.0 / std::sqrt((double)N));
+  const long long tot = (long long)L * p->E;
+  if (tot > 0)
+    PNP_LAUNCH(k_entry_values, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+               KIn{y, nullptr, nullptr, (long long)p->M, (long long)p->E}, p->rec, dcf, scale, L, w.yent);
+  const long long mstride = (long long)ny * Kx;               // one coil's half-transformed grid
+  if (fs_ok(p)) {
+    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, s);
+    for (int l = 0; l < L; ++l) PNP_FS_DISPATCH(Kx, rows_adj, p, 1, w.mid + l * mstride, ones, out + l * N, s);
+    return;
+  }
+  check_lds(p);
+  {
+    const size_t lds = cols_lds(p);
+    set_lds_limit((const void*)k_cols_adj_spread, lds);
+    PNP_LAUNCH(k_cols_adj_spread, dim3(p->ntx, L), dim3(kThreads), lds, s, w.yent, (long long)p->E, nx,
+               ny, Kx, p->ax[1].fft, p->tile, col_stride(p->ax[1].K), p->tile_off, p->rec, w.mid);
+  }
+  const size_t lds = rows_lds(Kx);
+  set_lds_limit((const void*)k_rows_adj, lds);
+  for (int l = 0; l < L; ++l)
+    PNP_LAUNCH(k_rows_adj, dim3(ny, 1), dim3(kThreads), lds, s, w.mid + l * mstride, ones, 1, nx, ny,
+               p->ax[0].deapod, p->ax[1].deapod, p->ax[0].fft, out + l * N);
+}
+
 void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps, int L,
                      const float* dcf, const OpWorkspace& w, hipStream_t s) {
   if (p->ndim == 3) return op3_normal_parts(p, in, smaps, L, dcf, w, s);

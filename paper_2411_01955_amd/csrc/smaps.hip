@@ -105,9 +105,12 @@ unsigned vec_blocks(long long N) {
 
 }  // namespace
 
+// coils per adjoint call (2D: the column pass serves them together)
+static int smaps_coil_batch(const pnp_plan* p) { return p->ndim == 2 ? 8 : 1; }
+
 size_t smaps_workspace_bytes(const pnp_plan* p) {
   const int64_t N = image_size(p);
-  size_t b = al(op_workspace_bytes(p, 1));
+  size_t b = al(op_workspace_bytes(p, smaps_coil_batch(p)));
   b += al(sizeof(float2) * N);           // unit map
   b += al(sizeof(float) * p->M);         // window * dcf
   b += al(sizeof(float) * N);            // root sum of squares
@@ -119,8 +122,9 @@ void smaps_estimate(const pnp_plan* p, const float2* y, int L, const float* dcf,
                     float2* out, void* ws, hipStream_t s) {
   const int64_t N = image_size(p);
   char* c = (char*)ws;
-  const OpWorkspace w = op_workspace(p, 1, c);
-  c += al(op_workspace_bytes(p, 1));
+  const int cb = smaps_coil_batch(p);
+  const OpWorkspace w = op_workspace(p, cb, c);
+  c += al(op_workspace_bytes(p, cb));
   float2* ones = (float2*)c;
   c += al(sizeof(float2) * N);
   float* wts = (float*)c;
@@ -133,8 +137,8 @@ void smaps_estimate(const pnp_plan* p, const float2* y, int L, const float* dcf,
   PNP_LAUNCH(k_ones, dim3(nb), dim3(kRedThreads), 0, s, (long long)N, ones);
   PNP_LAUNCH(k_window, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, (long long)p->M, p->ndim, p->traj,
              p->ax[0].n, p->ax[1].n, p->ax[2].n, (float)(0.5 * width), dcf, wts);
-  for (int l = 0; l < L; ++l)
-    op_adjoint(p, y + (long long)l * p->M, ones, 1, wts, out + (long long)l * N, w, s);
+  for (int l = 0; l < L; l += cb)
+    op_adjoint_coils(p, y + (long long)l * p->M, std::min(cb, L - l), wts, ones, out + (long long)l * N, w, s);
   PNP_LAUNCH(k_sos, dim3(nb), dim3(kRedThreads), 0, s, (long long)N, L, out, sos, parts);
   PNP_LAUNCH(k_sos_level, dim3(1), dim3(kRedThreads), 0, s, parts, (int)nb, (float)threshold, level);
   PNP_LAUNCH(k_normalise, dim3(nb), dim3(kRedThreads), 0, s, (long long)N, L, out, sos, level);
