@@ -119,6 +119,31 @@ def test_hqs_tiny_toeplitz_matches_oracle(pnp, precond):
     assert e_rho < 1e-3
 
 
+@pytest.mark.parametrize("toeplitz", [False, True])
+def test_hqs_reports_cg_breakdown(pnp, toeplitz):
+    """A non-finite k-space sample makes the CG inner products non-finite; the
+    step sizes (formed in the pass that uses them on the Toeplitz path) set the
+    breakdown flag and the solve reports PNP_ERR_NUMERIC.  The same data
+    without the bad sample solves normally."""
+    w = synth.config_tiny()
+    x, roi, S, k, dcf, y = _problem(w, 5)
+    Ln, _ = solver.opnorm(lambda v: ndft.normal(v, S, k, dcf), (w.n, w.n), tol=1e-12, maxit=3000)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    tp = pnp.Toeplitz(plan) if toeplitz else None
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, 3)
+    prior = pnp.WaveletPrior(0, 0.5)
+    lam = 3e4 / Ln
+    xg, _ = pnp.hqs_solve(plan, to_dev(y), to_dev(S), None, prior, sig, lam, "f1", 3, opnorm=Ln, report=True,
+                          toeplitz=tp)
+    assert np.all(np.isfinite(to_np(xg)))
+    yb = y.copy()
+    yb[1, 17] = np.nan
+    with pytest.raises(pnp.PnPError) as ei:
+        pnp.hqs_solve(plan, to_dev(yb), to_dev(S), None, prior, sig, lam, "f1", 3, opnorm=Ln, report=True,
+                      toeplitz=tp)
+    assert ei.value.status == -6
+
+
 def test_hqs_clinical_toeplitz_tuned_hyperparameters(pnp):
     """The clinical workload with its tuned hyperparameters (lambda*||N|| = 1e4,
     kappa = 0.75, F-1), Toeplitz normal operator, 3 outer iterations."""
