@@ -84,12 +84,15 @@ inline unsigned blocks_for(long long n, int per = kThreads) { return (unsigned)(
 
 // ------------------------------------------------------------ kernels
 // x0[p] = (bf(Re u), bf(Im u), bf(sigma_b), 0, ..., 0)
+// grid (pixel blocks, image): the image index comes from the grid, not from
+// a division per pixel
 __global__ void k_unet_pack(const float2* __restrict__ u, const float* __restrict__ sig, float sig_c,
-                            long long HW, long long P, uint16_t* __restrict__ x0) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
+                            long long HW, uint16_t* __restrict__ x0) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= HW) return;
+  const long long p = (long long)blockIdx.y * HW + i;
   const float2 v = u[p];
-  const float s = sig ? sig[p / HW] : sig_c;
+  const float s = sig ? sig[blockIdx.y] : sig_c;
   uint4 o;
   o.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
   o.y = (uint32_t)f2bf(s);
@@ -446,6 +449,10 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
                   relu ? 1 : 0, chunks};
   const long long P = (long long)g.B * g.H * g.W;
   const int nsteps = l.taps * (l.cp / 32);     // K steps of the tiled kernels
+  if (l.cp == 8 && l.taps == 9 && l.cout == 32) {  // the first layer (3 channels padded to 8)
+    PNP_LAUNCH(unet::k_conv_first, dim3(blocks_for(P, 128)), dim3(256), 0, s, v);
+    return;
+  }
   // larger tiles where the input channels come in 32-wide chunks and the
   // launch still has a workgroup per compute unit (K chunks in sequence);
   // else 64 x 64 tiles with one wave group per K chunk and a deeper load
@@ -675,8 +682,8 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
   const UWs w = unet_ws(B, H, W, false, ws);
   const Geo g0{B, H, W}, g1{B, H / 2, W / 2}, g2{B, H / 4, W / 4}, g3{B, H / 8, W / 8};
   const long long P0 = (long long)B * H * W;
-  PNP_LAUNCH(k_unet_pack, dim3(blocks_for(P0)), dim3(kThreads), 0, s, u, sigma, sigma_c, (long long)H * W, P0,
-             w.x0);
+  PNP_LAUNCH(k_unet_pack, dim3(blocks_for((long long)H * W), B), dim3(kThreads), 0, s, u, sigma, sigma_c,
+             (long long)H * W, w.x0);
   // encoder
   launch_conv_fwd(net, 0, A(w.x0, 8, 0, 8), A(w.e1a, 32, 0, 32), nullptr, g0, true, s);
   launch_conv_fwd(net, 1, A(w.e1a, 32, 0, 32), A(w.c1, 64, 0, 32), nullptr, g0, true, s);

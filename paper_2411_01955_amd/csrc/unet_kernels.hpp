@@ -427,6 +427,78 @@ __global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
   }
 }
 
+// First convolution of the network (3x3, Cp = 8 input channels -- Re, Im,
+// sigma, zero padding -- and 32 outputs): K = 72 fits one LDS stage as 12
+// tap slots of 8 channels (slots 9..11 zero), consumed in three 32-wide MFMA
+// steps in the order of k_mfma_gemm (k = tap * 8 + channel), so the results
+// are those of the generic kernel.  128 pixels per 256-thread workgroup;
+// thread t stages slots 6 (t & 1) .. + 5 of pixel t / 2 (one coordinate
+// decomposition each); wave w computes rows 32 w .. 32 w + 31, all columns.
+__global__ void __launch_bounds__(256) k_conv_first(ConvFwd v) {
+  constexpr int TM = 128, LDA = 12 * 8 + 8;     // row stride in BF16 elements (padded)
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDA];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[32][LDA];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * TM;
+  const int H = v.g.H, W = v.g.W, P = v.g.P();
+  const uint16_t* const zrow = reinterpret_cast<const uint16_t*>(kZeroRow);
+  {
+    const int r = tid >> 1, j0 = (tid & 1) * 6;
+    const int m = m0 + r;
+    const int px = m % W, py = m < P ? (m / W) % H : -(1 << 20);
+    const long long pa = (long long)m * v.in.cs + v.in.co;
+#pragma unroll
+    for (int jj = 0; jj < 6; ++jj) {
+      const int j = j0 + jj;
+      const int dy = j < 9 ? j / 3 - 1 : 0, dx = j < 9 ? j % 3 - 1 : 0;
+      const int y = py + dy, x = px + dx;
+      const bool ok = j < 9 && (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
+      *reinterpret_cast<uint4*>(&As[r][8 * j]) = ld16g(ok ? v.in.p + pa + (long long)(dy * W + dx) * v.in.cs : zrow);
+    }
+  }
+  {
+    const int n = tid >> 3;
+    for (int j = tid & 7; j < 12; j += 8) {
+      const bool ok = j < 9 && n < v.Cout;
+      *reinterpret_cast<uint4*>(&Bs[n][8 * j]) = ld16g(ok ? v.W + (long long)n * 72 + 8 * j : zrow);
+    }
+  }
+  __syncthreads();
+  const int wm = 32 * wave;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 3; ++ks) {
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + (lane & 15)][32 * ks + 8 * (lane >> 4)]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[16 * j + (lane & 15)][32 * ks + 8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  float e[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) e[j] = v.pre(0, 16 * j + (lane & 15));
+  epilogue_operands_ready();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+        v.store_px(m, m, 16 * j + (lane & 15), acc[i][j][q], e[j]);
+      }
+}
+
 // Convolution, gradient of the input:
 //   dIn[q][c] = sum_{t, o} dZ[q - off(t)][o] W[o][t][c]
 //   m = pixel q, k = t*Coutp + o, n = c; B read from WT[Cin][taps][Coutp].
