@@ -235,6 +235,13 @@ struct ConvFwd {
       out.p[px * out.cs + out.co + n] = f2bf(val);
   }
   __device__ void store(int m, int n, float val, float b) const { store_px(m, m, n, val, b); }
+  // coalesced BF16 epilogue of k_gemm_tiled: value of an element, output pixel
+  __device__ bool vec_store() const { return out_f32 == nullptr; }
+  __device__ float act(float val, float b) const {
+    val += b;
+    return relu ? fmaxf(val, 0.f) : val;
+  }
+  __device__ long long pix(int m) const { return m; }
 };
 
 // Forward convolution (view ConvFwd) and transposed convolution (UpFwd, one
@@ -415,6 +422,37 @@ __global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
 #pragma unroll
   for (int j = 0; j < BJ; ++j) e[j] = v.pre(0, n0 + wn + 16 * j + (lane & 15));
   epilogue_operands_ready();
+  if (v.vec_store()) {
+    // BF16 results of this wave's (16 BI) x 32 block staged in LDS, then
+    // written 8 channels (16 bytes) per lane: whole 16-byte pieces of a
+    // pixel's channel vector instead of 2-byte stores.  The staging area
+    // lies past the wave-group partial sums; each wave uses its own part.
+    constexpr int SROW = 32 + 8;                 // staged row, BF16 elements (80 bytes)
+    constexpr int SOFF = G == 1 ? 0 : (G - 1) * TM * TN * 2;
+    static_assert(SOFF + 4 * 16 * BI * SROW <= G * STAGE, "epilogue staging fits");
+    if constexpr (G == 1) __syncthreads();     // the last K step's operands are consumed
+    uint16_t* st = lds + SOFF + wave * (16 * BI * SROW);
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          st[(16 * i + 4 * (lane >> 4) + q) * SROW + 16 * j + (lane & 15)] = f2bf(v.act(tot[i][j][q], e[j]));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int it = lane; it < 16 * BI * 4; it += 64) {
+      const int r = it >> 2, g8 = it & 3;
+      const int m = m0 + wm + r;
+      if (m < P) {
+        const uint4 val = *reinterpret_cast<const uint4*>(&st[r * SROW + 8 * g8]);
+        *reinterpret_cast<uint4*>(v.out.p + v.pix(m) * v.out.cs + v.out.co + n0 + wn + 8 * g8) = val;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < BI; ++i) {
     const int mr = m0 + wm + 16 * i + 4 * (lane >> 4);
@@ -630,6 +668,9 @@ struct UpFwd {
     out.p[px * out.cs + out.co + n] = f2bf(val + b);
   }
   __device__ void store(int m, int n, float val, float b) const { store_px(m, up_pix(g, m, blockIdx.z), n, val, b); }
+  __device__ bool vec_store() const { return true; }
+  __device__ float act(float val, float b) const { return val + b; }
+  __device__ long long pix(int m) const { return up_pix(g, m, blockIdx.z); }
 };
 
 // Transposed convolution, gradient of the input:
