@@ -533,8 +533,26 @@ void launch_conv_dw(pnp_unet* net, int li, Act dz, Act in, Geo g, hipStream_t s)
 
 void launch_conv_dx(const pnp_unet* net, int li, Act dz, Act dx, Mask mask, Geo g, hipStream_t s) {
   const LayerInfo& l = layer(li);
-  unet::ConvDX v{dz, net->wt + l.wt_off, dx, mask, g, l.taps, l.coutp, l.cin};
   const long long P = (long long)g.B * g.H * g.W;
+  // the tiled kernels where the output-gradient channels come in 32-wide
+  // chunks (every layer but the 2-channel output); the generic kernel else
+  if (l.coutp % 32 == 0 && (l.taps * (l.coutp / 32)) % 3 == 0 && (l.cin == 32 || l.cin % 64 == 0)) {
+    unet::ConvDXT v{dz, net->wt + l.wt_off, dx, mask, g, l.taps, l.coutp, l.cin, 1};
+    if (l.cin == 32 && P / 256 >= 512)
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvDXT, 256, 32, 4, 1, 1, false>), dim3(blocks_for(P, 256), 1, 1),
+                 dim3(256), 0, s, v);
+    else if (l.cin == 32)
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvDXT, 128, 32, 4, 1, 1, false>), dim3(blocks_for(P, 128), 1, 1),
+                 dim3(256), 0, s, v);
+    else if ((P / 128) * (l.cin / 64) >= 256)
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvDXT, 128, 64, 2, 1, 1, false>),
+                 dim3(blocks_for(P, 128), l.cin / 64, 1), dim3(256), 0, s, v);
+    else
+      PNP_LAUNCH((unet::k_gemm_tiled<unet::ConvDXT, 64, 64, 2, 3, 1, false>), dim3(blocks_for(P, 64), l.cin / 64, 1),
+                 dim3(256), 0, s, v);
+    return;
+  }
+  unet::ConvDX v{dz, net->wt + l.wt_off, dx, mask, g, l.taps, l.coutp, l.cin};
   PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvDX>, dim3(blocks_for(P, 64), blocks_for(l.cin, 64), 1), dim3(256), 0,
              s, v);
 }

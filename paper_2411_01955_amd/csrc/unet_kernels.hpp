@@ -192,6 +192,7 @@ struct Mask {
 //   m = pixel, k = t*Cp + c, n = output channel.
 struct ConvFwd {
   static constexpr bool AK = false, BK = false;
+  static constexpr int TAP_SIGN = 1;      // k_gemm_tiled: input pixel = output pixel + tap offset
   Act in;
   const uint16_t* W;      // [Cout][taps][Cp] BF16
   const float* bias;      // [Cout] FP32
@@ -242,6 +243,7 @@ struct ConvFwd {
     return relu ? fmaxf(val, 0.f) : val;
   }
   __device__ long long pix(int m) const { return m; }
+  __device__ uint4 finish8(int, int, uint4 v8) const { return v8; }
 };
 
 // Forward convolution (view ConvFwd) and transposed convolution (UpFwd, one
@@ -313,7 +315,7 @@ __global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
   int ft = sbeg / cpc, fc = (sbeg - ft * cpc) * 32;
   const int lt = (send - 1) / cpc, lc = (send - 1 - lt * cpc) * 32;
   auto fetch = [&](int step, uint4 (&a)[RA], uint4& b) {
-    const int dy = tap_dy(v.taps, ft), dx = tap_dx(v.taps, ft);
+    const int dy = V::TAP_SIGN * tap_dy(v.taps, ft), dx = V::TAP_SIGN * tap_dx(v.taps, ft);
     const long long toff = (long long)(dy * W + dx) * v.in.cs + fc;
 #pragma unroll
     for (int i = 0; i < RA; ++i) {
@@ -418,7 +420,7 @@ __global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
           for (int q = 0; q < 4; ++q)
             tot[i][j][q] += red[((g - 1) * TM + wm + 16 * i + 4 * (lane >> 4) + q) * TN + wn + 16 * j + (lane & 15)];
   }
-  float e[BJ];                                   // the bias of this lane's columns
+  float e[BJ];                                   // the epilogue operand of this lane's columns (bias)
 #pragma unroll
   for (int j = 0; j < BJ; ++j) e[j] = v.pre(0, n0 + wn + 16 * j + (lane & 15));
   epilogue_operands_ready();
@@ -447,7 +449,7 @@ __global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
       const int r = it >> 2, g8 = it & 3;
       const int m = m0 + wm + r;
       if (m < P) {
-        const uint4 val = *reinterpret_cast<const uint4*>(&st[r * SROW + 8 * g8]);
+        const uint4 val = v.finish8(m, n0 + wn + 8 * g8, *reinterpret_cast<const uint4*>(&st[r * SROW + 8 * g8]));
         *reinterpret_cast<uint4*>(v.out.p + v.pix(m) * v.out.cs + v.out.co + n0 + wn + 8 * g8) = val;
       }
     }
@@ -570,6 +572,44 @@ struct ConvDX {
   }
 };
 
+// The input gradient in the form k_gemm_tiled reads: in = dz, W = WT
+// [Cin][taps][Coutp], out = dx, Cp = Coutp, Cout = Cin, taps mirrored.  The
+// producer's ReLU mask is applied to each 16-byte output piece in the
+// coalesced epilogue (a dropped element is BF16 zero, as in ConvDX::store).
+struct ConvDXT {
+  static constexpr int TAP_SIGN = -1;
+  Act in;
+  const uint16_t* W;
+  Act out;
+  Mask mask;
+  Geo g;
+  int taps, Cp, Cout, chunks;
+  __device__ const uint16_t* wrow(int n) const { return W + (long long)n * taps * Cp; }
+  __device__ float pre(int, int) const { return 0.f; }
+  __device__ bool vec_store() const { return true; }
+  __device__ float act(float val, float) const { return val; }
+  __device__ long long pix(int m) const { return m; }
+  // channels n .. n+7 of pixel m (mask.mc is a multiple of 8)
+  __device__ uint4 finish8(int m, int n, uint4 v8) const {
+    if (!mask.p || n >= mask.mc) return v8;
+    const uint4 h = ld16(mask.p + (long long)m * mask.cs + mask.co + n);
+    const uint32_t hw[4] = {h.x, h.y, h.z, h.w};
+    uint32_t vw[4] = {v8.x, v8.y, v8.z, v8.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t lo = bf_pos((uint16_t)(hw[k] & 0xffffu)) ? 0x0000ffffu : 0u;
+      const uint32_t hi = bf_pos((uint16_t)(hw[k] >> 16)) ? 0xffff0000u : 0u;
+      vw[k] &= lo | hi;
+    }
+    return make_uint4(vw[0], vw[1], vw[2], vw[3]);
+  }
+  __device__ void pix4(int m, long long (&o)[4]) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = m + q;
+  }
+  __device__ void store_px(int, long long, int, float, float) const {}   // (vec_store is always true)
+};
+
 // Convolution, gradient of the weights and bias, split over pixels:
 //   dW[o][t][c] += sum_p dZ[p][o] in[p + off(t)][c],   db[o] += sum_p dZ[p][o]
 //   m = o, n = t*Cin + c (n = taps*Cin is the bias column), k = pixel.
@@ -616,6 +656,7 @@ __device__ __forceinline__ long long up_pix(const Geo& g, int m, int t) {
 //   m = input pixel, k = c, n = output channel.
 struct UpFwd {
   static constexpr bool AK = false, BK = false;
+  static constexpr int TAP_SIGN = 1;
   Act in;
   const uint16_t* W;      // [Cout][4][Cin] BF16
   const float* bias;
@@ -671,6 +712,7 @@ struct UpFwd {
   __device__ bool vec_store() const { return true; }
   __device__ float act(float val, float b) const { return val + b; }
   __device__ long long pix(int m) const { return up_pix(g, m, blockIdx.z); }
+  __device__ uint4 finish8(int, int, uint4 v8) const { return v8; }
 };
 
 // Transposed convolution, gradient of the input:
