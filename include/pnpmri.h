@@ -389,22 +389,33 @@ pnp_status pnp_fista_wavelet(const pnp_plan* plan, const pnp_c64* y, const pnp_c
                              size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------ autotuning
- * The register-FFT row passes of a plan handle 2, 4 or 8 coils per
- * workgroup (default 4).  pnp_autotune times the normal operator the caller
- * will run -- Toeplitz when `toeplitz` is given, else the gridded one with
- * `dcf` -- for each choice on this device (after a warm-up, in interleaved
- * rounds), keeps the fastest in the plan (the default 4 unless another is
- * more than 2% faster) and
- * appends it to the JSON-lines file `cache_path` (NULL: no cache), keyed by
- * device, image shape, L, M, a hash of the histogram of gridding entries per
- * column strip, and the operator kind.  A cached key is applied without
- * timing.  Allocates and frees temporary device memory; waits for `stream`.
- * Workspaces sized by the query functions fit every choice. */
+ * The register-FFT row passes of a 2D plan handle 2, 4 or 8 coils per
+ * workgroup, chosen separately for the forward (image -> grid) and the
+ * adjoint (grid -> image) pass; both default to 4.  pnp_autotune times the
+ * normal operator the caller will run -- Toeplitz when `toeplitz` is given,
+ * else the gridded one with `dcf` -- on this device (after a warm-up, in
+ * interleaved rounds): first each adjoint choice with the forward one at 4,
+ * then each forward choice with the adjoint one fixed.  Each keeps the
+ * default 4 unless another choice is more than 2% faster.  The choices are
+ * stored in the plan and appended to the JSON-lines file `cache_path`
+ * (NULL: no cache), keyed by device, image shape, L, M, a hash of the
+ * histogram of gridding entries per column strip, and the operator kind.  A
+ * cached key is applied without timing.  Allocates and frees temporary
+ * device memory; waits for `stream`.  Workspaces sized by the query
+ * functions fit every choice.  2D plans only (PNP_ERR_UNSUPPORTED else).
+ *
+ * pnp_plan_set_row_coils sets both passes to one value;
+ * pnp_plan_get_row_coils returns the adjoint pass's value (which also sets
+ * the number of coil groups of the partial images); the _pair forms set and
+ * get the two separately.  Values other than 2, 4, 8: PNP_ERR_ARG.  Every
+ * choice gives the same results up to floating-point summation order. */
 typedef struct {
   uint32_t struct_size;      /* sizeof(pnp_tuning)                            */
-  int32_t row_coils;         /* out: the chosen coils per workgroup           */
-  double time_us[3];         /* out: operator time for 2, 4, 8 (0 if cached)  */
+  int32_t row_coils;         /* out: chosen coils per workgroup, adjoint pass */
+  double time_us[3];         /* out: operator time, adjoint 2, 4, 8 (0 if cached) */
   int32_t from_cache;        /* out: 1 when the choice came from the cache    */
+  int32_t row_coils_fwd;     /* out: chosen coils per workgroup, forward pass */
+  double time_fwd_us[3];     /* out: operator time, forward 2, 4, 8 (0 if cached) */
 } pnp_tuning;
 
 pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const float* dcf,
@@ -412,6 +423,8 @@ pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const f
                         hipStream_t stream);
 pnp_status pnp_plan_set_row_coils(pnp_plan* plan, int32_t row_coils);
 pnp_status pnp_plan_get_row_coils(const pnp_plan* plan, int32_t* row_coils);
+pnp_status pnp_plan_set_row_coils_pair(pnp_plan* plan, int32_t forward, int32_t adjoint);
+pnp_status pnp_plan_get_row_coils_pair(const pnp_plan* plan, int32_t* forward, int32_t* adjoint);
 
 /* ------------------------------------------------------- batched slices
  * Many independent 2D slices (different sizes, coil counts and trajectories)

@@ -173,7 +173,9 @@ class Plan:
 
     @property
     def row_coils(self):
-        """Coils per workgroup of the register-FFT row passes (2, 4 or 8)."""
+        """Coils per workgroup of the register-FFT adjoint row pass (2, 4 or
+        8; it also sets the coil groups of the partial images).  Assigning
+        sets the forward and the adjoint pass."""
         v = C.c_int32()
         check(load().pnp_plan_get_row_coils(self._h, C.byref(v)))
         return v.value
@@ -182,17 +184,33 @@ class Plan:
     def row_coils(self, value):
         check(load().pnp_plan_set_row_coils(self._h, int(value)))
 
+    @property
+    def row_coils_pair(self):
+        """(forward, adjoint) coils per workgroup of the row passes."""
+        f, a = C.c_int32(), C.c_int32()
+        check(load().pnp_plan_get_row_coils_pair(self._h, C.byref(f), C.byref(a)))
+        return f.value, a.value
+
+    @row_coils_pair.setter
+    def row_coils_pair(self, value):
+        f, a = value
+        check(load().pnp_plan_set_row_coils_pair(self._h, int(f), int(a)))
+
     def autotune(self, smaps, dcf=None, toeplitz=None, cache=None):
         """Time the normal operator for 2, 4 and 8 coils per row-pass
-        workgroup and keep the fastest; `cache`: JSON-lines file (read and
-        appended).  Returns {row_coils, time_us, from_cache}."""
+        workgroup, the adjoint pass first and then the forward one, and keep
+        the fastest of each; `cache`: JSON-lines file (read and appended).
+        Returns {row_coils (adjoint), row_coils_fwd, time_us (adjoint
+        sweep), time_fwd_us (forward sweep), from_cache}."""
         L = self._L(smaps)
         _need_f32(dcf, "dcf", (self.M,))
-        t = Tuning(C.sizeof(Tuning), 0, (C.c_double * 3)(), 0)
+        t = Tuning()
+        t.struct_size = C.sizeof(Tuning)
         check(load().pnp_autotune(self._h, _ptr(smaps), L, _ptr(dcf),
                                   toeplitz.handle if toeplitz is not None else None,
                                   cache.encode() if cache else None, C.byref(t), _stream()))
-        return {"row_coils": t.row_coils, "time_us": list(t.time_us), "from_cache": bool(t.from_cache)}
+        return {"row_coils": t.row_coils, "row_coils_fwd": t.row_coils_fwd, "time_us": list(t.time_us),
+                "time_fwd_us": list(t.time_fwd_us), "from_cache": bool(t.from_cache)}
 
     def opnorm(self, smaps, dcf=None, iters=50, seed=0):
         L = self._L(smaps)

@@ -63,6 +63,8 @@ class Tuning(C.Structure):
         ("row_coils", C.c_int32),
         ("time_us", C.c_double * 3),
         ("from_cache", C.c_int32),
+        ("row_coils_fwd", C.c_int32),
+        ("time_fwd_us", C.c_double * 3),
     ]
 
 
@@ -135,6 +137,8 @@ SIGNATURES = {
     "pnp_autotune": (_i32, [_vp, _vp, _i32, _vp, _vp, C.c_char_p, C.POINTER(Tuning), _vp]),
     "pnp_plan_set_row_coils": (_i32, [_vp, _i32]),
     "pnp_plan_get_row_coils": (_i32, [_vp, C.POINTER(_i32)]),
+    "pnp_plan_set_row_coils_pair": (_i32, [_vp, _i32, _i32]),
+    "pnp_plan_get_row_coils_pair": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
     "pnp_batch_create": (_i32, [C.POINTER(_vp), _i32, C.POINTER(Slice), _vp]),
     "pnp_batch_destroy": (_i32, [_vp]),
     "pnp_batch_normal": (_i32, [_vp, C.POINTER(_vp), C.POINTER(_vp), _vp]),

@@ -657,7 +657,7 @@ pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const f
 pnp_status pnp_plan_set_row_coils(pnp_plan* plan, int32_t row_coils) {
   return guarded([&] {
     need(plan, "plan");
-    plan_set_row_coils(plan, row_coils);
+    plan_set_row_coils(plan, row_coils, row_coils);
   });
 }
 
@@ -666,5 +666,22 @@ pnp_status pnp_plan_get_row_coils(const pnp_plan* plan, int32_t* row_coils) {
     need(plan, "plan");
     need(row_coils, "row_coils");
     *row_coils = plan->row_coils;
+  });
+}
+
+pnp_status pnp_plan_set_row_coils_pair(pnp_plan* plan, int32_t forward, int32_t adjoint) {
+  return guarded([&] {
+    need(plan, "plan");
+    plan_set_row_coils(plan, forward, adjoint);
+  });
+}
+
+pnp_status pnp_plan_get_row_coils_pair(const pnp_plan* plan, int32_t* forward, int32_t* adjoint) {
+  return guarded([&] {
+    need(plan, "plan");
+    need(forward, "forward");
+    need(adjoint, "adjoint");
+    *forward = plan->row_coils_fwd;
+    *adjoint = plan->row_coils;
   });
 }

@@ -99,7 +99,9 @@ struct pnp_plan {
   int W;                    // kernel width (6)
   double beta;              // Kaiser-Bessel shape
   int tile;                 // tile edge (grid columns) along the tiled axes
-  int row_coils;            // coils per workgroup in the register-FFT row passes (2, 4 or 8)
+  int row_coils;            // coils per workgroup in the register-FFT adjoint row pass (2, 4 or 8);
+                            // also the coil-group count of the partial images
+  int row_coils_fwd;        // coils per workgroup in the register-FFT forward row pass (2, 4 or 8)
   int ntx, nty;             // tiles along x and y (nty = 1 in 2D)
   int ntiles;
   int slots;                // max tiles a sample touches (2 in 2D, 4 in 3D)
@@ -313,7 +315,7 @@ pnp_toeplitz* toeplitz3_create(const pnp_plan* p, const float* dcf, hipStream_t 
 // autotuning
 void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const pnp_toeplitz* tp,
               const char* cache_path, pnp_tuning* out, hipStream_t s);
-void plan_set_row_coils(pnp_plan* p, int rc);
+void plan_set_row_coils(pnp_plan* p, int fwd, int adj);
 
 // batched slices
 pnp_batch* batch_create(int B, const pnp_slice* sl, hipStream_t s);

@@ -642,8 +642,12 @@ struct BatchLaunch {
 template <int K1, int K2>
 struct FSLaunch {
   // the plan's coils per workgroup, as instantiated for this grid size
+  // (adjoint and forward row passes)
   static int rc_of(const pnp_plan* p) {
     return p->row_coils == 2 ? 2 : (p->row_coils == 8 ? fit_rc<K1, K2>(8) : 4);
+  }
+  static int rc_fwd_of(const pnp_plan* p) {
+    return p->row_coils_fwd == 2 ? 2 : (p->row_coils_fwd == 8 ? fit_rc<K1, K2>(8) : 4);
   }
   template <int RC>
   static void rows_fwd_rc(const pnp_plan* p, const ImgIn& in, const float2* S, int L, const float* dax,
@@ -659,7 +663,7 @@ struct FSLaunch {
   }
   static void rows_fwd_any(const pnp_plan* p, const ImgIn& in, const float2* S, int L, const float* dax,
                            const float* day, float2* mid, hipStream_t s) {
-    switch (rc_of(p)) {
+    switch (rc_fwd_of(p)) {
       case 2: rows_fwd_rc<2>(p, in, S, L, dax, day, mid, s); break;
       case 8: rows_fwd_rc<fit_rc<K1, K2>(8)>(p, in, S, L, dax, day, mid, s); break;
       default: rows_fwd_rc<4>(p, in, S, L, dax, day, mid, s); break;

@@ -377,6 +377,7 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   const int64_t M = p->M;
   p->tile = 8;                  // strip width of the column passes
   p->row_coils = 4;
+  p->row_coils_fwd = 4;
   p->ntx = p->ax[0].K / 8;
   p->nty = 1;
   p->ntiles = 0;
@@ -492,6 +493,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     }
     p->tile = choose_tile(p->ax[0].K);
     p->row_coils = 4;
+    p->row_coils_fwd = 4;
     if (ndim == 3 && choose_tile(p->ax[1].K) != p->tile)
       fail(PNP_ERR_SHAPE, "3D x and y grids need a common tile size");
     if (p->tile == 0) fail(PNP_ERR_SHAPE, "no tile size divides grid size %d", p->ax[0].K);

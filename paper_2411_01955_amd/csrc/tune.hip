@@ -1,14 +1,18 @@
 // Autotuner for a plan's launch shape, with a JSON-lines cache.
 //
-// The tuned parameter is the number of coils a workgroup of the
-// register-FFT row passes handles (2, 4 or 8): it sets the workgroup count,
-// the threads and LDS per workgroup, and how often an image row and its
-// coil maps are read, and the best value depends on the grid size, the coil
-// count and the device.  Each candidate is timed on the normal operator the
-// caller will run (Toeplitz when a handle is given, else gridded), with HIP
-// events over repeated launches after a warm-up, in interleaved rounds (the
-// best round of each candidate counts); the default of 4 is kept unless
-// another choice is more than 2% faster.  Results are cached by (image
+// The tuned parameters are the numbers of coils a workgroup of the
+// register-FFT row passes handles (2, 4 or 8), one for the adjoint pass and
+// one for the forward pass: each sets that pass's workgroup count, the
+// threads and LDS per workgroup, and how often an image row and its coil
+// maps are read, and the best values depend on the grid size, the coil
+// count and the device.  The two passes are separate launches, so they are
+// tuned one after the other: first the adjoint choice with the forward pass
+// at the default, then the forward choice with the adjoint one fixed.  Each
+// candidate is timed on the normal operator the caller will run (Toeplitz
+// when a handle is given, else gridded), with HIP events over repeated
+// launches after a warm-up, in interleaved rounds (the best round of each
+// candidate counts); the default of 4 is kept unless another choice is more
+// than 2% faster.  Results are cached by (image
 // shape, coils, samples, a hash of the histogram of gridding entries per
 // column strip, operator kind, device).
 #include <hip/hip_runtime.h>
@@ -53,29 +57,42 @@ std::string tune_key(const pnp_plan* p, int L, bool toeplitz, hipStream_t s) {
   return buf;
 }
 
-// the cached row_coils of `key` (0 when absent)
-int cache_lookup(const char* path, const std::string& key) {
-  if (!path) return 0;
+bool valid_rc(int rc) { return rc == 2 || rc == 4 || rc == 8; }
+
+// the integer after `"name": ` in `line` (0 when absent)
+int field(const std::string& line, const char* name) {
+  const std::string tag = std::string("\"") + name + "\": ";
+  const size_t at = line.find(tag);
+  return at == std::string::npos ? 0 : std::atoi(line.c_str() + at + tag.size());
+}
+
+// the cached (adjoint, forward) choice of `key`; false when absent (lines
+// without both fields are ignored; the last matching line wins)
+bool cache_lookup(const char* path, const std::string& key, int* adj, int* fwd) {
+  if (!path) return false;
   std::ifstream f(path);
   std::string line;
   const std::string want = "\"key\": \"" + key + "\"";
-  int found = 0;
+  bool found = false;
   while (std::getline(f, line)) {
     if (line.find(want) == std::string::npos) continue;
-    const size_t at = line.find("\"row_coils\": ");
-    if (at == std::string::npos) continue;
-    const int rc = std::atoi(line.c_str() + at + 13);
-    if (rc == 2 || rc == 4 || rc == 8) found = rc;   // the last entry wins
+    const int a = field(line, "row_coils"), b = field(line, "row_coils_fwd");
+    if (valid_rc(a) && valid_rc(b)) {
+      *adj = a;
+      *fwd = b;
+      found = true;
+    }
   }
   return found;
 }
 
-void cache_append(const char* path, const std::string& key, int rc, const double* us) {
+void cache_append(const char* path, const std::string& key, const pnp_tuning& t) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
   if (!f) fail(PNP_ERR_ARG, "cannot write the tuning cache %s", path);
-  f << "{\"key\": \"" << key << "\", \"row_coils\": " << rc << ", \"us\": [" << us[0] << ", " << us[1] << ", "
-    << us[2] << "]}\n";
+  f << "{\"key\": \"" << key << "\", \"row_coils\": " << t.row_coils << ", \"row_coils_fwd\": " << t.row_coils_fwd
+    << ", \"us\": [" << t.time_us[0] << ", " << t.time_us[1] << ", " << t.time_us[2] << "], \"us_fwd\": ["
+    << t.time_fwd_us[0] << ", " << t.time_fwd_us[1] << ", " << t.time_fwd_us[2] << "]}\n";
 }
 
 }  // namespace
@@ -87,18 +104,23 @@ void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const p
   if (p->ndim != 2) fail(PNP_ERR_UNSUPPORTED, "autotuning covers 2D plans");
   const std::string key = tune_key(p, L, tp != nullptr, s);
   out->row_coils = 0;
+  out->row_coils_fwd = 0;
   for (double& t : out->time_us) t = 0.0;
+  for (double& t : out->time_fwd_us) t = 0.0;
   out->from_cache = 0;
-  if (const int rc = cache_lookup(cache_path, key)) {
-    p->row_coils = rc;
-    out->row_coils = rc;
+  int c_adj = 0, c_fwd = 0;
+  if (cache_lookup(cache_path, key, &c_adj, &c_fwd)) {
+    p->row_coils = c_adj;
+    p->row_coils_fwd = c_fwd;
+    out->row_coils = c_adj;
+    out->row_coils_fwd = c_fwd;
     out->from_cache = 1;
     return;
   }
   const long long N = image_size(p);
   void *x = nullptr, *o = nullptr, *ws = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
-  const int keep = p->row_coils;
+  const int keep = p->row_coils, keep_fwd = p->row_coils_fwd;
   auto release = [&] {
     if (x) (void)hipFree(x);
     if (o) (void)hipFree(o);
@@ -121,47 +143,56 @@ void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const p
       else
         op_normal(p, (const float2*)x, smaps, L, dcf, (float2*)o, w, s);
     };
-    // warm-up (clocks, caches), then interleaved rounds: each candidate's
-    // best round counts, and the default (4) is kept unless another choice
-    // is more than 2% faster
+    // one sweep: `slot` takes each candidate in interleaved rounds (each
+    // candidate's best round counts); returns the default (4) unless
+    // another choice is more than 2% faster
+    auto sweep = [&](int* slot, double* us) {
+      const int reps = 20, rounds = 3;
+      for (int c = 0; c < 3; ++c) us[c] = 1e30;
+      for (int round = 0; round < rounds; ++round) {
+        for (int c = 0; c < 3; ++c) {
+          *slot = kCandidates[c];
+          for (int r = 0; r < 3; ++r) run();
+          PNP_HIP(hipEventRecord(a, s));
+          for (int r = 0; r < reps; ++r) run();
+          PNP_HIP(hipEventRecord(b, s));
+          PNP_HIP(hipEventSynchronize(b));
+          float ms = 0.f;
+          PNP_HIP(hipEventElapsedTime(&ms, a, b));
+          us[c] = std::min(us[c], 1e3 * ms / reps);
+        }
+      }
+      int best_rc = 4;
+      double best = us[1];
+      for (int c = 0; c < 3; ++c)
+        if (us[c] < 0.98 * best) {
+          best = us[c];
+          best_rc = kCandidates[c];
+        }
+      *slot = best_rc;
+      return best_rc;
+    };
+    // warm-up (clocks, caches), then the adjoint pass's choice with the
+    // forward pass at the default, then the forward pass's choice
     p->row_coils = 4;
+    p->row_coils_fwd = 4;
     for (int r = 0; r < 50; ++r) run();
-    const int reps = 20, rounds = 3;
-    for (int c = 0; c < 3; ++c) out->time_us[c] = 1e30;
-    for (int round = 0; round < rounds; ++round) {
-      for (int c = 0; c < 3; ++c) {
-        p->row_coils = kCandidates[c];
-        for (int r = 0; r < 3; ++r) run();
-        PNP_HIP(hipEventRecord(a, s));
-        for (int r = 0; r < reps; ++r) run();
-        PNP_HIP(hipEventRecord(b, s));
-        PNP_HIP(hipEventSynchronize(b));
-        float ms = 0.f;
-        PNP_HIP(hipEventElapsedTime(&ms, a, b));
-        out->time_us[c] = std::min(out->time_us[c], 1e3 * ms / reps);
-      }
-    }
-    int best_rc = 4;
-    double best = out->time_us[1];
-    for (int c = 0; c < 3; ++c)
-      if (out->time_us[c] < 0.98 * best) {
-        best = out->time_us[c];
-        best_rc = kCandidates[c];
-      }
-    p->row_coils = best_rc;
-    out->row_coils = best_rc;
+    out->row_coils = sweep(&p->row_coils, out->time_us);
+    out->row_coils_fwd = sweep(&p->row_coils_fwd, out->time_fwd_us);
     release();
   } catch (...) {
     p->row_coils = keep;
+    p->row_coils_fwd = keep_fwd;
     release();
     throw;
   }
-  cache_append(cache_path, key, out->row_coils, out->time_us);
+  cache_append(cache_path, key, *out);
 }
 
-void plan_set_row_coils(pnp_plan* p, int rc) {
-  if (rc != 2 && rc != 4 && rc != 8) fail(PNP_ERR_ARG, "row_coils must be 2, 4 or 8");
-  p->row_coils = rc;
+void plan_set_row_coils(pnp_plan* p, int fwd, int adj) {
+  if (!valid_rc(fwd) || !valid_rc(adj)) fail(PNP_ERR_ARG, "row_coils must be 2, 4 or 8");
+  p->row_coils = adj;
+  p->row_coils_fwd = fwd;
 }
 
 }  // namespace pnp

@@ -1,6 +1,7 @@
 """Autotuned launch shape: the operators agree with the oracle for every
-coils-per-workgroup choice (2, 4, 8), and the tuner picks one, records it in
-its JSON-lines cache and reapplies it from there without timing."""
+coils-per-workgroup choice (2, 4, 8) of the forward and the adjoint row
+pass, alike and mixed, and the tuner picks a pair, records it in its
+JSON-lines cache and reapplies it from there without timing."""
 import json
 
 import numpy as np
@@ -23,7 +24,7 @@ def pnp():
     return pnp
 
 
-@pytest.mark.parametrize("rc", [2, 4, 8])
+@pytest.mark.parametrize("rc", [2, 4, 8, (8, 2), (2, 8), (4, 8)])
 def test_operators_match_oracle_for_every_row_coils(pnp, rc):
     w = synth.config_tiny()
     x, _ = synth.phantom2d(w.n, 5)
@@ -31,8 +32,12 @@ def test_operators_match_oracle_for_every_row_coils(pnp, rc):
     k = w.traj.k
     dcf = np.random.default_rng(7).uniform(0.5, 1.5, k.shape[0]).astype(np.float32)
     plan = pnp.Plan(to_dev(k), (w.n, w.n))
-    plan.row_coils = rc
-    assert plan.row_coils == rc
+    if isinstance(rc, tuple):
+        plan.row_coils_pair = rc
+        assert plan.row_coils_pair == rc and plan.row_coils == rc[1]
+    else:
+        plan.row_coils = rc
+        assert plan.row_coils == rc and plan.row_coils_pair == (rc, rc)
     xd, Sd, dd = to_dev(x), to_dev(S), to_dev(dcf)
     ref = ndft.normal(x, S, k, dcf)
     e_g = rel_l2(to_np(plan.normal(xd, Sd, dd)), ref)
@@ -52,18 +57,20 @@ def test_autotune_and_cache(pnp, tmp_path):
     tp = pnp.Toeplitz(plan, dcf)
     r1 = plan.autotune(S, dcf, toeplitz=tp, cache=cache)
     say(f"[tune] clinical Toeplitz: {r1}")
-    assert r1["row_coils"] in (2, 4, 8) and not r1["from_cache"]
-    assert all(t > 0 for t in r1["time_us"])
-    assert plan.row_coils == r1["row_coils"]
+    pair = (r1["row_coils_fwd"], r1["row_coils"])
+    assert set(pair) <= {2, 4, 8} and not r1["from_cache"]
+    assert all(t > 0 for t in r1["time_us"] + r1["time_fwd_us"])
+    assert plan.row_coils_pair == pair
     t = dict(zip((2, 4, 8), r1["time_us"]))
-    assert t[r1["row_coils"]] <= t[4]                 # never slower than the default
+    tf = dict(zip((2, 4, 8), r1["time_fwd_us"]))
+    assert t[pair[1]] <= t[4] and tf[pair[0]] <= tf[4]   # never slower than the default
     lines = [json.loads(l) for l in open(cache)]
-    assert len(lines) == 1 and lines[0]["row_coils"] == r1["row_coils"]
+    assert len(lines) == 1 and (lines[0]["row_coils_fwd"], lines[0]["row_coils"]) == pair
     # a second plan on the same trajectory takes the cached choice
     plan2 = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
-    plan2.row_coils = 2 if r1["row_coils"] != 2 else 8
+    plan2.row_coils_pair = tuple(2 if v != 2 else 8 for v in pair)
     r2 = plan2.autotune(S, dcf, toeplitz=pnp.Toeplitz(plan2, dcf), cache=cache)
-    assert r2["from_cache"] and r2["row_coils"] == r1["row_coils"] == plan2.row_coils
+    assert r2["from_cache"] and (r2["row_coils_fwd"], r2["row_coils"]) == pair == plan2.row_coils_pair
     # the gridded operator is a different key
     r3 = plan2.autotune(S, dcf, cache=cache)
     assert not r3["from_cache"]
@@ -89,3 +96,15 @@ def test_tuned_plan_gives_the_same_hqs(pnp):
     e = max(rel_l2(outs[2], outs[4]), rel_l2(outs[8], outs[4]))
     say(f"[tune] HQS with 2/4/8 coils per workgroup: max rel difference {e:.2e}")
     assert e < 1e-5
+
+
+def test_row_coils_rejects_other_values(pnp):
+    w = synth.config_tiny()
+    plan = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    with pytest.raises(pnp.PnPError):
+        plan.row_coils = 3
+    with pytest.raises(pnp.PnPError):
+        plan.row_coils_pair = (4, 6)
+    with pytest.raises(pnp.PnPError):
+        plan.row_coils_pair = (16, 4)
+    assert plan.row_coils_pair == (4, 4)
