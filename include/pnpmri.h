@@ -292,8 +292,12 @@ pnp_status pnp_unet_tensor(int32_t B, int32_t H, int32_t W, int32_t train, void*
  * (2D [ny][nx]; 3D [nz][ny][nx] is denoised slice by slice).  With a
  * `fallback` (a wavelet prior), pnp_hqs_solve replaces the UNet output by
  * the fallback's whenever it is not finite or its data-consistency residual
- * rho_k exceeds (1 + opts.rise_tol) rho_{k-1}.  Allocates its forward
- * workspace; keeps pointers to `net` and `fallback` (destroy them last). */
+ * rho_k exceeds (1 + opts.rise_tol) rho_{k-1}.  The check reads rho_k on
+ * the host from a small pinned buffer (one per host thread, allocated on
+ * first use and kept) while the next iteration's CG already runs; a
+ * rejection discards that CG and starts it again from the fallback image.
+ * Allocates its forward workspace; keeps pointers to `net` and `fallback`
+ * (destroy them last). */
 pnp_status pnp_prior_unet(pnp_prior** out, const pnp_unet* net, int32_t ndim, const int32_t* shape, double kappa,
                           const pnp_prior* fallback);
 

@@ -143,6 +143,7 @@ struct DevScalars {
   double inv;       // power iteration: 1/||w||
   int bad;          // set when a CG denominator is not positive / finite
   unsigned cnt;     // last-block ticket (reset by the last block)
+  int bad_saved;    // `bad` as of the last CG start (restored when a queued CG is discarded)
 };
 
 // Chronopoulos-Gear step sizes from g = <r,r> and d = Re<M r, r>:

@@ -51,6 +51,7 @@ __global__ void k_init_scalars(DevScalars* sc) {
     sc->rr = sc->pq = sc->alpha = sc->beta = sc->yw2 = sc->lam = sc->inv = 0.0;
     sc->bad = 0;
     sc->cnt = 0u;
+    sc->bad_saved = 0;
   }
 }
 
@@ -84,12 +85,20 @@ k_cg_init(long long N, int G, const float2* __restrict__ x, const float2* __rest
   block_parts<3>(acc, parts, blockIdx.x);
 }
 
-// one workgroup: the three sums of k_cg_init -> rr and rho
+// one workgroup: the three sums of k_cg_init -> rr and rho.  The breakdown
+// flag is saved (restore == 0) or put back to the saved value (restore != 0:
+// a CG queued after the previous start is being discarded).
 __global__ void __launch_bounds__(kFinThreads)
-k_cg_init_fin(const double* __restrict__ parts, int nblocks, DevScalars* sc, double* rho_out) {
+k_cg_init_fin(const double* __restrict__ parts, int nblocks, DevScalars* sc, double* rho_out, int restore) {
   double s[3];
   sum_parts<3>(parts, nblocks, s);
-  if (threadIdx.x == 0) cg_finish_init(sc, s[0], s[1], s[2], rho_out);
+  if (threadIdx.x == 0) {
+    if (restore)
+      sc->bad = sc->bad_saved;
+    else
+      sc->bad_saved = sc->bad;
+    cg_finish_init(sc, s[0], s[1], s[2], rho_out);
+  }
 }
 
 // w = c0 r + cg N r, block sums of g = <r,r> and d = Re<w,r> (turned into
@@ -340,12 +349,24 @@ void prior_apply(const pnp_prior* prior, int ndim, const int* n, const float2* u
   wavelet_apply(ndim, n, J, (float)(prior->kappa * sigma), u, x, s);
 }
 
-static double read_scalar(const double* d, hipStream_t s) {
-  double h = 0.0;
-  PNP_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s));
-  PNP_HIP(hipStreamSynchronize(s));
-  return h;
+// Pinned host copies of the residuals read by the prior check: one buffer
+// per host thread, allocated on first use and kept for the thread's
+// lifetime (a solve reads its values before it returns).
+static double* pinned_residuals() {
+  static thread_local double* buf = nullptr;
+  if (!buf) PNP_HIP(hipHostMalloc((void**)&buf, sizeof(double) * (kMaxOuter + 1), hipHostMallocDefault));
+  return buf;
 }
+
+struct EventHandle {
+  hipEvent_t e = nullptr;
+  EventHandle() = default;
+  EventHandle(const EventHandle&) = delete;
+  EventHandle& operator=(const EventHandle&) = delete;
+  ~EventHandle() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
 
 void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, double* rho_host,
                int* bad_host, int* fb_host) {
@@ -375,28 +396,37 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   const int nd[3] = {p->ax[0].n, p->ax[1].n, p->ax[2].n};
   // A prior with a fallback is checked after every outer iteration: when the
   // new image is not finite or its residual rho_k exceeds (1 + rise_tol)
-  // rho_{k-1}, it is replaced by the fallback prior's output.  This needs
-  // one host read of rho per outer iteration; the normal operator of the
-  // accepted image is reused by the next iteration's CG start.
+  // rho_{k-1}, it is replaced by the fallback prior's output.  The host
+  // reads rho from pinned memory while the GPU already runs the next
+  // iteration's CG, queued on the guess that the image is kept (that CG
+  // writes only its own vectors, so a rejection discards it and starts the
+  // CG again from the fallback image).  The normal operator of the accepted
+  // image is reused by the next iteration's CG start.
   const bool guard = a.prior->fallback != nullptr;
   bool started = false;   // N x and the CG start of iteration k already done
   double rho_prev = 0.0;
   if (fb_host)
     for (int k = 0; k < a.n_out; ++k) fb_host[k] = 0;
+  double* rho_pin = guard ? pinned_residuals() : nullptr;
+  EventHandle ev;
+  if (guard) PNP_HIP(hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
+  // rho_i to the pinned copy, then the event the host waits on
+  auto post_rho = [&](int i) {
+    PNP_HIP(hipMemcpyAsync(rho_pin + i, w.rho + i, sizeof(double), hipMemcpyDeviceToHost, s));
+    PNP_HIP(hipEventRecord(ev.e, s));
+  };
   // N x, then the CG start in set 0: u = x, r = gamma (b0 - N x), p = s = 0
-  auto cg_start = [&](double gamma, double* rho_out) {
+  auto cg_start = [&](double gamma, double* rho_out, int restore_bad) {
     normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u[0],
                w.r[0], w.p[0], w.s[0], w.parts);
-    PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, w.sc, rho_out);
+    PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, w.sc, rho_out, restore_bad);
   };
-
-  for (int k = 0; k < a.n_out; ++k) {
+  // the n_cg CG steps of outer iteration k from the CG start in set 0;
+  // returns the buffer that holds u
+  auto cg_solve = [&](int k) -> float2* {
     const double gamma = a.lambda * a.sigmas[k];
     const float cg = (float)(gamma - c1a);
-    if (!started) cg_start(gamma, w.rho + k);
-    started = false;
-    if (guard && k == 0) rho_prev = read_scalar(w.rho, s);
     // step 0: w = M r0; steps 1..n_cg-1: update (p, s, u, r) inside the
     // operator's first pass, w = M r; then the last u update.  The step
     // sizes of step j are formed by the pass that uses them (the first pass
@@ -421,25 +451,43 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     float2* u_res = w.u[1 - c];
     PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res,
                fin_of(a.n_cg - 1));
+    return u_res;
+  };
+
+  float2* u_next = nullptr;   // iteration k's CG, queued by iteration k - 1's check
+  for (int k = 0; k < a.n_out; ++k) {
+    if (!started) cg_start(a.lambda * a.sigmas[k], w.rho + k, 0);
+    started = false;
+    if (guard && k == 0) post_rho(0);
+    float2* u_res = u_next ? u_next : cg_solve(k);
+    u_next = nullptr;
     prior_apply(a.prior, p->ndim, nd, u_res, x, a.sigmas[k], s);
     if (!guard) continue;
     // candidate from the fallback, kept in Nv (free during the solve)
     prior_apply(a.prior->fallback, p->ndim, nd, u_res, w.Nv, a.sigmas[k], s);
     const double gnext = k + 1 < a.n_out ? a.lambda * a.sigmas[k + 1] : 0.0;
-    cg_start(gnext, w.rho + k + 1);
-    double rho = read_scalar(w.rho + k + 1, s);
+    cg_start(gnext, w.rho + k + 1, 0);
+    post_rho(k + 1);
+    if (k + 1 < a.n_out) u_next = cg_solve(k + 1);
+    PNP_HIP(hipEventSynchronize(ev.e));   // rho_0 .. rho_{k+1} are in the pinned copy
+    if (k == 0) rho_prev = rho_pin[0];
+    double rho = rho_pin[k + 1];
     if (!(rho <= (1.0 + a.rise_tol) * rho_prev)) {
       PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, x);
-      cg_start(gnext, w.rho + k + 1);
-      rho = read_scalar(w.rho + k + 1, s);
+      cg_start(gnext, w.rho + k + 1, 1);
+      post_rho(k + 1);
+      if (k + 1 < a.n_out) u_next = cg_solve(k + 1);
+      PNP_HIP(hipEventSynchronize(ev.e));
+      rho = rho_pin[k + 1];
       if (fb_host) fb_host[k] = 1;
     }
     rho_prev = rho;
     started = true;
   }
   if (rho_host) {
-    // residual of the final image (one extra normal operator)
-    cg_start(0.0, w.rho + a.n_out);
+    // residual of the final image (one extra normal operator, unless the
+    // check of the last iteration has formed it already)
+    if (!started) cg_start(0.0, w.rho + a.n_out, 0);
     std::vector<double> r(a.n_out + 1);
     DevScalars h;
     PNP_HIP(hipMemcpyAsync(r.data(), w.rho, sizeof(double) * (a.n_out + 1), hipMemcpyDeviceToHost, s));

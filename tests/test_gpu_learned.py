@@ -164,6 +164,33 @@ def test_fallback_replaces_a_broken_network(pnp):
     assert np.isfinite(to_np(xg)).all()
 
 
+def test_fallback_after_a_network_that_outputs_nan(pnp):
+    """A network whose output is NaN everywhere: every check rejects it.  The
+    next iteration's CG, queued before the check and run on the NaN image,
+    is discarded together with its breakdown flag, so the solve reports no
+    breakdown and equals wavelet-HQS."""
+    w = synth.config_tiny()
+    x, roi, S, k, dcf, y = _problem(w, 43)
+    shapes = {l["name"]: ((l["cout"], l["taps"], l["cin"]), (l["cout"],)) for l in pnp.unet_layers()}
+    params = synth.he_normal(shapes, 6)
+    Wo, bo = params["out"]
+    params["out"] = (Wo, np.full_like(bo, np.nan))
+    nan_net = pnp.UNet(params)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    Sd, yd = to_dev(S), to_dev(y)
+    nrm = plan.opnorm(Sd, None, iters=200, seed=2)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)
+    wav = pnp.WaveletPrior(0, KAPPA_W)
+    guarded = pnp.UNetPrior(nan_net, (w.n, w.n), KAPPA_U, fallback=wav)
+    xg, rep = pnp.hqs_solve(plan, yd, Sd, None, guarded, sig, LAM_L / nrm, "f1", w.n_cg, opnorm=nrm,
+                            report=True, rise_tol=0.5)
+    xw, rep_w = pnp.hqs_solve(plan, yd, Sd, None, wav, sig, LAM_L / nrm, "f1", w.n_cg, opnorm=nrm, report=True)
+    say(f"[fallback] NaN net: fallback taken {sum(rep['fallback'])}/{len(sig)}")
+    assert all(rep["fallback"])
+    assert rel_l2(to_np(xg), to_np(xw)) < 1e-6
+    assert np.allclose(rep["rho"], rep_w["rho"], rtol=1e-6)
+
+
 def test_fallback_keeps_a_good_network(pnp, net):
     w = synth.config_clinical()
     x, roi, S, k, dcf, y = _problem(w, 42)
