@@ -33,7 +33,8 @@
  *   - Every compute call is asynchronous on the given HIP stream and enqueues
  *     nothing when it returns an error.  Calls that return host scalars
  *     (pnp_opnorm, pnp_hqs_solve with a report or a computed norm) wait for
- *     the stream before returning.
+ *     the stream before returning; pnp_hqs_solve with a prior that has a
+ *     fallback also waits inside its loop (see pnp_prior_unet).
  *   - Workspace: the caller passes device scratch memory of at least the
  *     size the matching *_workspace_bytes query reports (256-byte aligned).
  *   - Errors: every call returns a pnp_status; pnp_last_error() gives a
@@ -335,7 +336,9 @@ pnp_status pnp_hqs_workspace_bytes(const pnp_plan* plan, int32_t L, size_t* byte
  *       x = D_{sigma[k]}(u)
  * with P = c0 - c1 alpha A^H D_w A (Id: 1,0; F-1: 2,1; Chebyshev: 4,10/3),
  * alpha = 1/opnorm.  CG inner products, step sizes and residual norms are
- * FP64 and stay on the device (no host synchronisation inside the loop).
+ * FP64 and stay on the device (no host synchronisation inside the loop,
+ * except the residual check of a prior with a fallback: the host waits for
+ * each rho_k while the next iteration's CG already runs).
  *   y       device pnp_c64 [L][M];  smaps device [L][N];  dcf device [M]|NULL
  *   sigmas  host double [n_out] (positive)
  *   x_out   device pnp_c64 [N]: x_{n_out}
