@@ -415,12 +415,16 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     PNP_HIP(hipMemcpyAsync(rho_pin + i, w.rho + i, sizeof(double), hipMemcpyDeviceToHost, s));
     PNP_HIP(hipEventRecord(ev.e, s));
   };
-  // N x, then the CG start in set 0: u = x, r = gamma (b0 - N x), p = s = 0
+  // N x, then the CG start in set 0: u = x, r = gamma (b0 - N x), p = s = 0.
+  // Its sums only form rho_k (the CG steps keep their own state), so their
+  // finisher runs only when rho is read: by the check or the report.
+  const bool want_rho = guard || rho_host != nullptr;
   auto cg_start = [&](double gamma, double* rho_out, int restore_bad) {
     normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u[0],
                w.r[0], w.p[0], w.s[0], w.parts);
-    PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, w.sc, rho_out, restore_bad);
+    if (want_rho)
+      PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, w.sc, rho_out, restore_bad);
   };
   // the n_cg CG steps of outer iteration k from the CG start in set 0;
   // returns the buffer that holds u
