@@ -263,6 +263,10 @@ int64_t image_size(const pnp_plan* p);
 // Haar prior
 void wavelet_apply(int ndim, const int* n_xyz, int levels, float tau, const float2* in, float2* out,
                    hipStream_t s);
+// The same prior applied to the last CG update u + alpha (r + beta p), with
+// alpha and beta formed from the step's block sums (fin)
+void wavelet_apply_cg(int ndim, const int* n_xyz, int levels, float tau, const float2* r, const float2* p,
+                      const float2* u, const CGFinish& fin, float2* out, hipStream_t s);
 int wavelet_default_levels(int nmin);
 // Batched 2D Haar prior over slices (device table, ordered by block0; the
 // slices' blocks 0 .. nx*ny/4^J - 1 are numbered from block0 on).

@@ -349,6 +349,15 @@ void prior_apply(const pnp_prior* prior, int ndim, const int* n, const float2* u
   wavelet_apply(ndim, n, J, (float)(prior->kappa * sigma), u, x, s);
 }
 
+// The wavelet prior applied to the last CG update u + alpha (r + beta p)
+static void prior_apply_cg(const pnp_prior* prior, int ndim, const int* n, const float2* r, const float2* pv,
+                           const float2* u, const CGFinish& fin, float2* x, double sigma, hipStream_t s) {
+  int nmin = n[0];
+  for (int a = 1; a < ndim; ++a) nmin = std::min(nmin, n[a]);
+  const int J = prior->levels > 0 ? prior->levels : wavelet_default_levels(nmin);
+  wavelet_apply_cg(ndim, n, J, (float)(prior->kappa * sigma), r, pv, u, fin, x, s);
+}
+
 // Pinned host copies of the residuals read by the prior check: one buffer
 // per host thread, allocated on first use and kept for the thread's
 // lifetime (a solve reads its values before it returns).
@@ -426,19 +435,20 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     if (want_rho)
       PNP_LAUNCH(k_cg_init_fin, dim3(1), dim3(kFinThreads), 0, s, w.parts, (int)nb, w.sc, rho_out, restore_bad);
   };
+  // step 0: w = M r0; steps 1..n_cg-1: update (p, s, u, r) inside the
+  // operator's first pass, w = M r; then the last u update.  The step sizes
+  // of step j are formed by the pass that uses them (the first pass of step
+  // j + 1, or the last update) from step j's block sums; step j's state goes
+  // to cgs[j % 2], the previous step's is read from the other.
+  auto fin_of = [&](int j) {
+    return CGFinish{w.parts, (int)nb, j == 0 ? 1 : 0, w.cgs + ((j + 1) & 1), w.cgs + (j & 1), &w.sc->bad};
+  };
   // the n_cg CG steps of outer iteration k from the CG start in set 0;
-  // returns the buffer that holds u
-  auto cg_solve = [&](int k) -> float2* {
+  // returns c, the set that holds the last step's (r, p, u); with `final`,
+  // the last u update is made into w.u[1 - c]
+  auto cg_solve = [&](int k, bool final) -> int {
     const double gamma = a.lambda * a.sigmas[k];
     const float cg = (float)(gamma - c1a);
-    // step 0: w = M r0; steps 1..n_cg-1: update (p, s, u, r) inside the
-    // operator's first pass, w = M r; then the last u update.  The step
-    // sizes of step j are formed by the pass that uses them (the first pass
-    // of step j + 1, or the last update) from step j's block sums; step j's
-    // state goes to cgs[j % 2], the previous step's is read from the other.
-    auto fin_of = [&](int j) {
-      return CGFinish{w.parts, (int)nb, j == 0 ? 1 : 0, w.cgs + ((j + 1) & 1), w.cgs + (j & 1), &w.sc->bad};
-    };
     int c = 0;
     for (int j = 0; j < a.n_cg; ++j) {
       NormalIn in = plain_input(w.r[0]);
@@ -452,18 +462,27 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
       PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg, w.w,
                  w.parts);
     }
-    float2* u_res = w.u[1 - c];
-    PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], u_res,
-               fin_of(a.n_cg - 1));
-    return u_res;
+    if (final)
+      PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], w.u[1 - c],
+                 fin_of(a.n_cg - 1));
+    return c;
   };
+  // a wavelet prior without a check forms the last u update while it loads
+  // its blocks (no separate update pass)
+  const bool fuse_final = !guard && a.prior->kind == 0;
 
   float2* u_next = nullptr;   // iteration k's CG, queued by iteration k - 1's check
   for (int k = 0; k < a.n_out; ++k) {
     if (!started) cg_start(a.lambda * a.sigmas[k], w.rho + k, 0);
     started = false;
     if (guard && k == 0) post_rho(0);
-    float2* u_res = u_next ? u_next : cg_solve(k);
+    if (fuse_final) {
+      const int c = cg_solve(k, false);
+      prior_apply_cg(a.prior, p->ndim, nd, w.r[c], w.p[c], w.u[c], fin_of(a.n_cg - 1), x, a.sigmas[k], s);
+      continue;
+    }
+    float2* u_res = u_next;
+    if (!u_res) u_res = w.u[1 - cg_solve(k, true)];
     u_next = nullptr;
     prior_apply(a.prior, p->ndim, nd, u_res, x, a.sigmas[k], s);
     if (!guard) continue;
@@ -472,7 +491,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     const double gnext = k + 1 < a.n_out ? a.lambda * a.sigmas[k + 1] : 0.0;
     cg_start(gnext, w.rho + k + 1, 0);
     post_rho(k + 1);
-    if (k + 1 < a.n_out) u_next = cg_solve(k + 1);
+    if (k + 1 < a.n_out) u_next = w.u[1 - cg_solve(k + 1, true)];
     PNP_HIP(hipEventSynchronize(ev.e));   // rho_0 .. rho_{k+1} are in the pinned copy
     if (k == 0) rho_prev = rho_pin[0];
     double rho = rho_pin[k + 1];
@@ -480,7 +499,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
       PNP_LAUNCH(k_copy, dim3(nb), dim3(kRedThreads), 0, s, N, w.Nv, x);
       cg_start(gnext, w.rho + k + 1, 1);
       post_rho(k + 1);
-      if (k + 1 < a.n_out) u_next = cg_solve(k + 1);
+      if (k + 1 < a.n_out) u_next = w.u[1 - cg_solve(k + 1, true)];
       PNP_HIP(hipEventSynchronize(ev.e));
       rho = rho_pin[k + 1];
       if (fb_host) fb_host[k] = 1;

@@ -7,6 +7,7 @@
 // Within a block the coefficients sit in the usual pyramid layout; the
 // single coarsest approximation coefficient of a block (index 0) is the
 // only one left unthresholded.  Soft threshold: c * max(0, 1 - tau/|c|).
+#include "cg_scalars.hpp"
 #include "common.hpp"
 #include "trace.hpp"
 
@@ -56,8 +57,10 @@ __device__ void haar_step(const float2* __restrict__ src, float2* __restrict__ d
 
 // One 2^J (per axis) block `blk` of the image: analysis, soft threshold
 // of every detail coefficient, synthesis; lds: 2 * 2^(J*ndim) float2.
-__device__ void haar_block(const float2* __restrict__ in, float2* __restrict__ out, int ndim, int nx, int ny,
-                           int J, float tau, int blk, float2* lds) {
+// load(i) gives the input pixel of linear index i.
+template <class Load>
+__device__ void haar_block(Load load, float2* __restrict__ out, int ndim, int nx, int ny, int J, float tau,
+                           int blk, float2* lds) {
   const int B = 1 << J;
   const int total = ndim == 3 ? B * B * B : B * B;
   float2* a = lds;
@@ -68,7 +71,7 @@ __device__ void haar_block(const float2* __restrict__ in, float2* __restrict__ o
   const int oz = ndim == 3 ? (blk / (bx * by)) * B : 0;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int x = t % B, y = (t / B) % B, z = ndim == 3 ? t / (B * B) : 0;
-    a[t] = in[((long long)(oz + z) * ny + (oy + y)) * nx + ox + x];
+    a[t] = load(((long long)(oz + z) * ny + (oy + y)) * nx + ox + x);
   }
   __syncthreads();
   for (int l = 0; l < J; ++l) {
@@ -104,7 +107,25 @@ __device__ void haar_block(const float2* __restrict__ in, float2* __restrict__ o
 __global__ void k_haar_prior(const float2* __restrict__ in, float2* __restrict__ out, int ndim,
                              int nx, int ny, int nz, int J, float tau) {
   extern __shared__ float2 lds[];
-  haar_block(in, out, ndim, nx, ny, J, tau, blockIdx.x, lds);
+  haar_block([in](long long i) { return in[i]; }, out, ndim, nx, ny, J, tau, blockIdx.x, lds);
+}
+
+// The prior applied to the last CG update u + alpha (r + beta p), formed on
+// the fly: alpha and beta come from the step's block sums, summed by every
+// wave in the fixed order (workgroup 0 records the step's state).
+__global__ void __launch_bounds__(256)
+k_haar_prior_cg(const float2* __restrict__ r, const float2* __restrict__ p, const float2* __restrict__ u,
+                CGFinish fin, float2* __restrict__ out, int ndim, int nx, int ny, int nz, int J, float tau) {
+  extern __shared__ float2 lds[];
+  const CgStep st = cg_finish_deferred(fin);
+  const float a = (float)st.alpha, b = (float)st.beta;
+  haar_block(
+      [=](long long i) {
+        const float2 rv = r[i], pv = p[i], uv = u[i];
+        const float2 pn = make_float2(fmaf(b, pv.x, rv.x), fmaf(b, pv.y, rv.y));
+        return make_float2(fmaf(a, pn.x, uv.x), fmaf(a, pn.y, uv.y));
+      },
+      out, ndim, nx, ny, J, tau, blockIdx.x, lds);
 }
 
 // Batched 2D prior: workgroup b belongs to the last slice with block0 <= b.
@@ -112,7 +133,9 @@ __global__ void k_haar_prior_batched(const HaarSlice* __restrict__ sl, int n_sli
   extern __shared__ float2 lds[];
   int s = 0;
   while (s + 1 < n_slices && sl[s + 1].block0 <= (int)blockIdx.x) ++s;
-  haar_block(sl[s].in, sl[s].out, 2, sl[s].nx, sl[s].ny, J, tau, blockIdx.x - sl[s].block0, lds);
+  const float2* in = sl[s].in;
+  haar_block([in](long long i) { return in[i]; }, sl[s].out, 2, sl[s].nx, sl[s].ny, J, tau,
+             blockIdx.x - sl[s].block0, lds);
 }
 
 }  // namespace
@@ -131,6 +154,20 @@ void wavelet_apply_batched(const HaarSlice* sl, int n_slices, int total_blocks, 
   const int B = 1 << levels;
   const size_t lds = sizeof(float2) * 2 * B * B;
   PNP_LAUNCH(k_haar_prior_batched, dim3((unsigned)total_blocks), dim3(256), lds, s, sl, n_slices, levels, tau);
+}
+
+void wavelet_apply_cg(int ndim, const int* n, int levels, float tau, const float2* r, const float2* p,
+                      const float2* u, const CGFinish& fin, float2* out, hipStream_t s) {
+  const int B = 1 << levels;
+  for (int a = 0; a < ndim; ++a)
+    if (n[a] % B) fail(PNP_ERR_SHAPE, "image side %d not divisible by 2^%d", n[a], levels);
+  long long blocks = 1;
+  for (int a = 0; a < ndim; ++a) blocks *= n[a] / B;
+  const int total = ndim == 3 ? B * B * B : B * B;
+  const size_t lds = sizeof(float2) * 2 * total;
+  PNP_LAUNCH(k_haar_prior_cg, dim3((unsigned)blocks), dim3(256), lds, s, r, p, u, fin, out, ndim, n[0], n[1],
+             ndim == 3 ? n[2] : 1, levels, tau);
+  PNP_CHECK_LAUNCH();
 }
 
 void wavelet_apply(int ndim, const int* n, int levels, float tau, const float2* in, float2* out,
