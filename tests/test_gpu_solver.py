@@ -120,6 +120,23 @@ def test_hqs_tiny_toeplitz_matches_oracle(pnp, precond):
 
 
 @pytest.mark.parametrize("toeplitz", [False, True])
+def test_hqs_image_does_not_depend_on_the_report(pnp, toeplitz):
+    """The residuals are formed only when a report asks for them; the
+    iterates never read them, so the image is bit-identical either way."""
+    w = synth.config_tiny()
+    x, roi, S, k, dcf, y = _problem(w, 6)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    tp = pnp.Toeplitz(plan) if toeplitz else None
+    Ln = plan.opnorm(to_dev(S), None, iters=200, seed=1)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, 4)
+    args = (plan, to_dev(y), to_dev(S), None, pnp.WaveletPrior(0, 0.5), sig, 3e4 / Ln, "f1", w.n_cg)
+    x_plain, none = pnp.hqs_solve(*args, opnorm=Ln, toeplitz=tp)
+    x_rep, rep = pnp.hqs_solve(*args, opnorm=Ln, toeplitz=tp, report=True)
+    assert none is None and len(rep["rho"]) == len(sig) and np.all(np.isfinite(rep["rho"]))
+    assert np.array_equal(to_np(x_plain), to_np(x_rep))
+
+
+@pytest.mark.parametrize("toeplitz", [False, True])
 def test_hqs_reports_cg_breakdown(pnp, toeplitz):
     """A non-finite k-space sample makes the CG inner products non-finite; the
     step sizes (formed in the pass that uses them on the Toeplitz path) set the
