@@ -137,6 +137,6 @@ def test_kb_gridding_error_matches_prediction(n):
 
 
 def test_predicted_kb_error_level():
-    # the survey-quoted level for W = 6, osf = 2: about 6.7e-6 rel-RMS in 2D
+    # Kaiser-Bessel aliasing level for W = 6, oversampling 2 (Beatty shape): about 6.7e-6 rel-RMS in 2D
     p = gridding.predicted_rel_rms_white(320, 2)
     assert 3e-6 < p < 1.2e-5
