@@ -36,7 +36,11 @@ Printed JSON line:
              with the wavelet prior and with the UNet applied slice by slice;
 * ``unet``   the denoiser's forward (320x320, batch 1 and 24) and training
              step (batch 10 x 128x128, forward + backward + Adam) in TFLOP/s
-             and as a fraction of the 2.5 PFLOP/s dense BF16 MFMA peak.
+             and as a fraction of the 2.5 PFLOP/s dense BF16 MFMA peak;
+* ``setup``  the once-per-trajectory and once-per-solve work of the clinical
+             slice, outside the timed step: plan creation, the Toeplitz
+             transfer function, the operator norm (100 power iterations), and
+             the gridded forward and adjoint operators alone.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu]
 """
@@ -202,6 +206,37 @@ def psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, n_slices):
     out["learned_over_wavelet"] = round(out["learned"]["slices_per_s"] / out["wavelet"]["slices_per_s"], 2)
     out["learned_prior"] = f"UNet (kappa {KAPPA_UNET}) with wavelet fallback (rise_tol {RISE_TOL})"
     return out
+
+
+def setup_times(pnp, torch, kt, shape, xd, Sd, dd, y, time_op):
+    """Plan creation, Toeplitz transfer function and operator norm (median of
+    3, each synchronised), and the gridded A and A^H alone (back to back)."""
+    def once(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, r
+
+    plan_ms, tp_ms, nrm_ms = [], [], []
+    for _ in range(3):
+        t, pl = once(lambda: pnp.Plan(kt, shape))
+        plan_ms.append(t)
+        t, tp = once(lambda: pnp.Toeplitz(pl, dd))
+        tp_ms.append(t)
+        nrm_ms.append(once(lambda: pl.opnorm(Sd, dd, iters=100, seed=1))[0])
+        tp.close()
+        pl.close()
+    pl = pnp.Plan(kt, shape)
+    ybuf = torch.empty_like(y)
+    xbuf = torch.empty_like(xd)
+    fwd_us = time_op(lambda: pl.forward(xd, Sd, out=ybuf))
+    adj_us = time_op(lambda: pl.adjoint(y, Sd, dd, out=xbuf))
+    pl.close()
+    med = lambda v: round(float(np.median(v)), 3)
+    return {"plan_create_ms": med(plan_ms), "toeplitz_transfer_function_ms": med(tp_ms),
+            "opnorm_100_iterations_ms": med(nrm_ms), "forward_us": round(fwd_us, 2),
+            "adjoint_us": round(adj_us, 2)}
 
 
 def pgd_fista(pnp, torch, plan, toep, Sd, dd, w, S, nrm, seed, b_alg):
@@ -590,6 +625,7 @@ def main():
         pnp.estimate_smaps(plan, y, dd)
     torch.cuda.synchronize()
     smaps_ms = (time.perf_counter() - t0) * 1e2
+    setup = setup_times(pnp, torch, kt, (n, n), xd, Sd, dd, y, time_op)
     unet = unet_rates(pnp, torch)
     batched = None if args.no_batched else batched_c4(pnp, torch)
     vol3d = None if args.no_3d else volume_3d(pnp, torch)
@@ -626,6 +662,7 @@ def main():
         "psnr_race": race,
         "pgd_fista": others,
         "smaps_estimate_ms": round(smaps_ms, 3),
+        "setup": setup,
         "batched": batched,
         "volume_3d": vol3d,
         "unet": unet,
