@@ -281,6 +281,68 @@ def test_fista_wavelet_reaches_the_pgd_minimiser():
     assert e_f < e_p
 
 
+def test_lanczos_norm_equals_max_eigenvalue():
+    """The Lanczos (ARPACK) norm is the top eigenvalue of the dense normal
+    matrix, and agrees with the power-iteration norm; a wrong eigenvalue
+    choice (smallest, or the largest in magnitude of a shifted matrix) or a
+    dropped DCF weighting would not."""
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    ev = np.linalg.eigvalsh(Nmat)
+    lam = solver.opnorm_lanczos(normal, (8, 8), tol=1e-12, seed=5)
+    assert abs(lam - ev[-1]) < 1e-10 * ev[-1]
+    lam_p, _ = solver.opnorm(normal, (8, 8), seed=3, tol=1e-13, maxit=5000)
+    assert abs(lam - lam_p) < 1e-9 * ev[-1]
+    # the weighting matters: the unweighted operator has another norm
+    ev_u = np.linalg.eigvalsh(A.conj().T @ A)[-1]
+    assert abs(ev_u - ev[-1]) > 1e-3 * ev[-1]
+    # full Cartesian sampling with SoS-1 maps: A^H A = I, so the norm is 1
+    n = 8
+    Sc = synth.smaps2d(n, 3).astype(np.complex128)
+    Sc /= np.sqrt((np.abs(Sc) ** 2).sum(0))
+    kc = synth.cartesian2d(n, np.float64)
+    assert abs(solver.opnorm_lanczos(lambda v: ndft.normal(v, Sc, kc), (n, n)) - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("precond", ["f1", "cheb"])
+def test_preconditioned_pgd_step_dense(precond):
+    """One PnP-PGD step with the identity denoiser against the dense formula
+    x - gamma (c0 I - c1 alpha N)(N x - b0), N the dense normal matrix built
+    from the brute-force NDFT matrix (Sec. 3.3 PnP-PGD with the Sec. 3.4
+    preconditioners).  A flipped sign of the c1 term, a dropped alpha or a
+    preconditioner applied to x instead of the gradient each fail."""
+    k, S, w, A, Nmat, normal = _tiny_problem()
+    Ln = np.linalg.eigvalsh(Nmat)[-1]
+    c0, c1 = {"f1": (2.0, 1.0), "cheb": (4.0, 10.0 / 3.0)}[precond]
+    P = c0 * np.eye(64) - (c1 / Ln) * Nmat
+    x = synth.white_complex((8, 8), 64).astype(np.complex128)
+    b0 = synth.white_complex((8, 8), 65).astype(np.complex128)
+    gamma = 0.8 / Ln
+    got = solver.pgd(b0, normal, x, gamma, 1, lambda u, s: u, 0.0, precond, Ln)
+    ref = x.ravel() - gamma * (P @ (Nmat @ x.ravel() - b0.ravel()))
+    assert np.max(np.abs(got.ravel() - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("precond", ["f1", "cheb"])
+def test_preconditioned_pgd_reaches_least_squares(precond):
+    """With D = identity, preconditioned gradient descent x <- x - gamma P (N x - b0)
+    converges to the least-squares solution N x = b0 (strongly convex tiny
+    problem), and faster than P = Id at the same gamma (the point of the
+    preconditioner, Sec. 3.4)."""
+    k, S, w, A, Nmat, normal = _tiny_problem(M=120)
+    y = synth.white_complex((2, 120), 66).astype(np.complex128)
+    b0 = ndft.adjoint(y, S, k, w)
+    Ln = np.linalg.eigvalsh(Nmat)[-1]
+    x_ls = np.linalg.solve(Nmat, b0.ravel())
+    ident = lambda u, s: u
+    gamma = 1.0 / Ln
+    # F-1: t p(t) <= 1 on [0, 1], Chebyshev: <= 1.2, so gamma = 1/L is a stable step for both
+    x = solver.pgd(b0, normal, b0, gamma, 4000, ident, 0.0, precond, Ln)
+    assert np.linalg.norm(x.ravel() - x_ls) < 1e-8 * np.linalg.norm(x_ls)
+    e_pre = np.linalg.norm(solver.pgd(b0, normal, b0, gamma, 40, ident, 0.0, precond, Ln).ravel() - x_ls)
+    e_id = np.linalg.norm(solver.pgd(b0, normal, b0, gamma, 40, ident, 0.0, "id", Ln).ravel() - x_ls)
+    assert e_pre < e_id
+
+
 def test_pgd_schedule_constant_equals_pgd():
     k, S, w, A, Nmat, normal = _tiny_problem()
     b0 = synth.white_complex((8, 8), 63).astype(np.complex128)
