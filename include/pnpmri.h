@@ -169,6 +169,24 @@ pnp_status pnp_toeplitz_destroy(pnp_toeplitz* tp);
 pnp_status pnp_normal_toeplitz(const pnp_toeplitz* tp, const pnp_c64* x, const pnp_c64* smaps,
                                int32_t L, pnp_c64* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * Toeplitz normal operator of pnp_normal_toeplitz (same arguments, results
+ * bit-identical) without a workspace argument.  Its scratch is a static
+ * device array inside the library of pnp_noalloc_scratch_bytes() bytes
+ * (64 MiB), one per device, held until the process ends; its address is
+ * looked up once per device (at pnp_toeplitz_create, or the first call on a
+ * device).  The call allocates nothing.  Requests whose workspace
+ * (pnp_workspace_bytes for this plan and L) exceeds the array return
+ * PNP_ERR_WORKSPACE before anything is enqueued (a 320 x 320 plan takes up
+ * to 16 coils at the clinical sampling; 3D plans rarely fit).  All calls on
+ * one device share the array: calls that overlap in time on one device
+ * (several streams or host threads) race and give wrong results.  Nothing
+ * in the array needs to start at zero. */
+pnp_status pnp_noalloc_scratch_bytes(size_t* bytes);
+pnp_status pnp_normal_toeplitz_noalloc(const pnp_toeplitz* tp, const pnp_c64* x, const pnp_c64* smaps,
+                                       int32_t L, pnp_c64* out, hipStream_t stream);
+
 /* ----------------------------------------------------------------- prior */
 typedef struct pnp_prior pnp_prior;
 

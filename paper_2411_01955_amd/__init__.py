@@ -246,6 +246,15 @@ class Toeplitz:
         check(load().pnp_normal_toeplitz(self._h, _ptr(x), _ptr(smaps), L, _ptr(o), _ptr(ws), nb, _stream()))
         return o
 
+    def normal_noalloc(self, x, smaps, out):
+        """The same operator through the entry point that allocates nothing
+        (the library's static per-device scratch; ``out`` is required)."""
+        L = self.plan._L(smaps)
+        _need_c64(x, "x", self.plan.shape)
+        _need_c64(out, "out", self.plan.shape)
+        check(load().pnp_normal_toeplitz_noalloc(self._h, _ptr(x), _ptr(smaps), L, _ptr(out), _stream()))
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             load().pnp_toeplitz_destroy(self._h)

@@ -105,6 +105,8 @@ SIGNATURES = {
     "pnp_toeplitz_create": (_i32, [C.POINTER(_vp), _vp, _vp, _vp]),
     "pnp_toeplitz_destroy": (_i32, [_vp]),
     "pnp_normal_toeplitz": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "pnp_noalloc_scratch_bytes": (_i32, [C.POINTER(_sz)]),
+    "pnp_normal_toeplitz_noalloc": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "pnp_prior_wavelet": (_i32, [C.POINTER(_vp), _i32, _dbl]),
     "pnp_prior_destroy": (_i32, [_vp]),
     "pnp_prior_apply": (_i32, [_vp, _i32, C.POINTER(_i32), _vp, _vp, _dbl, _vp]),

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -66,6 +67,32 @@ void need(const void* ptr, const char* name) {
 void check_plan_L(const pnp_plan* p, int32_t L) {
   need(p, "plan");
   if (L < 1) fail(PNP_ERR_SHAPE, "L must be >= 1 (got %d)", L);
+}
+
+// Static device scratch of the no-allocation entry point.  In host code
+// `scratch` only names the symbol: its device address is looked up once per
+// device with hipGetSymbolAddress (with that device current) and kept; the
+// kernels always receive that address.  Every call on one device shares the
+// array, so concurrent calls on one device race.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static void* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up on first use).
+void* noalloc_scratch() {
+  int dev = 0;
+  PNP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(PNP_ERR_UNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    PNP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(PNP_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
 }
 
 void check_ws(size_t have, size_t need_bytes, const void* ws) {
@@ -196,6 +223,7 @@ pnp_status pnp_toeplitz_create(pnp_toeplitz** out, const pnp_plan* plan, const f
     need(out, "out");
     need(plan, "plan");
     *out = nullptr;
+    (void)noalloc_scratch();   // set-up of the no-allocation entry point on this device
     *out = toeplitz_create(plan, plan->traj, dcf, stream);
   });
 }
@@ -217,6 +245,34 @@ pnp_status pnp_normal_toeplitz(const pnp_toeplitz* tp, const pnp_c64* x, const p
     check_ws(ws_bytes, op_workspace_bytes(tp->plan, L), ws);
     op_normal_toep(tp, (const float2*)x, (const float2*)smaps, L, (float2*)out,
                    op_workspace(tp->plan, L, ws), stream);
+  });
+}
+
+pnp_status pnp_noalloc_scratch_bytes(size_t* bytes) {
+  return guarded([&] {
+    need(bytes, "bytes");
+    *bytes = kNoAllocScratchBytes;
+  });
+}
+
+pnp_status pnp_normal_toeplitz_noalloc(const pnp_toeplitz* tp, const pnp_c64* x, const pnp_c64* smaps,
+                                       int32_t L, pnp_c64* out, hipStream_t stream) {
+  return guarded([&] {
+    need(tp, "toeplitz");
+    check_plan_L(tp->plan, L);
+    need(x, "x");
+    need(smaps, "smaps");
+    need(out, "out");
+    if ((const void*)x == (const void*)out) fail(PNP_ERR_ARG, "x and out must not alias");
+    const size_t need_bytes = op_workspace_bytes(tp->plan, L);
+    if (need_bytes > kNoAllocScratchBytes)
+      fail(PNP_ERR_WORKSPACE,
+           "pnp_normal_toeplitz_noalloc: %d coils on this plan need %zu bytes of scratch, more than the "
+           "library's static %zu; use pnp_normal_toeplitz with a caller workspace",
+           L, need_bytes, (size_t)kNoAllocScratchBytes);
+    void* ws = noalloc_scratch();
+    op_normal_toep(tp, (const float2*)x, (const float2*)smaps, L, (float2*)out, op_workspace(tp->plan, L, ws),
+                   stream);
   });
 }
 
