@@ -352,15 +352,20 @@ def batched_slice_table(count: int = 24):
         n = (256, 320, 384)[i % 3]
         L = (8, 16, 32)[(i // 3) % 3]
         af = (4, 8, 16)[(i // 9) % 3]
-        N = n * n
-        if i % 2 == 0:
-            S = 2 * n
-            tr = radial2d(max(1, round(N / (af * S))), S)
-        else:
-            S = round(1.25 * n)
-            tr = spiral2d(max(1, round(N / (af * S))), S)
-        out.append(dict(index=i, n=n, L=L, af=af, traj=tr))
+        out.append(dict(index=i, n=n, L=L, af=af, traj=uneven_slice_traj(n, af, i % 2 == 0)))
     return out
+
+
+def uneven_slice_traj(n: int, af: int, radial: bool) -> Trajectory:
+    """The trajectory rule of the uneven multi-slice table: golden-angle
+    radial with S = 2n samples and round(N/(AF*S)) spokes, or a VD spiral with
+    S = round(1.25 n) samples and round(N/(AF*S)) interleaves (N = n^2)."""
+    N = n * n
+    if radial:
+        S = 2 * n
+        return radial2d(max(1, round(N / (af * S))), S)
+    S = round(1.25 * n)
+    return spiral2d(max(1, round(N / (af * S))), S)
 
 
 # ------------------------------------------------------ denoiser training data
