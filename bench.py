@@ -8,10 +8,15 @@ i.e. 180 applications of the normal operator A^H D_w A.  Inputs are seeded
 synthetic phantoms already resident in HBM.
 
 Printed JSON line:
-* ``value``  effective A^H A bandwidth over the whole step:
-             180 * B_alg / step time, B_alg = the algorithmic bytes of one
-             normal operator (x, coil maps twice, output, trajectory, DCF and
-             four crossings of the oversampled coil grids);
+* ``value``  HBM bandwidth of the whole step on the bytes its kernels move:
+             the algorithmic (compulsory) bytes of every launch of the step
+             (``kernel_bytes`` per launch x the step's launch counts, checked
+             against a traced pass) / step time.  The Toeplitz operator the
+             step runs moves ~138 MB per normal operator;
+             ``value_b_alg_equivalent`` is the larger figure 180 * B_alg /
+             step time, B_alg = the bytes of the gridded normal operator (x,
+             coil maps twice, output, trajectory, DCF and four crossings of
+             the oversampled coil grids), which the Toeplitz form avoids;
 * ``roofline``  the dominant kernel's algorithmic bytes per launch over its
              mean launch time (HIP events around each launch, recorded on the
              kernel's stream over a second pass of the same steps), against
@@ -51,6 +56,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -118,7 +124,34 @@ def kernel_bytes(n, L, M, E, groups):
     out["k_cg_dots"] = 8 * N * (2 + groups)
     out["k_cg_init"] = 8 * N * (2 + groups + 4)
     out["k_cg_final"] = 8 * N * 4
+    # forward row pass with the CG update fused in: reads r, s, w, p, u and
+    # writes r', s', p', u' (coil group 0) besides the plain pass's bytes
+    out["k_rows_fwd_fs_cg"] = out["k_rows_fwd_fs"] - 8 * N + 8 * N * 9
+    # Haar prior on the last CG update u + alpha (r + beta p): r, p, u in, x out
+    out["k_haar_prior_cg"] = 8 * N * 4
+    out["k_wnorm"] = 8 * L * M + 4 * M
+    out["k_copy"] = 16 * N
+    out["k_init_scalars"] = 0
     return out
+
+
+def step_launches(n_out, n_cg):
+    """Launch counts of one wavelet-HQS solve on the Toeplitz operator (the
+    timed step): per outer iteration the CG start (N x: plain forward row
+    pass) and n_cg CG steps (the first on r0 with a plain row pass, the rest
+    with the CG update fused into it), the CG reductions and the prior on the
+    last update; once per solve b0 = A^H D_w y (gridded adjoint), ||y||_w^2,
+    x0 = b0 and the scalar reset."""
+    return {"k_rows_fwd_fs": 2 * n_out, "k_rows_fwd_fs_cg": (n_cg - 1) * n_out,
+            "k_cols_toep_fs": (1 + n_cg) * n_out, "k_rows_adj_fs": (1 + n_cg) * n_out + 1,
+            "k_cg_dots": n_cg * n_out, "k_cg_init": n_out, "k_haar_prior_cg": n_out,
+            "k_entry_values": 1, "k_cols_adj_fs": 1, "k_sum_groups": 1, "k_wnorm": 1, "k_copy": 1,
+            "k_init_scalars": 1}
+
+
+def toeplitz_normal_bytes(kb):
+    """Algorithmic bytes of one Toeplitz normal operator alone (plain input)."""
+    return kb["k_rows_fwd_fs"] + kb["k_cols_toep_fs"] + kb["k_rows_adj_fs"] + kb["k_sum_groups"]
 
 
 def _kname(s: str) -> str:
@@ -202,6 +235,7 @@ def psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, n_slices):
             torch.cuda.synchronize()
             secs.append(a.elapsed_time(b) / 1e3)
         out[m] = {"slices_per_s": round(1.0 / float(np.mean(secs)), 2), "mean_outer_iterations": round(float(np.mean(ks)), 2),
+                  "max_outer_iterations": int(max(ks)),
                   "reached_target": f"{reached}/{n_slices}", "ms_per_slice": round(1e3 * float(np.mean(secs)), 3)}
     out["learned_over_wavelet"] = round(out["learned"]["slices_per_s"] / out["wavelet"]["slices_per_s"], 2)
     out["learned_prior"] = f"UNet (kappa {KAPPA_UNET}) with wavelet fallback (rise_tol {RISE_TOL})"
@@ -210,7 +244,8 @@ def psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, n_slices):
 
 def setup_times(pnp, torch, kt, shape, xd, Sd, dd, y, time_op):
     """Plan creation, Toeplitz transfer function and operator norm (median of
-    3, each synchronised), and the gridded A and A^H alone (back to back)."""
+    3, each synchronised), and the gridded A and A^H alone (median of the
+    event-timed repetitions)."""
     def once(fn):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -230,8 +265,8 @@ def setup_times(pnp, torch, kt, shape, xd, Sd, dd, y, time_op):
     pl = pnp.Plan(kt, shape)
     ybuf = torch.empty_like(y)
     xbuf = torch.empty_like(xd)
-    fwd_us = time_op(lambda: pl.forward(xd, Sd, out=ybuf))
-    adj_us = time_op(lambda: pl.adjoint(y, Sd, dd, out=xbuf))
+    fwd_us = time_op(lambda: pl.forward(xd, Sd, out=ybuf))[0]
+    adj_us = time_op(lambda: pl.adjoint(y, Sd, dd, out=xbuf))[0]
     pl.close()
     med = lambda v: round(float(np.median(v)), 3)
     return {"plan_create_ms": med(plan_ms), "toeplitz_transfer_function_ms": med(tp_ms),
@@ -366,7 +401,10 @@ def volume_3d(pnp, torch, n_out=None):
     xd = torch.from_numpy(x).cuda()
     y = plan.forward(xd, Sd)
     y += torch.from_numpy(synth.complex_noise((L, M), synth.noise_variance(x, S), synth.SEED_NOISE)).cuda()
-    toep = pnp.Toeplitz(plan, dd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    toep = pnp.Toeplitz(plan, dd)      # exact FP64 transfer function (waits for the stream)
+    t_toep = time.perf_counter() - t0
     nrm = plan.opnorm(Sd, dd, iters=30, seed=1)
     out = torch.empty_like(xd)
 
@@ -398,7 +436,8 @@ def volume_3d(pnp, torch, n_out=None):
             "toeplitz_normal_op_frac_of_hbm": round(B / t_op / 1e9 / HBM_PEAK_GBPS, 4),
             "hqs_outer": n_out, "hqs_wavelet_s_per_volume": round(t_hqs, 3),
             "hqs_wavelet_GBps": round(n_ops * B / t_hqs / 1e9, 1),
-            "hqs_learned_slicewise_s_per_volume": round(t_lrn, 3)}
+            "hqs_learned_slicewise_s_per_volume": round(t_lrn, 3),
+            "toeplitz_transfer_function_s": round(t_toep, 3)}
 
 
 def unet_rates(pnp, torch):
@@ -458,14 +497,37 @@ def unet_rates(pnp, torch):
     return res
 
 
-def cpu_baseline(w, x, S, dcf, y, b_alg):
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, x, S, dcf, y, step_bytes):
     """Oracle (exact NDFT, numpy/OpenBLAS FP64) on one outer HQS iteration of
-    the same slice: 1 + n_cg normal operators plus the CG vector work."""
+    the same slice (1 + n_cg normal operators, the prior and the residual
+    operator) with all host threads, and one exact normal operator with one
+    thread; both extrapolated to a whole slice (30 outer iterations) and
+    reported in the step's unit: the step's bytes / the oracle's time per
+    slice (the GPU/CPU ratio of `value` is then the ratio of slice times)."""
     from oracle import ndft, solver, wavelet
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:
+        threadpool_limits = None
         cores = os.cpu_count()
     k = w.traj.k
     normal = lambda v: ndft.normal(v, S, k, dcf)
@@ -474,14 +536,23 @@ def cpu_baseline(w, x, S, dcf, y, b_alg):
     solver.hqs(b0, normal, [w.sigma0], 1.0, "f1", w.n_cg,
                lambda u, s: wavelet.wavelet_denoise(u, KAPPA * s), 17.0)
     dt = time.perf_counter() - t0
-    n_ops = 1 + w.n_cg + 1          # the loop also forms N x of its result
-    gbps = n_ops * b_alg / dt / 1e9
-    return {"value": round(gbps, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"one outer HQS iteration (1+{w.n_cg} CG normal operators + prior + residual "
-                      f"operator) of the 320x320/16-coil spiral slice, exact FP64 NDFT, {dt:.1f} s; "
-                      f"scaled as {n_ops} x B_alg / time; a full 30-iteration slice would take "
-                      f"~{dt * w.n_out:.0f} s",
-            "seconds_per_slice_extrapolated": round(dt * w.n_out, 1)}
+    per_slice = dt * w.n_out
+    out = {"value": round(step_bytes / per_slice / 1e9, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+           "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+           "sample": f"one outer HQS iteration (1+{w.n_cg} CG normal operators + prior + residual operator) of "
+                     f"the 320x320/16-coil spiral slice, exact FP64 NDFT, {dt:.1f} s with {cores} threads; "
+                     f"x {w.n_out} = {per_slice:.0f} s per slice; value = the step's bytes / that time",
+           "seconds_per_slice_extrapolated": round(per_slice, 1)}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            normal(x)
+            d1 = time.perf_counter() - t0
+        ops = w.n_out * (1 + w.n_cg + 1)
+        out["one_thread"] = {"normal_op_s": round(d1, 2), "seconds_per_slice_extrapolated": round(d1 * ops, 1),
+                             "value": round(step_bytes / (d1 * ops) / 1e9, 5),
+                             "sample": f"one exact normal operator with 1 thread, x {ops} operators per slice"}
+    return out
 
 
 def main():
@@ -495,7 +566,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1002)
     ap.add_argument("--reps", type=int, default=200,
                     help="back-to-back repetitions when timing the normal operators alone")
-    ap.add_argument("--psnr-slices", type=int, default=24,
+    ap.add_argument("--psnr-slices", type=int, default=100,
                     help="held-out phantoms of the learned-vs-wavelet PSNR race (0: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
@@ -546,15 +617,24 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for a, b in ev:
+        a.record()
         step()
+        b.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
+    step_ms = [a.elapsed_time(b) for a, b in ev]
     n_normal = w.n_out * (1 + w.n_cg)
     B = b_alg_normal(n, L, M)
-    value = n_normal * B / (ms / 1e3) / 1e9
+    groups = -(-L // plan.row_coils)
+    kb = kernel_bytes(n, L, M, info["entries"], groups)
+    launches_model = step_launches(w.n_out, w.n_cg)
+    step_bytes = sum(kb[k] * c for k, c in launches_model.items())
+    value = step_bytes / (ms / 1e3) / 1e9
+    value_b_alg = n_normal * B / (ms / 1e3) / 1e9
 
     # quality of the reconstruction (outside the timed region)
     xr = out.cpu().numpy()
@@ -565,18 +645,24 @@ def main():
     # normal operator alone, back to back: gridded and Toeplitz-embedded
     tmp = torch.empty_like(xd)
 
-    def time_op(fn, reps=max(1, args.reps)):
+    def time_op(fn, reps=max(100, args.reps)):
+        """Median (p10, p90) of `reps` back-to-back repetitions, each between
+        two HIP events on the launch stream, in microseconds."""
         for _ in range(5):
             fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record()
             fn()
+            b.record()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e6 / reps
+        us = np.array([a.elapsed_time(b) * 1e3 for a, b in evs])
+        return float(np.median(us)), float(np.percentile(us, 10)), float(np.percentile(us, 90))
 
-    gridded_us = time_op(lambda: plan.normal(xd, Sd, dd, out=tmp))
-    normal_us = time_op(lambda: toep.normal(xd, Sd, out=tmp))
+    gridded_us, gridded_p10, gridded_p90 = time_op(lambda: plan.normal(xd, Sd, dd, out=tmp))
+    normal_us, normal_p10, normal_p90 = time_op(lambda: toep.normal(xd, Sd, out=tmp))
+    toep_bytes = toeplitz_normal_bytes(kb)
 
     # traced pass: per-kernel durations with HIP events on the launch stream
     pnp.trace_enable(True)
@@ -589,8 +675,13 @@ def main():
         c0, t0 = tr.get(_kname(kname), (0, 0.0))
         tr[_kname(kname)] = (c0 + c, t0 + t)
     pnp.trace_enable(False)
-    groups = -(-L // plan.row_coils)
-    kb = kernel_bytes(n, L, M, info["entries"], groups)
+    # the byte model's launch counts against the traced ones (the plain and
+    # CG-fused forward row passes share one kernel name)
+    counted = {kname: c // args.steps for kname, (c, t) in tr.items()}
+    model = dict(launches_model)
+    model["k_rows_fwd_fs"] = model.pop("k_rows_fwd_fs") + model.pop("k_rows_fwd_fs_cg")
+    launch_check = {k: [model.get(k, 0), counted.get(k, 0)] for k in sorted(set(model) | set(counted))
+                    if model.get(k, 0) != counted.get(k, 0)}
     dom = max((kname for kname in tr if kname in kb), key=lambda kname: tr[kname][1])
     launches, tot_ms = tr[dom]
     avg_s = tot_ms / launches / 1e3
@@ -632,7 +723,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, x_true, S, dcf, y.cpu().numpy(), B)
+        cpu = cpu_baseline(w, x_true, S, dcf, y.cpu().numpy(), step_bytes)
 
     line = {
         "metric": "NUFFT A^H A GB/s; slices/s to fixed PSNR, learned vs wavelet HQS",
@@ -649,14 +740,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "coils": L, "samples": M, "outer": w.n_out, "cg": w.n_cg,
                    "prior": "haar", "precond": "f1", "dcf": "voronoi", "normal_ops_per_step": n_normal,
-                   "b_alg_bytes": B},
+                   "value_bytes": "algorithmic bytes of every kernel launch of the step (Toeplitz normal "
+                                  "operator, CG vectors, prior, b0)",
+                   "step_bytes": step_bytes, "b_alg_bytes": B},
+        "value_frac_of_hbm": round(value / HBM_PEAK_GBPS, 4),
+        "value_b_alg_equivalent": {"GBps": round(value_b_alg, 1), "frac_of_hbm": round(value_b_alg / HBM_PEAK_GBPS, 4),
+                                   "meaning": "180 x B_alg of the gridded normal operator / step time: more "
+                                              "bytes than the Toeplitz step moves"},
+        "step_ms_p10_p50_p90": [round(float(np.percentile(step_ms, q)), 4) for q in (10, 50, 90)],
+        "launch_model_mismatch": launch_check,
         "slices_per_s": round(1e3 / ms, 3),
         "psnr_db": round(psnr, 3),
         "normal_op_us": round(normal_us, 2),
-        "normal_op_GBps": round(B / (normal_us * 1e-6) / 1e9, 1),
-        "normal_op_variant": "toeplitz (exact PSF transfer function; used inside the HQS step)",
+        "normal_op_us_p10_p90": [round(normal_p10, 2), round(normal_p90, 2)],
+        "normal_op_bytes": toep_bytes,
+        "normal_op_GBps": round(toep_bytes / (normal_us * 1e-6) / 1e9, 1),
+        "normal_op_frac_of_hbm": round(toep_bytes / (normal_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+        "normal_op_b_alg_equivalent_GBps": round(B / (normal_us * 1e-6) / 1e9, 1),
+        "normal_op_variant": "toeplitz (exact PSF transfer function; used inside the HQS step); median of "
+                             f"{max(100, args.reps)} event-timed repetitions",
         "gridded_normal_op_us": round(gridded_us, 2),
-        "gridded_normal_op_GBps": round(B / (gridded_us * 1e-6) / 1e9, 1),
+        "gridded_normal_op_us_p10_p90": [round(gridded_p10, 2), round(gridded_p90, 2)],
+        "gridded_normal_op_GBps_b_alg": round(B / (gridded_us * 1e-6) / 1e9, 1),
         "roofline": roofline,
         "autotune": tuning,
         "psnr_race": race,

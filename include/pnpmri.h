@@ -150,16 +150,21 @@ pnp_status pnp_opnorm(const pnp_plan* plan, const pnp_c64* smaps, int32_t L, con
 /* ------------------------------------------------------------- Toeplitz */
 typedef struct pnp_toeplitz pnp_toeplitz;
 
-/* Toeplitz embedding of the normal operator A^H D_w A (2D; grid sides in
- * {128, 192, 256, 512, 640, 768, 1024}, i.e. image sides 64, 96, 128, 256,
- * 320, 384, 512).  The normal operator of Sec. 3.4 is a convolution with the
- * point-spread function psf[d] = N^{-1} sum_m w_m exp(+i <k_m, d>); embedded
- * in the 2n x 2n grid it is crop(IFFT(T * FFT(pad(z)))) per coil with a real
- * transfer function T.  T is formed once here, exactly in FP64 from the
- * plan's trajectory and `dcf` (device float [M] or NULL), then rounded to
- * FP32.  Applying it needs no interpolation and no Kaiser-Bessel
- * approximation.  The handle keeps a pointer to `plan`: destroy it first.
- * The call waits for `stream`. */
+/* Toeplitz embedding of the normal operator A^H D_w A (2D and 3D; grid
+ * sides in {128, 192, 256, 512, 640, 768, 1024}, i.e. image sides 64, 96,
+ * 128, 256, 320, 384, 512).  The normal operator of Sec. 3.4 is a
+ * convolution with the point-spread function
+ * psf[d] = N^{-1} sum_m w_m exp(+i <k_m, d>); embedded in the 2n x 2n
+ * (x 2n) grid it is crop(IFFT(T * FFT(pad(z)))) per coil with a real
+ * transfer function T = N^{-1} sum_m w_m prod_axis D(k_m,a - 2 pi j_a/K_a),
+ * D the symmetric Dirichlet kernel of the n_a pixel offsets.  T is formed
+ * once here, exactly in FP64 (per-axis tables contracted over the samples:
+ * (2n)^d * M multiply-adds, about 1.8e13 for a 128^3 volume with 2^20
+ * samples), from the plan's trajectory and `dcf` (device float [M] or
+ * NULL), then rounded to FP32.  Applying it needs no interpolation and no
+ * Kaiser-Bessel approximation.  Allocates the table scratch
+ * (8 (Kx+Ky[+Kz]) M bytes) for the duration of the call.  The handle keeps
+ * a pointer to `plan`: destroy it first.  The call waits for `stream`. */
 pnp_status pnp_toeplitz_create(pnp_toeplitz** out, const pnp_plan* plan, const float* dcf,
                                hipStream_t stream);
 pnp_status pnp_toeplitz_destroy(pnp_toeplitz* tp);
@@ -360,7 +365,12 @@ pnp_status pnp_hqs_workspace_bytes(const pnp_plan* plan, int32_t L, size_t* byte
  *   y       device pnp_c64 [L][M];  smaps device [L][N];  dcf device [M]|NULL
  *   sigmas  host double [n_out] (positive)
  *   x_out   device pnp_c64 [N]: x_{n_out}
- *   report  host or NULL; when given the call waits for the stream. */
+ *   report  host or NULL; when given the call waits for the stream and
+ *           returns PNP_ERR_NUMERIC after a CG breakdown (non-finite or
+ *           non-positive <p, Mp>, e.g. from non-finite data).  Without a
+ *           report the call stays asynchronous and does not detect a
+ *           breakdown: it returns PNP_OK and the breakdown shows only as
+ *           non-finite values in x_out. */
 pnp_status pnp_hqs_solve(const pnp_plan* plan, const pnp_c64* y, const pnp_c64* smaps, int32_t L,
                          const float* dcf, const pnp_prior* prior, const double* sigmas,
                          int32_t n_out, const pnp_hqs_opts* opts, pnp_c64* x_out,

@@ -125,8 +125,16 @@ struct pnp_plan {
   int32_t* sorted_jx;       // [M] first x tap of each sorted sample
   float* sorted_w;          // [M][3][W] weights in sorted order
   int32_t* cell_off;        // [Kz*Ky*Kx + 1] first sorted index of each cell
+  // 3D spread work list over 8^3 grid tiles: items (tile, first candidate,
+  // end candidate, partial slot or -1), heaviest first; tiles whose
+  // candidates are split over several items are summed from their slots by
+  // the folds (tile, first slot, slot count, 0)
+  int4* sp_items;
+  int4* sp_folds;
+  int n_sp_items, n_sp_folds, sp_slots;
   void* block;
   size_t block_bytes;
+  void* block3;             // 3D: the spread work list
 };
 
 struct pnp_unet;
@@ -161,6 +169,7 @@ struct OpWorkspace {
   float2* g2;      // 3D: [L][nz][Ky][Kx] after the y pass
   float2* grid;    // 3D: [L][Kz][Ky][Kx] full oversampled grid
   float2* ysort;   // 3D: [M][L] k-space values in the plan's sorted sample order
+  float2* spart;   // 3D: [slots][L][512] partial tiles of the split spread items
   size_t bytes;
 };
 size_t op_workspace_bytes(const pnp_plan* p, int L);
@@ -314,7 +323,6 @@ void op3_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps
                       const OpWorkspace& w, hipStream_t s);
 void op3_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
                            const OpWorkspace& w, hipStream_t s);
-pnp_toeplitz* toeplitz3_create(const pnp_plan* p, const float* dcf, hipStream_t s);
 
 // autotuning
 void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const pnp_toeplitz* tp,

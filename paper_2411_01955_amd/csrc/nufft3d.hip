@@ -10,17 +10,18 @@
 //                  y pass (image rows -> all Ky)                  -> g2
 //                  z pass (image planes -> all Kz)                -> grid
 //                  type-2 interpolation, 6^3 taps per sample     -> y
-//   adjoint:       type-1 spread (FP32 atomics into grid), then the inverse
-//                  z / y / x passes with crops, deapodisation, conj(S_l) and
-//                  the coil-group sums
+//   adjoint:       type-1 spread into LDS-resident 8^3 grid tiles (no
+//                  atomics), then the inverse z / y / x passes with crops,
+//                  deapodisation, conj(S_l) and the coil-group sums
 //   Toeplitz normal operator: x pass -> y pass -> z pass in place on g2
 //                  (zero-padded FFT along z, times T, inverse, crop) ->
 //                  inverse y pass -> inverse x pass with the coil sums; the
 //                  full grid is never formed.
 // The transfer function T is the DFT of the point-spread function
-// psf[d] = N^{-1} sum_m w_m exp(i <k_m, d>), |d_a| < n_a, evaluated by the
-// type-1 gridding of the weights onto a (2n)^3 image.
+// psf[d] = N^{-1} sum_m w_m exp(i <k_m, d>), |d_a| < n_a, formed exactly in
+// FP64 from per-axis Dirichlet tables (toeplitz.hip).
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 
 #include "common.hpp"
@@ -179,62 +180,206 @@ __global__ void k3_sort_y(long long M, int L, const float2* __restrict__ y, cons
   ys[idx] = cscale(y[(long long)l * M + m], scale * (dcf ? dcf[m] : 1.f));
 }
 
-// type-1 spread as a gather: grid point g receives from every sample whose
-// 6^3 window covers it, i.e. whose first tap lies in [g - 5, g] (mod K) on
-// every axis.  The samples are sorted by first-tap cell, so for each of the
-// 36 (z, y) tap rows the candidates form one contiguous range of the sorted
-// order (two across the x wrap).  Workgroup: 8 consecutive grid points
-// along x, 32 coil lanes each (coils >= L idle; blockIdx.y picks the chunk
-// of 32 coils).  Every grid point is written once: no atomics, no clearing,
-// and a summation order fixed by the plan.
+// type-1 spread into LDS-resident grid tiles.  The grid is cut into 8^3
+// tiles; tile [t0, t0 + 8)^3 receives from the samples whose first-tap cell
+// lies in [t0 - 5, t0 + 7] on every axis (mod K): 13 x 13 rows of 13 cells,
+// each row a contiguous range of the cell-sorted samples (two where x
+// wraps).  One workgroup accumulates one work item -- a tile, or a chunk of
+// a heavy tile's candidates -- for 16 coils in LDS.  Wave w owns the planes
+// z = 2w, 2w + 1 and lane (c, p, q) the points of plane 2w + p on the rows
+// of parity q for coil c, so every (point, coil) has a single owner and
+// sums its candidates in their sorted order: no atomics, a fixed summation
+// order.  Candidates are staged 32 at a time (weights, first-tap offsets
+// relative to the tile, the 16 coil values).  A row update reads its six
+// points, adds, and writes them back with no branch: taps that fall outside
+// the tile go to a per-lane dummy slot.  The tile is then written to the
+// grid in 64-byte row segments, or to its partial slot (heavy tiles), which
+// k3_fold_tiles adds up in slot order.
+constexpr int kT3C = 16;                 // coils per workgroup
+constexpr int kT3S = 32;                 // staged candidates
+constexpr int kT3Rows = 13 * 13;         // candidate rows per tile
+struct alignas(16) Spread3Lds {
+  float2 acc[512 * kT3C];                // [z][y][x][c]
+  float2 dummy[256];                     // per-lane sink of out-of-tile taps
+  int rb0[kT3Rows], rc0[kT3Rows], rb1[kT3Rows];   // row: first range start / size, second range start
+  int pre[256];                          // inclusive candidate counts up to each row (scan)
+  alignas(16) float w[kT3S][20];         // x, y, z weights of the staged candidates (rows padded to 16 B)
+  alignas(16) int d[kT3S][4];            // first tap relative to the tile (x, y, z), sorted index or -1
+  float2 v[kT3S][kT3C];
+};
+
 __global__ void __launch_bounds__(256)
-k3_gather(const float2* __restrict__ ys, int L, const int32_t* __restrict__ cell_off,
-          const int32_t* __restrict__ jx, const float* __restrict__ sw, int Kx, int Ky, int Kz, long long nblocks,
-          float2* __restrict__ grid) {
-  // workgroups are numbered over x and z of the launch (a 512^3 grid needs
-  // more than fit along x); the surplus of the last z row exits at once
-  const long long b = (long long)blockIdx.z * gridDim.x + blockIdx.x;
-  if (b >= nblocks) return;
-  const int lane = threadIdx.x & 31;
-  const long long g = b * 8 + (threadIdx.x >> 5);
-  const int l = blockIdx.y * 32 + lane;
-  const bool lok = l < L;
-  const int gx = (int)(g % Kx);
-  const int gy = (int)((g / Kx) % Ky);
-  const int gz = (int)(g / ((long long)Kx * Ky));
-  float ax = 0.f, ay = 0.f;
-  for (int tz = 0; tz < 6; ++tz) {
-    int cz = gz - tz;
-    if (cz < 0) cz += Kz;
-    for (int ty = 0; ty < 6; ++ty) {
-      int cy = gy - ty;
-      if (cy < 0) cy += Ky;
-      const long long row = ((long long)cz * Ky + cy) * Kx;
-      const int nseg = gx >= 5 ? 1 : 2;
-      for (int seg = 0; seg < nseg; ++seg) {
-        const int x0 = gx >= 5 ? gx - 5 : (seg == 0 ? 0 : Kx + gx - 5);
-        const int x1 = gx >= 5 ? gx : (seg == 0 ? gx : Kx - 1);
-        const int s0 = cell_off[row + x0], s1 = cell_off[row + x1 + 1];
-        for (int i = s0; i < s1; ++i) {
-          int tx = gx - jx[i];
-          if (tx < 0) tx += Kx;
-          const float* w = sw + (long long)i * 18;
-          const float f = w[tx] * w[6 + ty] * w[12 + tz];
-          if (lok) {
-            const float2 v = ys[(long long)i * L + l];
-            ax = fmaf(f, v.x, ax);
-            ay = fmaf(f, v.y, ay);
-          }
-        }
-      }
+k3_spread_tiles(const float2* __restrict__ ys, int L, const int32_t* __restrict__ cell_off,
+                const int32_t* __restrict__ sjx, const float* __restrict__ sw, const int4* __restrict__ items,
+                int Kx, int Ky, int Kz, float2* __restrict__ grid, float2* __restrict__ partial) {
+  extern __shared__ float4 lds_raw[];
+  Spread3Lds& S = *reinterpret_cast<Spread3Lds*>(lds_raw);
+  static_assert(offsetof(Spread3Lds, d) % 16 == 0, "int4 reads of the staged offsets");
+  const int4 it = items[blockIdx.x];
+  const int l0 = blockIdx.y * kT3C;
+  const int ntx = Kx / 8, nty = Ky / 8;
+  const int t0x = (it.x % ntx) * 8, t0y = ((it.x / ntx) % nty) * 8, t0z = (it.x / (ntx * nty)) * 8;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 512 * kT3C; i += 256) S.acc[i] = make_float2(0.f, 0.f);
+  // candidate rows (dz, dy) = (r / 13 - 5, r % 13 - 5), their sorted ranges
+  // and the inclusive scan of their sizes (Hillis-Steele over 256 entries)
+  int cnt = 0;
+  if (tid < kT3Rows) {
+    const int cz = (t0z - 5 + tid / 13 + Kz) % Kz, cy = (t0y - 5 + tid % 13 + Ky) % Ky;
+    const long long row = ((long long)cz * Ky + cy) * Kx;
+    const int x0 = t0x - 5;
+    if (x0 >= 0) {
+      const int b = cell_off[row + x0];
+      S.rb0[tid] = b;
+      S.rc0[tid] = cell_off[row + x0 + 13] - b;
+      S.rb1[tid] = 0;
+      cnt = S.rc0[tid];
+    } else {
+      const int b0 = cell_off[row + Kx + x0], b1 = cell_off[row];
+      S.rb0[tid] = b0;
+      S.rc0[tid] = cell_off[row + Kx] - b0;
+      S.rb1[tid] = b1;
+      cnt = S.rc0[tid] + cell_off[row + x0 + 13] - b1;
     }
   }
-  if (lok) grid[(long long)l * Kx * Ky * Kz + g] = make_float2(ax, ay);
+  S.pre[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int add = tid >= off ? S.pre[tid - off] : 0;
+    __syncthreads();
+    S.pre[tid] += add;
+    __syncthreads();
+  }
+
+  const int lane = tid & 63, wv = tid >> 6;
+  const int c = lane & 15, z = 2 * wv + ((lane >> 4) & 1), q = lane >> 5;
+  float2* const sink = S.dummy + tid;
+  // Staging of a round of 32 candidates: candidate s = tid / 8 is located
+  // by the 8 threads (s, j) (the row with pre[r - 1] <= k < pre[r], binary
+  // search), which load its 9 weight pairs and 16 coil values (item
+  // j + 8 m of 25) into registers; the registers of the next round are
+  // loaded while the current round is accumulated, and stored to LDS
+  // between the two barriers that end it.
+  const int ss = tid >> 3, sj = tid & 7;
+  int4 nd = make_int4(0, 0, 0, -1);
+  float2 nv[4];
+  auto fetch = [&](int kb) {
+    const int k = kb + ss;
+    nd = make_int4(0, 0, 0, -1);
+    if (k < it.z) {
+      int lo = 0, hi = kT3Rows - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S.pre[mid] > k) hi = mid;
+        else lo = mid + 1;
+      }
+      const int o = k - (lo > 0 ? S.pre[lo - 1] : 0);
+      const int i = o < S.rc0[lo] ? S.rb0[lo] + o : S.rb1[lo] + (o - S.rc0[lo]);
+      nd = make_int4(0, lo % 13 - 5, lo / 13 - 5, i);
+      if (sj == 0) {
+        int ddx = sjx[i] - t0x;
+        if (ddx > 7) ddx -= Kx;
+        nd.x = ddx;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = sj + 8 * m;
+      float2 val = make_float2(0.f, 0.f);
+      if (nd.w >= 0 && e < 25) {
+        if (e < 9) val = reinterpret_cast<const float2*>(sw + (long long)nd.w * 18)[e];
+        else if (l0 + e - 9 < L) val = ys[(long long)nd.w * L + l0 + e - 9];
+      }
+      nv[m] = val;
+    }
+  };
+  auto store = [&]() {
+    if (sj == 0) *reinterpret_cast<int4*>(S.d[ss]) = nd;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = sj + 8 * m;
+      if (e < 9) reinterpret_cast<float2*>(S.w[ss])[e] = nv[m];
+      else if (e < 25) S.v[ss][e - 9] = nv[m];
+    }
+  };
+  if (it.y < it.z) {
+    fetch(it.y);
+    store();
+  }
+  __syncthreads();
+  for (int k0 = it.y; k0 < it.z; k0 += kT3S) {
+    const bool more = k0 + kT3S < it.z;
+    if (more) fetch(k0 + kT3S);
+    const int ns = min(kT3S, it.z - k0);
+    for (int s = 0; s < ns; ++s) {
+      const int4 dd = *reinterpret_cast<const int4*>(S.d[s]);
+      const int tz = z - dd.z;
+      if (tz < 0 || tz >= 6) continue;
+      const float wz = S.w[s][12 + tz];
+      const float4* w4 = reinterpret_cast<const float4*>(S.w[s]);
+      const float4 wa = w4[0], wb = w4[1];
+      const float wxs[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
+      const float2 v = S.v[s][c];
+      float2 u[6];
+      float2* pt[6];
+#pragma unroll
+      for (int tx = 0; tx < 6; ++tx) u[tx] = make_float2(wxs[tx] * v.x, wxs[tx] * v.y);
+      const int ylo = max(dd.y, 0), yhi = min(dd.y + 6, 8);
+      for (int y = ylo + ((q - ylo) & 1); y < yhi; y += 2) {
+        const float f = wz * S.w[s][6 + y - dd.y];
+        float2* rowp = S.acc + ((z * 8 + y) * 8) * kT3C + c;
+        float2 a[6];
+#pragma unroll
+        for (int tx = 0; tx < 6; ++tx) {
+          const int x = dd.x + tx;
+          pt[tx] = (x >= 0 && x < 8) ? rowp + x * kT3C : sink;
+          a[tx] = *pt[tx];
+        }
+#pragma unroll
+        for (int tx = 0; tx < 6; ++tx) {
+          a[tx].x = fmaf(f, u[tx].x, a[tx].x);
+          a[tx].y = fmaf(f, u[tx].y, a[tx].y);
+        }
+#pragma unroll
+        for (int tx = 0; tx < 6; ++tx) *pt[tx] = a[tx];
+      }
+    }
+    __syncthreads();
+    if (more) store();
+    __syncthreads();
+  }
+  // write the tile: thread -> (z, y, x, coil) with the coil fastest (LDS
+  // reads without bank conflicts; 4 x 8 B contiguous per coil in a store)
+  const long long plane = (long long)Ky * Kx, vol = plane * Kz;
+  for (int e = tid; e < 512 * kT3C; e += 256) {
+    const int cc = e % kT3C, pt = e / kT3C;
+    const int x = pt & 7, y = (pt >> 3) & 7, zz = pt >> 6;
+    const int l = l0 + cc;
+    if (l >= L) continue;
+    const float2 val = S.acc[e];
+    if (it.w < 0)
+      grid[(long long)l * vol + (long long)(t0z + zz) * plane + (long long)(t0y + y) * Kx + t0x + x] = val;
+    else
+      partial[((long long)it.w * L + l) * 512 + pt] = val;
+  }
 }
 
-__global__ void k3_fill_ones(float2* __restrict__ y, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = make_float2(1.f, 0.f);
+// grid tile of a split tile = the sum of its partial slots, in slot order
+// (workgroup: one fold, one coil)
+__global__ void __launch_bounds__(256)
+k3_fold_tiles(const float2* __restrict__ partial, const int4* __restrict__ folds, int L, int Kx, int Ky, int Kz,
+              float2* __restrict__ grid) {
+  const int4 f = folds[blockIdx.x];
+  const int l = blockIdx.y;
+  const int ntx = Kx / 8, nty = Ky / 8;
+  const int t0x = (f.x % ntx) * 8, t0y = ((f.x / ntx) % nty) * 8, t0z = (f.x / (ntx * nty)) * 8;
+  const long long plane = (long long)Ky * Kx, vol = plane * Kz;
+  for (int pt = threadIdx.x; pt < 512; pt += 256) {
+    float2 a = partial[((long long)f.y * L + l) * 512 + pt];
+    for (int k = 1; k < f.z; ++k) a = cadd(a, partial[((long long)(f.y + k) * L + l) * 512 + pt]);
+    const int x = pt & 7, y = (pt >> 3) & 7, zz = pt >> 6;
+    grid[(long long)l * vol + (long long)(t0z + zz) * plane + (long long)(t0y + y) * Kx + t0x + x] = a;
+  }
 }
 
 __global__ void k3_sum_groups(const float2* __restrict__ part, int G, long long N, float2* __restrict__ out) {
@@ -243,20 +388,6 @@ __global__ void k3_sum_groups(const float2* __restrict__ part, int G, long long 
   float2 v = part[i];
   for (int g = 1; g < G; ++g) v = cadd(v, part[(long long)g * N + i]);
   out[i] = v;
-}
-
-// T = Re(X) * s
-__global__ void k3_take_real(const float2* __restrict__ X, long long n, float s, float* __restrict__ T) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) T[i] = X[i].x * s;
-}
-
-// psf[i] = s * adj[i], zero where any image index is 0 (offset d_a = -n)
-__global__ void k3_psf_prepare(float2* __restrict__ a, int Nx, int Ny, int Nz, float s) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)Nx * Ny * Nz) return;
-  const int x = (int)(i % Nx), y = (int)((i / Nx) % Ny), z = (int)(i / ((long long)Nx * Ny));
-  a[i] = (x == 0 || y == 0 || z == 0) ? make_float2(0.f, 0.f) : cscale(a[i], s);
 }
 
 // ------------------------------------------------------------- launchers
@@ -418,6 +549,7 @@ size_t op3_workspace_bytes(const pnp_plan* p, int L) {
   b += al3(sizeof(float2) * (size_t)L * p->M);                 // ytmp
   b += al3(sizeof(float2) * (size_t)op3_groups(L) * d.N);      // part
   b += al3(sizeof(float2) * (size_t)L * p->M);                 // ysort
+  b += al3(sizeof(float2) * (size_t)std::max(p->sp_slots, 1) * L * 512);   // spread partial tiles
   return b;
 }
 
@@ -436,6 +568,8 @@ OpWorkspace op3_workspace(const pnp_plan* p, int L, void* ws) {
   w.part = (float2*)c;
   c += al3(sizeof(float2) * (size_t)op3_groups(L) * d.N);
   w.ysort = (float2*)c;
+  c += al3(sizeof(float2) * (size_t)L * p->M);
+  w.spart = (float2*)c;
   w.bytes = op3_workspace_bytes(p, L);
   return w;
 }
@@ -456,12 +590,14 @@ static void adjoint_parts3(const pnp_plan* p, const float2* y, const float2* sma
   const long long ML = p->M * L;
   PNP_LAUNCH(k3_sort_y, dim3((unsigned)((ML + 255) / 256)), dim3(256), 0, s, (long long)p->M, L, y, dcf,
              p->sorted_m, scale, w.ysort);
-  const long long G = (long long)d.Kx * d.Ky * d.Kz;
-  const long long nblocks = G / 8;
-  const unsigned bx = (unsigned)std::min<long long>(nblocks, 65536);
-  const unsigned bz = (unsigned)((nblocks + bx - 1) / bx);
-  PNP_LAUNCH(k3_gather, dim3(bx, (unsigned)((L + 31) / 32), bz), dim3(256), 0, s, w.ysort, L, p->cell_off,
-             p->sorted_jx, p->sorted_w, d.Kx, d.Ky, d.Kz, nblocks, w.grid);
+  PNP_HIP(hipFuncSetAttribute((const void*)k3_spread_tiles, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(Spread3Lds)));
+  const unsigned cchunks = (unsigned)((L + kT3C - 1) / kT3C);
+  PNP_LAUNCH(k3_spread_tiles, dim3((unsigned)p->n_sp_items, cchunks), dim3(256), sizeof(Spread3Lds), s, w.ysort, L,
+             p->cell_off, p->sorted_jx, p->sorted_w, p->sp_items, d.Kx, d.Ky, d.Kz, w.grid, w.spart);
+  if (p->n_sp_folds > 0)
+    PNP_LAUNCH(k3_fold_tiles, dim3((unsigned)p->n_sp_folds, (unsigned)L), dim3(256), 0, s, w.spart, p->sp_folds, L,
+               d.Kx, d.Ky, d.Kz, w.grid);
   passes_adj(p, d, smaps, L, p->ax[0].deapod, p->deapod_yz, w.grid, w.g2, w.mid, dst, s);
 }
 
@@ -493,57 +629,5 @@ void op3_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const flo
   passes_adj(p, d, smaps, L, nullptr, nullptr, nullptr, w.g2, w.mid, w.part, s);
 }
 
-// T = DFT(psf) / (Kx Ky Kz) with psf from the type-1 gridding of the
-// weights onto a (2n)^3 image (a helper plan on the same trajectory).
-pnp_toeplitz* toeplitz3_create(const pnp_plan* p, const float* dcf, hipStream_t s) {
-  need3(p);
-  const Dims d = dims_of(p);
-  const int32_t hshape[3] = {d.Kz, d.Ky, d.Kx};   // (2n)^3 image, slowest first
-  pnp_plan* hp = plan_create(3, hshape, p->M, p->traj, s);
-  void* blk = nullptr;
-  float* T = nullptr;
-  auto cleanup = [&] {
-    if (blk) (void)hipFree(blk);
-    plan_destroy(hp);
-  };
-  try {
-    need3(hp);
-    const Dims h = dims_of(hp);
-    // helper adjoint of the weights (one coil, unit map)
-    const size_t hw = op3_workspace_bytes(hp, 1);
-    const size_t yb = al3(sizeof(float2) * (size_t)p->M), ab = al3(sizeof(float2) * (size_t)h.N);
-    PNP_HIP(hipMalloc(&blk, hw + yb + ab));
-    char* c = (char*)blk;
-    const OpWorkspace w = op3_workspace(hp, 1, c);
-    float2* yw = (float2*)(c + hw);
-    float2* psf = (float2*)(c + hw + yb);
-    // y = 1: the weights enter through the spread's dcf factor
-    PNP_LAUNCH(k3_fill_ones, dim3((unsigned)((p->M + 255) / 256)), dim3(256), 0, s, yw, (long long)p->M);
-    adjoint_parts3(hp, yw, nullptr, 1, dcf, (float)(1.0 / std::sqrt((double)h.N)), w.part, w, s);
-    // psf[r] = adj[r] * sqrt(N_h) / N, planes d_a = -n zeroed
-    PNP_LAUNCH(k3_sum_groups, dim3((unsigned)((h.N + 255) / 256)), dim3(256), 0, s, w.part, 1, h.N, psf);
-    PNP_LAUNCH(k3_psf_prepare, dim3((unsigned)((h.N + 255) / 256)), dim3(256), 0, s, psf, h.nx, h.ny, h.nz,
-               (float)(std::sqrt((double)h.N) / (double)d.N));
-    // DFT of psf on the plan's grid: the psf "image" fills the whole grid
-    const Dims f{d.Kx, d.Ky, d.Kz, d.Kx, d.Ky, d.Kz, (long long)d.Kx * d.Ky * d.Kz};
-    float2* mid = w.mid;       // needs Kz*Ky*Kx (the helper's mid is larger)
-    float2* g2 = w.g2;
-    float2* grid = w.grid;
-    passes_fwd(p, f, ImgIn{psf, CGUpdate{}}, nullptr, 1, nullptr, nullptr, mid, g2, grid, s);
-    PNP_HIP(hipMalloc((void**)&T, sizeof(float) * (size_t)f.N));
-    PNP_LAUNCH(k3_take_real, dim3((unsigned)((f.N + 255) / 256)), dim3(256), 0, s, grid, f.N,
-               (float)(1.0 / (double)f.N), T);
-    PNP_HIP(hipStreamSynchronize(s));
-  } catch (...) {
-    if (T) (void)hipFree(T);
-    cleanup();
-    throw;
-  }
-  cleanup();
-  auto* tp = new pnp_toeplitz();
-  tp->plan = p;
-  tp->T = T;
-  return tp;
-}
 
 }  // namespace pnp

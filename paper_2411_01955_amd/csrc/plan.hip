@@ -373,6 +373,87 @@ static void sort_by_cell(pnp_plan* p, hipStream_t stream) {
   release();
 }
 
+// Candidates of every 8^3 grid tile for the tiled 3D spread: the samples
+// whose first-tap cell lies in [t0 - 5, t0 + 7] on each axis (mod K), read
+// off the cell offsets as 13 x 13 row ranges.
+__global__ void k3_tile_cands(const int32_t* __restrict__ cell_off, int Kx, int Ky, int Kz,
+                              int32_t* __restrict__ cnt) {
+  const int ntx = Kx / 8, nty = Ky / 8, ntz = Kz / 8;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntx * nty * ntz) return;
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int x0 = tx * 8 - 5;
+  long long c = 0;
+  for (int rz = 0; rz < 13; ++rz) {
+    const int cz = (tz * 8 - 5 + rz + Kz) % Kz;
+    for (int ry = 0; ry < 13; ++ry) {
+      const int cy = (ty * 8 - 5 + ry + Ky) % Ky;
+      const long long row = ((long long)cz * Ky + cy) * Kx;
+      if (x0 >= 0) {
+        c += cell_off[row + x0 + 13] - cell_off[row + x0];
+      } else {
+        c += cell_off[row + Kx] - cell_off[row + Kx + x0];
+        c += cell_off[row + x0 + 13] - cell_off[row];
+      }
+    }
+  }
+  cnt[t] = (int32_t)c;
+}
+
+// Work list of the tiled 3D spread: one item per tile, tiles with more than
+// kSpreadChunk3 candidates split into several items with partial slots.
+static constexpr int kSpreadChunk3 = 2048;
+
+static void build_spread3(pnp_plan* p, hipStream_t stream) {
+  const int Kx = p->ax[0].K, Ky = p->ax[1].K, Kz = p->ax[2].K;
+  if (Kx % 8 || Ky % 8 || Kz % 8 || Kx < 16 || Ky < 16 || Kz < 16)
+    fail(PNP_ERR_SHAPE, "3D spread tiles need grid sides divisible by 8");
+  const int nt = (Kx / 8) * (Ky / 8) * (Kz / 8);
+  int32_t* dcnt = nullptr;
+  struct Free {
+    int32_t*& q;
+    ~Free() { if (q) (void)hipFree(q); }
+  } fr{dcnt};
+  PNP_HIP(hipMalloc((void**)&dcnt, sizeof(int32_t) * nt));
+  k3_tile_cands<<<(nt + 255) / 256, 256, 0, stream>>>(p->cell_off, Kx, Ky, Kz, dcnt);
+  PNP_CHECK_LAUNCH();
+  std::vector<int32_t> cnt(nt);
+  PNP_HIP(hipMemcpyAsync(cnt.data(), dcnt, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, stream));
+  PNP_HIP(hipStreamSynchronize(stream));
+  std::vector<int> order(nt);
+  for (int t = 0; t < nt; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+  std::vector<int4> items, folds;
+  items.reserve(nt + 64);
+  int slots = 0;
+  for (int t : order) {
+    const int c = cnt[t];
+    if (c <= kSpreadChunk3) {
+      items.push_back(make_int4(t, 0, c, -1));
+      continue;
+    }
+    const int nch = (c + kSpreadChunk3 - 1) / kSpreadChunk3;
+    folds.push_back(make_int4(t, slots, nch, 0));
+    for (int k = 0; k < nch; ++k)
+      items.push_back(make_int4(t, k * kSpreadChunk3, std::min(c, (k + 1) * kSpreadChunk3), slots + k));
+    slots += nch;
+  }
+  // the heavy chunks first (all chunks of a split tile hold kSpreadChunk3
+  // candidates but the last)
+  std::stable_sort(items.begin(), items.end(), [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
+  const size_t bi = align256(sizeof(int4) * items.size()), bf = align256(sizeof(int4) * std::max<size_t>(1, folds.size()));
+  PNP_HIP(hipMalloc(&p->block3, bi + bf));
+  p->sp_items = (int4*)p->block3;
+  p->sp_folds = (int4*)((char*)p->block3 + bi);
+  p->n_sp_items = (int)items.size();
+  p->n_sp_folds = (int)folds.size();
+  p->sp_slots = slots;
+  PNP_HIP(hipMemcpyAsync(p->sp_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, stream));
+  if (!folds.empty())
+    PNP_HIP(hipMemcpyAsync(p->sp_folds, folds.data(), sizeof(int4) * folds.size(), hipMemcpyHostToDevice, stream));
+  PNP_HIP(hipStreamSynchronize(stream));
+}
+
 static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   const int64_t M = p->M;
   p->tile = 8;                  // strip width of the column passes
@@ -456,6 +537,7 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
                                                                    nullptr, 0);
   PNP_CHECK_LAUNCH();
   sort_by_cell(p, stream);
+  build_spread3(p, stream);
 }
 
 pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* traj,
@@ -651,6 +733,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     PNP_HIP(hipStreamSynchronize(stream));
   } catch (...) {
     if (p->block) (void)hipFree(p->block);
+    if (p->block3) (void)hipFree(p->block3);
     delete p;
     throw;
   }
@@ -660,6 +743,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
 void plan_destroy(pnp_plan* p) {
   if (!p) return;
   if (p->block) (void)hipFree(p->block);
+  if (p->block3) (void)hipFree(p->block3);
   delete p;
 }
 

@@ -1,7 +1,9 @@
 """The learned prior inside annealed PnP-HQS (trained UNet, wavelet fallback).
 
 * parity: GPU UNet-HQS against the oracle's HQS with the oracle UNet (BF16
-  rounding mirrored).  The network's BF16 activations flip by one unit
+  rounding mirrored), at the clinical size over 6 outer iterations (the
+  timed race stops a slice at its first iteration reaching the PSNR target:
+  2.9 on average and at most 6 over the 100 held-out phantoms).  The network's BF16 activations flip by one unit
   wherever FP32 and FP64 values straddle a rounding boundary, so the
   learned solve is only as reproducible as the network: the oracle against
   itself, with its denoiser input jittered by 1e-6 (FP32-sized), differs by
@@ -64,7 +66,7 @@ def _oracle_unet_prior(params, kappa):
     return prior
 
 
-@pytest.mark.parametrize("cfg,n_out", [("tiny", 4), ("clinical", 2)])
+@pytest.mark.parametrize("cfg,n_out", [("tiny", 4), ("clinical", 6)])
 def test_learned_hqs_matches_oracle(pnp, net, cfg, n_out):
     w = synth.config_tiny() if cfg == "tiny" else synth.config_clinical()
     x, roi, S, k, dcf, y = _problem(w, 31)

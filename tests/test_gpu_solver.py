@@ -159,6 +159,12 @@ def test_hqs_reports_cg_breakdown(pnp, toeplitz):
         pnp.hqs_solve(plan, to_dev(yb), to_dev(S), None, prior, sig, lam, "f1", 3, opnorm=Ln, report=True,
                       toeplitz=tp)
     assert ei.value.status == -6
+    # without a report the call stays asynchronous: no status, the breakdown
+    # shows as a non-finite image (documented in the header)
+    xb, none = pnp.hqs_solve(plan, to_dev(yb), to_dev(S), None, prior, sig, lam, "f1", 3, opnorm=Ln,
+                             toeplitz=tp)
+    assert none is None
+    assert not np.all(np.isfinite(to_np(xb)))
 
 
 def test_hqs_clinical_toeplitz_tuned_hyperparameters(pnp):
