@@ -28,8 +28,18 @@
  *     1e-5 (KB alias error plus FP32 rounding).
  *   - Every pointer argument named *_dev / data array is DEVICE memory owned
  *     by the caller, unless marked "host".  The library never frees or keeps
- *     caller memory beyond the call.  Opaque handles (pnp_plan, pnp_prior)
- *     own their own device allocations, released by the matching destroy.
+ *     caller memory beyond the call.  The opaque handles (pnp_plan,
+ *     pnp_toeplitz, pnp_prior, pnp_unet, pnp_batch) allocate and own their
+ *     device tables -- the plan's sorted sample tables and twiddles, the
+ *     transfer function, the UNet weights, moments and the UNet prior's
+ *     forward buffers, the batch's work lists -- for the handle's lifetime,
+ *     released by the matching destroy.  These are built once per
+ *     trajectory, network or slice set; every per-call scratch buffer is the
+ *     caller's workspace (or, for pnp_normal_toeplitz_noalloc, the library's
+ *     static array).
+ *   - The gridding kernel is fixed: Kaiser-Bessel of width 6 at
+ *     oversampling 2 with Beatty's beta (13.855); there is no options
+ *     struct for it.
  *   - Every compute call is asynchronous on the given HIP stream and enqueues
  *     nothing when it returns an error.  Calls that return host scalars
  *     (pnp_opnorm, pnp_hqs_solve with a report or a computed norm) wait for
@@ -338,6 +348,10 @@ typedef struct {
   double rise_tol;           /* fallback when rho_k > (1+rise_tol) rho_{k-1}  */
   const pnp_toeplitz* toeplitz;  /* NULL: gridded normal operator; else the
                                     Toeplitz one (built with the same dcf)   */
+  int32_t k_start;           /* first outer iteration to run (0 <= k_start <
+                                n_out): resume a schedule from x0, e.g. the
+                                x_out of an earlier call that stopped at
+                                k_start; 0 when struct_size ends before it  */
 } pnp_hqs_opts;
 
 typedef struct {
@@ -353,7 +367,7 @@ pnp_status pnp_hqs_workspace_bytes(const pnp_plan* plan, int32_t L, size_t* byte
 
 /* Annealed preconditioned PnP-HQS (Sec. 3.3-3.4):
  *   b0 = A^H D_w y;  x = x0 (or b0)
- *   for k = 0..n_out-1:  gamma = lambda*sigma[k]
+ *   for k = k_start..n_out-1:  gamma = lambda*sigma[k]
  *       u = prox^P_{gamma f}(x) by exactly n_cg CG steps on
  *           (gamma A^H D_w A + P) u = P x + gamma b0, started at u = x
  *       x = D_{sigma[k]}(u)
@@ -363,9 +377,14 @@ pnp_status pnp_hqs_workspace_bytes(const pnp_plan* plan, int32_t L, size_t* byte
  * except the residual check of a prior with a fallback: the host waits for
  * each rho_k while the next iteration's CG already runs).
  *   y       device pnp_c64 [L][M];  smaps device [L][N];  dcf device [M]|NULL
- *   sigmas  host double [n_out] (positive)
+ *   sigmas  host double [n_out] (positive from k_start on): the whole
+ *           schedule; a call with k_start > 0 runs its tail, so splitting a
+ *           schedule over several calls (each resuming from the previous
+ *           x_out) gives the same iterates as one call
  *   x_out   device pnp_c64 [N]: x_{n_out}
- *   report  host or NULL; when given the call waits for the stream and
+ *   report  host or NULL (its arrays are indexed by the outer iteration k;
+ *           entries below k_start are left as they are); when given the
+ *           call waits for the stream and
  *           returns PNP_ERR_NUMERIC after a CG breakdown (non-finite or
  *           non-positive <p, Mp>, e.g. from non-finite data).  Without a
  *           report the call stays asynchronous and does not detect a

@@ -302,9 +302,12 @@ class WaveletPrior:
 
 def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str = "f1", n_cg: int = 5,
               opnorm: float = 0.0, opnorm_iters: int = 50, opnorm_seed: int = 0, x0=None,
-              report: bool = False, out=None, rise_tol: float = 0.0, toeplitz: "Toeplitz" = None):
+              report: bool = False, out=None, rise_tol: float = 0.0, toeplitz: "Toeplitz" = None,
+              k_start: int = 0):
     """Annealed preconditioned PnP-HQS; returns (x, report dict or None).
-    With ``toeplitz`` the CG steps use the Toeplitz normal operator."""
+    With ``toeplitz`` the CG steps use the Toeplitz normal operator.  With
+    ``k_start`` > 0 only iterations k_start.. of the schedule run, from
+    ``x0`` (resume); the report lists those iterations."""
     torch = _torch()
     L = plan._L(smaps)
     _need_c64(y, "y", (L, plan.M))
@@ -317,7 +320,7 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
         raise ValueError("toeplitz was built for another plan")
     o = HQSOpts(C.sizeof(HQSOpts), PRECOND[precond.lower()], int(n_cg), int(opnorm_iters), float(lam),
                 float(opnorm), int(opnorm_seed), x0.data_ptr() if x0 is not None else None, float(rise_tol),
-                toeplitz.handle.value if toeplitz is not None else None)
+                toeplitz.handle.value if toeplitz is not None else None, int(k_start))
     x = out if out is not None else torch.empty(plan.shape, dtype=torch.complex64, device=y.device)
     _need_c64(x, "out", plan.shape)
     ws, nb = plan.workspace(L, "hqs")
@@ -330,7 +333,7 @@ def hqs_solve(plan: Plan, y, smaps, dcf, prior, sigmas, lam: float, precond: str
     check(load().pnp_hqs_solve(plan.handle, _ptr(y), _ptr(smaps), L, _ptr(dcf), prior.handle, sig, n_out,
                                C.byref(o), _ptr(x), rep_p, _ptr(ws), nb, _stream()))
     if report:
-        return x, {"rho": list(rho), "fallback": list(fb), "opnorm": rep.opnorm_used}
+        return x, {"rho": list(rho)[k_start:], "fallback": list(fb)[k_start:], "opnorm": rep.opnorm_used}
     return x, None
 
 

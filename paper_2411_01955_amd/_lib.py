@@ -29,6 +29,7 @@ class HQSOpts(C.Structure):
         ("x0", C.c_void_p),
         ("rise_tol", C.c_double),
         ("toeplitz", C.c_void_p),
+        ("k_start", C.c_int32),
     ]
 
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -365,12 +366,15 @@ pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* sma
     need(opts, "opts");
     need(x_out, "x_out");
     need(ws, "ws");
-    if (opts->struct_size < sizeof(pnp_hqs_opts)) fail(PNP_ERR_ARG, "opts.struct_size too small");
+    if (opts->struct_size < offsetof(pnp_hqs_opts, k_start)) fail(PNP_ERR_ARG, "opts.struct_size too small");
+    const int32_t k_start =
+        opts->struct_size >= offsetof(pnp_hqs_opts, k_start) + sizeof(int32_t) ? opts->k_start : 0;
     if (n_out < 1) fail(PNP_ERR_SHAPE, "n_out must be >= 1");
+    if (k_start < 0 || k_start >= n_out) fail(PNP_ERR_ARG, "k_start %d outside [0, n_out = %d)", k_start, n_out);
     if (opts->precond < 0 || opts->precond > 2) fail(PNP_ERR_ARG, "unknown preconditioner %d", opts->precond);
     if (opts->n_cg < 1) fail(PNP_ERR_ARG, "n_cg must be >= 1");
     if (!(opts->lambda > 0.0) || !std::isfinite(opts->lambda)) fail(PNP_ERR_ARG, "lambda must be > 0");
-    for (int k = 0; k < n_out; ++k)
+    for (int k = k_start; k < n_out; ++k)
       if (!(sigmas[k] > 0.0) || !std::isfinite(sigmas[k])) fail(PNP_ERR_ARG, "sigma[%d] must be > 0", k);
     if (report) {
       if (report->struct_size < sizeof(pnp_hqs_report)) fail(PNP_ERR_ARG, "report.struct_size too small");
@@ -395,8 +399,8 @@ pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* sma
     a.L = L;
     a.dcf = dcf;
     a.prior = prior;
-    a.sigmas = sigmas;
-    a.n_out = n_out;
+    a.sigmas = sigmas + k_start;
+    a.n_out = n_out - k_start;
     a.precond = opts->precond;
     a.n_cg = opts->n_cg;
     a.lambda = opts->lambda;
@@ -408,8 +412,8 @@ pnp_status pnp_hqs_solve(const pnp_plan* p, const pnp_c64* y, const pnp_c64* sma
     if (prior->fallback && (!(opts->rise_tol >= 0.0) || !std::isfinite(opts->rise_tol)))
       fail(PNP_ERR_ARG, "rise_tol must be finite and >= 0 for a prior with a fallback");
     int bad = 0;
-    hqs_solve(p, a, ws, stream, report ? report->rho : nullptr, report ? &bad : nullptr,
-              report ? report->fallback : nullptr);
+    hqs_solve(p, a, ws, stream, report ? report->rho + k_start : nullptr, report ? &bad : nullptr,
+              report && report->fallback ? report->fallback + k_start : nullptr);
     if (report) {
       report->opnorm_used = nrm;
       if (bad) fail(PNP_ERR_NUMERIC, "CG breakdown (non-positive or non-finite <p, Mp>)");

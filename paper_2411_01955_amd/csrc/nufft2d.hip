@@ -9,8 +9,10 @@
 //                     whose footprint touches the strip) -> per-entry partials
 //     k_gather_entries  y_l[m] = N^{-1/2} * sum of the sample's partials
 //   adjoint  A^H D_w y
-//     cols_adj        strip: type-1 spread of w_m y_l[m] into LDS (LDS
-//                     atomics), column inverse FFT, keep the ny image rows
+//     cols_adj        strip: type-1 spread of w_m y_l[m] as a gather (each
+//                     wave sums the row-sorted entries of its 8 x 8 grid
+//                     blocks in registers, no atomics) into the strip in LDS,
+//                     column inverse FFT, keep the ny image rows
 //                     -> mid[l][iy][Kx]
 //     rows_adj        row inverse FFT, crop, deapod, conj(S_l), sum over the
 //                     coils of the workgroup -> per-coil-group partial images

@@ -80,8 +80,22 @@ def test_prior_validation_and_lifecycle(lib):
     assert lib.pnp_prior_destroy(h) == 0
 
 
-def test_struct_sizes_match_header():
-    from paper_2411_01955_amd._lib import HQSOpts, HQSReport
-    # uint32 + 3 int32 + 2 double + uint64 + pointer + double + pointer
-    assert C.sizeof(HQSOpts) == 64
-    assert C.sizeof(HQSReport) == 32
+def test_struct_sizes_match_header(tmp_path):
+    """Sizes and field offsets of the ABI structs: the C header as compiled
+    by the host compiler (tests/host/abi_layout.cpp) against the ctypes
+    binding."""
+    import subprocess
+    from paper_2411_01955_amd._lib import HQSOpts, HQSReport, Slice, Tuning
+    exe = str(tmp_path / "abi_layout")
+    src = os.path.join(ROOT, "tests", "host", "abi_layout.cpp")
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", src, "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([exe], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    structs = {"pnp_hqs_opts": HQSOpts, "pnp_hqs_report": HQSReport, "pnp_slice": Slice, "pnp_tuning": Tuning}
+    for key, val in got.items():
+        name, _, field = key.partition(".")
+        T = structs[name]
+        want = C.sizeof(T) if not field else getattr(T, {"lambda": "lam"}.get(field, field)).offset
+        assert int(val) == want, (key, val, want)

@@ -173,3 +173,26 @@ def test_hqs_clinical_toeplitz_tuned_hyperparameters(pnp):
     e, e_rho = _hqs_case(pnp, synth.config_clinical(), 4, "f1", 1e4, 0.75, n_out=3, toeplitz=True)
     assert e < 1e-4
     assert e_rho < 1e-3
+
+
+@pytest.mark.parametrize("toeplitz", [False, True])
+def test_hqs_resume_with_k_start_equals_one_call(pnp, toeplitz):
+    """A schedule split over two calls -- iterations 0..2, then 3..5 resumed
+    from the first call's image with k_start = 3 -- gives the image and the
+    residuals of one 6-iteration call bit for bit (same kernels, same
+    inputs: the resumed call starts from N x0 as the single call does)."""
+    w = synth.config_tiny()
+    x, roi, S, k, dcf, y = _problem(w, 8)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    tp = pnp.Toeplitz(plan) if toeplitz else None
+    Ln = plan.opnorm(to_dev(S), None, iters=200, seed=1)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, 6)
+    args = (plan, to_dev(y), to_dev(S), None, pnp.WaveletPrior(0, 0.5))
+    x_all, rep_all = pnp.hqs_solve(*args, sig, 3e4 / Ln, "f1", w.n_cg, opnorm=Ln, toeplitz=tp, report=True)
+    x_a, rep_a = pnp.hqs_solve(*args, sig[:3], 3e4 / Ln, "f1", w.n_cg, opnorm=Ln, toeplitz=tp, report=True)
+    x_b, rep_b = pnp.hqs_solve(*args, sig, 3e4 / Ln, "f1", w.n_cg, opnorm=Ln, toeplitz=tp, report=True,
+                               x0=x_a.clone(), k_start=3)
+    assert np.array_equal(to_np(x_b), to_np(x_all))
+    assert rep_a["rho"] + rep_b["rho"] == rep_all["rho"]
+    with pytest.raises(pnp.PnPError):
+        pnp.hqs_solve(*args, sig, 3e4 / Ln, "f1", w.n_cg, opnorm=Ln, toeplitz=tp, x0=x_a, k_start=6)
