@@ -450,7 +450,10 @@ pnp_status pnp_fista_wavelet(const pnp_plan* plan, const pnp_c64* y, const pnp_c
  * else the gridded one with `dcf` -- on this device (after a warm-up, in
  * interleaved rounds): first each adjoint choice with the forward one at 4,
  * then each forward choice with the adjoint one fixed.  Each keeps the
- * default 4 unless another choice is more than 2% faster.  The choices are
+ * default 4 unless another choice is more than 2% faster.  It then times
+ * the gridded adjoint (with `dcf`) for the 12 spread settings of
+ * pnp_plan_set_spread and keeps the default unless another is more than 2%
+ * faster.  The choices are
  * stored in the plan and appended to the JSON-lines file `cache_path`
  * (NULL: no cache), keyed by device, image shape, L, M, a hash of the
  * histogram of gridding entries per column strip, and the operator kind.  A
@@ -470,11 +473,31 @@ typedef struct {
   int32_t from_cache;        /* out: 1 when the choice came from the cache    */
   int32_t row_coils_fwd;     /* out: chosen coils per workgroup, forward pass */
   double time_fwd_us[3];     /* out: operator time, forward 2, 4, 8 (0 if cached) */
+  int32_t spread_split;      /* out: chosen split level of the adjoint spread */
+  int32_t spread_dense_min;  /* out: chosen dense-block threshold            */
+  double time_spread_us[12]; /* out: gridded adjoint time for split 0..3 x
+                                threshold 128, 256, 512 (0 if cached)        */
 } pnp_tuning;
 
 pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const float* dcf,
                         const pnp_toeplitz* toeplitz, const char* cache_path, pnp_tuning* out,
                         hipStream_t stream);
+/* The type-1 spread of the 2D adjoint (the column pass that gathers the
+ * weighted samples into each 8-column strip of the oversampled grid before
+ * its inverse FFT) runs one workgroup per strip, except that the strips
+ * with the most work (the k-space centre; 32 parts in all at most) are
+ * split into up to 8 parts, part p taking every P-th chunk of the strip's
+ * entries; each part is a workgroup of its own, and the parts' partial
+ * strips are added in part order before the strip's inverse FFT.  `split`
+ * 0 never splits; 1, 2, 3 aim at parts of about 4, 2 and 1 times the median
+ * strip's work.  Row blocks whose window holds
+ * `dense_min` or more entries are shared by all waves of their workgroup.
+ * Defaults: split 0, dense_min 128; pnp_autotune sweeps split 0..3 x
+ * dense_min 128, 256, 512 on the gridded adjoint.  Every choice gives the
+ * same results up to floating-point summation order.  2D plans only;
+ * pnp_plan_set_spread waits for `stream`. */
+pnp_status pnp_plan_set_spread(pnp_plan* plan, int32_t split, int32_t dense_min, hipStream_t stream);
+pnp_status pnp_plan_get_spread(const pnp_plan* plan, int32_t* split, int32_t* dense_min);
 pnp_status pnp_plan_set_row_coils(pnp_plan* plan, int32_t row_coils);
 pnp_status pnp_plan_get_row_coils(const pnp_plan* plan, int32_t* row_coils);
 pnp_status pnp_plan_set_row_coils_pair(pnp_plan* plan, int32_t forward, int32_t adjoint);

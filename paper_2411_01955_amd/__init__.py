@@ -196,6 +196,18 @@ class Plan:
         f, a = value
         check(load().pnp_plan_set_row_coils_pair(self._h, int(f), int(a)))
 
+    @property
+    def spread(self):
+        """(split level 0..3, dense-block threshold) of the 2D adjoint spread."""
+        a, b = C.c_int32(), C.c_int32()
+        check(load().pnp_plan_get_spread(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    @spread.setter
+    def spread(self, value):
+        split, dense_min = value
+        check(load().pnp_plan_set_spread(self._h, int(split), int(dense_min), _stream()))
+
     def autotune(self, smaps, dcf=None, toeplitz=None, cache=None):
         """Time the normal operator for 2, 4 and 8 coils per row-pass
         workgroup, the adjoint pass first and then the forward one, and keep
@@ -210,7 +222,9 @@ class Plan:
                                   toeplitz.handle if toeplitz is not None else None,
                                   cache.encode() if cache else None, C.byref(t), _stream()))
         return {"row_coils": t.row_coils, "row_coils_fwd": t.row_coils_fwd, "time_us": list(t.time_us),
-                "time_fwd_us": list(t.time_fwd_us), "from_cache": bool(t.from_cache)}
+                "time_fwd_us": list(t.time_fwd_us), "from_cache": bool(t.from_cache),
+                "spread_split": t.spread_split, "spread_dense_min": t.spread_dense_min,
+                "time_spread_us": list(t.time_spread_us)}
 
     def opnorm(self, smaps, dcf=None, iters=50, seed=0):
         L = self._L(smaps)

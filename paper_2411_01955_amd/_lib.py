@@ -66,6 +66,9 @@ class Tuning(C.Structure):
         ("from_cache", C.c_int32),
         ("row_coils_fwd", C.c_int32),
         ("time_fwd_us", C.c_double * 3),
+        ("spread_split", C.c_int32),
+        ("spread_dense_min", C.c_int32),
+        ("time_spread_us", C.c_double * 12),
     ]
 
 
@@ -106,6 +109,8 @@ SIGNATURES = {
     "pnp_toeplitz_create": (_i32, [C.POINTER(_vp), _vp, _vp, _vp]),
     "pnp_toeplitz_destroy": (_i32, [_vp]),
     "pnp_normal_toeplitz": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "pnp_plan_set_spread": (_i32, [_vp, _i32, _i32, _vp]),
+    "pnp_plan_get_spread": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
     "pnp_noalloc_scratch_bytes": (_i32, [C.POINTER(_sz)]),
     "pnp_normal_toeplitz_noalloc": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "pnp_prior_wavelet": (_i32, [C.POINTER(_vp), _i32, _dbl]),

@@ -714,6 +714,24 @@ pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const f
   });
 }
 
+pnp_status pnp_plan_set_spread(pnp_plan* plan, int32_t split, int32_t dense_min, hipStream_t stream) {
+  return guarded([&] {
+    need(plan, "plan");
+    plan_set_spread(plan, split, dense_min, stream);
+  });
+}
+
+pnp_status pnp_plan_get_spread(const pnp_plan* plan, int32_t* split, int32_t* dense_min) {
+  return guarded([&] {
+    need(plan, "plan");
+    need(split, "split");
+    need(dense_min, "dense_min");
+    if (plan->ndim != 2) fail(PNP_ERR_UNSUPPORTED, "the spread split applies to 2D plans");
+    *split = plan->adj_split;
+    *dense_min = plan->adj_dense_min;
+  });
+}
+
 pnp_status pnp_plan_set_row_coils(pnp_plan* plan, int32_t row_coils) {
   return guarded([&] {
     need(plan, "plan");

@@ -1,6 +1,8 @@
 // Internal definitions shared by the library's translation units.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -132,6 +134,15 @@ struct pnp_plan {
   int4* sp_items;
   int4* sp_folds;
   int n_sp_items, n_sp_folds, sp_slots;
+  // 2D adjoint spread work items (strip, part, parts, first slot or -1),
+  // heaviest first, and the split strips (strip, first slot, parts, 0);
+  // built from the per-(strip, row block) window entry counts adj_cost for
+  // a split level and a dense-block threshold (tuned)
+  int4* adj_items;
+  int4* adj_splits;
+  int n_adj_items, n_adj_splits;
+  int adj_split, adj_dense_min;
+  std::vector<int32_t> adj_cost;   // host [ntx][K_y / 8]
   void* block;
   size_t block_bytes;
   void* block3;             // 3D: the spread work list
@@ -169,7 +180,7 @@ struct OpWorkspace {
   float2* g2;      // 3D: [L][nz][Ky][Kx] after the y pass
   float2* grid;    // 3D: [L][Kz][Ky][Kx] full oversampled grid
   float2* ysort;   // 3D: [M][L] k-space values in the plan's sorted sample order
-  float2* spart;   // 3D: [slots][L][512] partial tiles of the split spread items
+  float2* spart;   // [L][slots][K_y][8] partial strips of the split 2D spread; 3D: [slots][L][512] partial tiles
   size_t bytes;
 };
 size_t op_workspace_bytes(const pnp_plan* p, int L);
@@ -177,6 +188,13 @@ OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws);
 // PNP_ERR_UNSUPPORTED when the 2D passes of plan p need more LDS than a
 // workgroup has (checked when the plan is created)
 void nufft2d_check_plan(const pnp_plan* p);
+// 2D adjoint spread: heavy strips are split into parts (kMaxAdjSlots parts
+// over all strips at most); adj_build_items rebuilds the plan's work items
+// for a split level (0: no split; 1, 2, 3: parts of about 4, 2, 1 times the
+// median strip's work) and the dense-block threshold, and waits for `s`
+constexpr int kMaxAdjSlots = 32;
+void adj_build_items(pnp_plan* p, int split, int dense_min, hipStream_t s);
+void plan_set_spread(pnp_plan* p, int split, int dense_min, hipStream_t s);
 
 void op_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y,
                 const OpWorkspace& w, hipStream_t s);

@@ -23,6 +23,7 @@
 // all others the LDS Stockham kernels.  Pixel r = i - n/2 sits at grid index
 // r mod K; grid index j is frequency j (mod K).
 #include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 #include "fft_lds.hpp"
@@ -317,17 +318,21 @@ constexpr int kAdjThreads = 512;    // spread uses all waves, the FFT the first 
 constexpr int kAdjWaves = kAdjThreads / 64;
 constexpr int kSpreadIlp = 8;       // entries in flight per lane in the gather loop
 constexpr int kMaxDense = 4;        // dense row blocks per strip shared by all waves
-constexpr int kDenseMin = 256;      // entries in a row block's window that make it dense
 static_assert(kMaxDense * kAdjWaves * 64 * sizeof(float2) <= kSpreadChunk * sizeof(EntryRec),
               "dense-block partial sums fit in the entry staging buffer");
 
-// Type-1 spread by gathering: wave w owns the 8x8 grid-point blocks
+// Type-1 spread by gathering: a work item is a strip of 8 grid columns --
+// the whole strip, or part p of P of a heavy strip (the k-space centre),
+// which takes every P-th staged chunk of the strip's entries starting at
+// chunk p; the parts run as separate workgroups, write partial grid strips
+// to their slots of `spart`, and k_cols_adj_fin_fs adds them in part order
+// and transforms the strip.  Wave w owns the 8x8 grid-point blocks
 // (rows 8*rb .. 8*rb+7 of the strip's 8 columns) with rb = w, w + 8, ...;
 // lane (row lr = lane/8, column lc = lane%8) accumulates in registers every
 // entry whose first row tap lies within 5 rows above its block (entries are
 // sorted by first row tap, row_start indexes them), reading the entry's taps,
 // weights and weighted k-space value from LDS as broadcasts.  Up to
-// kMaxDense blocks whose window holds kDenseMin or more entries (the densely
+// kMaxDense blocks whose window holds dense_min or more entries (the densely
 // sampled k-space centre) are shared by all waves instead: each wave takes a
 // fixed slice of every staged chunk of the block's entries, and the eight
 // partial sums are added in wave order.  Each grid point is written once: no
@@ -337,8 +342,8 @@ __global__ void __launch_bounds__(kAdjThreads)
 k_cols_adj_fs(const float2* __restrict__ yent, long long E,
               int nx, int ny, int Kx, const float2* __restrict__ tw, int tile,
               const int* __restrict__ tile_off, const int* __restrict__ row_start,
-              const int* __restrict__ tile_order, const EntryRec* __restrict__ rec,
-              float2* __restrict__ mid) {
+              const int4* __restrict__ items, int dense_min, const EntryRec* __restrict__ rec,
+              float2* __restrict__ mid, float2* __restrict__ spart, int nslots) {
   using F = FS<K1, K2>;
   constexpr int NRB = F::K / 8;                                  // row blocks per strip
   constexpr int RBW = (NRB + kAdjWaves - 1) / kAdjWaves;         // row blocks per wave
@@ -349,7 +354,8 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   __shared__ int sdense[kMaxDense + 1];                          // count, then row blocks
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;           // FFT threads: t < K1
-  const int s = tile_order[blockIdx.y];    // strips by descending entry count; coils of a strip adjacent
+  const int4 item = items[blockIdx.y];     // (strip, part, parts, first slot); heaviest first, coils adjacent
+  const int s = item.x;
   const int l = blockIdx.x;
   const int c0 = s * tile;
   const bool colok = c < tile && t < K1;
@@ -374,7 +380,7 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
     for (int rb = 0; rb < NRB && nd < kMaxDense; ++rb) {
       int ra0, rb0, ra1, rb1;
       window(rb, ra0, rb0, ra1, rb1);
-      if ((rb0 - ra0) + (rb1 - ra1) >= kDenseMin) sdense[1 + nd++] = rb;
+      if ((rb0 - ra0) + (rb1 - ra1) >= dense_min) sdense[1 + nd++] = rb;
     }
     sdense[0] = nd;
   }
@@ -385,7 +391,7 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   for (int d = 0; d < kMaxDense; ++d) accd[d] = make_float2(0.f, 0.f);
   const int e0 = tile_off[s], e1 = tile_off[s + 1];
   const float* srec_f = reinterpret_cast<const float*>(srec);
-  int cb = e0;
+  int cb = e0 + item.y * kSpreadChunk;
   // entries [ea, eb) of the staged chunk starting at cb into grid point
   // (row, gc): kSpreadIlp independent entries per step, all LDS reads of a
   // step issued before any is consumed; out-of-range entries are clamped to a
@@ -425,7 +431,7 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
       }
     }
   };
-  for (; cb < e1; cb += kSpreadChunk) {
+  for (; cb < e1; cb += item.z * kSpreadChunk) {
     const int n = min(kSpreadChunk, e1 - cb);
     __syncthreads();  // previous chunk consumed (and the dense list written)
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -487,6 +493,59 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
       sum = make_float2(sum.x + v.x, sum.y + v.y);
     }
     if (lc < tile) lds[lc * F::GS + sdense[1 + wave] * 8 + lr] = sum;
+  }
+  __syncthreads();
+  if (item.w >= 0) {
+    // a part: its partial grid strip to slot item.w + part (row-major, 8 columns)
+    float2* sp = spart + ((long long)l * nslots + item.w + item.y) * F::K * 8;
+    for (int i = threadIdx.x; i < F::K * 8; i += blockDim.x) sp[i] = lds[(i & 7) * F::GS + (i >> 3)];
+    return;
+  }
+  float2 v[K1];
+  if (colok && t < K2) {
+#pragma unroll
+    for (int n1 = 0; n1 < K1; ++n1) v[n1] = lds[c * F::GS + n1 * K2 + t];
+  }
+  __syncthreads();
+  if (colok && t < K2) {
+    reg::dft<K1, true>(v);
+    fs_twiddle<K1, K2, true>(v, t, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];
+  }
+  __syncthreads();
+  if (colok) {
+    float2 u[K2];
+#pragma unroll
+    for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
+    reg::dft<K2, true>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) {
+      const int iy = img_of_grid(t + K1 * k2, ny, F::K);
+      if (iy >= 0) mid[((long long)l * ny + iy) * Kx + c0 + c] = u[k2];
+    }
+  }
+}
+
+// grid strips of split items: the parts' partial strips added in part order,
+// then the column inverse FFT and the image rows
+template <int K1, int K2>
+__global__ void __launch_bounds__(8 * K1)
+k_cols_adj_fin_fs(const float2* __restrict__ spart, int nslots, const int4* __restrict__ splits, int ny, int Kx,
+                  const float2* __restrict__ tw, int tile, float2* __restrict__ mid) {
+  using F = FS<K1, K2>;
+  __shared__ float2 lds[8 * F::CSTR];
+  const int l = blockIdx.x;
+  const int4 sp = splits[blockIdx.y];      // (strip, first slot, parts, 0)
+  const int c = threadIdx.x % 8;
+  const int t = threadIdx.x / 8;
+  const int c0 = sp.x * tile;
+  const bool colok = c < tile;
+  const float2* src = spart + ((long long)l * nslots + sp.y) * F::K * 8;
+  for (int i = threadIdx.x; i < F::K * 8; i += blockDim.x) {
+    float2 a = src[i];
+    for (int q = 1; q < sp.z; ++q) a = cadd(a, src[(long long)q * F::K * 8 + i]);
+    lds[(i & 7) * F::GS + (i >> 3)] = a;
   }
   __syncthreads();
   float2 v[K1];
@@ -689,10 +748,13 @@ struct FSLaunch {
                p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off, p->rec,
                (long long)p->E, ypart);
   }
-  static void cols_adj(const pnp_plan* p, int L, const float2* yent, float2* mid, hipStream_t s) {
-    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(L, p->ntx), dim3(kAdjThreads), 0, s, yent, (long long)p->E,
+  static void cols_adj(const pnp_plan* p, int L, const float2* yent, float2* mid, float2* spart, hipStream_t s) {
+    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(L, p->n_adj_items), dim3(kAdjThreads), 0, s, yent, (long long)p->E,
                p->ax[0].n, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off,
-               p->row_start, p->tile_order, p->rec, mid);
+               p->row_start, p->adj_items, p->adj_dense_min, p->rec, mid, spart, kMaxAdjSlots);
+    if (p->n_adj_splits > 0)
+      PNP_LAUNCH((k_cols_adj_fin_fs<K1, K2>), dim3(L, p->n_adj_splits), dim3(8 * K1), 0, s, spart, kMaxAdjSlots,
+                 p->adj_splits, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, mid);
   }
   static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                        hipStream_t s) {
@@ -757,6 +819,7 @@ size_t op_workspace_bytes(const pnp_plan* p, int L) {
   b += al(sizeof(float2) * (size_t)L * p->M);             // ytmp
   b += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));  // yent
   b += al(sizeof(float2) * (size_t)G * N);                 // part
+  b += al(sizeof(float2) * (size_t)L * kMaxAdjSlots * p->ax[1].K * 8);   // split strips of the spread
   return b;
 }
 
@@ -777,8 +840,56 @@ OpWorkspace op_workspace(const pnp_plan* p, int L, void* ws) {
   c += al(sizeof(float2) * (size_t)L * (size_t)std::max<int64_t>(p->E, 1));
   w.part = (float2*)c;
   c += al(sizeof(float2) * (size_t)G * N);
+  w.spart = (float2*)c;
+  c += al(sizeof(float2) * (size_t)L * kMaxAdjSlots * p->ax[1].K * 8);
   w.bytes = (size_t)(c - (char*)ws);
   return w;
+}
+
+void adj_build_items(pnp_plan* p, int split, int dense_min, hipStream_t s) {
+  const int ns = p->ntiles, nrb = p->ax[1].K / 8;
+  if (split < 0 || split > 3) fail(PNP_ERR_ARG, "spread split level %d outside 0..3", split);
+  if (dense_min < 1) fail(PNP_ERR_ARG, "dense-block threshold %d must be >= 1", dense_min);
+  // a strip's work: the entries of every row block's window
+  std::vector<long long> cost(ns);
+  for (int t = 0; t < ns; ++t) {
+    long long c = 0;
+    for (int rb = 0; rb < nrb; ++rb) c += p->adj_cost[(size_t)t * nrb + rb];
+    cost[t] = c;
+  }
+  std::vector<long long> sorted(cost);
+  std::sort(sorted.begin(), sorted.end());
+  const long long median = std::max<long long>(1, sorted[ns / 2]);
+  const long long target = split == 0 ? (1ll << 62) : median * (split == 1 ? 4 : split == 2 ? 2 : 1);
+  std::vector<int> order(ns);
+  for (int t = 0; t < ns; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  struct It { int4 v; long long c; };
+  std::vector<It> items;
+  std::vector<int4> splits;
+  int slots = 0;
+  for (int t : order) {
+    int parts = (int)std::min<long long>(8, (cost[t] + target - 1) / target);
+    parts = std::min(parts, kMaxAdjSlots - slots);
+    if (parts <= 1) {
+      items.push_back({make_int4(t, 0, 1, -1), cost[t]});
+      continue;
+    }
+    splits.push_back(make_int4(t, slots, parts, 0));
+    for (int k = 0; k < parts; ++k) items.push_back({make_int4(t, k, parts, slots), cost[t] / parts});
+    slots += parts;
+  }
+  std::stable_sort(items.begin(), items.end(), [](const It& a, const It& b) { return a.c > b.c; });
+  std::vector<int4> v(items.size());
+  for (size_t i = 0; i < items.size(); ++i) v[i] = items[i].v;
+  PNP_HIP(hipMemcpyAsync(p->adj_items, v.data(), sizeof(int4) * v.size(), hipMemcpyHostToDevice, s));
+  if (!splits.empty())
+    PNP_HIP(hipMemcpyAsync(p->adj_splits, splits.data(), sizeof(int4) * splits.size(), hipMemcpyHostToDevice, s));
+  PNP_HIP(hipStreamSynchronize(s));
+  p->n_adj_items = (int)v.size();
+  p->n_adj_splits = (int)splits.size();
+  p->adj_split = split;
+  p->adj_dense_min = dense_min;
 }
 
 // A 2D plan whose grid is served by the general passes must fit their LDS
@@ -833,7 +944,7 @@ static void adjoint_to_groups(const pnp_plan* p, const KIn& kin, const float2* s
                  scale, L, w.yent);
   }
   if (fs_ok(p)) {
-    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, s);
+    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, w.spart, s);
     PNP_FS_DISPATCH(Kx, rows_adj, p, L, w.mid, smaps, dst, s);
     return;
   }
@@ -891,7 +1002,7 @@ void op_adjoint_coils(const pnp_plan* p, const float2* y, int L, const float* dc
                KIn{y, nullptr, nullptr, (long long)p->M, (long long)p->E}, p->rec, dcf, scale, L, w.yent);
   const long long mstride = (long long)ny * Kx;               // one coil's half-transformed grid
   if (fs_ok(p)) {
-    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, s);
+    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, w.spart, s);
     for (int l = 0; l < L; ++l) PNP_FS_DISPATCH(Kx, rows_adj, p, 1, w.mid + l * mstride, ones, out + l * N, s);
     return;
   }

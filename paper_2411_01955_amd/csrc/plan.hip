@@ -626,6 +626,8 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     const size_t o_rec = take(sizeof(EntryRec) * (ndim == 2 ? Emax : 1));
     const size_t o_traj = take(sizeof(float) * M * ndim);
     const size_t o_ord = take(sizeof(int) * p->ntiles);
+    const size_t o_ai = take(sizeof(int4) * ((size_t)p->ntiles + kMaxAdjSlots));
+    const size_t o_as = take(sizeof(int4) * kMaxAdjSlots);
     // set-up scratch (freed below)
     size_t soff = 0;
     const size_t s_cnt = soff; soff += align256(sizeof(int) * p->ntiles);
@@ -652,6 +654,8 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     p->rec = (EntryRec*)(base + o_rec);
     p->traj = (float*)(base + o_traj);
     p->tile_order = (int32_t*)(base + o_ord);
+    p->adj_items = (int4*)(base + o_ai);
+    p->adj_splits = (int4*)(base + o_as);
     PNP_HIP(hipMemcpyAsync(p->traj, traj, sizeof(float) * M * ndim, hipMemcpyDeviceToDevice, stream));
 
     struct Scratch {
@@ -729,6 +733,23 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
                        [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
       PNP_HIP(hipMemcpyAsync(p->tile_order, ord.data(), sizeof(int32_t) * p->ntiles, hipMemcpyHostToDevice,
                              stream));
+    }
+    // work items of the 2D adjoint spread: the entries in the window of every
+    // (strip, 8-row block), first row taps [8 rb - 5, 8 rb + 8) wrapped
+    if (ndim == 2) {
+      std::vector<int32_t> rs((size_t)p->ntiles * (R + 1));
+      PNP_HIP(hipMemcpyAsync(rs.data(), p->row_start, sizeof(int32_t) * rs.size(), hipMemcpyDeviceToHost, stream));
+      PNP_HIP(hipStreamSynchronize(stream));
+      const int nrb = R / 8;
+      p->adj_cost.assign((size_t)p->ntiles * nrb, 0);
+      for (int t = 0; t < p->ntiles; ++t) {
+        const int32_t* r = rs.data() + (size_t)t * (R + 1);
+        for (int rb = 0; rb < nrb; ++rb) {
+          const int lo = rb * 8 - 5, hi = rb * 8 + 8;
+          p->adj_cost[(size_t)t * nrb + rb] = lo >= 0 ? r[hi] - r[lo] : (r[R] - r[R + lo]) + (r[hi] - r[0]);
+        }
+      }
+      adj_build_items(p, 0, 128, stream);
     }
     PNP_HIP(hipStreamSynchronize(stream));
   } catch (...) {

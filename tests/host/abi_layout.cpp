@@ -28,5 +28,7 @@ int main() {
   OFF(pnp_tuning, time_us);
   OFF(pnp_tuning, row_coils_fwd);
   OFF(pnp_tuning, time_fwd_us);
+  OFF(pnp_tuning, spread_split);
+  OFF(pnp_tuning, time_spread_us);
   return 0;
 }

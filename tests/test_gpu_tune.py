@@ -48,6 +48,38 @@ def test_operators_match_oracle_for_every_row_coils(pnp, rc):
     assert max(e_g, e_a) < 2e-5 and e_t < 2e-6
 
 
+@pytest.fixture(scope="module")
+def clinical_adjoint_ref():
+    w = synth.config_clinical()
+    S = synth.smaps2d(w.n, w.L)
+    dcf = synth.voronoi_dcf(w.traj, w.n)
+    y = synth.white_complex((w.L, w.traj.k.shape[0]), 21)
+    return w, S, dcf, y, ndft.adjoint(y, S, w.traj.k, dcf)
+
+
+@pytest.mark.parametrize("split", [0, 1, 2, 3])
+@pytest.mark.parametrize("dense_min", [128, 512])
+def test_adjoint_matches_oracle_for_every_spread_setting(pnp, clinical_adjoint_ref, split, dense_min):
+    """The clinical spiral's heavy strips (the k-space centre) split into 0
+    to several parts, and the dense-block threshold: the adjoint against the
+    exact NDFT for each setting, and bit-identical to the unsplit spread
+    where no row block changes hands between the shared and the per-wave
+    form (same dense threshold, so the per-block sums are the same)."""
+    w, S, dcf, y, ref = clinical_adjoint_ref
+    plan = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
+    plan.spread = (split, dense_min)
+    assert plan.spread == (split, dense_min)
+    Sd, dd, yd = to_dev(S), to_dev(dcf), to_dev(y)
+    got = to_np(plan.adjoint(yd, Sd, dd))
+    e = rel_l2(got, ref)
+    plan.spread = (0, dense_min)
+    base = to_np(plan.adjoint(yd, Sd, dd))
+    say(f"[tune] spread split={split} dense_min={dense_min}: adjoint {e:.2e}, "
+        f"max |split - unsplit| = {np.abs(got - base).max():.2e}")
+    assert e < 2e-5
+    assert rel_l2(got, base) < 1e-6
+
+
 def test_autotune_and_cache(pnp, tmp_path):
     w = synth.config_clinical()
     S = to_dev(synth.smaps2d(w.n, w.L))
@@ -61,6 +93,12 @@ def test_autotune_and_cache(pnp, tmp_path):
     assert set(pair) <= {2, 4, 8} and not r1["from_cache"]
     assert all(t > 0 for t in r1["time_us"] + r1["time_fwd_us"])
     assert plan.row_coils_pair == pair
+    assert plan.spread == (r1["spread_split"], r1["spread_dense_min"])
+    assert r1["spread_split"] in (0, 1, 2, 3) and r1["spread_dense_min"] in (128, 256, 512)
+    assert all(t > 0 for t in r1["time_spread_us"])
+    ts = r1["time_spread_us"]
+    chosen = ts[3 * r1["spread_split"] + (128, 256, 512).index(r1["spread_dense_min"])]
+    assert chosen <= ts[0]                               # never slower than the default (split 0, 128)
     t = dict(zip((2, 4, 8), r1["time_us"]))
     tf = dict(zip((2, 4, 8), r1["time_fwd_us"]))
     assert t[pair[1]] <= t[4] and tf[pair[0]] <= tf[4]   # never slower than the default
@@ -69,8 +107,10 @@ def test_autotune_and_cache(pnp, tmp_path):
     # a second plan on the same trajectory takes the cached choice
     plan2 = pnp.Plan(to_dev(w.traj.k), (w.n, w.n))
     plan2.row_coils_pair = tuple(2 if v != 2 else 8 for v in pair)
+    plan2.spread = (0, 512)
     r2 = plan2.autotune(S, dcf, toeplitz=pnp.Toeplitz(plan2, dcf), cache=cache)
     assert r2["from_cache"] and (r2["row_coils_fwd"], r2["row_coils"]) == pair == plan2.row_coils_pair
+    assert plan2.spread == (r1["spread_split"], r1["spread_dense_min"])
     # the gridded operator is a different key
     r3 = plan2.autotune(S, dcf, cache=cache)
     assert not r3["from_cache"]
