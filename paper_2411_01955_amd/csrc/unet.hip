@@ -43,6 +43,9 @@ constexpr int kDef[kLayers][3] = {
     {kUp, 128, 64},     {kConv3, 128, 64},  {kConv3, 64, 64},
     {kUp, 64, 32},      {kConv3, 64, 32},   {kConv3, 32, 32},
     {kConv1, 32, 2}};
+// resolution level (halvings of H and W) of the pixels each layer's weight
+// gradient sums over: a convolution's own, a transposed convolution's input
+constexpr int kDWLevel[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0};
 
 struct NetLayout {
   LayerInfo L[kLayers];
@@ -342,11 +345,14 @@ __global__ void k_unet_wt(WTTable tab, const uint16_t* __restrict__ wbf, uint16_
 }
 
 // ------------------------------------------------------------ workspace
+long long dw_part_total(int B, int H, int W);
+
 struct UWs {
   uint16_t *x0, *e1a, *c1, *d1a, *d1b, *p1, *e2a, *c2, *d2a, *d2b, *p2, *e3a, *c3, *d3a, *d3b, *p3, *ba, *bb;
   float* out;
   uint16_t *gout, *gd1b, *gd1a, *gc1, *gd2b, *gd2a, *gc2, *gd3b, *gd3a, *gc3, *gbb, *gba, *gp3, *ge3a, *gp2,
       *ge2a, *gp1, *ge1a;
+  float* dwpart;   // weight-gradient partial tiles of every layer (dw_layout)
   size_t bytes;
 };
 
@@ -399,6 +405,7 @@ UWs unet_ws(int B, int H, int W, bool train, void* base) {
     w.ge2a = bf(P1 * 64);
     w.gp1 = bf(P1 * 32);
     w.ge1a = bf(P0 * 32);
+    w.dwpart = reinterpret_cast<float*>(bf(2 * dw_part_total(B, H, W)));
   }
   w.bytes = (off + 255) & ~(size_t)255;
   return w;
@@ -427,6 +434,52 @@ namespace pnp {
 namespace {
 
 const LayerInfo& layer(int i) { return layout().L[i]; }
+
+// Weight-gradient launch shape of a layer over P pixels: a 32 x 128 output
+// tile where Cout <= 32, else 64 x 64 (a transposed convolution: one GEMM
+// per tap, N = Cin + 1); the pixels split into a multiple of 8 slices of
+// whole 128-pixel stages (slices past the end are empty and contribute
+// zeros), about 1024 workgroups and >= 4 stages a slice where the pixels
+// allow.
+struct DWPlan {
+  int tm, tn, mt, nt, taps, M, N, kchunk, splits;
+  long long part_floats() const { return (long long)taps * splits * M * N; }
+};
+DWPlan dw_plan(const LayerInfo& l, long long P) {
+  DWPlan d;
+  const bool up = l.kind == kUp;
+  d.tm = l.cout <= 32 ? 32 : 64;
+  d.tn = 4096 / d.tm;
+  d.M = l.cout;
+  d.N = up ? l.cp + 1 : l.taps * l.cp + 1;
+  d.taps = up ? 4 : 1;
+  d.mt = (int)blocks_for(d.M, d.tm);
+  d.nt = (int)blocks_for(d.N, d.tn);
+  const long long tiles = (long long)d.mt * d.nt * d.taps;
+  long long sp = std::max<long long>(1, std::min<long long>(P / 512, (1024 + tiles - 1) / tiles));
+  sp = (sp + 7) / 8 * 8;
+  long long kc = (P + sp - 1) / sp;
+  kc = (kc + 127) / 128 * 128;
+  d.kchunk = (int)kc;
+  d.splits = (int)sp;
+  return d;
+}
+
+// every layer's partial tiles, one after another (256-byte aligned)
+struct DWLayout {
+  long long off[kLayers];
+  long long total;
+};
+DWLayout dw_layout(int B, int H, int W) {
+  DWLayout t{};
+  for (int i = 0; i < kLayers; ++i) {
+    t.off[i] = t.total;
+    const long long P = (long long)B * (H >> kDWLevel[i]) * (W >> kDWLevel[i]);
+    t.total += (dw_plan(layer(i), P).part_floats() + 63) / 64 * 64;
+  }
+  return t;
+}
+long long dw_part_total(int B, int H, int W) { return dw_layout(B, H, W).total; }
 
 // K chunks of a forward convolution on the tiled kernels: fixed by the layer
 // and the image size, never by the batch, so every image of a batch gets
@@ -511,24 +564,46 @@ void launch_pool_bwd(Act fin, Act gout, Act gin, Geo go, int C, hipStream_t s) {
   PNP_LAUNCH(k_unet_pool_bwd, dim3(blocks_for(n)), dim3(kThreads), 0, s, fin, gout, gin, go, C);
 }
 
-// split-K choice for the weight gradients: about 2048 workgroups, chunks a
-// multiple of the 32-wide K step (a K step never crosses a chunk boundary)
-void split_k(long long P, long long tiles, int* kchunk, int* splits) {
-  long long sp = std::max<long long>(1, std::min<long long>((P + 255) / 256, 2048 / std::max<long long>(1, tiles)));
-  long long kc = (P + sp - 1) / sp;
-  kc = (kc + 31) / 32 * 32;
-  *kchunk = (int)kc;
-  *splits = (int)((P + kc - 1) / kc);
-}
-
-void launch_conv_dw(pnp_unet* net, int li, Act dz, Act in, Geo g, hipStream_t s) {
+// Partial weight-gradient tiles of layer li (dz: output gradient, in: the
+// layer input, g: the pixel space of the sum) into its part of dwpart
+void launch_dw(int li, Act dz, Act in, Geo g, float* dwpart, hipStream_t s) {
   const LayerInfo& l = layer(li);
   const long long P = (long long)g.B * g.H * g.W;
-  const unsigned mt = blocks_for(l.cout, 64), nt = blocks_for((long long)l.taps * l.cp + 1, 64);
-  int kc, sp;
-  split_k(P, (long long)mt * nt, &kc, &sp);
-  unet::ConvDW v{dz, in, net->grad + l.w_off, g, l.taps, l.cp, l.cout, kc};
-  PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvDW>, dim3(mt, nt, sp), dim3(256), 0, s, v);
+  const DWPlan d = dw_plan(l, P);
+  const DWLayout lay = dw_layout(g.B, g.H << kDWLevel[li], g.W << kDWLevel[li]);
+  const bool up = l.kind == kUp;
+  unet::DWArgs a{dz.p + dz.co, in.p + in.co, dwpart + lay.off[li], dz.cs, in.cs, g.H, g.W, (int)P,
+                 up ? 1 : l.taps, l.cp, d.M, d.N, up ? 1 : 0, d.kchunk, 128 % g.W, (128 / g.W) % g.H,
+                 d.mt, d.mt * d.nt, d.mt * d.nt * d.taps, d.splits};
+  const dim3 grid((unsigned)(d.mt * d.nt * d.taps * d.splits));
+  const bool al = g.W % 8 == 0;
+  if (d.tm == 32 && al) PNP_LAUNCH((unet::k_dw_gemm<32, 128, true>), grid, dim3(256), 0, s, a);
+  if (d.tm == 32 && !al) PNP_LAUNCH((unet::k_dw_gemm<32, 128, false>), grid, dim3(256), 0, s, a);
+  if (d.tm == 64 && al) PNP_LAUNCH((unet::k_dw_gemm<64, 64, true>), grid, dim3(256), 0, s, a);
+  if (d.tm == 64 && !al) PNP_LAUNCH((unet::k_dw_gemm<64, 64, false>), grid, dim3(256), 0, s, a);
+}
+
+// Every layer's dW and db from its partial tiles (each gradient entry is
+// written: the gradient buffer needs no clearing)
+void launch_dw_reduce(pnp_unet* net, int B, int H, int W, const float* dwpart, hipStream_t s) {
+  const DWLayout lay = dw_layout(B, H, W);
+  unet::DWJobs jobs{};
+  unsigned blocks = 0;
+  for (int i = 0; i < kLayers; ++i) {
+    const LayerInfo& l = layer(i);
+    const long long P = (long long)B * (H >> kDWLevel[i]) * (W >> kDWLevel[i]);
+    const DWPlan d = dw_plan(l, P);
+    const bool up = l.kind == kUp;
+    // slice groups: at most 8 slices a thread where 16 groups allow
+    int G = 1;
+    while (G < 16 && d.splits > 8 * G) G *= 2;
+    const long long entries = (long long)d.M * (up ? 4 * l.cp + 1 : d.N);
+    unet::DWJob& J = jobs.j[jobs.n++];
+    J = unet::DWJob{dwpart + lay.off[i], net->grad + l.w_off, net->grad + l.b_off, d.splits, d.M, d.N,
+                    up ? 1 : 0, l.cp, G, blocks};
+    blocks += (unsigned)((entries + 256 / G - 1) / (256 / G));
+  }
+  PNP_LAUNCH(unet::k_dw_reduce, dim3(blocks), dim3(256), 0, s, jobs);
 }
 
 void launch_conv_dx(const pnp_unet* net, int li, Act dz, Act dx, Mask mask, Geo g, hipStream_t s) {
@@ -555,16 +630,6 @@ void launch_conv_dx(const pnp_unet* net, int li, Act dz, Act dx, Mask mask, Geo 
   unet::ConvDX v{dz, net->wt + l.wt_off, dx, mask, g, l.taps, l.coutp, l.cin};
   PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvDX>, dim3(blocks_for(P, 64), blocks_for(l.cin, 64), 1), dim3(256), 0,
              s, v);
-}
-
-void launch_up_dw(pnp_unet* net, int li, Act dout, Act in, Geo g, hipStream_t s) {
-  const LayerInfo& l = layer(li);
-  const long long P = (long long)g.B * g.H * g.W;
-  const unsigned mt = blocks_for(l.cout, 64), nt = blocks_for((long long)l.cin + 1, 64);
-  int kc, sp;
-  split_k(P, (long long)mt * nt * 4, &kc, &sp);
-  unet::UpDW v{dout, in, net->grad + l.w_off, g, l.cin, l.cout, kc, sp};
-  PNP_LAUNCH(unet::k_mfma_gemm<unet::UpDW>, dim3(mt, nt, 4 * sp), dim3(256), 0, s, v);
 }
 
 void launch_up_dx(const pnp_unet* net, int li, Act dout, Act dx, Mask mask, Geo g, hipStream_t s) {
@@ -736,46 +801,47 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
 static void unet_backprop(pnp_unet* net, const UWs& w, int B, int H, int W, hipStream_t s) {
   const Geo g0{B, H, W}, g1{B, H / 2, W / 2}, g2{B, H / 4, W / 4}, g3{B, H / 8, W / 8};
   // output layer and the last decoder stage
-  launch_conv_dw(net, 17, A(w.gout, 8, 0, 2), A(w.d1b, 32, 0, 32), g0, s);
+  launch_dw(17, A(w.gout, 8, 0, 2), A(w.d1b, 32, 0, 32), g0, w.dwpart, s);
   launch_conv_dx(net, 17, A(w.gout, 8, 0, 8), A(w.gd1b, 32, 0, 32), relu_mask(w.d1b, 32, 0, 32), g0, s);
-  launch_conv_dw(net, 16, A(w.gd1b, 32, 0, 32), A(w.d1a, 32, 0, 32), g0, s);
+  launch_dw(16, A(w.gd1b, 32, 0, 32), A(w.d1a, 32, 0, 32), g0, w.dwpart, s);
   launch_conv_dx(net, 16, A(w.gd1b, 32, 0, 32), A(w.gd1a, 32, 0, 32), relu_mask(w.d1a, 32, 0, 32), g0, s);
-  launch_conv_dw(net, 15, A(w.gd1a, 32, 0, 32), A(w.c1, 64, 0, 64), g0, s);
+  launch_dw(15, A(w.gd1a, 32, 0, 32), A(w.c1, 64, 0, 64), g0, w.dwpart, s);
   launch_conv_dx(net, 15, A(w.gd1a, 32, 0, 32), A(w.gc1, 64, 0, 64), relu_mask(w.c1, 64, 0, 32), g0, s);
-  launch_up_dw(net, 14, A(w.gc1, 64, 32, 32), A(w.d2b, 64, 0, 64), g1, s);
+  launch_dw(14, A(w.gc1, 64, 32, 32), A(w.d2b, 64, 0, 64), g1, w.dwpart, s);
   launch_up_dx(net, 14, A(w.gc1, 64, 32, 32), A(w.gd2b, 64, 0, 64), relu_mask(w.d2b, 64, 0, 64), g1, s);
-  launch_conv_dw(net, 13, A(w.gd2b, 64, 0, 64), A(w.d2a, 64, 0, 64), g1, s);
+  launch_dw(13, A(w.gd2b, 64, 0, 64), A(w.d2a, 64, 0, 64), g1, w.dwpart, s);
   launch_conv_dx(net, 13, A(w.gd2b, 64, 0, 64), A(w.gd2a, 64, 0, 64), relu_mask(w.d2a, 64, 0, 64), g1, s);
-  launch_conv_dw(net, 12, A(w.gd2a, 64, 0, 64), A(w.c2, 128, 0, 128), g1, s);
+  launch_dw(12, A(w.gd2a, 64, 0, 64), A(w.c2, 128, 0, 128), g1, w.dwpart, s);
   launch_conv_dx(net, 12, A(w.gd2a, 64, 0, 64), A(w.gc2, 128, 0, 128), relu_mask(w.c2, 128, 0, 64), g1, s);
-  launch_up_dw(net, 11, A(w.gc2, 128, 64, 64), A(w.d3b, 128, 0, 128), g2, s);
+  launch_dw(11, A(w.gc2, 128, 64, 64), A(w.d3b, 128, 0, 128), g2, w.dwpart, s);
   launch_up_dx(net, 11, A(w.gc2, 128, 64, 64), A(w.gd3b, 128, 0, 128), relu_mask(w.d3b, 128, 0, 128), g2, s);
-  launch_conv_dw(net, 10, A(w.gd3b, 128, 0, 128), A(w.d3a, 128, 0, 128), g2, s);
+  launch_dw(10, A(w.gd3b, 128, 0, 128), A(w.d3a, 128, 0, 128), g2, w.dwpart, s);
   launch_conv_dx(net, 10, A(w.gd3b, 128, 0, 128), A(w.gd3a, 128, 0, 128), relu_mask(w.d3a, 128, 0, 128), g2, s);
-  launch_conv_dw(net, 9, A(w.gd3a, 128, 0, 128), A(w.c3, 256, 0, 256), g2, s);
+  launch_dw(9, A(w.gd3a, 128, 0, 128), A(w.c3, 256, 0, 256), g2, w.dwpart, s);
   launch_conv_dx(net, 9, A(w.gd3a, 128, 0, 128), A(w.gc3, 256, 0, 256), relu_mask(w.c3, 256, 0, 128), g2, s);
-  launch_up_dw(net, 8, A(w.gc3, 256, 128, 128), A(w.bb, 256, 0, 256), g3, s);
+  launch_dw(8, A(w.gc3, 256, 128, 128), A(w.bb, 256, 0, 256), g3, w.dwpart, s);
   launch_up_dx(net, 8, A(w.gc3, 256, 128, 128), A(w.gbb, 256, 0, 256), relu_mask(w.bb, 256, 0, 256), g3, s);
   // bottleneck
-  launch_conv_dw(net, 7, A(w.gbb, 256, 0, 256), A(w.ba, 256, 0, 256), g3, s);
+  launch_dw(7, A(w.gbb, 256, 0, 256), A(w.ba, 256, 0, 256), g3, w.dwpart, s);
   launch_conv_dx(net, 7, A(w.gbb, 256, 0, 256), A(w.gba, 256, 0, 256), relu_mask(w.ba, 256, 0, 256), g3, s);
-  launch_conv_dw(net, 6, A(w.gba, 256, 0, 256), A(w.p3, 128, 0, 128), g3, s);
+  launch_dw(6, A(w.gba, 256, 0, 256), A(w.p3, 128, 0, 128), g3, w.dwpart, s);
   launch_conv_dx(net, 6, A(w.gba, 256, 0, 256), A(w.gp3, 128, 0, 128), kNoMask, g3, s);
   // encoder (skip gradients already hold the decoder's share)
   launch_pool_bwd(A(w.c3, 256, 0, 128), A(w.gp3, 128, 0, 128), A(w.gc3, 256, 0, 128), g3, 128, s);
-  launch_conv_dw(net, 5, A(w.gc3, 256, 0, 128), A(w.e3a, 128, 0, 128), g2, s);
+  launch_dw(5, A(w.gc3, 256, 0, 128), A(w.e3a, 128, 0, 128), g2, w.dwpart, s);
   launch_conv_dx(net, 5, A(w.gc3, 256, 0, 128), A(w.ge3a, 128, 0, 128), relu_mask(w.e3a, 128, 0, 128), g2, s);
-  launch_conv_dw(net, 4, A(w.ge3a, 128, 0, 128), A(w.p2, 64, 0, 64), g2, s);
+  launch_dw(4, A(w.ge3a, 128, 0, 128), A(w.p2, 64, 0, 64), g2, w.dwpart, s);
   launch_conv_dx(net, 4, A(w.ge3a, 128, 0, 128), A(w.gp2, 64, 0, 64), kNoMask, g2, s);
   launch_pool_bwd(A(w.c2, 128, 0, 64), A(w.gp2, 64, 0, 64), A(w.gc2, 128, 0, 64), g2, 64, s);
-  launch_conv_dw(net, 3, A(w.gc2, 128, 0, 64), A(w.e2a, 64, 0, 64), g1, s);
+  launch_dw(3, A(w.gc2, 128, 0, 64), A(w.e2a, 64, 0, 64), g1, w.dwpart, s);
   launch_conv_dx(net, 3, A(w.gc2, 128, 0, 64), A(w.ge2a, 64, 0, 64), relu_mask(w.e2a, 64, 0, 64), g1, s);
-  launch_conv_dw(net, 2, A(w.ge2a, 64, 0, 64), A(w.p1, 32, 0, 32), g1, s);
+  launch_dw(2, A(w.ge2a, 64, 0, 64), A(w.p1, 32, 0, 32), g1, w.dwpart, s);
   launch_conv_dx(net, 2, A(w.ge2a, 64, 0, 64), A(w.gp1, 32, 0, 32), kNoMask, g1, s);
   launch_pool_bwd(A(w.c1, 64, 0, 32), A(w.gp1, 32, 0, 32), A(w.gc1, 64, 0, 32), g1, 32, s);
-  launch_conv_dw(net, 1, A(w.gc1, 64, 0, 32), A(w.e1a, 32, 0, 32), g0, s);
+  launch_dw(1, A(w.gc1, 64, 0, 32), A(w.e1a, 32, 0, 32), g0, w.dwpart, s);
   launch_conv_dx(net, 1, A(w.gc1, 64, 0, 32), A(w.ge1a, 32, 0, 32), relu_mask(w.e1a, 32, 0, 32), g0, s);
-  launch_conv_dw(net, 0, A(w.ge1a, 32, 0, 32), A(w.x0, 8, 0, 8), g0, s);
+  launch_dw(0, A(w.ge1a, 32, 0, 32), A(w.x0, 8, 0, 8), g0, w.dwpart, s);
+  launch_dw_reduce(net, B, H, W, w.dwpart, s);
 }
 
 void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, int H, int W, double* loss,
@@ -783,7 +849,6 @@ void unet_backward(pnp_unet* net, const float2* u, const float2* target, int B, 
   check_dims(B, H, W);
   const UWs w = unet_ws(B, H, W, true, ws);
   const long long P0 = (long long)B * H * W;
-  PNP_HIP(hipMemsetAsync(net->grad, 0, (size_t)layout().n_params * 4, s));
   PNP_HIP(hipMemsetAsync(loss, 0, sizeof(double), s));
   {
     const unsigned nb = std::min<unsigned>(blocks_for(P0), 1024);
@@ -824,7 +889,6 @@ void unet_n2n_backward(pnp_unet* net, const float2* x, const uint8_t* codes, dou
   unet_forward(net, x, nullptr, 0.f, B, H, W, fx, ws_full, s);        // f(x), no gradient
   unet_forward(net, g1, nullptr, 0.f, B, h, wd, dsub, ws_sub, s);    // f(g1(x)), activations kept
   const UWs w = unet_ws(B, h, wd, true, ws_sub);
-  PNP_HIP(hipMemsetAsync(net->grad, 0, (size_t)layout().n_params * 4, s));
   PNP_HIP(hipMemsetAsync(loss, 0, sizeof(double), s));
   PNP_LAUNCH(k_n2n_loss, dim3(nb), dim3(kThreads), 0, s, dsub, g2, fx, codes, h, wd, p, (float)eta,
              (float)(0.5 / (double)p), w.gout, loss);

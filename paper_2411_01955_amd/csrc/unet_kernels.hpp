@@ -610,40 +610,6 @@ struct ConvDXT {
   __device__ void store_px(int, long long, int, float, float) const {}   // (vec_store is always true)
 };
 
-// Convolution, gradient of the weights and bias, split over pixels:
-//   dW[o][t][c] += sum_p dZ[p][o] in[p + off(t)][c],   db[o] += sum_p dZ[p][o]
-//   m = o, n = t*Cin + c (n = taps*Cin is the bias column), k = pixel.
-struct ConvDW {
-  static constexpr bool AK = true, BK = true;
-  Act dz, in;
-  float* dW;              // [Cout][taps][Cin] then db[Cout], FP32, accumulated
-  Geo g;
-  int taps, Cin, Cout, kchunk;
-  __device__ int k_lo(int z) const { return z * kchunk; }
-  __device__ int k_hi(int z) const { return min((z + 1) * kchunk, g.P()); }
-  __device__ uint4 loadA(int k, int m) const {
-    if (m >= Cout || k >= g.P()) return zero4();
-    return ld16(dz.p + (long long)k * dz.cs + dz.co + m);
-  }
-  __device__ uint4 loadB(int k, int n) const {
-    if (k >= g.P() || n > taps * Cin) return zero4();
-    if (n == taps * Cin) return make_uint4(0x3f80u, 0u, 0u, 0u);   // BF16 1.0 in the bias column
-    const int t = n / Cin, c = n - t * Cin;
-    const int x = k % g.W + tap_dx(taps, t), y = (k / g.W) % g.H + tap_dy(taps, t);
-    if ((unsigned)y >= (unsigned)g.H || (unsigned)x >= (unsigned)g.W) return zero4();
-    const long long pix = ((long long)(k / (g.W * g.H)) * g.H + y) * g.W + x;
-    return ld16(in.p + pix * in.cs + in.co + c);
-  }
-  __device__ float pre(int, int) const { return 0.f; }
-  __device__ void store(int m, int n, float val, float) const {
-    if (m >= Cout || n > taps * Cin) return;
-    if (n == taps * Cin)
-      atomicAdd(&dW[(long long)Cout * taps * Cin + m], val);
-    else
-      atomicAdd(&dW[(long long)m * taps * Cin + n], val);
-  }
-};
-
 // Output pixel of the 2x2 stride-2 transposed convolution for input pixel m
 // (geometry g) and tap t = 2a + b.
 __device__ __forceinline__ long long up_pix(const Geo& g, int m, int t) {
@@ -745,36 +711,271 @@ struct UpDX {
   }
 };
 
-// Transposed convolution, gradient of the weights and bias; grid slice
-// z = t * splits + split:
-//   dW[o][t][c] += sum_{i,j} dOut[2i+a][2j+b][o] in[i][j][c],  db[o] += dOut sums
-//   m = o, n = c (n = Cin is the bias column), k = input pixel.
-struct UpDW {
-  static constexpr bool AK = true, BK = true;
-  Act dout, in;
-  float* dW;              // [Cout][4][Cin] then db[Cout]
-  Geo g;                  // input geometry
-  int Cin, Cout, kchunk, splits;
-  __device__ int k_lo(int z) const { return (z % splits) * kchunk; }
-  __device__ int k_hi(int z) const { return min((z % splits + 1) * kchunk, g.P()); }
-  __device__ uint4 loadA(int k, int m) const {
-    if (m >= Cout || k >= g.P()) return zero4();
-    return ld16(dout.p + up_pix(g, k, blockIdx.z / splits) * dout.cs + dout.co + m);
-  }
-  __device__ uint4 loadB(int k, int n) const {
-    if (k >= g.P() || n > Cin) return zero4();
-    if (n == Cin) return make_uint4(0x3f80u, 0u, 0u, 0u);
-    return ld16(in.p + (long long)k * in.cs + in.co + n);
-  }
-  __device__ float pre(int, int) const { return 0.f; }
-  __device__ void store(int m, int n, float val, float) const {
-    if (m >= Cout || n > Cin) return;
-    if (n == Cin)
-      atomicAdd(&dW[(long long)Cout * 4 * Cin + m], val);
-    else
-      atomicAdd(&dW[((long long)m * 4 + blockIdx.z / splits) * Cin + n], val);
-  }
+// ------------------------------------------------ weight gradients
+// dW[m][n] = sum_p dZ[p][m] B[p][n] over the pixels p of a slice, with dZ
+// the output gradient (m = output channel) and B the im2col row of the
+// layer input (n = t*Cin + c; n = taps*Cin is the bias column of ones), so
+// that the bias gradient is the last column.  For the 2x2 stride-2
+// transposed convolutions p runs over input pixels and each tap t is a GEMM
+// of its own: A(p, m) = dOut[output pixel of (p, t)][m], B(p, n) = in[p][n],
+// N = Cin + 1.  Both operands are pixel-major in memory, 8 channels per
+// 16-byte load; MFMA wants them channel-major (8 consecutive pixels of one
+// channel per lane).  A thread owns a "slot" (8 channels x 8 consecutive
+// pixels of one operand), loads it with 8 16-byte loads and transposes it
+// in registers into 8 LDS rows of 16 bytes.  The 16-byte chunks of a row
+// are XOR-swizzled so that both the transposing stores and the MFMA reads
+// spread over the banks.  The next 128-pixel stage's loads are held in
+// registers during the current stage's MFMAs.
+//
+// Pixel slice z owns pixels [z*kchunk, (z+1)*kchunk) and stores its partial
+// tile with plain stores into part[t][z][M][N]; k_dw_reduce adds the slices
+// up in a fixed order (deterministic, no atomics).  The grid is 1D over
+// splits x tiles, splits a multiple of 8: the hardware deals workgroups to
+// the 8 XCDs round-robin, so workgroup w runs slice (w mod 8) + 8*(w / 8 /
+// tiles) -- every tile of a slice on one XCD, whose L2 then fetches the
+// slice's operands once.
+struct DWArgs {
+  const uint16_t* dz;   // pixel p, channel m at dz[p*dzs + m] (output pixels for the transposed convolution)
+  const uint16_t* in;   // pixel p, channel c at in[p*ins + c]
+  float* part;          // [taps of the transposed convolution or 1][splits][M][N]
+  int dzs, ins;
+  int H, W, P;          // pixel space of the sum
+  int taps, Cin, M, N;  // convolution: N = taps*Cin + 1; transposed convolution: taps = 1, N = Cin + 1
+  int up;               // 1: transposed convolution (tile index = tap, N tile, M tile)
+  int kchunk;           // a multiple of the 128-pixel stage
+  int sx, sy;           // a step of 128 pixels: x += sx, y += sy, carry x into y, y mod H
+  int mt, mn, tiles;    // M tiles; M x N tiles; all tiles (x 4 taps for the transposed convolution)
+  int splits;
 };
+
+static __device__ __attribute__((aligned(16))) const uint32_t kOneRow[4] = {0x3f80u, 0u, 0u, 0u};
+
+// LDS element offset of row r, 16-byte chunk c (16 chunks of 8 BF16 per row)
+__device__ __forceinline__ int dw_lds(int r, int c) { return r * 128 + 8 * (c ^ ((r ^ (r >> 3)) & 7)); }
+
+// ALIGNED: W % 8 == 0, so that the 8 pixels of a slot lie in one image row
+// (and P, a multiple of 8, ends no slot part-way)
+template <int TM, int TN, bool ALIGNED>
+__global__ void __launch_bounds__(256) k_dw_gemm(DWArgs a) {
+  static_assert((TM / 32) * (TN / 32) == 4, "four 32 x 32 wave blocks");
+  constexpr int SA = 2 * TM, SB = 2 * TN;          // slots: (TM/8 channel groups) x (16 pixel chunks)
+  constexpr int NS = (SA + SB + 255) / 256;         // slots per thread
+  static_assert(SA % 64 == 0, "a wave's slots are all of one operand");
+  __shared__ __attribute__((aligned(16))) uint16_t L[(TM + TN) * 128];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = blockIdx.x >> 3, zl = j / a.tiles, tile = j - zl * a.tiles;
+  const int z = (blockIdx.x & 7) + 8 * zl;
+  const int tap = tile / a.mn, mnt = tile - tap * a.mn;
+  const int m0 = (mnt % a.mt) * TM, n0 = (mnt / a.mt) * TN;
+  const int wm = (wave / (TN / 32)) * 32, wn = (wave % (TN / 32)) * 32;
+  const int klo = min(z * a.kchunk, a.P), khi = min(klo + a.kchunk, a.P);
+  const uint16_t* zrow = reinterpret_cast<const uint16_t*>(kZeroRow);
+
+  // slot set-up: source address of pixel 0 (tap offset included), address
+  // steps per pixel index and per image column, tap offset, LDS row, pixel
+  // chunk, image position of the chunk's first pixel
+  const uint16_t* src[NS];
+  int stride[NS], xstride[NS], dx[NS], dy[NS], row[NS], chunk[NS], px[NS], py[NS];
+  bool live[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int sl = tid + 256 * u;
+    live[u] = sl < SA + SB;
+    dx[u] = dy[u] = 0;
+    xstride[u] = 0;
+    if (sl < SA) {
+      const int g = sl % (TM / 8), m = m0 + 8 * g;
+      chunk[u] = sl / (TM / 8);
+      row[u] = 8 * g;
+      src[u] = m < a.M ? a.dz + m : zrow;
+      stride[u] = m < a.M ? a.dzs : 0;
+      if (a.up && m < a.M) {
+        // output pixel of input pixel p = (b*H + y)*W + x, tap (ty, tx):
+        // (b*2H + 2y + ty)*2W + 2x + tx = 4p - 2x + 2W*ty + tx
+        src[u] += (long long)(2 * a.W * (tap >> 1) + (tap & 1)) * a.dzs;
+        stride[u] = 4 * a.dzs;
+        xstride[u] = -2 * a.dzs;
+      }
+    } else {
+      const int s2 = min(sl, SA + SB - 1) - SA, g = s2 % (TN / 8), n = n0 + 8 * g;
+      chunk[u] = s2 / (TN / 8);
+      row[u] = TM + 8 * g;
+      if (n < a.taps * a.Cin) {
+        const int t = n / a.Cin, c = n - t * a.Cin;
+        dy[u] = tap_dy(a.taps, t);
+        dx[u] = tap_dx(a.taps, t);
+        src[u] = a.in + c + (long long)(dy[u] * a.W + dx[u]) * a.ins;
+        stride[u] = a.ins;
+      } else {
+        src[u] = n == a.taps * a.Cin ? reinterpret_cast<const uint16_t*>(kOneRow) : zrow;
+        stride[u] = 0;
+      }
+    }
+    const int p = klo + 8 * chunk[u];
+    px[u] = p % a.W;
+    py[u] = (p / a.W) % a.H;
+  }
+  uint4 r[NS][8];
+  // loads of the stage at k0 (called for consecutive stages); then advances
+  // the slot positions by one stage
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int p0 = k0 + 8 * chunk[u];
+      const uint16_t* s0 = src[u] + (long long)p0 * stride[u] + (long long)px[u] * xstride[u];
+      if constexpr (ALIGNED) {
+        const bool rowok = live[u] && p0 < khi && (unsigned)(py[u] + dy[u]) < (unsigned)a.H;
+        const bool lok = !(dx[u] < 0 && px[u] == 0), rok = !(dx[u] > 0 && px[u] + 8 == a.W);
+        const int step = stride[u] + xstride[u];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = rowok && (e > 0 || lok) && (e < 7 || rok);
+          r[u][e] = ld16g(ok ? s0 + e * step : zrow);
+        }
+      } else {
+        int x = px[u], y = py[u];
+        const uint16_t* s = s0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = live[u] && p0 + e < khi && (unsigned)(x + dx[u]) < (unsigned)a.W &&
+                          (unsigned)(y + dy[u]) < (unsigned)a.H;
+          r[u][e] = ld16g(ok ? s : zrow);
+          s += stride[u] + xstride[u];
+          if (++x == a.W) {
+            x = 0;
+            y = y + 1 == a.H ? 0 : y + 1;
+            s -= (long long)a.W * xstride[u];
+          }
+        }
+      }
+      px[u] += a.sx;
+      py[u] += a.sy;
+      if (px[u] >= a.W) { px[u] -= a.W; ++py[u]; }
+      if (py[u] >= a.H) py[u] -= a.H;
+    }
+  };
+  // channel i of the 8 pixels -> one 16-byte row chunk
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      if (!live[u]) continue;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t sel = (i & 1) ? 0x07060302u : 0x05040100u;
+        uint32_t w[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint4& v = r[u][e];
+          w[e] = (i >> 1) == 0 ? v.x : (i >> 1) == 1 ? v.y : (i >> 1) == 2 ? v.z : v.w;
+        }
+        const uint4 o = make_uint4(__builtin_amdgcn_perm(w[1], w[0], sel), __builtin_amdgcn_perm(w[3], w[2], sel),
+                                   __builtin_amdgcn_perm(w[5], w[4], sel), __builtin_amdgcn_perm(w[7], w[6], sel));
+        *reinterpret_cast<uint4*>(&L[dw_lds(row[u] + i, chunk[u])]) = o;
+      }
+    }
+  };
+
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) acc[i][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (klo < khi) fetch(klo);
+  for (int k0 = klo; k0 < khi; k0 += 128) {
+    put();
+    __syncthreads();
+    if (k0 + 128 < khi) fetch(k0 + 128);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      bf16x8 fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        fa[i] = *reinterpret_cast<const bf16x8*>(&L[dw_lds(wm + 16 * i + (lane & 15), 4 * ks + (lane >> 4))]);
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+        fb[jj] = *reinterpret_cast<const bf16x8*>(&L[dw_lds(TM + wn + 16 * jj + (lane & 15), 4 * ks + (lane >> 4))]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[jj], acc[i][jj], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // partial tile: lane holds rows 4*(lane/16) + q of column lane%16 of each block
+  float* out = a.part + ((long long)tap * a.splits + z) * a.M * a.N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q, n = n0 + wn + 16 * jj + (lane & 15);
+        if (m < a.M && n < a.N) out[(long long)m * a.N + n] = acc[i][jj][q];
+      }
+}
+
+// The reductions of every layer's partial tiles, one launch.  Job j owns
+// blocks [first[j], first[j+1]); a block of 256 threads takes E = 256/G
+// consecutive gradient entries, thread (e, g) adds the slices
+// [S'*g/G, S'*(g+1)/G) of entry e in order, and thread (e, 0) then adds the G
+// sums in order: a fixed order for a given shape.
+//   convolution, entry (m, n), S' = S: sum_z part[z][m][n]; n < N-1 -> dW[m][n], n = N-1 -> db[m]
+//   transposed convolution, entry (m, t*Cin + c), S' = S: sum_z part[t][z][m][c] -> dW[m][t][c];
+//   entry (m, 4*Cin), S' = 4S: sum over the 4 taps' slices of part[.][.][m][Cin] -> db[m]
+struct DWJob {
+  const float* part;
+  float *dW, *db;
+  int S, M, N, up, Cin, G;
+  unsigned first;
+};
+constexpr int kMaxDWJobs = 18;
+struct DWJobs {
+  DWJob j[kMaxDWJobs];
+  int n;
+};
+
+__global__ void __launch_bounds__(256) k_dw_reduce(DWJobs jobs) {
+  __shared__ float red[256];
+  int ji = 0;
+  for (int k = 1; k < jobs.n; ++k)
+    if (blockIdx.x >= jobs.j[k].first) ji = k;
+  const DWJob& J = jobs.j[ji];
+  const int E = 256 / J.G, e = threadIdx.x % E, g = threadIdx.x / E;
+  const int per_row = J.up ? 4 * J.Cin + 1 : J.N;   // gradient entries of one output channel
+  const long long cnt = (long long)J.M * per_row;
+  const long long idx = (long long)(blockIdx.x - J.first) * E + e;
+  const bool ok = idx < cnt;
+  const int m = ok ? (int)(idx / per_row) : 0, n = ok ? (int)(idx - (long long)m * per_row) : 0;
+  const bool bias = n == per_row - 1;
+  // slices of this entry: address of slice k = base + k * step
+  const long long MN = (long long)J.M * J.N;
+  long long base, step = MN;
+  int S2 = J.S;
+  if (!J.up) {
+    base = (long long)m * J.N + n;
+  } else if (!bias) {
+    const int t = n / J.Cin, c = n - t * J.Cin;
+    base = (long long)t * J.S * MN + (long long)m * J.N + c;
+  } else {
+    base = (long long)m * J.N + J.Cin;
+    S2 = 4 * J.S;
+  }
+  const int z0 = (int)((long long)S2 * g / J.G), z1 = (int)((long long)S2 * (g + 1) / J.G);
+  float acc = 0.f;
+  if (ok) {
+#pragma unroll 4
+    for (int k = z0; k < z1; ++k) acc += J.part[base + k * step];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (g != 0 || !ok) return;
+  for (int h = 1; h < J.G; ++h) acc += red[h * E + e];
+  if (bias)
+    J.db[m] = acc;
+  else
+    J.dW[(long long)m * (per_row - 1) + n] = acc;
+}
 
 }  // namespace unet
 }  // namespace pnp

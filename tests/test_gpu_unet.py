@@ -112,8 +112,11 @@ def test_forward_layers_teacher_forced(pnp):
     assert rel_l2(Dg, u + (out[..., 0] + 1j * out[..., 1])) < 1e-6
 
 
-def test_backward_layers_teacher_forced(pnp):
-    B, H, W = 2, 32, 32
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (3, 48, 48)])
+def test_backward_layers_teacher_forced(pnp, B, H, W):
+    """(3, 48, 48): the weight gradients of the full-resolution layers split
+    over 11 pixel slices of 640 with a 512-pixel tail, and the 6 x 6
+    bottleneck's 16-pixel steps wrap rows and images."""
     params, net, u, sigma = _setup(pnp, B, H, W, seed=5)
     target = (0.7 * u + 0.1 * synth.white_complex(u.shape, 6)).astype(np.complex64)
     ud, td = _dev(u), _dev(target)
@@ -172,7 +175,7 @@ def test_backward_layers_teacher_forced(pnp):
     for name, fn, x, dz, m, got in steps:
         dx, dW, db = fn(name, x, dz, m)
         eW, eb = rel_l2(grads[name][0], dW), rel_l2(grads[name][1], db)
-        msg = f"[unet bwd] {name}: dW {eW:.2e} db {eb:.2e}"
+        msg = f"[unet bwd {B}x{H}x{W}] {name}: dW {eW:.2e} db {eb:.2e}"
         if got is not None:
             ex = rel_l2(got, dx)
             msg += f" dX {ex:.2e}"
@@ -328,6 +331,25 @@ def test_rejects_bad_shapes(pnp):
     with pytest.raises(pnp.PnPError) as ei:
         net.forward(x, _dev(sigma))
     assert ei.value.status == -2
+
+
+def test_weight_gradients_are_deterministic(pnp):
+    """Two backward passes over the same training batch (10 x 128 x 128, the
+    training patch size) give bit-identical weight and bias gradients: each
+    pixel slice's partial tile is added in a fixed order, no atomics."""
+    B, H, W = 10, 128, 128
+    params, net, u, sigma = _setup(pnp, B, H, W, seed=21)
+    target = (0.8 * u).astype(np.complex64)
+    ud, td, sd = _dev(u), _dev(target), _dev(sigma)
+    runs = []
+    for _ in range(2):
+        net.forward(ud, sd, train=True)
+        net.backward(ud, td)
+        runs.append(pnp.unpack_unet_params(net.get("grad").cpu().numpy()))
+    for n in U.NAMES:
+        assert np.array_equal(runs[0][n][0], runs[1][n][0]) and np.array_equal(runs[0][n][1], runs[1][n][1]), n
+        assert np.abs(runs[0][n][0]).max() > 0, n
+    say(f"[unet bwd] {B}x{H}x{W}: all {len(U.NAMES)} layers' gradients bit-identical over two passes")
 
 
 def test_training_reduces_the_loss(pnp):
