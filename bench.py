@@ -21,7 +21,11 @@ Printed JSON line:
              mean launch time (HIP events around each launch, recorded on the
              kernel's stream over a second pass of the same steps), against
              8 TB/s; ``traffic`` from the committed rocprofv3 counter summary
-             when it matches the current kernel sources;
+             when it matches the current kernel sources; ``issue`` the same
+             kernel against its FP32 VALU issue time (committed SQ counters
+             of the same sources, 4 cycles per wave instruction on 1024
+             SIMDs at 2.4 GHz) and its FP32 rate against 78.6 TFLOP/s (no
+             packed FP32 instructions in this build);
 * ``cpu_baseline``  the FP64 oracle (exact NDFT) timed on the host on one
              outer HQS iteration of the same slice (6 normal operators),
              scaled to the same unit;
@@ -73,6 +77,15 @@ KAPPA = 0.75
 KAPPA_UNET = 1.0       # UNet conditioning level = kappa * sigma_k
 RISE_TOL = 0.5         # wavelet fallback when the residual rises by more than 50%
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical.json")
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_clinical.json")
+# FP32 vector issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4
+# cycles; 256 CUs x 4 SIMDs at 2.4 GHz.  Packed FP32 instructions are not
+# generated in this build, so the FP32 peak is 256 x 4 x 16 lanes x 2 (FMA) x
+# 2.4 GHz = 78.6 TFLOP/s, half the packed figure.
+VALU_CYCLES_PER_INST = 4
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+FP32_PEAK_NONPACKED_TFLOPS = 78.6
 KERNEL_SOURCES = ["paper_2411_01955_amd/csrc/nufft2d.hip", "paper_2411_01955_amd/csrc/fs_bodies.hpp",
                   "paper_2411_01955_amd/csrc/fft_lds.hpp", "paper_2411_01955_amd/csrc/fft_reg.hpp",
                   "paper_2411_01955_amd/csrc/common.hpp", "paper_2411_01955_amd/csrc/cg_scalars.hpp",
@@ -404,6 +417,7 @@ def volume_3d(pnp, torch, n_out=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     toep = pnp.Toeplitz(plan, dd)      # exact FP64 transfer function (waits for the stream)
+    progress("3D plan and transfer function built")
     t_toep = time.perf_counter() - t0
     nrm = plan.opnorm(Sd, dd, iters=30, seed=1)
     out = torch.empty_like(xd)
@@ -555,6 +569,14 @@ def cpu_baseline(w, x, S, dcf, y, step_bytes):
     return out
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg} ({time.perf_counter() - _T0:.0f} s)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -696,6 +718,22 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom,
                 "alg_bytes_per_launch": kb[dom], "avg_launch_us": round(avg_s * 1e6, 2)}
+    # the same kernel against its FP32 issue bound, from the committed SQ
+    # instruction counters of the same sources (null once they changed)
+    roofline["issue"] = None
+    if os.path.exists(SQ_FILE):
+        with open(SQ_FILE) as f:
+            sq = json.load(f)
+        ent = sq.get("kernels", {}).get(dom)
+        if ent and sq.get("source_hash") == kernel_source_hash():
+            issue_s = ent["valu_per_launch"] * VALU_CYCLES_PER_INST / SIMDS / CLOCK_HZ
+            roofline["issue"] = {
+                "valu_instructions_per_launch": ent["valu_per_launch"],
+                "valu_issue_us": round(issue_s * 1e6, 2),
+                "frac": round(issue_s / avg_s, 4),
+                "fp32_flops_per_launch": ent["fp32_flops_per_launch"],
+                "fp32_tflops": round(ent["fp32_flops_per_launch"] / avg_s / 1e12, 2),
+                "fp32_peak_nonpacked_tflops": FP32_PEAK_NONPACKED_TFLOPS}
     kernel_table = {kname: {"launches": c, "avg_us": round(t / c * 1e3, 2),
                             "share": round(t / sum(v[1] for v in tr.values()), 4)}
                     for kname, (c, t) in sorted(tr.items(), key=lambda kv: -kv[1][1])}
@@ -706,8 +744,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    progress("timed HQS step and operators done")
     race = psnr_race(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.psnr_slices) if args.psnr_slices > 0 else None
+    progress("PSNR race done")
     others = None if args.no_pgd else pgd_fista(pnp, torch, plan, toep, Sd, dd, w, S, nrm, args.seed, B)
+    progress("PGD / FISTA done")
     # coil sensitivity estimate from the k-space centre of the same data (20 x 20 Hamming window)
     pnp.estimate_smaps(plan, y, dd)
     torch.cuda.synchronize()
@@ -717,13 +758,18 @@ def main():
     torch.cuda.synchronize()
     smaps_ms = (time.perf_counter() - t0) * 1e2
     setup = setup_times(pnp, torch, kt, (n, n), xd, Sd, dd, y, time_op)
+    progress("coil maps and set-up times done")
     unet = unet_rates(pnp, torch)
+    progress("UNet rates done")
     batched = None if args.no_batched else batched_c4(pnp, torch)
+    progress("batched slices done")
     vol3d = None if args.no_3d else volume_3d(pnp, torch)
+    progress("3D volume done")
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, x_true, S, dcf, y.cpu().numpy(), step_bytes)
+        progress("CPU oracle baseline done")
 
     line = {
         "metric": "NUFFT A^H A GB/s; slices/s to fixed PSNR, learned vs wavelet HQS",
