@@ -51,7 +51,9 @@
  *     message for the calling thread's last failure.  Arguments are checked
  *     before anything is enqueued; no C++ exception crosses this ABI.
  *   - Calls on one plan from several streams at once must use separate
- *     workspaces; a plan itself is read-only after creation.
+ *     workspaces.  A plan is read-only after creation except for its launch
+ *     settings (pnp_autotune, pnp_plan_set_row_coils*, pnp_plan_set_spread),
+ *     which must not be changed while a call on the plan may still run.
  */
 #ifndef PNPMRI_H
 #define PNPMRI_H
