@@ -712,7 +712,7 @@ struct UpDX {
 };
 
 // ------------------------------------------------ 3x3 convolution from an LDS halo tile
-// Forward 3x3 convolution for layers with CP (32 or 64) padded input
+// Forward 3x3 convolution for layers with CP (32, 64 or 128) padded input
 // channels: a workgroup computes an 8 x 16-pixel output patch for TN (32 or
 // 64) output channels.  It stages the 10 x 18-pixel input patch (the 3x3
 // halo, zeros outside the image) once in LDS; the K loop -- taps in order,
