@@ -506,24 +506,23 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
     PNP_LAUNCH(unet::k_conv_first, dim3(blocks_for(P, 128)), dim3(256), 0, s, v);
     return;
   }
-  // 3x3 layers with 32, 64 or 128 input channels and one K chunk: the
-  // halo-tile kernel (bit-identical to the single-chunk tiled kernel)
-  if (l.taps == 9 && (l.cp == 32 || l.cp == 64 || l.cp == 128) && l.cout % 32 == 0 && chunks == 1 &&
-      out32 == nullptr) {
+  // 3x3 layers with 32, 64 or 128 input channels: the halo-tile kernel, one
+  // group of four waves per K chunk (bit-identical to the tiled kernel)
+  if (l.taps == 9 && (l.cp == 32 || l.cp == 64 || l.cp == 128) && l.cout % 32 == 0 && out32 == nullptr &&
+      (chunks == 1 || chunks == 2 || chunks == 4)) {
     const unsigned patches = (unsigned)(g.B * ((g.H + unet::kHaloPY - 1) / unet::kHaloPY) *
                                         ((g.W + unet::kHaloPX - 1) / unet::kHaloPX));
-    if (l.cout % 64 == 0) {
-      const dim3 grid(patches, l.cout / 64);
-      if (l.cp == 32) PNP_LAUNCH((unet::k_conv3_halo<32, 64>), grid, dim3(256), 0, s, v);
-      else if (l.cp == 64) PNP_LAUNCH((unet::k_conv3_halo<64, 64>), grid, dim3(256), 0, s, v);
-      else PNP_LAUNCH((unet::k_conv3_halo<128, 64>), grid, dim3(256), 0, s, v);
-    } else {
-      const dim3 grid(patches, l.cout / 32);
-      if (l.cp == 32) PNP_LAUNCH((unet::k_conv3_halo<32, 32>), grid, dim3(256), 0, s, v);
-      else if (l.cp == 64) PNP_LAUNCH((unet::k_conv3_halo<64, 32>), grid, dim3(256), 0, s, v);
-      else PNP_LAUNCH((unet::k_conv3_halo<128, 32>), grid, dim3(256), 0, s, v);
-    }
-    return;
+    const bool wide = l.cout % 64 == 0 && chunks <= 2;   // 64 output channels a workgroup
+    const dim3 grid(patches, l.cout / (wide ? 64 : 32)), block(256 * chunks);
+#define PNP_HALO(CPV, TNV, GV)                                                           \
+  if (l.cp == CPV && (wide ? 64 : 32) == TNV && chunks == GV) {                          \
+    PNP_LAUNCH((unet::k_conv3_halo<CPV, TNV, GV>), grid, block, 0, s, v);                \
+    return;                                                                              \
+  }
+    PNP_HALO(32, 32, 1) PNP_HALO(32, 64, 1) PNP_HALO(64, 32, 1) PNP_HALO(64, 64, 1)
+    PNP_HALO(128, 32, 1) PNP_HALO(128, 64, 1)
+    PNP_HALO(64, 32, 2) PNP_HALO(64, 64, 2) PNP_HALO(128, 32, 2) PNP_HALO(128, 64, 2) PNP_HALO(128, 32, 4)
+#undef PNP_HALO
   }
   // larger tiles where the input channels come in 32-wide chunks and the
   // launch still has a workgroup per compute unit (K chunks in sequence);

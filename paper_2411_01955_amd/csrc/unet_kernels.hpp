@@ -720,34 +720,40 @@ struct UpDX {
 // from LDS at a compile-time offset (16 pixels of one patch row, 8 channels
 // a lane: one 16-byte read) and the B fragments straight from the BF16
 // weights in global memory, already in the MFMA lane layout, RING steps
-// ahead.  No barrier inside the K loop.  The waves split the output
-// channels (16 each: every weight is loaded by one wave only) and, for
-// TN = 32, the patch rows in two halves.  The output goes through LDS and
-// leaves as 16-byte pieces (8 channels of a pixel).  The per-element sum
-// order is that of k_gemm_tiled's single-chunk path (the same MFMA operands
-// step by step), so results are bit-identical.
+// ahead.  No barrier inside the K loop.  In a group of four waves the waves
+// split the output channels (16 each: every weight is loaded by one wave
+// only) and, for TN = 32, the patch rows in two halves.  Layers whose K
+// range k_gemm_tiled sums in G chunks run G such groups, one per chunk,
+// each from zero; group 0 adds the other groups' sums in chunk order.  The
+// output goes through LDS and leaves as 16-byte pieces (8 channels of a
+// pixel).  Per element, the sum order is k_gemm_tiled's (the same MFMA
+// operands step by step, the same chunk sums), so results are bit-identical.
 constexpr int kHaloPY = 8, kHaloPX = 16;    // output patch
-template <int CP, int TN>
+template <int CP, int TN, int G>
 struct Halo {
   static constexpr int PS = CP + 8;                      // BF16 per staged pixel (16-byte pad: no bank conflicts)
   static constexpr int HY = kHaloPY + 2, HX = kHaloPX + 2;
-  static constexpr int ELEMS = HY * HX * PS;
+  static constexpr int ELEMS = HY * HX * PS;             // staged input (BF16)
+  static constexpr int PIX = kHaloPY * kHaloPX;
+  static constexpr int RED = (G - 1) * PIX * TN * 2;     // chunk sums of groups 1..G-1 (FP32, in BF16 units)
   static constexpr int OS = TN + 8;                      // output staging row (BF16 per pixel)
-  static constexpr int OUT = kHaloPY * kHaloPX * OS;
+  static constexpr int OUT = RED + PIX * OS;
   static constexpr int LDS = ELEMS > OUT ? ELEMS : OUT;
   static constexpr int WN = TN / 16, WM = 4 / WN, BI = kHaloPY / WM;   // waves along N, along M; rows a wave
 };
 
-template <int CP, int TN>
-__global__ void __launch_bounds__(256) k_conv3_halo(ConvFwd v) {
-  using Hl = Halo<CP, TN>;
+template <int CP, int TN, int G>
+__global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
+  using Hl = Halo<CP, TN, G>;
   constexpr int NSTEPS = 9 * (CP / 32);
-  constexpr int RING = NSTEPS < 8 ? NSTEPS : 8;
+  static_assert(NSTEPS % G == 0, "whole chunks");
+  constexpr int CST = NSTEPS / G;                        // steps of one chunk
+  constexpr int RING = CST < 8 ? CST : 8;
   constexpr int CHUNKS = Hl::HY * Hl::HX * (CP / 8);     // 16-byte pieces of the halo patch
-  constexpr int CPT = (CHUNKS + 255) / 256;
+  constexpr int CPT = (CHUNKS + 256 * G - 1) / (256 * G);
   constexpr int BI = Hl::BI;
   __shared__ __attribute__((aligned(16))) uint16_t L[Hl::LDS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, grp = tid >> 8, lane = tid & 63, wave = (tid & 255) >> 6;
   const int wn = wave % Hl::WN, wm = wave / Hl::WN;
   const int H = v.g.H, W = v.g.W;
   const int npx = (W + kHaloPX - 1) / kHaloPX, npy = (H + kHaloPY - 1) / kHaloPY;
@@ -760,7 +766,7 @@ __global__ void __launch_bounds__(256) k_conv3_halo(ConvFwd v) {
   uint4 h[CPT];
 #pragma unroll
   for (int u = 0; u < CPT; ++u) {
-    const int q = tid + 256 * u;
+    const int q = tid + 256 * G * u;
     const int pix = q / (CP / 8), c8 = q - pix * (CP / 8);
     const int hy = pix / Hl::HX, hx = pix - hy * Hl::HX;
     const int y = y0 + hy - 1, x = x0 + hx - 1;
@@ -768,17 +774,18 @@ __global__ void __launch_bounds__(256) k_conv3_halo(ConvFwd v) {
     const long long gp = ((long long)b * H + y) * W + x;
     h[u] = ld16g(ok ? v.in.p + gp * v.in.cs + v.in.co + 8 * c8 : zrow);
   }
-  // B fragments of this wave's 16 output channels: lane (column lane%16, k group lane/16),
-  // step s = tap*(CP/32) + cb at element offset 32 s of the channel's weights
+  // B fragments of this wave's 16 output channels for its group's chunk: lane (column lane%16,
+  // k group lane/16), step s = tap*(CP/32) + cb at element offset 32 s of the channel's weights
   const int nb = n0 + 16 * wn + (lane & 15);
-  const uint16_t* wb = nb < v.Cout ? v.W + (long long)nb * 9 * CP + 8 * (lane >> 4) : zrow;
+  const int s0 = grp * CST;
+  const uint16_t* wb = nb < v.Cout ? v.W + (long long)nb * 9 * CP + 8 * (lane >> 4) + 32 * s0 : zrow;
   const int wstep = nb < v.Cout ? 32 : 0;
   uint4 rb[RING];
 #pragma unroll
   for (int s = 0; s < RING; ++s) rb[s] = ld16g(wb + s * wstep);
 #pragma unroll
   for (int u = 0; u < CPT; ++u) {
-    const int q = tid + 256 * u;
+    const int q = tid + 256 * G * u;
     if (q < CHUNKS) {
       const int pix = q / (CP / 8), c8 = q - pix * (CP / 8);
       *reinterpret_cast<uint4*>(&L[pix * Hl::PS + 8 * c8]) = h[u];
@@ -791,42 +798,77 @@ __global__ void __launch_bounds__(256) k_conv3_halo(ConvFwd v) {
   // A fragment base: patch row BI*wm + i, pixel lane%16, channels 8*(lane/16)
   const uint16_t* abase = L + ((BI * wm) * Hl::HX + (lane & 15)) * Hl::PS + 8 * (lane >> 4);
 #pragma unroll
-  for (int s = 0; s < NSTEPS; ++s) {
+  for (int sl = 0; sl < CST; ++sl) {
+    // step s = s0 + sl: tap t, channel block cb (runtime for G > 1: one offset add)
+    const int s = s0 + sl;
     const int t = s / (CP / 32), cb = s % (CP / 32);
     const int dy = t / 3, dx = t % 3;                   // halo offsets of tap t (input = output + t - 1)
-    const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&rb[s % RING]);
-    if (s + RING < NSTEPS) rb[s % RING] = ld16g(wb + (s + RING) * wstep);
+    const uint16_t* ap = abase + (dy * Hl::HX + dx) * Hl::PS + 32 * cb;
+    const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&rb[sl % RING]);
+    if (sl + RING < CST) rb[sl % RING] = ld16g(wb + (sl + RING) * wstep);
 #pragma unroll
     for (int i = 0; i < BI; ++i) {
-      const bf16x8 fa = *reinterpret_cast<const bf16x8*>(abase + ((i + dy) * Hl::HX + dx) * Hl::PS + 32 * cb);
+      const bf16x8 fa = *reinterpret_cast<const bf16x8*>(ap + i * Hl::HX * Hl::PS);
       acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[i], 0, 0, 0);
     }
     // keep each step's LDS reads within the step (hoisting them across the
     // unrolled loop costs more registers than it hides latency)
     if constexpr (BI > 4) __builtin_amdgcn_sched_barrier(0);
   }
-  // epilogue: bias, ReLU, BF16 into LDS as [pixel][channel], then 16-byte stores
   const float bias = v.pre(0, nb);
   __syncthreads();                                     // every wave is done with the halo
+  float* red = reinterpret_cast<float*>(L);
+  uint16_t* ost = L + Hl::RED;
+  if constexpr (G > 1) {
+    // chunk sums: groups 1..G-1 through LDS, group 0 adds them in chunk order
+    if (grp > 0) {
 #pragma unroll
-  for (int i = 0; i < BI; ++i)
+      for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int pix = (BI * wm + i) * kHaloPX + 4 * (lane >> 4) + q;
-      L[pix * Hl::OS + 16 * wn + (lane & 15)] = f2bf(v.act(acc[i][q], bias));
+        for (int q = 0; q < 4; ++q) {
+          const int pix = (BI * wm + i) * kHaloPX + 4 * (lane >> 4) + q;
+          red[((grp - 1) * Hl::PIX + pix) * TN + 16 * wn + (lane & 15)] = acc[i][q];
+        }
     }
-  __syncthreads();
-  constexpr int PIECES = kHaloPY * kHaloPX * (TN / 8);
+    __syncthreads();
+    if (grp == 0) {
 #pragma unroll
-  for (int u = 0; u < PIECES / 256; ++u) {
-    const int q = tid + 256 * u;
+      for (int i = 0; i < BI; ++i) {
+        f32x4 tot = f32x4{0.f, 0.f, 0.f, 0.f};
+        tot += acc[i];
+#pragma unroll
+        for (int g = 1; g < G; ++g)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int pix = (BI * wm + i) * kHaloPX + 4 * (lane >> 4) + q;
+            tot[q] += red[((g - 1) * Hl::PIX + pix) * TN + 16 * wn + (lane & 15)];
+          }
+        acc[i] = tot;
+      }
+    }
+  }
+  // epilogue: bias, ReLU, BF16 into LDS as [pixel][channel], then 16-byte stores
+  if (grp == 0) {
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pix = (BI * wm + i) * kHaloPX + 4 * (lane >> 4) + q;
+        ost[pix * Hl::OS + 16 * wn + (lane & 15)] = f2bf(v.act(acc[i][q], bias));
+      }
+  }
+  __syncthreads();
+  constexpr int PIECES = Hl::PIX * (TN / 8);
+#pragma unroll
+  for (int u = 0; u < (PIECES + 256 * G - 1) / (256 * G); ++u) {
+    const int q = tid + 256 * G * u;
     const int pix = q / (TN / 8), c8 = q % (TN / 8);
     const int y = y0 + pix / kHaloPX, x = x0 + pix % kHaloPX;
     const int n = n0 + 8 * c8;
-    if (y < H && x < W && n < v.Cout) {
+    if (q < PIECES && y < H && x < W && n < v.Cout) {
       const long long gp = ((long long)b * H + y) * W + x;
       *reinterpret_cast<uint4*>(v.out.p + gp * v.out.cs + v.out.co + n) =
-          *reinterpret_cast<const uint4*>(&L[pix * Hl::OS + 8 * c8]);
+          *reinterpret_cast<const uint4*>(&ost[pix * Hl::OS + 8 * c8]);
     }
   }
 }
