@@ -494,8 +494,11 @@ int conv_chunks(const LayerInfo& l, int H, int W) {
   return c;
 }
 
-void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32, Geo g, bool relu,
-                     hipStream_t s) {
+// `pool` (optional, pool.p == nullptr: none): the 2x2 max-pool of the output
+// into that slice, fused where the halo-tile kernel runs; returns whether it
+// was fused (else the caller pools).
+bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32, Geo g, bool relu,
+                     hipStream_t s, Act pool = Act{nullptr, 0, 0, 0}) {
   const LayerInfo& l = layer(li);
   const int chunks = conv_chunks(l, g.H, g.W);
   unet::ConvFwd v{in, net->wbf + l.w_off, net->master + l.b_off, out, out32, g, l.taps, l.cp, l.cout,
@@ -504,7 +507,7 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
   const int nsteps = l.taps * (l.cp / 32);     // K steps of the tiled kernels
   if (l.cp == 8 && l.taps == 9 && l.cout == 32) {  // the first layer (3 channels padded to 8)
     PNP_LAUNCH(unet::k_conv_first, dim3(blocks_for(P, 128)), dim3(256), 0, s, v);
-    return;
+    return false;
   }
   // 3x3 layers with 32, 64 or 128 input channels: the halo-tile kernel, one
   // group of four waves per K chunk (bit-identical to the tiled kernel)
@@ -516,8 +519,9 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
     const dim3 grid(patches, l.cout / (wide ? 64 : 32)), block(256 * chunks);
 #define PNP_HALO(CPV, TNV, GV)                                                           \
   if (l.cp == CPV && (wide ? 64 : 32) == TNV && chunks == GV) {                          \
+    v.pool = g.H % 2 == 0 && g.W % 2 == 0 ? pool : Act{nullptr, 0, 0, 0};               \
     PNP_LAUNCH((unet::k_conv3_halo<CPV, TNV, GV>), grid, block, 0, s, v);                \
-    return;                                                                              \
+    return v.pool.p != nullptr;                                                          \
   }
     PNP_HALO(32, 32, 1) PNP_HALO(32, 64, 1) PNP_HALO(64, 32, 1) PNP_HALO(64, 64, 1)
     PNP_HALO(128, 32, 1) PNP_HALO(128, 64, 1)
@@ -552,6 +556,7 @@ void launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
     PNP_LAUNCH(unet::k_mfma_gemm<unet::ConvFwd>, dim3(blocks_for(P, 64), blocks_for(l.cout, 64), 1), dim3(256),
                0, s, v);
   }
+  return false;
 }
 
 void launch_up_fwd(const pnp_unet* net, int li, Act in, Act out, Geo g, hipStream_t s) {
@@ -787,14 +792,15 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
              (long long)H * W, w.x0);
   // encoder
   launch_conv_fwd(net, 0, A(w.x0, 8, 0, 8), A(w.e1a, 32, 0, 32), nullptr, g0, true, s);
-  launch_conv_fwd(net, 1, A(w.e1a, 32, 0, 32), A(w.c1, 64, 0, 32), nullptr, g0, true, s);
-  launch_pool(A(w.c1, 64, 0, 32), A(w.p1, 32, 0, 32), g1, 32, s);
+  if (!launch_conv_fwd(net, 1, A(w.e1a, 32, 0, 32), A(w.c1, 64, 0, 32), nullptr, g0, true, s, A(w.p1, 32, 0, 32)))
+    launch_pool(A(w.c1, 64, 0, 32), A(w.p1, 32, 0, 32), g1, 32, s);
   launch_conv_fwd(net, 2, A(w.p1, 32, 0, 32), A(w.e2a, 64, 0, 64), nullptr, g1, true, s);
-  launch_conv_fwd(net, 3, A(w.e2a, 64, 0, 64), A(w.c2, 128, 0, 64), nullptr, g1, true, s);
-  launch_pool(A(w.c2, 128, 0, 64), A(w.p2, 64, 0, 64), g2, 64, s);
+  if (!launch_conv_fwd(net, 3, A(w.e2a, 64, 0, 64), A(w.c2, 128, 0, 64), nullptr, g1, true, s, A(w.p2, 64, 0, 64)))
+    launch_pool(A(w.c2, 128, 0, 64), A(w.p2, 64, 0, 64), g2, 64, s);
   launch_conv_fwd(net, 4, A(w.p2, 64, 0, 64), A(w.e3a, 128, 0, 128), nullptr, g2, true, s);
-  launch_conv_fwd(net, 5, A(w.e3a, 128, 0, 128), A(w.c3, 256, 0, 128), nullptr, g2, true, s);
-  launch_pool(A(w.c3, 256, 0, 128), A(w.p3, 128, 0, 128), g3, 128, s);
+  if (!launch_conv_fwd(net, 5, A(w.e3a, 128, 0, 128), A(w.c3, 256, 0, 128), nullptr, g2, true, s,
+                       A(w.p3, 128, 0, 128)))
+    launch_pool(A(w.c3, 256, 0, 128), A(w.p3, 128, 0, 128), g3, 128, s);
   launch_conv_fwd(net, 6, A(w.p3, 128, 0, 128), A(w.ba, 256, 0, 256), nullptr, g3, true, s);
   launch_conv_fwd(net, 7, A(w.ba, 256, 0, 256), A(w.bb, 256, 0, 256), nullptr, g3, true, s);
   // decoder

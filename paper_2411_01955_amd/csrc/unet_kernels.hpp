@@ -201,6 +201,7 @@ struct ConvFwd {
   Geo g;
   int taps, Cp, Cout, relu;
   int chunks;             // K chunks summed in order (k_gemm_tiled; 1 elsewhere)
+  Act pool;               // k_conv3_halo: also the 2x2 max-pool of the output (pool.p == nullptr: none)
   __device__ int k_lo(int) const { return 0; }
   __device__ int k_hi(int) const { return taps * Cp; }
   // start of output channel n's weights (k_gemm_tiled)
@@ -869,6 +870,42 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
       const long long gp = ((long long)b * H + y) * W + x;
       *reinterpret_cast<uint4*>(v.out.p + gp * v.out.cs + v.out.co + n) =
           *reinterpret_cast<const uint4*>(&ost[pix * Hl::OS + 8 * c8]);
+    }
+  }
+  // fused 2x2 max-pool (H, W even; the patch covers whole windows): the
+  // first maximum in window order (0,0), (0,1), (1,0), (1,1), as k_unet_pool
+  if (v.pool.p) {
+    constexpr int PP = (kHaloPY / 2) * (kHaloPX / 2) * (TN / 8);
+#pragma unroll
+    for (int u = 0; u < (PP + 256 * G - 1) / (256 * G); ++u) {
+      const int q = tid + 256 * G * u;
+      const int pp = q / (TN / 8), c8 = q % (TN / 8);
+      const int py = pp / (kHaloPX / 2), px = pp % (kHaloPX / 2);
+      const int y = (y0 >> 1) + py, x = (x0 >> 1) + px;
+      const int n = n0 + 8 * c8;
+      if (q < PP && 2 * y < H && 2 * x < W && n < v.Cout) {
+        uint16_t best[8];
+        float bv[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int pix = (2 * py + (k >> 1)) * kHaloPX + 2 * px + (k & 1);
+          const uint4 w4 = *reinterpret_cast<const uint4*>(&ost[pix * Hl::OS + 8 * c8]);
+          const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const uint16_t hv = (uint16_t)((w[c >> 1] >> (16 * (c & 1))) & 0xffffu);
+            const float f = bf2f(hv);
+            if (k == 0 || f > bv[c]) {
+              bv[c] = f;
+              best[c] = hv;
+            }
+          }
+        }
+        const long long gp = ((long long)b * (H >> 1) + y) * (W >> 1) + x;
+        *reinterpret_cast<uint4*>(v.pool.p + gp * v.pool.cs + v.pool.co + n) =
+            make_uint4(best[0] | ((uint32_t)best[1] << 16), best[2] | ((uint32_t)best[3] << 16),
+                       best[4] | ((uint32_t)best[5] << 16), best[6] | ((uint32_t)best[7] << 16));
+      }
     }
   }
 }
