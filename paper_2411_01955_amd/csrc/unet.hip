@@ -497,8 +497,14 @@ int conv_chunks(const LayerInfo& l, int H, int W) {
 // `pool` (optional, pool.p == nullptr: none): the 2x2 max-pool of the output
 // into that slice, fused where the halo-tile kernel runs; returns whether it
 // was fused (else the caller pools).
+// `head` (optional): the output layer's operands, fused likewise.
+struct HeadOut {
+  const float2* u;
+  float2* o;
+  float2* dst;
+};
 bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32, Geo g, bool relu,
-                     hipStream_t s, Act pool = Act{nullptr, 0, 0, 0}) {
+                     hipStream_t s, Act pool = Act{nullptr, 0, 0, 0}, const HeadOut* head = nullptr) {
   const LayerInfo& l = layer(li);
   const int chunks = conv_chunks(l, g.H, g.W);
   unet::ConvFwd v{in, net->wbf + l.w_off, net->master + l.b_off, out, out32, g, l.taps, l.cp, l.cout,
@@ -520,8 +526,16 @@ bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
 #define PNP_HALO(CPV, TNV, GV)                                                           \
   if (l.cp == CPV && (wide ? 64 : 32) == TNV && chunks == GV) {                          \
     v.pool = g.H % 2 == 0 && g.W % 2 == 0 ? pool : Act{nullptr, 0, 0, 0};               \
+    if (head && TNV == 32 && l.cout == 32) {                                             \
+      const LayerInfo& lh = layer(kLayers - 1);                                          \
+      v.head_w = net->wbf + lh.w_off;                                                    \
+      v.head_b = net->master + lh.b_off;                                                 \
+      v.head_u = head->u;                                                                \
+      v.head_o = head->o;                                                                \
+      v.head_dst = head->dst;                                                            \
+    }                                                                                    \
     PNP_LAUNCH((unet::k_conv3_halo<CPV, TNV, GV>), grid, block, 0, s, v);                \
-    return v.pool.p != nullptr;                                                          \
+    return head ? v.head_w != nullptr : v.pool.p != nullptr;                             \
   }
     PNP_HALO(32, 32, 1) PNP_HALO(32, 64, 1) PNP_HALO(64, 32, 1) PNP_HALO(64, 64, 1)
     PNP_HALO(128, 32, 1) PNP_HALO(128, 64, 1)
@@ -812,8 +826,9 @@ void unet_forward(const pnp_unet* net, const float2* u, const float* sigma, floa
   launch_conv_fwd(net, 13, A(w.d2a, 64, 0, 64), A(w.d2b, 64, 0, 64), nullptr, g1, true, s);
   launch_up_fwd(net, 14, A(w.d2b, 64, 0, 64), A(w.c1, 64, 32, 32), g1, s);
   launch_conv_fwd(net, 15, A(w.c1, 64, 0, 64), A(w.d1a, 32, 0, 32), nullptr, g0, true, s);
-  launch_conv_fwd(net, 16, A(w.d1a, 32, 0, 32), A(w.d1b, 32, 0, 32), nullptr, g0, true, s);
-  {
+  const HeadOut head{u, reinterpret_cast<float2*>(w.out), out};
+  if (!launch_conv_fwd(net, 16, A(w.d1a, 32, 0, 32), A(w.d1b, 32, 0, 32), nullptr, g0, true, s,
+                       Act{nullptr, 0, 0, 0}, &head)) {
     const LayerInfo& l = layer(17);
     PNP_LAUNCH(k_unet_head, dim3(blocks_for(P0)), dim3(kThreads), 0, s, w.d1b, net->wbf + l.w_off,
                net->master + l.b_off, u, P0, reinterpret_cast<float2*>(w.out), out);

@@ -202,6 +202,14 @@ struct ConvFwd {
   int taps, Cp, Cout, relu;
   int chunks;             // K chunks summed in order (k_gemm_tiled; 1 elsewhere)
   Act pool;               // k_conv3_halo: also the 2x2 max-pool of the output (pool.p == nullptr: none)
+  // k_conv3_halo, a 32-channel output: also the network's 1 x 1 output layer
+  // and residual (head_w == nullptr: none): head_o[p] = head_b + head_w . out[p]
+  // (FP32, channels in order) and head_dst[p] = head_u[p] + head_o[p] when set
+  const uint16_t* head_w;  // BF16 [2][32]
+  const float* head_b;     // FP32 [2]
+  const float2* head_u;
+  float2* head_o;
+  float2* head_dst;
   __device__ int k_lo(int) const { return 0; }
   __device__ int k_hi(int) const { return taps * Cp; }
   // start of output channel n's weights (k_gemm_tiled)
@@ -870,6 +878,29 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
       const long long gp = ((long long)b * H + y) * W + x;
       *reinterpret_cast<uint4*>(v.out.p + gp * v.out.cs + v.out.co + n) =
           *reinterpret_cast<const uint4*>(&ost[pix * Hl::OS + 8 * c8]);
+    }
+  }
+  // fused output layer: one thread per pixel, the dot products in channel
+  // order as k_unet_head (TN = 32 = all channels in this workgroup)
+  if constexpr (TN == 32) {
+    if (v.head_w && tid < Hl::PIX) {
+      const int y = y0 + tid / kHaloPX, x = x0 + tid % kHaloPX;
+      if (y < H && x < W) {
+        float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+          const float f = bf2f(ost[tid * Hl::OS + c]);
+          a0 = fmaf(f, bf2f(v.head_w[c]), a0);
+          a1 = fmaf(f, bf2f(v.head_w[32 + c]), a1);
+        }
+        const long long gp = ((long long)b * H + y) * W + x;
+        const float2 r = make_float2(a0 + v.head_b[0], a1 + v.head_b[1]);
+        v.head_o[gp] = r;
+        if (v.head_dst) {
+          const float2 uu = v.head_u[gp];
+          v.head_dst[gp] = make_float2(uu.x + r.x, uu.y + r.y);
+        }
+      }
     }
   }
   // fused 2x2 max-pool (H, W even; the patch covers whole windows): the
