@@ -534,7 +534,7 @@ bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
       v.head_o = head->o;                                                                \
       v.head_dst = head->dst;                                                            \
     }                                                                                    \
-    PNP_LAUNCH((unet::k_conv3_halo<CPV, TNV, GV>), grid, block, 0, s, v);                \
+    PNP_LAUNCH((unet::k_conv3_halo<unet::ConvFwd, CPV, TNV, GV>), grid, block, 0, s, v); \
     return head ? v.head_w != nullptr : v.pool.p != nullptr;                             \
   }
     PNP_HALO(32, 32, 1) PNP_HALO(32, 64, 1) PNP_HALO(64, 32, 1) PNP_HALO(64, 64, 1)
@@ -646,6 +646,23 @@ void launch_dw_reduce(pnp_unet* net, int B, int H, int W, const float* dwpart, h
 void launch_conv_dx(const pnp_unet* net, int li, Act dz, Act dx, Mask mask, Geo g, hipStream_t s) {
   const LayerInfo& l = layer(li);
   const long long P = (long long)g.B * g.H * g.W;
+  // 3x3 layers whose output gradient has 32, 64 or 128 channels: the
+  // halo-tile kernel (mirrored taps; bit-identical to the tiled kernel)
+  if (l.taps == 9 && (l.coutp == 32 || l.coutp == 64 || l.coutp == 128) && l.cin % 32 == 0) {
+    unet::ConvDXT v{dz, net->wt + l.wt_off, dx, mask, g, l.taps, l.coutp, l.cin, 1};
+    const unsigned patches = (unsigned)(g.B * ((g.H + unet::kHaloPY - 1) / unet::kHaloPY) *
+                                        ((g.W + unet::kHaloPX - 1) / unet::kHaloPX));
+    const bool wide = l.cin % 64 == 0;
+    const dim3 grid(patches, l.cin / (wide ? 64 : 32));
+#define PNP_HALO_DX(CPV, TNV)                                                            \
+  if (l.coutp == CPV && (wide ? 64 : 32) == TNV) {                                       \
+    PNP_LAUNCH((unet::k_conv3_halo<unet::ConvDXT, CPV, TNV, 1>), grid, dim3(256), 0, s, v); \
+    return;                                                                              \
+  }
+    PNP_HALO_DX(32, 32) PNP_HALO_DX(32, 64) PNP_HALO_DX(64, 32) PNP_HALO_DX(64, 64) PNP_HALO_DX(128, 32)
+    PNP_HALO_DX(128, 64)
+#undef PNP_HALO_DX
+  }
   // the tiled kernels where the output-gradient channels come in 32-wide
   // chunks (every layer but the 2-channel output); the generic kernel else
   if (l.coutp % 32 == 0 && (l.taps * (l.coutp / 32)) % 3 == 0 && (l.cin == 32 || l.cin % 64 == 0)) {

@@ -24,6 +24,8 @@
 // Channel counts, strides and offsets are multiples of 8 (16-byte loads).
 #pragma once
 
+#include <type_traits>
+
 #include <cstring>
 
 #include "common.hpp"
@@ -721,9 +723,11 @@ struct UpDX {
 };
 
 // ------------------------------------------------ 3x3 convolution from an LDS halo tile
-// Forward 3x3 convolution for layers with CP (32, 64 or 128) padded input
-// channels: a workgroup computes an 8 x 16-pixel output patch for TN (32 or
-// 64) output channels.  It stages the 10 x 18-pixel input patch (the 3x3
+// 3x3 convolution for layers with CP (32, 64 or 128) padded input channels
+// -- the forward pass (view ConvFwd) or the input gradient (ConvDXT: input
+// dZ, the transposed weights, mirrored taps, the producer's ReLU mask on the
+// output) -- : a workgroup computes an 8 x 16-pixel output patch for TN (32
+// or 64) output channels.  It stages the 10 x 18-pixel input patch (the 3x3
 // halo, zeros outside the image) once in LDS; the K loop -- taps in order,
 // 32 channels a step, as in k_gemm_tiled -- then reads every A fragment
 // from LDS at a compile-time offset (16 pixels of one patch row, 8 channels
@@ -751,8 +755,9 @@ struct Halo {
   static constexpr int WN = TN / 16, WM = 4 / WN, BI = kHaloPY / WM;   // waves along N, along M; rows a wave
 };
 
-template <int CP, int TN, int G>
-__global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
+template <class V, int CP, int TN, int G>
+__global__ void __launch_bounds__(256 * G) k_conv3_halo(V v) {
+  constexpr bool FWD = std::is_same<V, ConvFwd>::value;
   using Hl = Halo<CP, TN, G>;
   constexpr int NSTEPS = 9 * (CP / 32);
   static_assert(NSTEPS % G == 0, "whole chunks");
@@ -811,7 +816,8 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
     // step s = s0 + sl: tap t, channel block cb (runtime for G > 1: one offset add)
     const int s = s0 + sl;
     const int t = s / (CP / 32), cb = s % (CP / 32);
-    const int dy = t / 3, dx = t % 3;                   // halo offsets of tap t (input = output + t - 1)
+    // halo offsets of tap t: input = output + (t/3 - 1, t%3 - 1), mirrored for the input gradient
+    const int dy = V::TAP_SIGN > 0 ? t / 3 : 2 - t / 3, dx = V::TAP_SIGN > 0 ? t % 3 : 2 - t % 3;
     const uint16_t* ap = abase + (dy * Hl::HX + dx) * Hl::PS + 32 * cb;
     const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&rb[sl % RING]);
     if (sl + RING < CST) rb[sl % RING] = ld16g(wb + (sl + RING) * wstep);
@@ -877,12 +883,12 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
     if (q < PIECES && y < H && x < W && n < v.Cout) {
       const long long gp = ((long long)b * H + y) * W + x;
       *reinterpret_cast<uint4*>(v.out.p + gp * v.out.cs + v.out.co + n) =
-          *reinterpret_cast<const uint4*>(&ost[pix * Hl::OS + 8 * c8]);
+          v.finish8((int)gp, n, *reinterpret_cast<const uint4*>(&ost[pix * Hl::OS + 8 * c8]));
     }
   }
   // fused output layer: one thread per pixel, the dot products in channel
   // order as k_unet_head (TN = 32 = all channels in this workgroup)
-  if constexpr (TN == 32) {
+  if constexpr (FWD && TN == 32) {
     if (v.head_w && tid < Hl::PIX) {
       const int y = y0 + tid / kHaloPX, x = x0 + tid % kHaloPX;
       if (y < H && x < W) {
@@ -905,6 +911,7 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
   }
   // fused 2x2 max-pool (H, W even; the patch covers whole windows): the
   // first maximum in window order (0,0), (0,1), (1,0), (1,1), as k_unet_pool
+  if constexpr (FWD) {
   if (v.pool.p) {
     constexpr int PP = (kHaloPY / 2) * (kHaloPX / 2) * (TN / 8);
 #pragma unroll
@@ -938,6 +945,7 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(ConvFwd v) {
                        best[4] | ((uint32_t)best[5] << 16), best[6] | ((uint32_t)best[7] << 16));
       }
     }
+  }
   }
 }
 
