@@ -497,6 +497,16 @@ int conv_chunks(const LayerInfo& l, int H, int W) {
 // `pool` (optional, pool.p == nullptr: none): the 2x2 max-pool of the output
 // into that slice, fused where the halo-tile kernel runs; returns whether it
 // was fused (else the caller pools).
+// k_conv3_halo with its dynamic LDS (above 64 KB for 256 input channels)
+template <class V, int CP, int TN, int G>
+void launch_halo(dim3 grid, dim3 block, const V& v, hipStream_t s) {
+  const size_t bytes = sizeof(uint16_t) * unet::Halo<CP, TN, G>::LDS;
+  if (bytes > 65536)
+    PNP_HIP(hipFuncSetAttribute((const void*)unet::k_conv3_halo<V, CP, TN, G>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  PNP_LAUNCH((unet::k_conv3_halo<V, CP, TN, G>), grid, block, bytes, s, v);
+}
+
 // `head` (optional): the output layer's operands, fused likewise.
 struct HeadOut {
   const float2* u;
@@ -517,8 +527,8 @@ bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
   }
   // 3x3 layers with 32, 64 or 128 input channels: the halo-tile kernel, one
   // group of four waves per K chunk (bit-identical to the tiled kernel)
-  if (l.taps == 9 && (l.cp == 32 || l.cp == 64 || l.cp == 128) && l.cout % 32 == 0 && out32 == nullptr &&
-      (chunks == 1 || chunks == 2 || chunks == 4)) {
+  if (l.taps == 9 && (l.cp == 32 || l.cp == 64 || l.cp == 128 || l.cp == 256) && l.cout % 32 == 0 &&
+      out32 == nullptr && (chunks == 1 || chunks == 2 || chunks == 4)) {
     const unsigned patches = (unsigned)(g.B * ((g.H + unet::kHaloPY - 1) / unet::kHaloPY) *
                                         ((g.W + unet::kHaloPX - 1) / unet::kHaloPX));
     const bool wide = l.cout % 64 == 0 && chunks <= 2;   // 64 output channels a workgroup
@@ -534,12 +544,13 @@ bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
       v.head_o = head->o;                                                                \
       v.head_dst = head->dst;                                                            \
     }                                                                                    \
-    PNP_LAUNCH((unet::k_conv3_halo<unet::ConvFwd, CPV, TNV, GV>), grid, block, 0, s, v); \
+    launch_halo<unet::ConvFwd, CPV, TNV, GV>(grid, block, v, s);                         \
     return head ? v.head_w != nullptr : v.pool.p != nullptr;                             \
   }
     PNP_HALO(32, 32, 1) PNP_HALO(32, 64, 1) PNP_HALO(64, 32, 1) PNP_HALO(64, 64, 1)
     PNP_HALO(128, 32, 1) PNP_HALO(128, 64, 1)
     PNP_HALO(64, 32, 2) PNP_HALO(64, 64, 2) PNP_HALO(128, 32, 2) PNP_HALO(128, 64, 2) PNP_HALO(128, 32, 4)
+    PNP_HALO(256, 32, 1) PNP_HALO(256, 64, 1) PNP_HALO(256, 32, 2) PNP_HALO(256, 64, 2) PNP_HALO(256, 32, 4)
 #undef PNP_HALO
   }
   // larger tiles where the input channels come in 32-wide chunks and the
@@ -648,7 +659,7 @@ void launch_conv_dx(const pnp_unet* net, int li, Act dz, Act dx, Mask mask, Geo 
   const long long P = (long long)g.B * g.H * g.W;
   // 3x3 layers whose output gradient has 32, 64 or 128 channels: the
   // halo-tile kernel (mirrored taps; bit-identical to the tiled kernel)
-  if (l.taps == 9 && (l.coutp == 32 || l.coutp == 64 || l.coutp == 128) && l.cin % 32 == 0) {
+  if (l.taps == 9 && (l.coutp == 32 || l.coutp == 64 || l.coutp == 128 || l.coutp == 256) && l.cin % 32 == 0) {
     unet::ConvDXT v{dz, net->wt + l.wt_off, dx, mask, g, l.taps, l.coutp, l.cin, 1};
     const unsigned patches = (unsigned)(g.B * ((g.H + unet::kHaloPY - 1) / unet::kHaloPY) *
                                         ((g.W + unet::kHaloPX - 1) / unet::kHaloPX));
@@ -656,11 +667,11 @@ void launch_conv_dx(const pnp_unet* net, int li, Act dz, Act dx, Mask mask, Geo 
     const dim3 grid(patches, l.cin / (wide ? 64 : 32));
 #define PNP_HALO_DX(CPV, TNV)                                                            \
   if (l.coutp == CPV && (wide ? 64 : 32) == TNV) {                                       \
-    PNP_LAUNCH((unet::k_conv3_halo<unet::ConvDXT, CPV, TNV, 1>), grid, dim3(256), 0, s, v); \
+    launch_halo<unet::ConvDXT, CPV, TNV, 1>(grid, dim3(256), v, s);                      \
     return;                                                                              \
   }
     PNP_HALO_DX(32, 32) PNP_HALO_DX(32, 64) PNP_HALO_DX(64, 32) PNP_HALO_DX(64, 64) PNP_HALO_DX(128, 32)
-    PNP_HALO_DX(128, 64)
+    PNP_HALO_DX(128, 64) PNP_HALO_DX(256, 32) PNP_HALO_DX(256, 64)
 #undef PNP_HALO_DX
   }
   // the tiled kernels where the output-gradient channels come in 32-wide

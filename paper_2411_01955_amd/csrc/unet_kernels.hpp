@@ -723,7 +723,7 @@ struct UpDX {
 };
 
 // ------------------------------------------------ 3x3 convolution from an LDS halo tile
-// 3x3 convolution for layers with CP (32, 64 or 128) padded input channels
+// 3x3 convolution for layers with CP (32, 64, 128 or 256) padded input channels
 // -- the forward pass (view ConvFwd) or the input gradient (ConvDXT: input
 // dZ, the transposed weights, mirrored taps, the producer's ReLU mask on the
 // output) -- : a workgroup computes an 8 x 16-pixel output patch for TN (32
@@ -766,7 +766,7 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(V v) {
   constexpr int CHUNKS = Hl::HY * Hl::HX * (CP / 8);     // 16-byte pieces of the halo patch
   constexpr int CPT = (CHUNKS + 256 * G - 1) / (256 * G);
   constexpr int BI = Hl::BI;
-  __shared__ __attribute__((aligned(16))) uint16_t L[Hl::LDS];
+  extern __shared__ __attribute__((aligned(16))) uint16_t L[];   // Hl::LDS elements (dynamic: CP = 256 needs 95 KB)
   const int tid = threadIdx.x, grp = tid >> 8, lane = tid & 63, wave = (tid & 255) >> 6;
   const int wn = wave % Hl::WN, wm = wave / Hl::WN;
   const int H = v.g.H, W = v.g.W;
@@ -777,17 +777,38 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(V v) {
   const int n0 = blockIdx.y * TN;
   const uint16_t* zrow = reinterpret_cast<const uint16_t*>(kZeroRow);
   // the halo patch first (the critical path): piece q = (pixel, 8-channel group), pixel = hy*HX + hx
-  uint4 h[CPT];
+  // (in batches of at most HB pieces a thread, the last batch held across the weight loads)
+  constexpr int HB = CPT < 12 ? CPT : 12;
+  uint4 h[HB];
+  auto hload = [&](int u0) {
 #pragma unroll
-  for (int u = 0; u < CPT; ++u) {
-    const int q = tid + 256 * G * u;
-    const int pix = q / (CP / 8), c8 = q - pix * (CP / 8);
-    const int hy = pix / Hl::HX, hx = pix - hy * Hl::HX;
-    const int y = y0 + hy - 1, x = x0 + hx - 1;
-    const bool ok = q < CHUNKS && (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
-    const long long gp = ((long long)b * H + y) * W + x;
-    h[u] = ld16g(ok ? v.in.p + gp * v.in.cs + v.in.co + 8 * c8 : zrow);
+    for (int u = 0; u < HB; ++u) {
+      const int q = tid + 256 * G * (u0 + u);
+      const int pix = q / (CP / 8), c8 = q - pix * (CP / 8);
+      const int hy = pix / Hl::HX, hx = pix - hy * Hl::HX;
+      const int y = y0 + hy - 1, x = x0 + hx - 1;
+      const bool ok = u0 + u < CPT && q < CHUNKS && (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
+      const long long gp = ((long long)b * H + y) * W + x;
+      h[u] = ld16g(ok ? v.in.p + gp * v.in.cs + v.in.co + 8 * c8 : zrow);
+    }
+  };
+  auto hstore = [&](int u0) {
+#pragma unroll
+    for (int u = 0; u < HB; ++u) {
+      const int q = tid + 256 * G * (u0 + u);
+      if (u0 + u < CPT && q < CHUNKS) {
+        const int pix = q / (CP / 8), c8 = q - pix * (CP / 8);
+        *reinterpret_cast<uint4*>(&L[pix * Hl::PS + 8 * c8]) = h[u];
+      }
+    }
+  };
+#pragma unroll
+  for (int u0 = 0; u0 + HB < CPT; u0 += HB) {
+    hload(u0);
+    hstore(u0);
   }
+  constexpr int HLAST = (CPT - 1) / HB * HB;
+  hload(HLAST);
   // B fragments of this wave's 16 output channels for its group's chunk: lane (column lane%16,
   // k group lane/16), step s = tap*(CP/32) + cb at element offset 32 s of the channel's weights
   const int nb = n0 + 16 * wn + (lane & 15);
@@ -797,14 +818,7 @@ __global__ void __launch_bounds__(256 * G) k_conv3_halo(V v) {
   uint4 rb[RING];
 #pragma unroll
   for (int s = 0; s < RING; ++s) rb[s] = ld16g(wb + s * wstep);
-#pragma unroll
-  for (int u = 0; u < CPT; ++u) {
-    const int q = tid + 256 * G * u;
-    if (q < CHUNKS) {
-      const int pix = q / (CP / 8), c8 = q - pix * (CP / 8);
-      *reinterpret_cast<uint4*>(&L[pix * Hl::PS + 8 * c8]) = h[u];
-    }
-  }
+  hstore(HLAST);
   __syncthreads();
   f32x4 acc[BI];
 #pragma unroll
