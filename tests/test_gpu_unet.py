@@ -60,8 +60,11 @@ FWD = ("x0", "e1a", "c1", "d1a", "d1b", "p1", "e2a", "c2", "d2a", "d2b", "p2", "
        "p3", "ba", "bb", "out")
 
 
-def test_forward_layers_teacher_forced(pnp):
-    B, H, W = 2, 32, 40
+@pytest.mark.parametrize("B,H,W", [(2, 32, 40), (1, 40, 72)])
+def test_forward_layers_teacher_forced(pnp, B, H, W):
+    """(1, 40, 72): 8 x 16-pixel output patches cut at the right edge on every
+    level (72 = 4.5 patches) and a 5 x 9 bottleneck; the max-pools and the
+    output layer come from the convolutions' fused epilogues."""
     params, net, u, sigma = _setup(pnp, B, H, W)
     D = net.forward(_dev(u), _dev(sigma), train=True)
     a = _acts(net, FWD, B, H, W)
@@ -100,7 +103,7 @@ def test_forward_layers_teacher_forced(pnp):
     ]
     for name, ref, got in checks:
         e = rel_l2(got, ref)
-        say(f"[unet fwd] {name}: rel {e:.2e}  ({np.count_nonzero(got != ref)} of {ref.size} differ)")
+        say(f"[unet fwd {B}x{H}x{W}] {name}: rel {e:.2e}  ({np.count_nonzero(got != ref)} of {ref.size} differ)")
         if name.startswith("p"):
             assert np.array_equal(got, ref), name     # max of identical BF16 values
         elif name == "out":
@@ -112,7 +115,7 @@ def test_forward_layers_teacher_forced(pnp):
     assert rel_l2(Dg, u + (out[..., 0] + 1j * out[..., 1])) < 1e-6
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (3, 48, 48)])
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (3, 48, 48), (1, 40, 72)])
 def test_backward_layers_teacher_forced(pnp, B, H, W):
     """(3, 48, 48): the weight gradients of the full-resolution layers split
     over 11 pixel slices of 640 with a 512-pixel tail, and the 6 x 6
