@@ -313,30 +313,50 @@ k_cols_fwd_fs(const float2* __restrict__ mid, int nx, int ny, int Kx, const floa
   }
 }
 
-constexpr int kSpreadChunk = 256;   // entries staged in LDS at a time
 constexpr int kAdjThreads = 512;    // spread uses all waves, the FFT the first 8*K1 threads
+constexpr int kSpreadChunk = kAdjThreads;   // entries staged in LDS at a time, one per thread
 constexpr int kAdjWaves = kAdjThreads / 64;
-constexpr int kSpreadIlp = 8;       // entries in flight per lane in the gather loop
+constexpr int kSpreadRB = 16;       // grid rows per spread block (the M side of one MFMA tile)
 constexpr int kMaxDense = 4;        // dense row blocks per strip shared by all waves
-static_assert(kMaxDense * kAdjWaves * 64 * sizeof(float2) <= kSpreadChunk * sizeof(EntryRec),
-              "dense-block partial sums fit in the entry staging buffer");
 
-// Type-1 spread by gathering: a work item is a strip of 8 grid columns --
-// the whole strip, or part p of P of a heavy strip (the k-space centre),
-// which takes every P-th staged chunk of the strip's entries starting at
-// chunk p; the parts run as separate workgroups, write partial grid strips
-// to their slots of `spart`, and k_cols_adj_fin_fs adds them in part order
-// and transforms the strip.  Wave w owns the 8x8 grid-point blocks
-// (rows 8*rb .. 8*rb+7 of the strip's 8 columns) with rb = w, w + 8, ...;
-// lane (row lr = lane/8, column lc = lane%8) accumulates in registers every
-// entry whose first row tap lies within 5 rows above its block (entries are
-// sorted by first row tap, row_start indexes them), reading the entry's taps,
-// weights and weighted k-space value from LDS as broadcasts.  Up to
-// kMaxDense blocks whose window holds dense_min or more entries (the densely
-// sampled k-space centre) are shared by all waves instead: each wave takes a
-// fixed slice of every staged chunk of the block's entries, and the eight
-// partial sums are added in wave order.  Each grid point is written once: no
-// atomics, deterministic summation order.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// LDS of the spread kernel: the grid strip, and -- while the entries are
+// gathered -- the staged chunk (its MFMA operands), then the dense blocks'
+// per-wave partial tiles; the three uses follow each other in time.
+template <int K1, int K2>
+struct AdjLds {
+  static constexpr int STRIP = 8 * FS<K1, K2>::CSTR * 8;
+  static constexpr int STAGE = kSpreadChunk * (16 + 8 + 1) * 4;   // B rows, row weights, first rows
+  static constexpr int DENSE = kMaxDense * kAdjWaves * 256 * 4;
+  static constexpr int M1 = STRIP > STAGE ? STRIP : STAGE;
+  static constexpr int BYTES = M1 > DENSE ? M1 : DENSE;
+};
+
+// Type-1 spread by gathering, as dense products on the matrix cores.  A work
+// item is a strip of 8 grid columns -- the whole strip, or part p of P of a
+// heavy strip (the k-space centre), which takes every P-th staged chunk of
+// the strip's entries starting at chunk p; the parts run as separate
+// workgroups, write partial grid strips to their slots of `spart`, and
+// k_cols_adj_fin_fs adds them in part order and transforms the strip.
+//
+// The kernel's weight factors over the two axes, so the contribution of a
+// set of entries to a block of 16 grid rows of the strip is a product
+//   G[r][c] += sum_e  wy_e(r - jy_e) * (w_e y_e) wx_e(c - jx_e)
+// of a 16 x E matrix of row weights and an E x 8 complex matrix of weighted
+// values times column weights (stored as 16 real columns, re then im): one
+// v_mfma_f32_16x16x4_f32 takes four entries.  Staging a chunk computes each
+// entry's B row once (its 16 values for this strip) and its row weights;
+// the MFMA loop only places the row weights (lane row i of the block gets
+// wy_e(16 rb + i - jy_e), or 0 outside the window).  Wave w owns the row
+// blocks rb = w, w + 8, ... and keeps their 16 x 16 tiles in registers,
+// taking every entry whose first row tap lies within 5 rows above the block
+// (entries are sorted by first row tap, row_start indexes them).  Up to
+// kMaxDense blocks whose window holds dense_min or more entries (the most
+// such blocks first: the densely sampled k-space centre) are shared by all
+// waves instead: each wave takes a fixed slice of every staged chunk of the
+// block's entries, and the eight partial tiles are added in wave order.
+// Each grid point is written once: no atomics, a fixed summation order.
 template <int K1, int K2>
 __global__ void __launch_bounds__(kAdjThreads)
 k_cols_adj_fs(const float2* __restrict__ yent, long long E,
@@ -345,13 +365,18 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
               const int4* __restrict__ items, int dense_min, const EntryRec* __restrict__ rec,
               float2* __restrict__ mid, float2* __restrict__ spart, int nslots) {
   using F = FS<K1, K2>;
-  constexpr int NRB = F::K / 8;                                  // row blocks per strip
+  constexpr int NRB = F::K / kSpreadRB;                          // row blocks per strip
   constexpr int RBW = (NRB + kAdjWaves - 1) / kAdjWaves;         // row blocks per wave
-  __shared__ float2 lds[8 * F::CSTR];
-  __shared__ EntryRec srec[kSpreadChunk];
-  __shared__ float2 sval[kSpreadChunk];
+  static_assert(F::K % kSpreadRB == 0, "row blocks tile the column");
+  __shared__ f32x4 U[AdjLds<K1, K2>::BYTES / 16];
   __shared__ int srs[F::K + 1];
   __shared__ int sdense[kMaxDense + 1];                          // count, then row blocks
+  float2* lds = reinterpret_cast<float2*>(U);                    // the grid strip (after the gather)
+  float* ldsf = reinterpret_cast<float*>(U);
+  float* Bs = reinterpret_cast<float*>(U);                       // [chunk][16] B rows
+  float* Wy = Bs + kSpreadChunk * 16;                            // [chunk][8] row weights
+  int* Jy = reinterpret_cast<int*>(Wy + kSpreadChunk * 8);       // [chunk] first row tap
+  f32x4* dpart = U;                                              // [dense][wave][lane] partial tiles
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;           // FFT threads: t < K1
   const int4 item = items[blockIdx.y];     // (strip, part, parts, first slot); heaviest first, coils adjacent
@@ -361,83 +386,124 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   const bool colok = c < tile && t < K1;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int lr = lane >> 3, lc = lane & 7;
-  int gc = c0 + lc;
-  if (gc >= Kx) gc -= Kx;
+  const int i16 = lane & 15, k4 = lane >> 4;   // MFMA: A row / B column i16, K index k4
+  const int e0 = tile_off[s], e1 = tile_off[s + 1];
+  int cb = e0 + item.y * kSpreadChunk;
+  // this thread's entry of the next chunk to stage, loaded ahead: first
+  // taps, column and row weights, weighted k-space value
+  struct Staged {
+    int jx, jy;
+    float wx[6], wy[6];
+    float2 v;
+  } nx_e;
+  auto fetch = [&](int cs) {
+    const int e = cs + (int)threadIdx.x;
+    if (cs < e1 && e < e1) {
+      const EntryRec r = rec[e];
+      nx_e.jx = r.idx.x;
+      nx_e.jy = r.idx.y;
+      nx_e.wx[0] = r.w0.x; nx_e.wx[1] = r.w0.y; nx_e.wx[2] = r.w0.z; nx_e.wx[3] = r.w0.w;
+      nx_e.wx[4] = r.w1.x; nx_e.wx[5] = r.w1.y;
+      nx_e.wy[0] = r.w1.z; nx_e.wy[1] = r.w1.w;
+      nx_e.wy[2] = r.w2.x; nx_e.wy[3] = r.w2.y; nx_e.wy[4] = r.w2.z; nx_e.wy[5] = r.w2.w;
+      nx_e.v = yent[(long long)l * E + e];
+    }
+  };
+  fetch(cb);
   for (int i = threadIdx.x; i <= F::K; i += blockDim.x) srs[i] = row_start[(long long)s * (F::K + 1) + i];
   __syncthreads();
-  // entry range(s) of the window of row block rb: rows [8 rb - 5, 8 rb + 8), wrapped
+  // entry range(s) of the window of row block rb: first row taps in
+  // [16 rb - 5, 16 rb + 16), wrapped
   auto window = [&](int rb, int& ra0, int& rb0, int& ra1, int& rb1) {
-    const int lo = rb * 8 - 5, hi = rb * 8 + 8;
+    const int lo = rb * kSpreadRB - 5, hi = rb * kSpreadRB + kSpreadRB;
     if (lo >= 0) {
       ra0 = srs[lo]; rb0 = srs[hi]; ra1 = 0; rb1 = 0;
     } else {
       ra0 = srs[F::K + lo]; rb0 = srs[F::K]; ra1 = srs[0]; rb1 = srs[hi];
     }
   };
-  if (threadIdx.x == 0) {
-    int nd = 0;
-    for (int rb = 0; rb < NRB && nd < kMaxDense; ++rb) {
+  static_assert(NRB <= 64, "one lane per row block");
+  if (wave == 0) {
+    // the kMaxDense fullest windows holding dense_min or more entries (ties:
+    // lower block first), in that order; lane rb scores block rb
+    int key = -1;
+    if (lane < NRB) {
       int ra0, rb0, ra1, rb1;
-      window(rb, ra0, rb0, ra1, rb1);
-      if ((rb0 - ra0) + (rb1 - ra1) >= dense_min) sdense[1 + nd++] = rb;
+      window(lane, ra0, rb0, ra1, rb1);
+      const int n = (rb0 - ra0) + (rb1 - ra1);
+      if (n >= dense_min) key = min(n, 1 << 24) * 64 + (63 - lane);
     }
-    sdense[0] = nd;
+    int nd = 0;
+    for (int d = 0; d < kMaxDense; ++d) {
+      int best = key;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) best = max(best, __shfl_xor(best, off));
+      if (best < 0) break;
+      if (lane == 0) sdense[1 + d] = 63 - (best & 63);
+      if (key == best) key = -1;
+      ++nd;
+    }
+    if (lane == 0) sdense[0] = nd;
   }
-  float2 acc[RBW], accd[kMaxDense];
+  f32x4 acc[RBW], accd[kMaxDense];
 #pragma unroll
-  for (int k = 0; k < RBW; ++k) acc[k] = make_float2(0.f, 0.f);
+  for (int k = 0; k < RBW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int d = 0; d < kMaxDense; ++d) accd[d] = make_float2(0.f, 0.f);
-  const int e0 = tile_off[s], e1 = tile_off[s + 1];
-  const float* srec_f = reinterpret_cast<const float*>(srec);
-  int cb = e0 + item.y * kSpreadChunk;
-  // entries [ea, eb) of the staged chunk starting at cb into grid point
-  // (row, gc): kSpreadIlp independent entries per step, all LDS reads of a
-  // step issued before any is consumed; out-of-range entries are clamped to a
-  // valid index and masked to zero weight
-  auto gather = [&](int ea, int eb, int row, float2& a) {
-    for (int e = ea; e < eb; e += kSpreadIlp) {
-      int ii[kSpreadIlp], dxc[kSpreadIlp], dyc[kSpreadIlp];
-      bool ok[kSpreadIlp];
-      int4 idx[kSpreadIlp];
+  for (int d = 0; d < kMaxDense; ++d) accd[d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // entries [ea, eb) of the staged chunk starting at cb into the 16-row block
+  // starting at row0, four entries per MFMA and two MFMAs per step (all LDS
+  // reads of a step issued first); lanes past eb get weight 0 and read a
+  // valid slot.  ea and eb are wave-uniform.
+  auto gather = [&](int ea, int eb, int row0, f32x4& a) {
+    ea = __builtin_amdgcn_readfirstlane(ea);
+    eb = __builtin_amdgcn_readfirstlane(eb);
+    const int row = row0 + i16;
+    for (int e = ea; e < eb; e += 8) {
+      int ii[2], jy[2];
 #pragma unroll
-      for (int u = 0; u < kSpreadIlp; ++u) {
-        ii[u] = min(e + u, eb - 1) - cb;
-        idx[u] = srec[ii[u]].idx;
+      for (int u = 0; u < 2; ++u) {
+        ii[u] = min(e + 4 * u + k4, eb - 1) - cb;
+        jy[u] = Jy[ii[u]];
       }
+      float av[2], bv[2];
 #pragma unroll
-      for (int u = 0; u < kSpreadIlp; ++u) {
-        int dx = gc - idx[u].x;
-        dx += dx < 0 ? Kx : 0;
-        int dy = row - idx[u].y;
+      for (int u = 0; u < 2; ++u) {
+        int dy = row - jy[u];
         dy += dy < 0 ? F::K : 0;
-        ok[u] = dx < 6 && dy < 6 && e + u < eb;
-        dxc[u] = ok[u] ? dx : 0;
-        dyc[u] = ok[u] ? dy : 0;
+        const bool ok = e + 4 * u + k4 < eb && dy < 6;
+        av[u] = Wy[ii[u] * 8 + (ok ? dy : 0)];
+        av[u] = ok ? av[u] : 0.f;
+        bv[u] = Bs[ii[u] * 16 + i16];
       }
-      float wx[kSpreadIlp], wy[kSpreadIlp];
-      float2 sv[kSpreadIlp];
-#pragma unroll
-      for (int u = 0; u < kSpreadIlp; ++u) {
-        wx[u] = srec_f[16 * ii[u] + 4 + dxc[u]];
-        wy[u] = srec_f[16 * ii[u] + 10 + dyc[u]];
-        sv[u] = sval[ii[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < kSpreadIlp; ++u) {
-        const float wgt = ok[u] ? wx[u] * wy[u] : 0.f;
-        a = make_float2(fmaf(wgt, sv[u].x, a.x), fmaf(wgt, sv[u].y, a.y));
-      }
+      a = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], bv[0], a, 0, 0, 0);
+      a = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], bv[1], a, 0, 0, 0);
     }
   };
   for (; cb < e1; cb += item.z * kSpreadChunk) {
     const int n = min(kSpreadChunk, e1 - cb);
     __syncthreads();  // previous chunk consumed (and the dense list written)
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      srec[i] = rec[cb + i];
-      sval[i] = yent[(long long)l * E + cb + i];
+    // staging: each thread forms its entry's B row (re and im of the 8 strip
+    // columns) and stores its row weights, then loads its entry of the next
+    // chunk, which arrives while this one is gathered
+    if ((int)threadIdx.x < n) {
+      const int i = threadIdx.x;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int gc = c0 + q;
+        if (gc >= Kx) gc -= Kx;
+        int dx = gc - nx_e.jx;
+        dx += dx < 0 ? Kx : 0;
+        float w = 0.f;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) w = dx == a ? nx_e.wx[a] : w;
+        Bs[i * 16 + q] = nx_e.v.x * w;
+        Bs[i * 16 + 8 + q] = nx_e.v.y * w;
+      }
+      Jy[i] = nx_e.jy;
+      *reinterpret_cast<float4*>(Wy + i * 8) = make_float4(nx_e.wy[0], nx_e.wy[1], nx_e.wy[2], nx_e.wy[3]);
+      *reinterpret_cast<float2*>(Wy + i * 8 + 4) = make_float2(nx_e.wy[4], nx_e.wy[5]);
     }
+    fetch(cb + item.z * kSpreadChunk);
     __syncthreads();
     const int ce = cb + n;
     const int nd = sdense[0];
@@ -450,8 +516,8 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
       if (rb < NRB && !shared) {
         int ra0, rb0, ra1, rb1;
         window(rb, ra0, rb0, ra1, rb1);
-        gather(max(ra0, cb), min(rb0, ce), rb * 8 + lr, acc[k]);
-        gather(max(ra1, cb), min(rb1, ce), rb * 8 + lr, acc[k]);
+        gather(max(ra0, cb), min(rb0, ce), rb * kSpreadRB, acc[k]);
+        gather(max(ra1, cb), min(rb1, ce), rb * kSpreadRB, acc[k]);
       }
     }
 #pragma unroll
@@ -465,35 +531,43 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
           const int ea = max(ra[part], cb), eb = min(rz[part], ce);
           if (ea < eb) {
             const long long len = eb - ea;
-            gather(ea + (int)(len * wave / kAdjWaves), ea + (int)(len * (wave + 1) / kAdjWaves), rb * 8 + lr,
-                   accd[d]);
+            gather(ea + (int)(len * wave / kAdjWaves), ea + (int)(len * (wave + 1) / kAdjWaves),
+                   rb * kSpreadRB, accd[d]);
           }
         }
       }
     }
   }
-  __syncthreads();
+  __syncthreads();                         // gather done: the staging area is free
   const int nd = sdense[0];
-  float2* dpart = reinterpret_cast<float2*>(srec);               // staging buffer is free now
-  if (lc < tile) {
+  f32x4 dsum = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (nd > 0) {                            // (uniform) dense partial tiles, added in wave order
 #pragma unroll
-    for (int k = 0; k < RBW; ++k) {
-      const int rb = wave + k * kAdjWaves;
-      if (rb < NRB) lds[lc * F::GS + rb * 8 + lr] = acc[k];
+    for (int d = 0; d < kMaxDense; ++d)
+      if (d < nd) dpart[(d * kAdjWaves + wave) * 64 + lane] = accd[d];
+    __syncthreads();
+    if (wave < nd) {                       // wave d adds dense block d's tiles
+      for (int w = 0; w < kAdjWaves; ++w) dsum += dpart[(wave * kAdjWaves + w) * 64 + lane];
     }
+    __syncthreads();                       // tiles read: the strip may overwrite them
   }
+  // tile element (4 k4 + j, i16) -> strip column i16 % 8 (re / im: i16 / 8)
+  auto put = [&](int rb, const f32x4& a) {
+    const int cc = i16 & 7, ri = i16 >> 3;
+    if (cc < tile) {
 #pragma unroll
-  for (int d = 0; d < kMaxDense; ++d)
-    if (d < nd) dpart[(d * kAdjWaves + wave) * 64 + lane] = accd[d];
-  __syncthreads();
-  if (wave < nd) {                         // wave d adds dense block d's partial sums in wave order
-    float2 sum = make_float2(0.f, 0.f);
-    for (int w = 0; w < kAdjWaves; ++w) {
-      const float2 v = dpart[(wave * kAdjWaves + w) * 64 + lane];
-      sum = make_float2(sum.x + v.x, sum.y + v.y);
+      for (int j = 0; j < 4; ++j) ldsf[2 * (cc * F::GS + rb * kSpreadRB + 4 * k4 + j) + ri] = a[j];
     }
-    if (lc < tile) lds[lc * F::GS + sdense[1 + wave] * 8 + lr] = sum;
+  };
+#pragma unroll
+  for (int k = 0; k < RBW; ++k) {
+    const int rb = wave + k * kAdjWaves;
+    bool shared = false;
+#pragma unroll
+    for (int d = 0; d < kMaxDense; ++d) shared |= d < nd && sdense[1 + d] == rb;
+    if (rb < NRB && !shared) put(rb, acc[k]);
   }
+  if (wave < nd) put(sdense[1 + wave], dsum);
   __syncthreads();
   if (item.w >= 0) {
     // a part: its partial grid strip to slot item.w + part (row-major, 8 columns)
