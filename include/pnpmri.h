@@ -494,7 +494,7 @@ pnp_status pnp_autotune(pnp_plan* plan, const pnp_c64* smaps, int32_t L, const f
  * 0 never splits; 1, 2, 3 aim at parts of about 4, 2 and 1 times the median
  * strip's work.  Row blocks whose window holds
  * `dense_min` or more entries are shared by all waves of their workgroup.
- * Defaults: split 0, dense_min 128; pnp_autotune sweeps split 0..3 x
+ * Defaults: split 1, dense_min 128; pnp_autotune sweeps split 0..3 x
  * dense_min 128, 256, 512 on the gridded adjoint.  Every choice gives the
  * same results up to floating-point summation order.  2D plans only;
  * pnp_plan_set_spread waits for `stream`. */

@@ -10,9 +10,10 @@
 //     k_gather_entries  y_l[m] = N^{-1/2} * sum of the sample's partials
 //   adjoint  A^H D_w y
 //     cols_adj        strip: type-1 spread of w_m y_l[m] as a gather (each
-//                     wave sums the row-sorted entries of its 8 x 8 grid
-//                     blocks in registers, no atomics) into the strip in LDS,
-//                     column inverse FFT, keep the ny image rows
+//                     wave accumulates the row-sorted entries of its 16-row
+//                     grid blocks as FP32 MFMA products of row weights and
+//                     column-weighted values, no atomics) into the strip in
+//                     LDS, column inverse FFT, keep the ny image rows
 //                     -> mid[l][iy][Kx]
 //     rows_adj        row inverse FFT, crop, deapod, conj(S_l), sum over the
 //                     coils of the workgroup -> per-coil-group partial images
@@ -313,7 +314,7 @@ k_cols_fwd_fs(const float2* __restrict__ mid, int nx, int ny, int Kx, const floa
   }
 }
 
-constexpr int kAdjThreads = 512;    // spread uses all waves, the FFT the first 8*K1 threads
+constexpr int kAdjThreads = 256;    // = 8 * K1 for K1 = 32: every wave gathers and transforms
 constexpr int kSpreadChunk = kAdjThreads;   // entries staged in LDS at a time, one per thread
 constexpr int kAdjWaves = kAdjThreads / 64;
 constexpr int kSpreadRB = 16;       // grid rows per spread block (the M side of one MFMA tile)
@@ -348,17 +349,17 @@ struct AdjLds {
 // v_mfma_f32_16x16x4_f32 takes four entries.  Staging a chunk computes each
 // entry's B row once (its 16 values for this strip) and its row weights;
 // the MFMA loop only places the row weights (lane row i of the block gets
-// wy_e(16 rb + i - jy_e), or 0 outside the window).  Wave w owns the row
-// blocks rb = w, w + 8, ... and keeps their 16 x 16 tiles in registers,
+// wy_e(16 rb + i - jy_e), or 0 outside the window).  Wave w of the four owns
+// the row blocks rb = w, w + 4, ... and keeps their 16 x 16 tiles in registers,
 // taking every entry whose first row tap lies within 5 rows above the block
 // (entries are sorted by first row tap, row_start indexes them).  Up to
 // kMaxDense blocks whose window holds dense_min or more entries (the most
 // such blocks first: the densely sampled k-space centre) are shared by all
 // waves instead: each wave takes a fixed slice of every staged chunk of the
-// block's entries, and the eight partial tiles are added in wave order.
+// block's entries, and the four partial tiles are added in wave order.
 // Each grid point is written once: no atomics, a fixed summation order.
 template <int K1, int K2>
-__global__ void __launch_bounds__(kAdjThreads)
+__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_cols_adj_fs(const float2* __restrict__ yent, long long E,
               int nx, int ny, int Kx, const float2* __restrict__ tw, int tile,
               const int* __restrict__ tile_off, const int* __restrict__ row_start,
@@ -368,6 +369,7 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   constexpr int NRB = F::K / kSpreadRB;                          // row blocks per strip
   constexpr int RBW = (NRB + kAdjWaves - 1) / kAdjWaves;         // row blocks per wave
   static_assert(F::K % kSpreadRB == 0, "row blocks tile the column");
+  static_assert(kMaxDense <= kAdjWaves && 8 * K1 <= kAdjThreads, "one wave per dense block; FFT threads");
   __shared__ f32x4 U[AdjLds<K1, K2>::BYTES / 16];
   __shared__ int srs[F::K + 1];
   __shared__ int sdense[kMaxDense + 1];                          // count, then row blocks
@@ -602,24 +604,45 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
 }
 
 // grid strips of split items: the parts' partial strips added in part order,
-// then the column inverse FFT and the image rows
+// then the column inverse FFT and the image rows.  Every part's values of a
+// thread's elements are loaded before any is added (all in flight at once);
+// parts past the strip's count read as zero and are added last.
+constexpr int kFinThreads = 1024;
+constexpr int kMaxParts = 8;
 template <int K1, int K2>
-__global__ void __launch_bounds__(8 * K1)
+__global__ void __launch_bounds__(kFinThreads)
 k_cols_adj_fin_fs(const float2* __restrict__ spart, int nslots, const int4* __restrict__ splits, int ny, int Kx,
                   const float2* __restrict__ tw, int tile, float2* __restrict__ mid) {
   using F = FS<K1, K2>;
+  constexpr int NE = F::K * 8;                                   // elements of a strip
+  constexpr int PER = (NE + kFinThreads - 1) / kFinThreads;      // per thread
+  constexpr int R = PER <= 5 ? PER : (PER + 1) / 2;              // per round of loads
   __shared__ float2 lds[8 * F::CSTR];
   const int l = blockIdx.x;
-  const int4 sp = splits[blockIdx.y];      // (strip, first slot, parts, 0)
+  const int4 sp = splits[blockIdx.y];      // (strip, first slot, parts <= kMaxParts, 0)
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;
   const int c0 = sp.x * tile;
-  const bool colok = c < tile;
-  const float2* src = spart + ((long long)l * nslots + sp.y) * F::K * 8;
-  for (int i = threadIdx.x; i < F::K * 8; i += blockDim.x) {
-    float2 a = src[i];
-    for (int q = 1; q < sp.z; ++q) a = cadd(a, src[(long long)q * F::K * 8 + i]);
-    lds[(i & 7) * F::GS + (i >> 3)] = a;
+  const bool colok = c < tile && t < K1;
+  const float2* src = spart + ((long long)l * nslots + sp.y) * NE;
+  for (int j0 = 0; j0 < PER; j0 += R) {
+    float2 b[kMaxParts][R];
+#pragma unroll
+    for (int q = 0; q < kMaxParts; ++q) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int i = (int)threadIdx.x + (j0 + j) * kFinThreads;
+        b[q][j] = q < sp.z && i < NE ? src[(long long)q * NE + i] : make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = (int)threadIdx.x + (j0 + j) * kFinThreads;
+      float2 a = b[0][j];
+#pragma unroll
+      for (int q = 1; q < kMaxParts; ++q) a = cadd(a, b[q][j]);
+      if (i < NE) lds[(i & 7) * F::GS + (i >> 3)] = a;
+    }
   }
   __syncthreads();
   float2 v[K1];
@@ -827,7 +850,7 @@ struct FSLaunch {
                p->ax[0].n, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off,
                p->row_start, p->adj_items, p->adj_dense_min, p->rec, mid, spart, kMaxAdjSlots);
     if (p->n_adj_splits > 0)
-      PNP_LAUNCH((k_cols_adj_fin_fs<K1, K2>), dim3(L, p->n_adj_splits), dim3(8 * K1), 0, s, spart, kMaxAdjSlots,
+      PNP_LAUNCH((k_cols_adj_fin_fs<K1, K2>), dim3(L, p->n_adj_splits), dim3(kFinThreads), 0, s, spart, kMaxAdjSlots,
                  p->adj_splits, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, mid);
   }
   static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
@@ -943,7 +966,7 @@ void adj_build_items(pnp_plan* p, int split, int dense_min, hipStream_t s) {
   std::vector<int4> splits;
   int slots = 0;
   for (int t : order) {
-    int parts = (int)std::min<long long>(8, (cost[t] + target - 1) / target);
+    int parts = (int)std::min<long long>(kMaxParts, (cost[t] + target - 1) / target);
     parts = std::min(parts, kMaxAdjSlots - slots);
     if (parts <= 1) {
       items.push_back({make_int4(t, 0, 1, -1), cost[t]});

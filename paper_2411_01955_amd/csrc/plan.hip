@@ -749,7 +749,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
           p->adj_cost[(size_t)t * nrb + rb] = lo >= 0 ? r[hi] - r[lo] : (r[R] - r[R + lo]) + (r[hi] - r[0]);
         }
       }
-      adj_build_items(p, 0, 128, stream);
+      adj_build_items(p, 1, 128, stream);
     }
     PNP_HIP(hipStreamSynchronize(stream));
   } catch (...) {

@@ -228,7 +228,7 @@ void autotune(pnp_plan* p, const float2* smaps, int L, const float* dcf, const p
           us[c] = std::min(us[c], 1e3 * ms / reps);
         }
       }
-      int best_c = 0;                                  // split 0, 128: the default
+      int best_c = 3;                                  // split 1, 128: the default
       double best = us[best_c];
       for (int c = 0; c < 12; ++c)
         if (us[c] < 0.98 * best) {
