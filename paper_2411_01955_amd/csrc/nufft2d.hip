@@ -278,8 +278,11 @@ k_cols_fwd_fs(const float2* __restrict__ mid, int nx, int ny, int Kx, const floa
   __shared__ float2 lds[8 * F::CSTR];
   const int c = threadIdx.x % 8;
   const int t = threadIdx.x / 8;
-  const int s = blockIdx.x;
-  const int l = blockIdx.y;
+  // (strip, coil) in XCD order, coil fastest: the coils of a strip run on one
+  // XCD, so the strip's entry records come from that XCD's L2 after the first
+  const int lin = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int s = lin / gridDim.y;
+  const int l = lin % gridDim.y;
   const int c0 = s * tile;
   const bool colok = c < tile;
   if (colok && t < K2) {
@@ -359,8 +362,8 @@ struct AdjLds {
 // block's entries, and the four partial tiles are added in wave order.
 // Each grid point is written once: no atomics, a fixed summation order.
 template <int K1, int K2>
-__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(3)))
-k_cols_adj_fs(const float2* __restrict__ yent, long long E,
+__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(K1 * K2 >= 1024 ? 2 : 3)))
+k_cols_adj_fs(KIn kin, const float* __restrict__ dcf, float scale,
               int nx, int ny, int Kx, const float2* __restrict__ tw, int tile,
               const int* __restrict__ tile_off, const int* __restrict__ row_start,
               const int4* __restrict__ items, int dense_min, const EntryRec* __restrict__ rec,
@@ -392,7 +395,9 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
   const int e0 = tile_off[s], e1 = tile_off[s + 1];
   int cb = e0 + item.y * kSpreadChunk;
   // this thread's entry of the next chunk to stage, loaded ahead: first
-  // taps, column and row weights, weighted k-space value
+  // taps, column and row weights, and the weighted k-space value
+  // scale * w_m * y_l[m] of its sample m (y given, or the sum of the
+  // sample's interpolation partials inside the normal operator)
   struct Staged {
     int jx, jy;
     float wx[6], wy[6];
@@ -408,7 +413,8 @@ k_cols_adj_fs(const float2* __restrict__ yent, long long E,
       nx_e.wx[4] = r.w1.x; nx_e.wx[5] = r.w1.y;
       nx_e.wy[0] = r.w1.z; nx_e.wy[1] = r.w1.w;
       nx_e.wy[2] = r.w2.x; nx_e.wy[3] = r.w2.y; nx_e.wy[4] = r.w2.z; nx_e.wy[5] = r.w2.w;
-      nx_e.v = yent[(long long)l * E + e];
+      const int m = r.idx.z;
+      nx_e.v = cscale(k_at(kin, l, m), dcf ? dcf[m] * scale : scale);
     }
   };
   fetch(cb);
@@ -845,8 +851,9 @@ struct FSLaunch {
                p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off, p->rec,
                (long long)p->E, ypart);
   }
-  static void cols_adj(const pnp_plan* p, int L, const float2* yent, float2* mid, float2* spart, hipStream_t s) {
-    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(L, p->n_adj_items), dim3(kAdjThreads), 0, s, yent, (long long)p->E,
+  static void cols_adj(const pnp_plan* p, int L, const KIn& kin, const float* dcf, float scale, float2* mid,
+                       float2* spart, hipStream_t s) {
+    PNP_LAUNCH((k_cols_adj_fs<K1, K2>), dim3(L, p->n_adj_items), dim3(kAdjThreads), 0, s, kin, dcf, scale,
                p->ax[0].n, p->ax[1].n, p->ax[0].K, p->ax[1].fft.tw, p->tile, p->tile_off,
                p->row_start, p->adj_items, p->adj_dense_min, p->rec, mid, spart, kMaxAdjSlots);
     if (p->n_adj_splits > 0)
@@ -1033,17 +1040,17 @@ static void adjoint_to_groups(const pnp_plan* p, const KIn& kin, const float2* s
                               hipStream_t s) {
   const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
   const int G = op_groups(p, L);
-  // weighted k-space values in entry order (coalesced staging in the spread)
+  if (fs_ok(p)) {   // the spread weights the k-space values as it stages them
+    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, kin, dcf, scale, w.mid, w.spart, s);
+    PNP_FS_DISPATCH(Kx, rows_adj, p, L, w.mid, smaps, dst, s);
+    return;
+  }
+  // weighted k-space values in entry order
   {
     const long long tot = (long long)L * p->E;
     if (tot > 0)
       PNP_LAUNCH(k_entry_values, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, kin, p->rec, dcf,
                  scale, L, w.yent);
-  }
-  if (fs_ok(p)) {
-    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, w.spart, s);
-    PNP_FS_DISPATCH(Kx, rows_adj, p, L, w.mid, smaps, dst, s);
-    return;
   }
   check_lds(p);
   {
@@ -1093,16 +1100,17 @@ void op_adjoint_coils(const pnp_plan* p, const float2* y, int L, const float* dc
   }
   const int nx = p->ax[0].n, ny = p->ax[1].n, Kx = p->ax[0].K;
   const float scale = (float)(1.0 / std::sqrt((double)N));
-  const long long tot = (long long)L * p->E;
-  if (tot > 0)
-    PNP_LAUNCH(k_entry_values, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-               KIn{y, nullptr, nullptr, (long long)p->M, (long long)p->E}, p->rec, dcf, scale, L, w.yent);
+  const KIn kin{y, nullptr, nullptr, (long long)p->M, (long long)p->E};
   const long long mstride = (long long)ny * Kx;               // one coil's half-transformed grid
   if (fs_ok(p)) {
-    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, w.yent, w.mid, w.spart, s);
+    PNP_FS_DISPATCH(p->ax[1].K, cols_adj, p, L, kin, dcf, scale, w.mid, w.spart, s);
     for (int l = 0; l < L; ++l) PNP_FS_DISPATCH(Kx, rows_adj, p, 1, w.mid + l * mstride, ones, out + l * N, s);
     return;
   }
+  const long long tot = (long long)L * p->E;
+  if (tot > 0)
+    PNP_LAUNCH(k_entry_values, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, kin, p->rec, dcf, scale, L,
+               w.yent);
   check_lds(p);
   {
     const size_t lds = cols_lds(p);
