@@ -130,6 +130,9 @@ def kernel_bytes(n, L, M, E, groups):
     out["k_cols_adj_fs"] = out["k_cols_adj_spread"]
     out["k_rows_adj_fs"] = out["k_rows_adj"]
     out["k_entry_values"] = 64 * E + 8 * L * E * 2 + 8 * M * 2 + 8 * L * E
+    # parts of split strips added: no compulsory bytes beyond the spread's own
+    # (its mid term counts every image row of every strip once)
+    out["k_cols_adj_fin_fs"] = 0
     # Toeplitz column pass: mid in and out (image rows only) + the real transfer function once
     out["k_cols_toep_fs"] = 2 * mid + 4 * (2 * n) ** 2
     # CG vector kernels: w = c0 r + cg sum_g part_g (r, G partials in; w out),
@@ -148,18 +151,19 @@ def kernel_bytes(n, L, M, E, groups):
     return out
 
 
-def step_launches(n_out, n_cg):
+def step_launches(n_out, n_cg, split_strips):
     """Launch counts of one wavelet-HQS solve on the Toeplitz operator (the
     timed step): per outer iteration the CG start (N x: plain forward row
     pass) and n_cg CG steps (the first on r0 with a plain row pass, the rest
     with the CG update fused into it), the CG reductions and the prior on the
-    last update; once per solve b0 = A^H D_w y (gridded adjoint), ||y||_w^2,
-    x0 = b0 and the scalar reset."""
+    last update; once per solve b0 = A^H D_w y (gridded adjoint: the spread,
+    plus the pass that adds split strips' parts when the plan splits any),
+    ||y||_w^2, x0 = b0 and the scalar reset."""
     return {"k_rows_fwd_fs": 2 * n_out, "k_rows_fwd_fs_cg": (n_cg - 1) * n_out,
             "k_cols_toep_fs": (1 + n_cg) * n_out, "k_rows_adj_fs": (1 + n_cg) * n_out + 1,
             "k_cg_dots": n_cg * n_out, "k_cg_init": n_out, "k_haar_prior_cg": n_out,
-            "k_entry_values": 1, "k_cols_adj_fs": 1, "k_sum_groups": 1, "k_wnorm": 1, "k_copy": 1,
-            "k_init_scalars": 1}
+            "k_cols_adj_fs": 1, "k_cols_adj_fin_fs": 1 if split_strips else 0, "k_sum_groups": 1,
+            "k_wnorm": 1, "k_copy": 1, "k_init_scalars": 1}
 
 
 def toeplitz_normal_bytes(kb):
@@ -653,7 +657,7 @@ def main():
     B = b_alg_normal(n, L, M)
     groups = -(-L // plan.row_coils)
     kb = kernel_bytes(n, L, M, info["entries"], groups)
-    launches_model = step_launches(w.n_out, w.n_cg)
+    launches_model = step_launches(w.n_out, w.n_cg, plan.spread[0] > 0)
     step_bytes = sum(kb[k] * c for k, c in launches_model.items())
     value = step_bytes / (ms / 1e3) / 1e9
     value_b_alg = n_normal * B / (ms / 1e3) / 1e9
