@@ -143,6 +143,11 @@ def kernel_bytes(n, L, M, E, groups):
     # forward row pass with the CG update fused in: reads r, s, w, p, u and
     # writes r', s', p', u' (coil group 0) besides the plain pass's bytes
     out["k_rows_fwd_fs_cg"] = out["k_rows_fwd_fs"] - 8 * N + 8 * N * 9
+    # the same with the step's inner products formed in the row passes: w is
+    # rebuilt from r and the coil-group partial images (read instead of w),
+    # and the adjoint row pass also reads r for its per-row sums of Re<part, r>
+    out["k_rows_fwd_fs_cgf"] = out["k_rows_fwd_fs_cg"] + 8 * N * (groups - 1)
+    out["k_rows_adj_fs_dots"] = out["k_rows_adj_fs"] + 8 * N
     # Haar prior on the last CG update u + alpha (r + beta p): r, p, u in, x out
     out["k_haar_prior_cg"] = 8 * N * 4
     out["k_wnorm"] = 8 * L * M + 4 * M
@@ -155,13 +160,14 @@ def step_launches(n_out, n_cg, split_strips):
     """Launch counts of one wavelet-HQS solve on the Toeplitz operator (the
     timed step): per outer iteration the CG start (N x: plain forward row
     pass) and n_cg CG steps (the first on r0 with a plain row pass, the rest
-    with the CG update fused into it), the CG reductions and the prior on the
+    with the CG update fused into it; the row passes of every step also form
+    its inner products, so there is no reduction pass) and the prior on the
     last update; once per solve b0 = A^H D_w y (gridded adjoint: the spread,
     plus the pass that adds split strips' parts when the plan splits any),
     ||y||_w^2, x0 = b0 and the scalar reset."""
-    return {"k_rows_fwd_fs": 2 * n_out, "k_rows_fwd_fs_cg": (n_cg - 1) * n_out,
-            "k_cols_toep_fs": (1 + n_cg) * n_out, "k_rows_adj_fs": (1 + n_cg) * n_out + 1,
-            "k_cg_dots": n_cg * n_out, "k_cg_init": n_out, "k_haar_prior_cg": n_out,
+    return {"k_rows_fwd_fs": 2 * n_out, "k_rows_fwd_fs_cgf": (n_cg - 1) * n_out,
+            "k_cols_toep_fs": (1 + n_cg) * n_out, "k_rows_adj_fs": n_out + 1,
+            "k_rows_adj_fs_dots": n_cg * n_out, "k_cg_init": n_out, "k_haar_prior_cg": n_out,
             "k_cols_adj_fs": 1, "k_cols_adj_fin_fs": 1 if split_strips else 0, "k_sum_groups": 1,
             "k_wnorm": 1, "k_copy": 1, "k_init_scalars": 1}
 
@@ -702,10 +708,11 @@ def main():
         tr[_kname(kname)] = (c0 + c, t0 + t)
     pnp.trace_enable(False)
     # the byte model's launch counts against the traced ones (the plain and
-    # CG-fused forward row passes share one kernel name)
+    # CG-fused row passes share their kernels' names)
     counted = {kname: c // args.steps for kname, (c, t) in tr.items()}
     model = dict(launches_model)
-    model["k_rows_fwd_fs"] = model.pop("k_rows_fwd_fs") + model.pop("k_rows_fwd_fs_cg")
+    model["k_rows_fwd_fs"] = model.pop("k_rows_fwd_fs") + model.pop("k_rows_fwd_fs_cgf")
+    model["k_rows_adj_fs"] = model.pop("k_rows_adj_fs") + model.pop("k_rows_adj_fs_dots")
     launch_check = {k: [model.get(k, 0), counted.get(k, 0)] for k in sorted(set(model) | set(counted))
                     if model.get(k, 0) != counted.get(k, 0)}
     dom = max((kname for kname in tr if kname in kb), key=lambda kname: tr[kname][1])

@@ -102,12 +102,29 @@ constexpr int kFinThreads = 64;
 template <int Q>
 __device__ void sum_parts(const double* __restrict__ parts, int nblocks, double (&out)[Q]) {
   const int lane = threadIdx.x & 63;
+  // eight sets per lane loaded before they are added (in the same order)
+  double s[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) s[q] = 0.0;
+  int b = lane;
+  for (; b + 7 * 64 < nblocks; b += 8 * 64) {
+    double v[8][Q];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[u][q] = parts[(b + u * 64) * Q + q];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s[q] += v[u][q];
+  }
+  for (; b < nblocks; b += 64)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] += parts[b * Q + q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    double s = 0.0;
-    for (int b = lane; b < nblocks; b += 64) s += parts[b * Q + q];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    out[q] = s;
+    for (int o = 32; o > 0; o >>= 1) s[q] += __shfl_xor(s[q], o, 64);
+    out[q] = s[q];
   }
 }
 
@@ -186,6 +203,7 @@ __device__ inline void cg_finish_dots(DevScalars* sc, double g, double d, int fi
 __device__ inline CgStep cg_finish_deferred(const CGFinish& f) {
   double s[2];
   sum_parts_any<2>(f.parts, f.nparts, s);
+  if (f.fused) s[1] = (double)f.c0 * s[0] + (double)f.cg * s[1];
   const double rr_prev = f.first ? 0.0 : f.prev->rr;
   const double alpha_prev = f.first ? 0.0 : f.prev->alpha;
   const CgStep st = cg_step(s[0], s[1], f.first, rr_prev, alpha_prev);

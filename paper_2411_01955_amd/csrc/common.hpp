@@ -230,16 +230,37 @@ struct CGFinish {
   const DevScalars* prev;  // rr and alpha of the step before (unused when first)
   DevScalars* next;        // receives alpha, beta, rr, pq of this step
   int* bad;                // set to 1 on a non-positive or non-finite denominator
+  // fused: the second sums are Re<N r, r> (FusedDots), and
+  // Re<w, r> = c0 <r, r> + cg Re<N r, r> is formed here
+  int fused;
+  float c0, cg;
+};
+// CG inner products of a step formed by the Toeplitz operator's row passes
+// instead of a pass of their own: the forward row pass's workgroups of coil
+// group 0 put (sum over image row iy of |r|^2, 0) into slot iy of `parts`,
+// the adjoint row pass's workgroup of row iy and coil group g puts
+// (0, sum over the row of Re<part_g, r>) into slot ny + g ny + iy.
+struct FusedDots {
+  double* parts;           // [ny (1 + G)][2]; nullptr: not formed
+  const float2* r;         // the operator's input r (read by the adjoint row pass)
+  int ny;
 };
 struct CGUpdate {
   const float2 *r, *p, *s, *u, *w;
   float2 *r2, *p2, *s2, *u2;
   const double *alpha, *beta;
   CGFinish fin;
+  // w == nullptr: w = c0 r + cg sum_g part[g N + i] is formed on the fly
+  // from the previous operator's coil-group partial images
+  const float2* part;
+  int G;
+  long long N;
+  float c0, cg;
 };
 struct NormalIn {
   const float2* x;
   CGUpdate cg;
+  FusedDots fd;
 };
 inline NormalIn plain_input(const float2* x) { return NormalIn{x, CGUpdate{}}; }
 // Coil groups of the row passes: partial images left in w.part by the
@@ -280,6 +301,9 @@ void op_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps,
 bool toeplitz_supported(const pnp_plan* p);
 pnp_toeplitz* toeplitz_create(const pnp_plan* p, const float* traj, const float* dcf, hipStream_t s);
 void toeplitz_destroy(pnp_toeplitz* tp);
+// The 2D Toeplitz operator on the register-FFT passes forms a CG step's
+// inner products in its row passes when NormalIn::fd asks for them.
+bool toep_fused_dots(const pnp_toeplitz* tp);
 void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const float2* smaps, int L,
                           const OpWorkspace& w, hipStream_t s);
 void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps, int L, float2* out,

@@ -52,7 +52,29 @@ __device__ __forceinline__ void st_off(T* __restrict__ base, OFF byte_off, T v) 
 struct ImgIn {
   const float2* x;
   CGUpdate cg;   // cg.r == nullptr: plain image input
+  FusedDots fd;  // fd.parts: the coil-group-0 workgroups also sum |input|^2 over their row
 };
+
+// Sum of one double over a workgroup of NT threads (NT < 64: one partial
+// wave, shuffles of that width); a fixed order, so deterministic.  Every
+// thread receives the sum.  sh: NT / 64 doubles of LDS.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* sh) {
+  if constexpr (NT < 64) {
+#pragma unroll
+    for (int o = NT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, NT);
+    return v;
+  } else {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += sh[w];
+    return t;
+  }
+}
 
 struct ImgScal {
   float alpha, beta;
@@ -71,7 +93,15 @@ __device__ __forceinline__ float2 img_at(const ImgIn& in, long long row0, int ix
   const unsigned b = (unsigned)ix * 8u;
   if (!in.cg.r) return ld_off(in.x + row0, b);
   const CGUpdate& c = in.cg;
-  const float2 rv = ld_off(c.r + row0, b), sv = ld_off(c.s + row0, b), wv = ld_off(c.w + row0, b);
+  const float2 rv = ld_off(c.r + row0, b), sv = ld_off(c.s + row0, b);
+  float2 wv;
+  if (c.w) {
+    wv = ld_off(c.w + row0, b);
+  } else {   // w = c0 r + cg N r from the previous operator's coil-group partial images
+    float2 nv = ld_off(c.part + row0, b);
+    for (int g = 1; g < c.G; ++g) nv = cadd(nv, ld_off(c.part + (long long)g * c.N + row0, b));
+    wv = make_float2(c.c0 * rv.x + c.cg * nv.x, c.c0 * rv.y + c.cg * nv.y);
+  }
   const float2 sn = make_float2(fmaf(sc.beta, sv.x, wv.x), fmaf(sc.beta, sv.y, wv.y));
   const float2 rn = make_float2(fmaf(-sc.alpha, sn.x, rv.x), fmaf(-sc.alpha, sn.y, rv.y));
   if (store) {
@@ -144,8 +174,21 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
     const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
     const ImgScal bt = img_scal(in);
     const bool store = g == 0;
-    for (int ix = threadIdx.x; ix < nx; ix += RC * K1)
-      X[ix] = cscale(img_at(in, row0, ix, bt, store), (dax ? dax[ix] : 1.f) * sy);
+    const bool dots = in.fd.parts && g == 0;  // (uniform)
+    double rr = 0.0;
+    for (int ix = threadIdx.x; ix < nx; ix += RC * K1) {
+      const float2 v = img_at(in, row0, ix, bt, store);
+      if (dots) rr += (double)v.x * v.x + (double)v.y * v.y;
+      X[ix] = cscale(v, (dax ? dax[ix] : 1.f) * sy);
+    }
+    if (dots) {
+      __shared__ double sh[(RC * K1 + 63) / 64];
+      rr = wg_sum<RC * K1>(rr, sh);
+      if (threadIdx.x == 0) {
+        in.fd.parts[2 * iy] = rr;
+        in.fd.parts[2 * iy + 1] = 0.0;
+      }
+    }
   }
   __syncthreads();
   float2* Al = A + line * F::LA;
@@ -200,7 +243,8 @@ template <int K1, int K2, int RC, bool HALF, typename OFF>
 __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, const float2* __restrict__ S, int L,
                                               int nx, int ny, const float* __restrict__ dax,
                                               const float* __restrict__ day, const float2* __restrict__ tw,
-                                              float2* __restrict__ part, int iy, int g, float2* A) {
+                                              float2* __restrict__ part, int iy, int g, float2* A,
+                                              const FusedDots& fd) {
   using F = FS<K1, K2>;
   const int line = threadIdx.x / K1;
   const int t = threadIdx.x % K1;
@@ -269,10 +313,26 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   const int nl = min(RC, L - l0);
   const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
   float2* pg = part + (long long)g * N + (long long)iy * nx;
+  const float2* rrow = fd.r ? fd.r + (long long)iy * nx : nullptr;
+  double d = 0.0;
   for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
     float2 acc = Z[ix];
     for (int li = 1; li < nl; ++li) acc = cadd(acc, Z[li * nx + ix]);
-    pg[ix] = cscale(acc, (dax ? dax[ix] : 1.f) * sy);
+    const float2 v = cscale(acc, (dax ? dax[ix] : 1.f) * sy);
+    pg[ix] = v;
+    if (rrow) {
+      const float2 rv = rrow[ix];
+      d += (double)v.x * rv.x + (double)v.y * rv.y;
+    }
+  }
+  if (fd.parts) {                             // (uniform) Re<part_g, r> over the row
+    __shared__ double sh[(RC * K1 + 63) / 64];
+    d = wg_sum<RC * K1>(d, sh);
+    if (threadIdx.x == 0) {
+      double* slot = fd.parts + 2 * ((long long)fd.ny * (1 + g) + iy);
+      slot[0] = 0.0;
+      slot[1] = d;
+    }
   }
 }
 

@@ -681,9 +681,9 @@ template <int K1, int K2, int RC>
 __global__ void __launch_bounds__(RC * K1)
 k_rows_adj_fs(const float2* __restrict__ mid, const float2* __restrict__ S, int L, int nx, int ny,
               const float* __restrict__ dax, const float* __restrict__ day,
-              const float2* __restrict__ tw, float2* __restrict__ part) {
+              const float2* __restrict__ tw, float2* __restrict__ part, FusedDots fd) {
   __shared__ float2 A[RC * FS<K1, K2>::LA];
-  rows_adj_body<K1, K2, RC, true, unsigned>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A);
+  rows_adj_body<K1, K2, RC, true, unsigned>(mid, S, L, nx, ny, dax, day, tw, part, blockIdx.x, blockIdx.y, A, fd);
 }
 
 template <int K1, int K2>
@@ -786,7 +786,7 @@ k_batch_rows_adj(const BatchSlice* __restrict__ sl, const int4* __restrict__ ite
   const int4 w = items[xcd_order(blockIdx.x, n_items)];
   const BatchSlice& b = sl[w.x];
   rows_adj_body<K1, K2, kRowCoils, true, unsigned>(b.mid, b.S, b.L, b.nx, b.ny, nullptr, nullptr, b.tw, b.part, w.y,
-                                                   w.z, A);
+                                                   w.z, A, FusedDots{});
 }
 
 template <int K1, int K2>
@@ -821,9 +821,9 @@ struct FSLaunch {
   }
   template <int RC>
   static void rows_adj_rc(const pnp_plan* p, int L, const float2* mid, const float2* S, const float* dax,
-                          const float* day, float2* part, hipStream_t s) {
+                          const float* day, float2* part, const FusedDots& fd, hipStream_t s) {
     PNP_LAUNCH((k_rows_adj_fs<K1, K2, RC>), dim3(p->ax[1].n, (L + RC - 1) / RC), dim3(RC * K1), 0, s, mid, S, L,
-               p->ax[0].n, p->ax[1].n, dax, day, p->ax[0].fft.tw, part);
+               p->ax[0].n, p->ax[1].n, dax, day, p->ax[0].fft.tw, part, fd);
   }
   static void rows_fwd_any(const pnp_plan* p, const ImgIn& in, const float2* S, int L, const float* dax,
                            const float* day, float2* mid, hipStream_t s) {
@@ -834,11 +834,11 @@ struct FSLaunch {
     }
   }
   static void rows_adj_any(const pnp_plan* p, int L, const float2* mid, const float2* S, const float* dax,
-                           const float* day, float2* part, hipStream_t s) {
+                           const float* day, float2* part, const FusedDots& fd, hipStream_t s) {
     switch (rc_of(p)) {
-      case 2: rows_adj_rc<2>(p, L, mid, S, dax, day, part, s); break;
-      case 8: rows_adj_rc<fit_rc<K1, K2>(8)>(p, L, mid, S, dax, day, part, s); break;
-      default: rows_adj_rc<4>(p, L, mid, S, dax, day, part, s); break;
+      case 2: rows_adj_rc<2>(p, L, mid, S, dax, day, part, fd, s); break;
+      case 8: rows_adj_rc<fit_rc<K1, K2>(8)>(p, L, mid, S, dax, day, part, fd, s); break;
+      default: rows_adj_rc<4>(p, L, mid, S, dax, day, part, fd, s); break;
     }
   }
   static void rows_fwd(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
@@ -862,7 +862,7 @@ struct FSLaunch {
   }
   static void rows_adj(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
                        hipStream_t s) {
-    rows_adj_any(p, L, mid, S, p->ax[0].deapod, p->ax[1].deapod, part, s);
+    rows_adj_any(p, L, mid, S, p->ax[0].deapod, p->ax[1].deapod, part, FusedDots{}, s);
   }
   // Toeplitz variants: no deapodisation, column pass = FFT * T * IFFT
   static void rows_fwd_toep(const pnp_plan* p, const ImgIn& in, const float2* S, int L, float2* mid,
@@ -874,8 +874,8 @@ struct FSLaunch {
                p->ax[1].fft.tw, p->tile, T);
   }
   static void rows_adj_toep(const pnp_plan* p, int L, const float2* mid, const float2* S, float2* part,
-                            hipStream_t s) {
-    rows_adj_any(p, L, mid, S, nullptr, nullptr, part, s);
+                            const FusedDots& fd, hipStream_t s) {
+    rows_adj_any(p, L, mid, S, nullptr, nullptr, part, fd, s);
   }
 };
 
@@ -899,6 +899,8 @@ bool fs_ok(const pnp_plan* p) {
 }
 
 }  // namespace
+
+bool toep_fused_dots(const pnp_toeplitz* tp) { return tp && tp->plan->ndim == 2 && fs_ok(tp->plan); }
 
 int op_groups(const pnp_plan* p, int L) {
   if (p->ndim == 3) return op3_groups(L);
@@ -1171,10 +1173,10 @@ void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const floa
                           const OpWorkspace& w, hipStream_t s) {
   const pnp_plan* p = tp->plan;
   if (p->ndim == 3) return op3_normal_toep_parts(tp, in, smaps, L, w, s);
-  const ImgIn im{in.x, in.cg};
+  const ImgIn im{in.x, in.cg, in.fd};
   PNP_FS_DISPATCH(p->ax[0].K, rows_fwd_toep, p, im, smaps, L, w.mid, s);
   PNP_FS_DISPATCH(p->ax[1].K, cols_toep, p, L, tp->T, w.mid, s);
-  PNP_FS_DISPATCH(p->ax[0].K, rows_adj_toep, p, L, w.mid, smaps, w.part, s);
+  PNP_FS_DISPATCH(p->ax[0].K, rows_adj_toep, p, L, w.mid, smaps, w.part, in.fd, s);
 }
 
 void op_normal_toep(const pnp_toeplitz* tp, const float2* x, const float2* smaps, int L, float2* out,

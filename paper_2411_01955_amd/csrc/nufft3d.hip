@@ -59,7 +59,8 @@ k3_rows_adj(const float2* __restrict__ mid, const float2* __restrict__ S, int L,
             const float* __restrict__ dax, const float* __restrict__ dyz, const float2* __restrict__ tw,
             float2* __restrict__ part) {
   __shared__ float2 A[kRowCoils3 * FS<K1, K2>::LA];
-  rows_adj_body<K1, K2, kRowCoils3, HALF, OFF>(mid, S, L, nx, nrows, dax, dyz, tw, part, blockIdx.x, blockIdx.y, A);
+  rows_adj_body<K1, K2, kRowCoils3, HALF, OFF>(mid, S, L, nx, nrows, dax, dyz, tw, part, blockIdx.x, blockIdx.y, A,
+                                               FusedDots{});
 }
 
 // A set of columns: workgroup (strip, set) works on columns c0 .. c0+7 of

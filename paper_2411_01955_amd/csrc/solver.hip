@@ -261,7 +261,13 @@ struct SolverWs {
   DevScalars* sc;
   DevScalars* cgs;   // [2] CG step state, alternating between steps
   double* rho;   // [kMaxOuter + 1]
+  double* fparts[2];   // CG inner products formed by the row passes (FusedDots), by step parity
 };
+
+// slots of one FusedDots set: image rows x (1 + coil groups); 2D only
+static long long fused_slots(const pnp_plan* p, int L) {
+  return p->ndim == 2 ? (long long)p->ax[1].n * (1 + op_groups_max(L)) : 0;
+}
 
 size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
   const int64_t N = image_size(p);
@@ -270,6 +276,7 @@ size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
   b += al(sizeof(double) * 4 * kRedBlocks);
   b += al(sizeof(DevScalars) * 3);
   b += al(sizeof(double) * (kMaxOuter + 1));
+  b += 2 * al(sizeof(double) * 2 * (size_t)std::max<long long>(1, fused_slots(p, L)));
   return b;
 }
 
@@ -291,6 +298,11 @@ static SolverWs solver_ws(const pnp_plan* p, int L, void* ws) {
   w.cgs = w.sc + 1;
   c += al(sizeof(DevScalars) * 3);
   w.rho = (double*)c;
+  c += al(sizeof(double) * (kMaxOuter + 1));
+  for (int i = 0; i < 2; ++i) {
+    w.fparts[i] = (double*)c;
+    c += al(sizeof(double) * 2 * (size_t)std::max<long long>(1, fused_slots(p, L)));
+  }
   return w;
 }
 
@@ -440,23 +452,49 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   // of step j are formed by the pass that uses them (the first pass of step
   // j + 1, or the last update) from step j's block sums; step j's state goes
   // to cgs[j % 2], the previous step's is read from the other.
-  auto fin_of = [&](int j) {
-    return CGFinish{w.parts, (int)nb, j == 0 ? 1 : 0, w.cgs + ((j + 1) & 1), w.cgs + (j & 1), &w.sc->bad};
+  // On the 2D register-FFT Toeplitz operator the row passes form the sums
+  // (FusedDots, by step parity) and the next pass forms w = c0 r + cg N r
+  // from the coil-group partial images; elsewhere k_cg_dots does both.
+  const bool fused = toep_fused_dots(a.toep);
+  const int ny = p->ax[1].n;
+  auto cg_of = [&](int k) { return (float)(a.lambda * a.sigmas[k] - c1a); };
+  auto fin_of = [&](int k, int j) {
+    CGFinish f{w.parts, (int)nb, j == 0 ? 1 : 0, w.cgs + ((j + 1) & 1), w.cgs + (j & 1), &w.sc->bad};
+    if (fused) {
+      f.parts = w.fparts[j & 1];
+      f.nparts = ny * (1 + G);
+      f.fused = 1;
+      f.c0 = (float)c0;
+      f.cg = cg_of(k);
+    }
+    return f;
   };
   // the n_cg CG steps of outer iteration k from the CG start in set 0;
   // returns c, the set that holds the last step's (r, p, u); with `final`,
   // the last u update is made into w.u[1 - c]
   auto cg_solve = [&](int k, bool final) -> int {
-    const double gamma = a.lambda * a.sigmas[k];
-    const float cg = (float)(gamma - c1a);
+    const float cg = cg_of(k);
     int c = 0;
     for (int j = 0; j < a.n_cg; ++j) {
       NormalIn in = plain_input(w.r[0]);
       if (j > 0) {
         in.x = nullptr;
         in.cg = CGUpdate{w.r[c], w.p[c], w.s[c], w.u[c], w.w, w.r[1 - c], w.p[1 - c], w.s[1 - c], w.u[1 - c],
-                         nullptr, nullptr, fin_of(j - 1)};
+                         nullptr, nullptr, fin_of(k, j - 1)};
+        if (fused) {
+          in.cg.w = nullptr;
+          in.cg.part = w.op.part;
+          in.cg.G = G;
+          in.cg.N = N;
+          in.cg.c0 = (float)c0;
+          in.cg.cg = cg;
+        }
         c = 1 - c;
+      }
+      if (fused) {
+        in.fd = FusedDots{w.fparts[j & 1], w.r[c], ny};
+        normal_parts(p, a.toep, in, a.smaps, a.L, a.dcf, w.op, s);
+        continue;
       }
       normal_parts(p, a.toep, in, a.smaps, a.L, a.dcf, w.op, s);
       PNP_LAUNCH(k_cg_dots, dim3(nb), dim3(kRedThreads), 0, s, N, G, w.r[c], w.op.part, (float)c0, cg, w.w,
@@ -464,7 +502,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     }
     if (final)
       PNP_LAUNCH(k_cg_final, dim3(nb), dim3(kRedThreads), 0, s, N, w.r[c], w.p[c], w.u[c], w.u[1 - c],
-                 fin_of(a.n_cg - 1));
+                 fin_of(k, a.n_cg - 1));
     return c;
   };
   // a wavelet prior without a check forms the last u update while it loads
@@ -478,7 +516,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     if (guard && k == 0) post_rho(0);
     if (fuse_final) {
       const int c = cg_solve(k, false);
-      prior_apply_cg(a.prior, p->ndim, nd, w.r[c], w.p[c], w.u[c], fin_of(a.n_cg - 1), x, a.sigmas[k], s);
+      prior_apply_cg(a.prior, p->ndim, nd, w.r[c], w.p[c], w.u[c], fin_of(k, a.n_cg - 1), x, a.sigmas[k], s);
       continue;
     }
     float2* u_res = u_next;
