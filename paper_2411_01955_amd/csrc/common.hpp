@@ -235,14 +235,13 @@ struct CGFinish {
   int fused;
   float c0, cg;
 };
-// CG inner products of a step formed by the Toeplitz operator's row passes
-// instead of a pass of their own: the forward row pass's workgroups of coil
-// group 0 put (sum over image row iy of |r|^2, 0) into slot iy of `parts`,
-// the adjoint row pass's workgroup of row iy and coil group g puts
-// (0, sum over the row of Re<part_g, r>) into slot ny + g ny + iy.
+// CG inner products of a step formed by the Toeplitz operator's adjoint row
+// pass instead of a pass of their own: its workgroup of image row iy and
+// coil group g puts (sum over the row of |r|^2 for g = 0, else 0; sum over
+// the row of Re<part_g, r>) into slot g ny + iy of `parts`.
 struct FusedDots {
-  double* parts;           // [ny (1 + G)][2]; nullptr: not formed
-  const float2* r;         // the operator's input r (read by the adjoint row pass)
+  double* parts;           // [G ny][2]; nullptr: not formed
+  const float2* r;         // the operator's input r
   int ny;
 };
 struct CGUpdate {

@@ -52,7 +52,6 @@ __device__ __forceinline__ void st_off(T* __restrict__ base, OFF byte_off, T v) 
 struct ImgIn {
   const float2* x;
   CGUpdate cg;   // cg.r == nullptr: plain image input
-  FusedDots fd;  // fd.parts: the coil-group-0 workgroups also sum |input|^2 over their row
 };
 
 // Sum of one double over a workgroup of NT threads (NT < 64: one partial
@@ -174,21 +173,8 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
     const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
     const ImgScal bt = img_scal(in);
     const bool store = g == 0;
-    const bool dots = in.fd.parts && g == 0;  // (uniform)
-    double rr = 0.0;
-    for (int ix = threadIdx.x; ix < nx; ix += RC * K1) {
-      const float2 v = img_at(in, row0, ix, bt, store);
-      if (dots) rr += (double)v.x * v.x + (double)v.y * v.y;
-      X[ix] = cscale(v, (dax ? dax[ix] : 1.f) * sy);
-    }
-    if (dots) {
-      __shared__ double sh[(RC * K1 + 63) / 64];
-      rr = wg_sum<RC * K1>(rr, sh);
-      if (threadIdx.x == 0) {
-        in.fd.parts[2 * iy] = rr;
-        in.fd.parts[2 * iy + 1] = 0.0;
-      }
-    }
+    for (int ix = threadIdx.x; ix < nx; ix += RC * K1)
+      X[ix] = cscale(img_at(in, row0, ix, bt, store), (dax ? dax[ix] : 1.f) * sy);
   }
   __syncthreads();
   float2* Al = A + line * F::LA;
@@ -314,7 +300,7 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   const float sy = day ? day[iy] : 1.f;     // no deapodisation table: Toeplitz operator
   float2* pg = part + (long long)g * N + (long long)iy * nx;
   const float2* rrow = fd.r ? fd.r + (long long)iy * nx : nullptr;
-  double d = 0.0;
+  double rr = 0.0, d = 0.0;
   for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
     float2 acc = Z[ix];
     for (int li = 1; li < nl; ++li) acc = cadd(acc, Z[li * nx + ix]);
@@ -323,14 +309,16 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
     if (rrow) {
       const float2 rv = rrow[ix];
       d += (double)v.x * rv.x + (double)v.y * rv.y;
+      if (g == 0) rr += (double)rv.x * rv.x + (double)rv.y * rv.y;
     }
   }
-  if (fd.parts) {                             // (uniform) Re<part_g, r> over the row
-    __shared__ double sh[(RC * K1 + 63) / 64];
-    d = wg_sum<RC * K1>(d, sh);
+  if (fd.parts) {                             // (uniform) |r|^2 (group 0) and Re<part_g, r> over the row
+    __shared__ double sh[2][(RC * K1 + 63) / 64];
+    d = wg_sum<RC * K1>(d, sh[0]);
+    if (g == 0) rr = wg_sum<RC * K1>(rr, sh[1]);
     if (threadIdx.x == 0) {
-      double* slot = fd.parts + 2 * ((long long)fd.ny * (1 + g) + iy);
-      slot[0] = 0.0;
+      double* slot = fd.parts + 2 * ((long long)fd.ny * g + iy);
+      slot[0] = rr;
       slot[1] = d;
     }
   }

@@ -1173,7 +1173,7 @@ void op_normal_toep_parts(const pnp_toeplitz* tp, const NormalIn& in, const floa
                           const OpWorkspace& w, hipStream_t s) {
   const pnp_plan* p = tp->plan;
   if (p->ndim == 3) return op3_normal_toep_parts(tp, in, smaps, L, w, s);
-  const ImgIn im{in.x, in.cg, in.fd};
+  const ImgIn im{in.x, in.cg};
   PNP_FS_DISPATCH(p->ax[0].K, rows_fwd_toep, p, im, smaps, L, w.mid, s);
   PNP_FS_DISPATCH(p->ax[1].K, cols_toep, p, L, tp->T, w.mid, s);
   PNP_FS_DISPATCH(p->ax[0].K, rows_adj_toep, p, L, w.mid, smaps, w.part, in.fd, s);

@@ -264,9 +264,9 @@ struct SolverWs {
   double* fparts[2];   // CG inner products formed by the row passes (FusedDots), by step parity
 };
 
-// slots of one FusedDots set: image rows x (1 + coil groups); 2D only
+// slots of one FusedDots set: image rows x coil groups; 2D only
 static long long fused_slots(const pnp_plan* p, int L) {
-  return p->ndim == 2 ? (long long)p->ax[1].n * (1 + op_groups_max(L)) : 0;
+  return p->ndim == 2 ? (long long)p->ax[1].n * op_groups_max(L) : 0;
 }
 
 size_t hqs_workspace_bytes(const pnp_plan* p, int L) {
@@ -462,7 +462,7 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     CGFinish f{w.parts, (int)nb, j == 0 ? 1 : 0, w.cgs + ((j + 1) & 1), w.cgs + (j & 1), &w.sc->bad};
     if (fused) {
       f.parts = w.fparts[j & 1];
-      f.nparts = ny * (1 + G);
+      f.nparts = ny * G;
       f.fused = 1;
       f.c0 = (float)c0;
       f.cg = cg_of(k);
