@@ -44,6 +44,24 @@ __device__ __forceinline__ void st_off(T* __restrict__ base, OFF byte_off, T v) 
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Buffer accesses at a workgroup-uniform base: the byte offset is the
+// thread's own part (a register) plus a workgroup-uniform part (a scalar
+// register), so an access needs no per-thread address arithmetic.  Raw
+// untyped buffer of 2^31 - 1 bytes (32-bit format word).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ float buf_ld1(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float2 v) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+
 // Image input of the forward row pass: the image x, or -- inside CG -- the
 // next residual r' = r - alpha (w + beta s) formed on the fly from the
 // previous CG vectors (alpha, beta read from the device scalars); the
@@ -125,12 +143,16 @@ struct FS {
   static_assert(K1 % 4 == 0 && K2 % 4 == 0, "padding patterns need factors divisible by 4");
 };
 
+// Twiddles of the four-step split (t < K2): W^(t k1) from the table's
+// second part, laid out [k1][t] after the K roots, so the row offset
+// k1 K2 is workgroup-uniform and the thread's offset t is shared by all k1.
 template <int K1, int K2, bool INV>
 __device__ __forceinline__ void fs_twiddle(float2 (&v)[K1], int t, const float2* __restrict__ tw) {
+  const auto rsrc = buf_rsrc(tw + K1 * K2);
   const unsigned tb = (unsigned)t * 8u;
 #pragma unroll
   for (int k1 = 1; k1 < K1; ++k1) {
-    float2 w = ld_off(tw, tb * (unsigned)k1);
+    float2 w = buf_ld2(rsrc, tb + (unsigned)(k1 * K2 * 8), 0u);
     if (INV) w.y = -w.y;
     v[k1] = cmul(v[k1], w);
   }
@@ -347,7 +369,16 @@ __device__ __forceinline__ void col_fwd(const float2* __restrict__ strip, OFF rs
     float2 v[K1];
     const OFF rb = rs * 8u;
     const OFF cb = (OFF)c * 8u + (OFF)t * rb;
-    if constexpr (HALF) {
+    if constexpr (HALF && sizeof(OFF) == 4) {
+      constexpr int Q = K1 / 4;
+      const auto rsrc = buf_rsrc(strip);
+#pragma unroll
+      for (int n1 = 0; n1 < K1; ++n1) {
+        if (n1 < Q) v[n1] = buf_ld2(rsrc, cb, (unsigned)((n1 + Q) * K2) * rb);
+        else if (n1 >= 3 * Q) v[n1] = buf_ld2(rsrc, cb, (unsigned)((n1 - 3 * Q) * K2) * rb);
+        else v[n1] = make_float2(0.f, 0.f);
+      }
+    } else if constexpr (HALF) {
       constexpr int Q = K1 / 4;
 #pragma unroll
       for (int n1 = 0; n1 < K1; ++n1) {
@@ -386,10 +417,12 @@ __device__ __forceinline__ void col_inv(float2* __restrict__ strip, OFF rs, int 
   const int t = threadIdx.x / 8;
   if (colok) {
     reg::dft<K2, true>(u);
+    // W^(t r2) from the table's third part, laid out [r2][t] (t < K1)
+    const auto rsrc = buf_rsrc(tw + 2 * K1 * K2);
     const unsigned tb = (unsigned)t * 8u;
 #pragma unroll
     for (int r2 = 1; r2 < K2; ++r2) {
-      float2 w = ld_off(tw, tb * (unsigned)r2);
+      float2 w = buf_ld2(rsrc, tb + (unsigned)(r2 * K1 * 8), 0u);
       w.y = -w.y;
       u[r2] = cmul(u[r2], w);
     }
@@ -404,7 +437,15 @@ __device__ __forceinline__ void col_inv(float2* __restrict__ strip, OFF rs, int 
     reg::dft<K1, true>(z);
     const OFF rb = rs * 8u;
     const OFF cb = (OFF)c * 8u + (OFF)t * rb;
-    if constexpr (HALF) {
+    if constexpr (HALF && sizeof(OFF) == 4) {
+      constexpr int Q = K1 / 4;
+      const auto rsrc = buf_rsrc(strip);
+#pragma unroll
+      for (int r1 = 0; r1 < K1; ++r1) {
+        if (r1 < Q) buf_st2(rsrc, cb, (unsigned)(K2 * (r1 + Q)) * rb, z[r1]);
+        else if (r1 >= 3 * Q) buf_st2(rsrc, cb, (unsigned)(K2 * (r1 - 3 * Q)) * rb, z[r1]);
+      }
+    } else if constexpr (HALF) {
       constexpr int Q = K1 / 4;
 #pragma unroll
       for (int r1 = 0; r1 < K1; ++r1) {
@@ -437,10 +478,10 @@ __device__ __forceinline__ void cols_toep_body(float2* __restrict__ mid, int ny,
   float2 u[K2];
   col_fwd<K1, K2, true, unsigned>(strip, (unsigned)Kx, ny, colok, tw, lds, u);
   if (colok) {
-    const float* Ts = T + c0;
+    const auto rsrc = buf_rsrc(T + c0);
     const unsigned tb = ((unsigned)c + (unsigned)t * (unsigned)Kx) * 4u;
 #pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, tb + (unsigned)(K1 * k2) * (unsigned)Kx * 4u));
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], buf_ld1(rsrc, tb, (unsigned)(K1 * k2) * (unsigned)Kx * 4u));
   }
   col_inv<K1, K2, true, unsigned>(strip, (unsigned)Kx, ny, colok, tw, lds, u);
 }

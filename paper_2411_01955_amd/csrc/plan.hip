@@ -24,6 +24,7 @@
 #include <hipcub/device/device_radix_sort.hpp>
 
 #include "common.hpp"
+#include "fft_reg.hpp"
 
 namespace pnp {
 
@@ -47,6 +48,19 @@ __global__ void k_twiddles(float2* tw, int K) {
   double s, c;
   sincospi(-2.0 * (double)t / (double)K, &s, &c);
   tw[t] = make_float2((float)c, (float)s);
+}
+
+// The roots the register passes take for their four-step split K = K1 K2,
+// in two layouts after the K roots: [k1][t] = W^(t k1) (t < K2) and
+// [r2][t] = W^(t r2) (t < K1), the same values as tw[t k1] and tw[t r2].
+__global__ void k_twiddles_fs(float2* tw, int K, int K1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int K2 = K / K1;
+  if (i >= 2 * K) return;
+  const int j = i < K ? (i % K2) * (i / K2) : ((i - K) % K1) * ((i - K) / K1);
+  double s, c;
+  sincospi(-2.0 * (double)j / (double)K, &s, &c);
+  tw[K + i] = make_float2((float)c, (float)s);
 }
 
 __global__ void k_deapod(float* dp, int n, int K, int W, double beta) {
@@ -487,7 +501,7 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
   };
   size_t o_tw[3], o_dp[3];
   for (int a = 0; a < 3; ++a) {
-    o_tw[a] = take(sizeof(float2) * p->ax[a].K);
+    o_tw[a] = take(sizeof(float2) * 3 * p->ax[a].K);
     o_dp[a] = take(sizeof(float) * p->ax[a].n);
   }
   const size_t o_yz = take(sizeof(float) * p->ax[1].n * p->ax[2].n);
@@ -525,6 +539,10 @@ static void plan_create_3d(pnp_plan* p, const float* traj, hipStream_t stream) {
     const int K = p->ax[a].K, n = p->ax[a].n;
     k_twiddles<<<(K + 255) / 256, 256, 0, stream>>>((float2*)p->ax[a].fft.tw, K);
     PNP_CHECK_LAUNCH();
+    if (const int k1 = four_step_k1(K)) {
+      k_twiddles_fs<<<(2 * K + 255) / 256, 256, 0, stream>>>((float2*)p->ax[a].fft.tw, K, k1);
+      PNP_CHECK_LAUNCH();
+    }
     k_deapod<<<(n + 255) / 256, 256, 0, stream>>>(p->ax[a].deapod, n, K, p->W, p->beta);
     PNP_CHECK_LAUNCH();
   }
@@ -614,7 +632,7 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
     };
     size_t o_tw[3], o_dp[3];
     for (int a = 0; a < ndim; ++a) {
-      o_tw[a] = take(sizeof(float2) * p->ax[a].K);
+      o_tw[a] = take(sizeof(float2) * 3 * p->ax[a].K);
       o_dp[a] = take(sizeof(float) * p->ax[a].n);
     }
     const size_t o_j0 = take(sizeof(int4) * M);
@@ -675,6 +693,10 @@ pnp_plan* plan_create(int ndim, const int32_t* shape, int64_t M, const float* tr
       const int K = p->ax[a].K, n = p->ax[a].n;
       k_twiddles<<<(K + 255) / 256, 256, 0, stream>>>((float2*)p->ax[a].fft.tw, K);
       PNP_CHECK_LAUNCH();
+      if (const int k1 = four_step_k1(K)) {
+        k_twiddles_fs<<<(2 * K + 255) / 256, 256, 0, stream>>>((float2*)p->ax[a].fft.tw, K, k1);
+        PNP_CHECK_LAUNCH();
+      }
       k_deapod<<<(n + 255) / 256, 256, 0, stream>>>(p->ax[a].deapod, n, K, p->W, p->beta);
       PNP_CHECK_LAUNCH();
     }
