@@ -106,13 +106,17 @@ __device__ void sum_parts(const double* __restrict__ parts, int nblocks, double 
   double s[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) s[q] = 0.0;
+  // (buffer loads: the set offsets u * 64 * Q doubles are scalar, the lane's own offset shared)
+  const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(parts), (short)0, 0x7fffffff, 0x00020000);
   int b = lane;
   for (; b + 7 * 64 < nblocks; b += 8 * 64) {
     double v[8][Q];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int q = 0; q < Q; ++q) v[u][q] = parts[(b + u * 64) * Q + q];
+      for (int q = 0; q < Q; ++q)
+        v[u][q] = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(rsrc, (b * Q + q) * 8, u * 64 * Q * 8, 0));
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll

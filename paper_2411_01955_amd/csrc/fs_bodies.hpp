@@ -106,28 +106,30 @@ __device__ __forceinline__ ImgScal img_scal(const ImgIn& in) {
   return ImgScal{(float)*in.cg.alpha, (float)*in.cg.beta};
 }
 // element ix of the image row starting at pixel row0
+// (buffer accesses: the row's base is workgroup-uniform, ix * 8 the thread's offset)
 __device__ __forceinline__ float2 img_at(const ImgIn& in, long long row0, int ix, ImgScal sc, bool store) {
   const unsigned b = (unsigned)ix * 8u;
-  if (!in.cg.r) return ld_off(in.x + row0, b);
+  if (!in.cg.r) return buf_ld2(buf_rsrc(in.x + row0), b, 0u);
   const CGUpdate& c = in.cg;
-  const float2 rv = ld_off(c.r + row0, b), sv = ld_off(c.s + row0, b);
+  const float2 rv = buf_ld2(buf_rsrc(c.r + row0), b, 0u), sv = buf_ld2(buf_rsrc(c.s + row0), b, 0u);
   float2 wv;
   if (c.w) {
-    wv = ld_off(c.w + row0, b);
+    wv = buf_ld2(buf_rsrc(c.w + row0), b, 0u);
   } else {   // w = c0 r + cg N r from the previous operator's coil-group partial images
-    float2 nv = ld_off(c.part + row0, b);
-    for (int g = 1; g < c.G; ++g) nv = cadd(nv, ld_off(c.part + (long long)g * c.N + row0, b));
+    const auto rp = buf_rsrc(c.part + row0);
+    float2 nv = buf_ld2(rp, b, 0u);
+    for (int g = 1; g < c.G; ++g) nv = cadd(nv, buf_ld2(rp, b, (unsigned)((long long)g * c.N * 8)));
     wv = make_float2(c.c0 * rv.x + c.cg * nv.x, c.c0 * rv.y + c.cg * nv.y);
   }
   const float2 sn = make_float2(fmaf(sc.beta, sv.x, wv.x), fmaf(sc.beta, sv.y, wv.y));
   const float2 rn = make_float2(fmaf(-sc.alpha, sn.x, rv.x), fmaf(-sc.alpha, sn.y, rv.y));
   if (store) {
-    const float2 pv = ld_off(c.p + row0, b), uv = ld_off(c.u + row0, b);
+    const float2 pv = buf_ld2(buf_rsrc(c.p + row0), b, 0u), uv = buf_ld2(buf_rsrc(c.u + row0), b, 0u);
     const float2 pn = make_float2(fmaf(sc.beta, pv.x, rv.x), fmaf(sc.beta, pv.y, rv.y));
-    st_off(c.p2 + row0, b, pn);
-    st_off(c.s2 + row0, b, sn);
-    st_off(c.u2 + row0, b, make_float2(fmaf(sc.alpha, pn.x, uv.x), fmaf(sc.alpha, pn.y, uv.y)));
-    st_off(c.r2 + row0, b, rn);
+    buf_st2(buf_rsrc(c.p2 + row0), b, 0u, pn);
+    buf_st2(buf_rsrc(c.s2 + row0), b, 0u, sn);
+    buf_st2(buf_rsrc(c.u2 + row0), b, 0u, make_float2(fmaf(sc.alpha, pn.x, uv.x), fmaf(sc.alpha, pn.y, uv.y)));
+    buf_st2(buf_rsrc(c.r2 + row0), b, 0u, rn);
   }
   return rn;
 }
@@ -206,16 +208,20 @@ __device__ __forceinline__ void rows_fwd_body(const ImgIn& in, const float2* __r
       return S ? cmul(ld_off(Sg, sb + (OFF)ix * 8u), X[ix]) : X[ix];
     };
     if constexpr (HALF) {
+      // (S is uniform: one branch, not a select per element)
+      if (S) {
 #pragma unroll
-      for (int n1 = 0; n1 < K1; ++n1) {
-        if (n1 < Q) {
-          const int ix = (n1 + Q) * K2 + t;
-          v[n1] = S ? cmul(sp[n1], X[ix]) : X[ix];
-        } else if (n1 >= 3 * Q) {
-          const int ix = (n1 - 3 * Q) * K2 + t;
-          v[n1] = S ? cmul(sp[n1 - 2 * Q], X[ix]) : X[ix];
-        } else {
-          v[n1] = make_float2(0.f, 0.f);
+        for (int n1 = 0; n1 < K1; ++n1) {
+          if (n1 < Q) v[n1] = cmul(sp[n1], X[(n1 + Q) * K2 + t]);
+          else if (n1 >= 3 * Q) v[n1] = cmul(sp[n1 - 2 * Q], X[(n1 - 3 * Q) * K2 + t]);
+          else v[n1] = make_float2(0.f, 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int n1 = 0; n1 < K1; ++n1) {
+          if (n1 < Q) v[n1] = X[(n1 + Q) * K2 + t];
+          else if (n1 >= 3 * Q) v[n1] = X[(n1 - 3 * Q) * K2 + t];
+          else v[n1] = make_float2(0.f, 0.f);
         }
       }
     } else {
@@ -266,7 +272,14 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   // grid row, ahead of the transforms that produce the values they multiply
   constexpr int P = K2 / 4;
   float2 sp[HALF ? 2 * P : 1];
-  if constexpr (HALF) {
+  if constexpr (HALF && sizeof(OFF) == 4) {
+    if (active && S) {   // (buffer loads: the thread's offset plus a constant scalar one)
+      const auto rs = buf_rsrc(Sg);
+#pragma unroll
+      for (int m = 0; m < 2 * P; ++m)
+        sp[m] = buf_ld2(rs, (unsigned)sbm + (unsigned)t * 8u, (unsigned)(K1 * (m < P ? m + P : m - P) * 8));
+    }
+  } else if constexpr (HALF) {
     if (active && S) {
 #pragma unroll
       for (int m = 0; m < 2 * P; ++m) {
@@ -279,8 +292,14 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
     float2 v[K1];
     const float2* src = mid + ((long long)l0 * ny + iy) * F::K;
     const OFF sb = ((OFF)line * (OFF)ny * (OFF)F::K + (OFF)t) * 8u;
+    if constexpr (sizeof(OFF) == 4) {
+      const auto rs = buf_rsrc(src);
 #pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) v[n1] = ld_off(src, sb + (OFF)(n1 * K2 * 8));
+      for (int n1 = 0; n1 < K1; ++n1) v[n1] = buf_ld2(rs, (unsigned)sb, (unsigned)(n1 * K2 * 8));
+    } else {
+#pragma unroll
+      for (int n1 = 0; n1 < K1; ++n1) v[n1] = ld_off(src, sb + (OFF)(n1 * K2 * 8));
+    }
     reg::dft<K1, true>(v);
     fs_twiddle<K1, K2, true>(v, t, tw);
 #pragma unroll
@@ -299,14 +318,18 @@ __device__ __forceinline__ void rows_adj_body(const float2* __restrict__ mid, co
   if (active) {
     auto put = [&](int ix, float2 v) { Z[line * nx + ix] = S ? cmulc(ld_off(Sg, sbm + (OFF)ix * 8u), v) : v; };
     if constexpr (HALF) {
+      // (S is uniform: one branch, not a select per element)
+      if (S) {
 #pragma unroll
-      for (int k2 = 0; k2 < K2; ++k2) {
-        if (k2 < P) {
-          const int ix = t + K1 * (k2 + P);
-          Z[line * nx + ix] = S ? cmulc(sp[k2], u[k2]) : u[k2];
-        } else if (k2 >= 3 * P) {
-          const int ix = t + K1 * (k2 - 3 * P);
-          Z[line * nx + ix] = S ? cmulc(sp[k2 - 2 * P], u[k2]) : u[k2];
+        for (int k2 = 0; k2 < K2; ++k2) {
+          if (k2 < P) Z[line * nx + t + K1 * (k2 + P)] = cmulc(sp[k2], u[k2]);
+          else if (k2 >= 3 * P) Z[line * nx + t + K1 * (k2 - 3 * P)] = cmulc(sp[k2 - 2 * P], u[k2]);
+        }
+      } else {
+#pragma unroll
+        for (int k2 = 0; k2 < K2; ++k2) {
+          if (k2 < P) Z[line * nx + t + K1 * (k2 + P)] = u[k2];
+          else if (k2 >= 3 * P) Z[line * nx + t + K1 * (k2 - 3 * P)] = u[k2];
         }
       }
     } else {
