@@ -76,22 +76,33 @@ __device__ __forceinline__ Taps load_taps(const EntryRec* __restrict__ rec, int 
 }
 
 // type-2 interpolation of one entry from a strip held in LDS as columns
-// g[c*GS + row], c < tile (grid columns c0 + c)
+// g[c*GS + row], c < tile (grid columns c0 + c).  The entry's first tap
+// column relative to the strip, d in [-5, 7], gives every tap's column by
+// one add; rows that do not wrap (jy <= Ky - 6, all but the last rows) are
+// read at constant offsets from the column's first tap row.
 __device__ __forceinline__ float2 interp_entry(const Taps& t, const float2* __restrict__ g, int GS,
                                                int c0, int tile, int Kx, int Ky) {
+  int d = t.jx - c0;
+  if (d > 7) d -= Kx;
+  if (d < -5) d += Kx;
+  const bool nowrap = t.jy <= Ky - 6;
   float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
   for (int ta = 0; ta < 6; ++ta) {
-    int col = t.jx + ta;
-    if (col >= Kx) col -= Kx;
-    const int c = col - c0;
+    const int c = d + ta;
     if ((unsigned)c < (unsigned)tile) {
       float2 sum = make_float2(0.f, 0.f);
+      const float2* gc = g + c * GS;
+      if (nowrap) {
 #pragma unroll
-      for (int tb = 0; tb < 6; ++tb) {
-        int row = t.jy + tb;
-        if (row >= Ky) row -= Ky;
-        sum = cfma(t.wy[tb], g[c * GS + row], sum);
+        for (int tb = 0; tb < 6; ++tb) sum = cfma(t.wy[tb], gc[t.jy + tb], sum);
+      } else {
+#pragma unroll
+        for (int tb = 0; tb < 6; ++tb) {
+          int row = t.jy + tb;
+          if (row >= Ky) row -= Ky;
+          sum = cfma(t.wy[tb], gc[row], sum);
+        }
       }
       acc = cfma(t.wx[ta], sum, acc);
     }
@@ -285,26 +296,9 @@ k_cols_fwd_fs(const float2* __restrict__ mid, int nx, int ny, int Kx, const floa
   const int l = lin % gridDim.y;
   const int c0 = s * tile;
   const bool colok = c < tile;
-  if (colok && t < K2) {
-    float2 v[K1];
-#pragma unroll
-    for (int n1 = 0; n1 < K1; ++n1) {
-      const int iy = img_of_grid(n1 * K2 + t, ny, F::K);
-      v[n1] = iy >= 0 ? mid[((long long)l * ny + iy) * Kx + c0 + c] : make_float2(0.f, 0.f);
-    }
-    reg::dft<K1, false>(v);
-    fs_twiddle<K1, K2, false>(v, t, tw);
-#pragma unroll
-    for (int k1 = 0; k1 < K1; ++k1) lds[c * F::CS + k1 * F::AS + t] = v[k1];
-  }
-  __syncthreads();
+  // the zero-padded column transform (image rows ny = K/2), as in the Toeplitz pass
   float2 u[K2];
-  if (colok) {
-#pragma unroll
-    for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
-    reg::dft<K2, false>(u);
-  }
-  __syncthreads();
+  col_fwd<K1, K2, true, unsigned>(mid + (long long)l * ny * Kx + c0, (unsigned)Kx, ny, colok, tw, lds, u);
   if (colok) {
 #pragma unroll
     for (int k2 = 0; k2 < K2; ++k2) lds[c * F::GS + t + K1 * k2] = u[k2];
@@ -314,6 +308,23 @@ k_cols_fwd_fs(const float2* __restrict__ mid, int nx, int ny, int Kx, const floa
   for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const Taps tp = load_taps(rec, e);
     ypart[(long long)l * E + e] = interp_entry(tp, lds, F::GS, c0, tile, Kx, F::K);
+  }
+}
+
+// Image rows of an inverse column transform (grid rows j = t + K1 k2 of a
+// zero-padded column, image side K/2: rows with P <= k2 < 3P, P = K2/4, are
+// padding) stored into the strip whose column c of row i sits at
+// strip[c + i * rs], as buffer stores at workgroup-uniform row offsets.
+template <int K1, int K2>
+__device__ __forceinline__ void store_image_rows(float2* __restrict__ strip, unsigned rs, int c, int t,
+                                                 const float2 (&u)[K2]) {
+  constexpr int P = K2 / 4;
+  const auto rsrc = buf_rsrc(strip);
+  const unsigned vo = ((unsigned)c + (unsigned)t * rs) * 8u;
+#pragma unroll
+  for (int k2 = 0; k2 < K2; ++k2) {
+    if (k2 < P) buf_st2(rsrc, vo, (unsigned)(K1 * (k2 + P)) * rs * 8u, u[k2]);
+    else if (k2 >= 3 * P) buf_st2(rsrc, vo, (unsigned)(K1 * (k2 - 3 * P)) * rs * 8u, u[k2]);
   }
 }
 
@@ -601,11 +612,7 @@ k_cols_adj_fs(KIn kin, const float* __restrict__ dcf, float scale,
 #pragma unroll
     for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
     reg::dft<K2, true>(u);
-#pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) {
-      const int iy = img_of_grid(t + K1 * k2, ny, F::K);
-      if (iy >= 0) mid[((long long)l * ny + iy) * Kx + c0 + c] = u[k2];
-    }
+    store_image_rows<K1, K2>(mid + (long long)l * ny * Kx + c0, (unsigned)Kx, c, t, u);
   }
 }
 
@@ -669,11 +676,7 @@ k_cols_adj_fin_fs(const float2* __restrict__ spart, int nslots, const int4* __re
 #pragma unroll
     for (int n2 = 0; n2 < K2; ++n2) u[n2] = lds[c * F::CS + t * F::AS + n2];
     reg::dft<K2, true>(u);
-#pragma unroll
-    for (int k2 = 0; k2 < K2; ++k2) {
-      const int iy = img_of_grid(t + K1 * k2, ny, F::K);
-      if (iy >= 0) mid[((long long)l * ny + iy) * Kx + c0 + c] = u[k2];
-    }
+    store_image_rows<K1, K2>(mid + (long long)l * ny * Kx + c0, (unsigned)Kx, c, t, u);
   }
 }
 
