@@ -85,8 +85,14 @@ k3_cols_fwd(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
   float2 u[K2];
   col_fwd<K1, K2, HALF, OFF>(src, (OFF)cs.rs_in, nimg, true, tw, lds, u);
   const OFF rb = (OFF)cs.rs_out * 8u, cb = (OFF)c * 8u + (OFF)t * rb;
+  if constexpr (sizeof(OFF) == 4) {   // buffer stores: row offsets are workgroup-uniform
+    const auto rsrc = buf_rsrc(dst);
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) st_off(dst, cb + (OFF)(K1 * k2) * rb, u[k2]);
+    for (int k2 = 0; k2 < K2; ++k2) buf_st2(rsrc, cb, (unsigned)(K1 * k2) * rb, u[k2]);
+  } else {
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) st_off(dst, cb + (OFF)(K1 * k2) * rb, u[k2]);
+  }
 }
 
 // inverse: all K rows -> image rows (nimg), cropped
@@ -102,8 +108,14 @@ k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
   float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
   const OFF rb = (OFF)cs.rs_in * 8u, cb = (OFF)c * 8u + (OFF)t * rb;
+  if constexpr (sizeof(OFF) == 4) {
+    const auto rsrc = buf_rsrc(src);
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) u[k2] = ld_off(src, cb + (OFF)(K1 * k2) * rb);
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = buf_ld2(rsrc, cb, (unsigned)(K1 * k2) * rb);
+  } else {
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = ld_off(src, cb + (OFF)(K1 * k2) * rb);
+  }
   col_inv<K1, K2, HALF, OFF>(dst, (OFF)cs.rs_out, nimg, true, tw, lds, u);
 }
 
@@ -126,8 +138,14 @@ k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float
   col_fwd<K1, K2, true, OFF>(strip, (OFF)plane, nz, true, tw, lds, u);
   const float* Ts = T + (long long)ky * Kx + c0;
   const OFF tb = (OFF)plane * 4u, cb = (OFF)c * 4u + (OFF)t * tb;
+  if constexpr (sizeof(OFF) == 4) {
+    const auto rsrc = buf_rsrc(Ts);
 #pragma unroll
-  for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, cb + (OFF)(K1 * k2) * tb));
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], buf_ld1(rsrc, cb, (unsigned)(K1 * k2) * tb));
+  } else {
+#pragma unroll
+    for (int k2 = 0; k2 < K2; ++k2) u[k2] = cscale(u[k2], ld_off(Ts, cb + (OFF)(K1 * k2) * tb));
+  }
   col_inv<K1, K2, true, OFF>(strip, (OFF)plane, nz, true, tw, lds, u);
 }
 
