@@ -485,7 +485,17 @@ __global__ void __launch_bounds__(256 * G) k_gemm_tiled(V v) {
 // are those of the generic kernel.  128 pixels per 256-thread workgroup;
 // thread t stages slots 6 (t & 1) .. + 5 of pixel t / 2 (one coordinate
 // decomposition each); wave w computes rows 32 w .. 32 w + 31, all columns.
-__global__ void __launch_bounds__(256) k_conv_first(ConvFwd v) {
+// With fi.u, the input slots are formed here from the complex image and the
+// noise level (Re, Im, sigma, zeros: as the packing pass forms them) instead
+// of read, and the pixel's own slot is also stored to fi.x0 (the packed input
+// the weight gradient of this layer reads).
+struct FirstIn {
+  const float2* u;     // [B][H][W]; nullptr: read the packed input v.in
+  const float* sig;    // [B], or nullptr: sig_c for every image
+  float sig_c;
+  uint16_t* x0;        // [B H W][8] packed input written alongside
+};
+__global__ void __launch_bounds__(256) k_conv_first(ConvFwd v, FirstIn fi) {
   constexpr int TM = 128, LDA = 12 * 8 + 8;     // row stride in BF16 elements (padded)
   __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDA];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[32][LDA];
@@ -498,13 +508,24 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvFwd v) {
     const int m = m0 + r;
     const int px = m % W, py = m < P ? (m / W) % H : -(1 << 20);
     const long long pa = (long long)m * v.in.cs + v.in.co;
+    const float sg = fi.u ? (fi.sig ? fi.sig[m < P ? m / (H * W) : 0] : fi.sig_c) : 0.f;
+    const uint32_t sbf = f2bf(sg);
 #pragma unroll
     for (int jj = 0; jj < 6; ++jj) {
       const int j = j0 + jj;
       const int dy = j < 9 ? j / 3 - 1 : 0, dx = j < 9 ? j % 3 - 1 : 0;
       const int y = py + dy, x = px + dx;
       const bool ok = j < 9 && (unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W;
-      *reinterpret_cast<uint4*>(&As[r][8 * j]) = ld16g(ok ? v.in.p + pa + (long long)(dy * W + dx) * v.in.cs : zrow);
+      uint4 slot;
+      if (fi.u) {   // (uniform)
+        const float2 uv = ok ? fi.u[(long long)m + dy * W + dx] : make_float2(0.f, 0.f);
+        slot = ok ? make_uint4((uint32_t)f2bf(uv.x) | ((uint32_t)f2bf(uv.y) << 16), sbf, 0u, 0u)
+                  : make_uint4(0u, 0u, 0u, 0u);
+        if (j == 4 && m < P) *reinterpret_cast<uint4*>(fi.x0 + (long long)m * 8) = slot;
+      } else {
+        slot = ld16g(ok ? v.in.p + pa + (long long)(dy * W + dx) * v.in.cs : zrow);
+      }
+      *reinterpret_cast<uint4*>(&As[r][8 * j]) = slot;
     }
   }
   {
