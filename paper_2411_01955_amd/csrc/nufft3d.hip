@@ -78,8 +78,12 @@ k3_cols_fwd(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
             const float2* __restrict__ tw) {
   __shared__ float2 lds[8 * FS<K1, K2>::CS];
   const int c = threadIdx.x % 8, t = threadIdx.x / 8;
-  const int a = blockIdx.y / cs.nb, b = blockIdx.y % cs.nb;
-  const int c0 = blockIdx.x * 8;
+  // (set, strip) in XCD order, strip fastest: neighbouring strips -- the two
+  // halves of each 128-byte line of a row -- run back to back on one XCD
+  const int lin = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int set = lin / gridDim.x;
+  const int a = set / cs.nb, b = set % cs.nb;
+  const int c0 = (lin % gridDim.x) * 8;
   const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0;
   float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
@@ -102,8 +106,12 @@ k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
             const float2* __restrict__ tw) {
   __shared__ float2 lds[8 * FS<K1, K2>::CS];
   const int c = threadIdx.x % 8, t = threadIdx.x / 8;
-  const int a = blockIdx.y / cs.nb, b = blockIdx.y % cs.nb;
-  const int c0 = blockIdx.x * 8;
+  // (set, strip) in XCD order, strip fastest: neighbouring strips -- the two
+  // halves of each 128-byte line of a row -- run back to back on one XCD
+  const int lin = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int set = lin / gridDim.x;
+  const int a = set / cs.nb, b = set % cs.nb;
+  const int c0 = (lin % gridDim.x) * 8;
   const float2* src = in + a * cs.in_sa + b * cs.in_sb + c0;
   float2* dst = out + a * cs.out_sa + b * cs.out_sb + c0;
   float2 u[K2];
@@ -120,7 +128,8 @@ k3_cols_inv(const float2* __restrict__ in, float2* __restrict__ out, ColSets cs,
 }
 
 // z pass of the Toeplitz operator, in place on g2: sets (coil l, row ky),
-// visited in XCD order with the coil fastest (T slices shared in L2)
+// visited in XCD order with the coil fastest (T slices shared in L2; an
+// order with neighbouring strips back to back measured 2% slower)
 template <int K1, int K2, typename OFF>
 __global__ void __launch_bounds__(8 * K1)
 k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float2* __restrict__ tw,
