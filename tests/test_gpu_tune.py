@@ -48,6 +48,37 @@ def test_operators_match_oracle_for_every_row_coils(pnp, rc):
     assert max(e_g, e_a) < 2e-5 and e_t < 2e-6
 
 
+@pytest.mark.parametrize("rc", [(4, 4), (2, 8), (8, 4)])
+def test_toeplitz_hqs_with_ragged_coil_groups(pnp, rc):
+    """Toeplitz HQS with 6 coils, whose CG inner products are summed per coil
+    group by the adjoint row pass (three groups of 2, two of 4 with a partial
+    last one, or one partial group of 8), against the oracle's HQS."""
+    import dataclasses
+    from oracle import solver, wavelet
+    w = dataclasses.replace(synth.config_tiny(), L=6, n_out=6)
+    x, _ = synth.phantom2d(w.n, 4)
+    S = synth.smaps2d(w.n, w.L)
+    k = w.traj.k
+    dcf = np.random.default_rng(9).uniform(0.5, 1.5, k.shape[0]).astype(np.float32)
+    nu = synth.noise_variance(x, S)
+    y = (ndft.forward(x, S, k) + synth.complex_noise((w.L, k.shape[0]), nu, synth.SEED_NOISE + 4)).astype(np.complex64)
+    normal = lambda v: ndft.normal(v, S, k, dcf)
+    # the norm only parameterises the problem and is handed to both sides
+    Ln, _ = solver.opnorm(normal, (w.n, w.n), tol=1e-8, maxit=300)
+    sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)
+    lam = 30000.0 / Ln
+    x_ref = solver.hqs(ndft.adjoint(y, S, k, dcf), normal, sig, lam, "f1", w.n_cg,
+                       lambda u, s: wavelet.wavelet_denoise(u, 0.5 * s), Ln)
+    plan = pnp.Plan(to_dev(k), (w.n, w.n))
+    plan.row_coils_pair = rc
+    dd = to_dev(dcf)
+    xg, _ = pnp.hqs_solve(plan, to_dev(y), to_dev(S), dd, pnp.WaveletPrior(0, 0.5), sig, lam, "f1", w.n_cg,
+                          opnorm=Ln, toeplitz=pnp.Toeplitz(plan, dd))
+    e = rel_l2(to_np(xg), x_ref)
+    say(f"[tune] Toeplitz HQS, 6 coils, row_coils={rc}: image rel {e:.3e}")
+    assert e < 1e-4
+
+
 @pytest.fixture(scope="module")
 def clinical_adjoint_ref():
     w = synth.config_clinical()
