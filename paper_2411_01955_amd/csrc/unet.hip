@@ -439,8 +439,10 @@ const LayerInfo& layer(int i) { return layout().L[i]; }
 // tile where Cout <= 32, else 64 x 64 (a transposed convolution: one GEMM
 // per tap, N = Cin + 1); the pixels split into a multiple of 8 slices of
 // whole 128-pixel stages (slices past the end are empty and contribute
-// zeros), about 1024 workgroups and >= 4 stages a slice where the pixels
-// allow.
+// zeros), about 512 workgroups and >= 4 stages a slice where the pixels
+// allow.  (Fewer slices mean fewer partial tiles for k_dw_reduce to read:
+// 10 x 128^2 training step 0.789 ms at 1024 workgroups, 0.776 at 512 and
+// 384, 0.799 at 256.)
 struct DWPlan {
   int tm, tn, mt, nt, taps, M, N, kchunk, splits;
   long long part_floats() const { return (long long)taps * splits * M * N; }
@@ -456,7 +458,7 @@ DWPlan dw_plan(const LayerInfo& l, long long P) {
   d.mt = (int)blocks_for(d.M, d.tm);
   d.nt = (int)blocks_for(d.N, d.tn);
   const long long tiles = (long long)d.mt * d.nt * d.taps;
-  long long sp = std::max<long long>(1, std::min<long long>(P / 512, (1024 + tiles - 1) / tiles));
+  long long sp = std::max<long long>(1, std::min<long long>(P / 512, (512 + tiles - 1) / tiles));
   sp = (sp + 7) / 8 * 8;
   long long kc = (P + sp - 1) / sp;
   kc = (kc + 127) / 128 * 128;
