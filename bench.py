@@ -603,6 +603,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 measurement")
     ap.add_argument("--no-pgd", action="store_true", help="skip the PnP-PGD / FISTA-Wavelet measurement")
+    ap.add_argument("--row-coils", default="",
+                    help="FWD,ADJ coils per row-pass workgroup (2, 4 or 8) instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): slices are independent "
@@ -641,7 +643,14 @@ def main():
     out = torch.empty((n, n), dtype=torch.complex64, device=dev)
     ws, _ = plan.workspace(L, "hqs")
     toep = pnp.Toeplitz(plan, dd)      # transfer function built once per (trajectory, DCF)
-    tuning = plan.autotune(Sd, dd, toeplitz=toep)   # coils per row-pass workgroup, timed on this GPU
+    if args.row_coils:
+        # fixed launch shape (profiling runs: a profiler's per-launch overhead
+        # hides the differences the tuner times)
+        fwd_rc, adj_rc = (int(v) for v in args.row_coils.split(","))
+        plan.row_coils_pair = (fwd_rc, adj_rc)
+        tuning = {"row_coils": adj_rc, "row_coils_fwd": fwd_rc, "fixed": True}
+    else:
+        tuning = plan.autotune(Sd, dd, toeplitz=toep)   # coils per row-pass workgroup, timed on this GPU
 
     def step():
         pnp.hqs_solve(plan, y, Sd, dd, prior, sig, lam, "f1", w.n_cg, opnorm=nrm, out=out, toeplitz=toep)
