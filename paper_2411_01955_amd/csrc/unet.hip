@@ -535,7 +535,10 @@ bool launch_conv_fwd(const pnp_unet* net, int li, Act in, Act out, float* out32,
       out32 == nullptr && (chunks == 1 || chunks == 2 || chunks == 4)) {
     const unsigned patches = (unsigned)(g.B * ((g.H + unet::kHaloPY - 1) / unet::kHaloPY) *
                                         ((g.W + unet::kHaloPX - 1) / unet::kHaloPX));
-    const bool wide = l.cout % 64 == 0 && chunks <= 2;   // 64 output channels a workgroup
+    // 64 output channels a workgroup, unless that leaves fewer than 256
+    // workgroups (single small images: 32, bit-identical; 320^2 forward at
+    // batch 1 161.8 -> 159.3 us)
+    const bool wide = l.cout % 64 == 0 && chunks <= 2 && (long long)patches * (l.cout / 64) >= 256;
     const dim3 grid(patches, l.cout / (wide ? 64 : 32)), block(256 * chunks);
 #define PNP_HALO(CPV, TNV, GV)                                                           \
   if (l.cp == CPV && (wide ? 64 : 32) == TNV && chunks == GV) {                          \
