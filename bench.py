@@ -147,6 +147,9 @@ def kernel_bytes(n, L, M, E, groups):
     # rebuilt from r and the coil-group partial images (read instead of w),
     # and the adjoint row pass also reads r for its per-row sums of Re<part, r>
     out["k_rows_fwd_fs_cgf"] = out["k_rows_fwd_fs_cg"] + 8 * N * (groups - 1)
+    # the first CG step's forward row pass with the CG start fused in: reads
+    # b0 and the partial images of N x besides x, writes u, r, p, s (group 0)
+    out["k_rows_fwd_fs_cgi"] = out["k_rows_fwd_fs"] + 8 * N * (1 + groups + 4)
     out["k_rows_adj_fs_dots"] = out["k_rows_adj_fs"] + 8 * N
     # Haar prior on the last CG update u + alpha (r + beta p): r, p, u in, x out
     out["k_haar_prior_cg"] = 8 * N * 4
@@ -158,16 +161,16 @@ def kernel_bytes(n, L, M, E, groups):
 
 def step_launches(n_out, n_cg, split_strips):
     """Launch counts of one wavelet-HQS solve on the Toeplitz operator (the
-    timed step): per outer iteration the CG start (N x: plain forward row
-    pass) and n_cg CG steps (the first on r0 with a plain row pass, the rest
-    with the CG update fused into it; the row passes of every step also form
-    its inner products, so there is no reduction pass) and the prior on the
-    last update; once per solve b0 = A^H D_w y (gridded adjoint: the spread,
+    timed step): per outer iteration N x (plain forward row pass) and n_cg
+    CG steps (the first with the CG start r0 = gamma (b0 - N x) fused into
+    its forward row pass, the rest with the CG update fused into it; the row
+    passes of every step also form its inner products, so there is no
+    reduction pass) and the prior on the last update; once per solve b0 = A^H D_w y (gridded adjoint: the spread,
     plus the pass that adds split strips' parts when the plan splits any),
     ||y||_w^2, x0 = b0 and the scalar reset."""
-    return {"k_rows_fwd_fs": 2 * n_out, "k_rows_fwd_fs_cgf": (n_cg - 1) * n_out,
+    return {"k_rows_fwd_fs": n_out, "k_rows_fwd_fs_cgi": n_out, "k_rows_fwd_fs_cgf": (n_cg - 1) * n_out,
             "k_cols_toep_fs": (1 + n_cg) * n_out, "k_rows_adj_fs": n_out + 1,
-            "k_rows_adj_fs_dots": n_cg * n_out, "k_cg_init": n_out, "k_haar_prior_cg": n_out,
+            "k_rows_adj_fs_dots": n_cg * n_out, "k_haar_prior_cg": n_out,
             "k_cols_adj_fs": 1, "k_cols_adj_fin_fs": 1 if split_strips else 0, "k_sum_groups": 1,
             "k_wnorm": 1, "k_copy": 1, "k_init_scalars": 1}
 
@@ -720,7 +723,8 @@ def main():
     # CG-fused row passes share their kernels' names)
     counted = {kname: c // args.steps for kname, (c, t) in tr.items()}
     model = dict(launches_model)
-    model["k_rows_fwd_fs"] = model.pop("k_rows_fwd_fs") + model.pop("k_rows_fwd_fs_cgf")
+    model["k_rows_fwd_fs"] = (model.pop("k_rows_fwd_fs") + model.pop("k_rows_fwd_fs_cgi")
+                              + model.pop("k_rows_fwd_fs_cgf"))
     model["k_rows_adj_fs"] = model.pop("k_rows_adj_fs") + model.pop("k_rows_adj_fs_dots")
     launch_check = {k: [model.get(k, 0), counted.get(k, 0)] for k in sorted(set(model) | set(counted))
                     if model.get(k, 0) != counted.get(k, 0)}

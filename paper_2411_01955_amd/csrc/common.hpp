@@ -255,6 +255,11 @@ struct CGUpdate {
   int G;
   long long N;
   float c0, cg;
+  // b0 != nullptr: the CG start instead of a step, r = gamma (b0 - sum_g
+  // part[g N + i]) for the image held in u; stores u2 = u, r2 = r and
+  // p2 = s2 = 0, and the operator is applied to r (r, p, s, w, fin unused)
+  const float2* b0;
+  float gamma;
 };
 struct NormalIn {
   const float2* x;

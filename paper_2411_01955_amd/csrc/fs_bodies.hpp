@@ -109,8 +109,23 @@ __device__ __forceinline__ ImgScal img_scal(const ImgIn& in) {
 // (buffer accesses: the row's base is workgroup-uniform, ix * 8 the thread's offset)
 __device__ __forceinline__ float2 img_at(const ImgIn& in, long long row0, int ix, ImgScal sc, bool store) {
   const unsigned b = (unsigned)ix * 8u;
-  if (!in.cg.r) return buf_ld2(buf_rsrc(in.x + row0), b, 0u);
   const CGUpdate& c = in.cg;
+  if (c.b0) {   // the CG start: r = gamma (b0 - N x) from the previous operator's partial images
+    const auto rp = buf_rsrc(c.part + row0);
+    float2 nv = buf_ld2(rp, b, 0u);
+    for (int g = 1; g < c.G; ++g) nv = cadd(nv, buf_ld2(rp, b, (unsigned)((long long)g * c.N * 8)));
+    const float2 bv = buf_ld2(buf_rsrc(c.b0 + row0), b, 0u);
+    const float2 rv = make_float2(c.gamma * (bv.x - nv.x), c.gamma * (bv.y - nv.y));
+    if (store) {
+      const float2 z = make_float2(0.f, 0.f);
+      buf_st2(buf_rsrc(c.u2 + row0), b, 0u, buf_ld2(buf_rsrc(c.u + row0), b, 0u));
+      buf_st2(buf_rsrc(c.r2 + row0), b, 0u, rv);
+      buf_st2(buf_rsrc(c.p2 + row0), b, 0u, z);
+      buf_st2(buf_rsrc(c.s2 + row0), b, 0u, z);
+    }
+    return rv;
+  }
+  if (!c.r) return buf_ld2(buf_rsrc(in.x + row0), b, 0u);
   const float2 rv = buf_ld2(buf_rsrc(c.r + row0), b, 0u), sv = buf_ld2(buf_rsrc(c.s + row0), b, 0u);
   float2 wv;
   if (c.w) {

@@ -439,9 +439,16 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
   // N x, then the CG start in set 0: u = x, r = gamma (b0 - N x), p = s = 0.
   // Its sums only form rho_k (the CG steps keep their own state), so their
   // finisher runs only when rho is read: by the check or the report.
+  // Without rho the start's vectors are formed by the first CG step's first
+  // pass instead (CGUpdate::b0), with the same arithmetic.
   const bool want_rho = guard || rho_host != nullptr;
+  double start_gamma = 0.0;
   auto cg_start = [&](double gamma, double* rho_out, int restore_bad) {
     normal_parts(p, a.toep, plain_input(x), a.smaps, a.L, a.dcf, w.op, s);
+    if (!want_rho) {
+      start_gamma = gamma;
+      return;
+    }
     PNP_LAUNCH(k_cg_init, dim3(nb), dim3(kRedThreads), 0, s, N, G, x, w.op.part, w.b0, (float)gamma, w.u[0],
                w.r[0], w.p[0], w.s[0], w.parts);
     if (want_rho)
@@ -477,6 +484,18 @@ void hqs_solve(const pnp_plan* p, const HQSArgs& a, void* ws, hipStream_t s, dou
     int c = 0;
     for (int j = 0; j < a.n_cg; ++j) {
       NormalIn in = plain_input(w.r[0]);
+      if (j == 0 && !want_rho) {
+        in.cg.u = x;
+        in.cg.b0 = w.b0;
+        in.cg.gamma = (float)start_gamma;
+        in.cg.part = w.op.part;
+        in.cg.G = G;
+        in.cg.N = N;
+        in.cg.r2 = w.r[0];
+        in.cg.p2 = w.p[0];
+        in.cg.s2 = w.s[0];
+        in.cg.u2 = w.u[0];
+      }
       if (j > 0) {
         in.x = nullptr;
         in.cg = CGUpdate{w.r[c], w.p[c], w.s[c], w.u[c], w.w, w.r[1 - c], w.p[1 - c], w.s[1 - c], w.u[1 - c],
