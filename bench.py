@@ -25,7 +25,7 @@ Printed JSON line:
              kernel against its FP32 VALU issue time (committed SQ counters
              of the same sources, 4 cycles per wave instruction on 1024
              SIMDs at 2.4 GHz) and its FP32 rate against 78.6 TFLOP/s (no
-             packed FP32 instructions in this build);
+             packed FP32 instructions: the library is compiled without them);
 * ``cpu_baseline``  the FP64 oracle (exact NDFT) timed on the host on one
              outer HQS iteration of the same slice (6 normal operators),
              scaled to the same unit;
@@ -80,7 +80,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical.json")
 SQ_FILE = os.path.join(ROOT, "profiles", "sq_clinical.json")
 # FP32 vector issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4
 # cycles; 256 CUs x 4 SIMDs at 2.4 GHz.  Packed FP32 instructions are not
-# generated in this build, so the FP32 peak is 256 x 4 x 16 lanes x 2 (FMA) x
+# generated (the library is compiled without them), so the FP32 peak is 256 x 4 x 16 lanes x 2 (FMA) x
 # 2.4 GHz = 78.6 TFLOP/s, half the packed figure.
 VALU_CYCLES_PER_INST = 4
 SIMDS = 1024
