@@ -448,6 +448,10 @@ def volume_3d(pnp, torch, n_out=None):
 
     B = b_alg_normal(n, L, M, d=3)
     t_op = timed(lambda: toep.normal(xd, Sd, out=out), 5)
+    yt = torch.empty_like(y)
+    t_fwd = timed(lambda: plan.forward(xd, Sd, out=yt), 3)
+    del yt
+    t_adj = timed(lambda: plan.adjoint(y, Sd, dd, out=out), 3)   # b0's gridded adjoint (type-1 spread)
     n_out = n_out or w.n_out
     sig = synth.geometric_sigmas(w.sigma0, w.sigma_end, w.n_out)[:n_out]
     lam = LAM_TIMES_NORM / nrm
@@ -461,6 +465,7 @@ def volume_3d(pnp, torch, n_out=None):
     return {"workload": w.name, "b_alg_bytes_per_normal_op": B, "toeplitz_normal_op_ms": round(t_op * 1e3, 3),
             "toeplitz_normal_op_GBps": round(B / t_op / 1e9, 1),
             "toeplitz_normal_op_frac_of_hbm": round(B / t_op / 1e9 / HBM_PEAK_GBPS, 4),
+            "forward_ms": round(t_fwd * 1e3, 3), "adjoint_ms": round(t_adj * 1e3, 3),
             "hqs_outer": n_out, "hqs_wavelet_s_per_volume": round(t_hqs, 3),
             "hqs_wavelet_GBps": round(n_ops * B / t_hqs / 1e9, 1),
             "hqs_learned_slicewise_s_per_volume": round(t_lrn, 3),

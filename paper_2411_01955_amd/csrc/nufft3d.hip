@@ -208,32 +208,38 @@ __global__ void k3_sort_y(long long M, int L, const float2* __restrict__ y, cons
   ys[idx] = cscale(y[(long long)l * M + m], scale * (dcf ? dcf[m] : 1.f));
 }
 
-// type-1 spread into LDS-resident grid tiles.  The grid is cut into 8^3
-// tiles; tile [t0, t0 + 8)^3 receives from the samples whose first-tap cell
-// lies in [t0 - 5, t0 + 7] on every axis (mod K): 13 x 13 rows of 13 cells,
-// each row a contiguous range of the cell-sorted samples (two where x
+// type-1 spread into grid tiles on the matrix cores.  The grid is cut into
+// 8^3 tiles; tile [t0, t0 + 8)^3 receives from the samples whose first-tap
+// cell lies in [t0 - 5, t0 + 7] on every axis (mod K): 13 x 13 rows of 13
+// cells, each row a contiguous range of the cell-sorted samples (two where x
 // wraps).  One workgroup accumulates one work item -- a tile, or a chunk of
-// a heavy tile's candidates -- for 16 coils in LDS.  Wave w owns the planes
-// z = 2w, 2w + 1 and lane (c, p, q) the points of plane 2w + p on the rows
-// of parity q for coil c, so every (point, coil) has a single owner and
-// sums its candidates in their sorted order: no atomics, a fixed summation
-// order.  Candidates are staged 32 at a time (weights, first-tap offsets
-// relative to the tile, the 16 coil values).  A row update reads its six
-// points, adds, and writes them back with no branch: taps that fall outside
-// the tile go to a per-lane dummy slot.  The tile is then written to the
-// grid in 64-byte row segments, or to its partial slot (heavy tiles), which
-// k3_fold_tiles adds up in slot order.
+// a heavy tile's candidates -- for 16 coils.  The kernel's weight factors
+// over the axes, so a block of 16 tile points (two rows of 8 at one z)
+// receives
+//   G[p][c] += sum_s  wz_s(z - dz_s) wy_s(y_p - dy_s) wx_s(x_p - dx_s) v_s[c]
+// a 16 x S matrix of weight products (0 outside a sample's window) times an
+// S x 16 matrix of the coil values (8 coils as re, im columns): one
+// v_mfma_f32_16x16x4_f32 per four candidates and coil half.  The 32 blocks
+// of the tile are dealt to the four waves diagonally (wave w owns, at each
+// z, the row pair (w - z) mod 4), so the blocks a group of four neighbouring
+// candidates touches spread over all waves; a wave skips, uniformly, the
+// blocks outside the group's window.  Every tile point is summed by one
+// lane in candidate order: no atomics, a fixed summation order.
+// Candidates are staged 32 at a time (weights, first-tap offsets relative to
+// the tile, the 16 coil values).  The tile goes to the grid in 64-byte row
+// segments, or to its partial slot (heavy tiles), which k3_fold_tiles adds up
+// in slot order.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kT3C = 16;                 // coils per workgroup
 constexpr int kT3S = 32;                 // staged candidates
 constexpr int kT3Rows = 13 * 13;         // candidate rows per tile
 struct alignas(16) Spread3Lds {
-  float2 acc[512 * kT3C];                // [z][y][x][c]
-  float2 dummy[256];                     // per-lane sink of out-of-tile taps
   int rb0[kT3Rows], rc0[kT3Rows], rb1[kT3Rows];   // row: first range start / size, second range start
   int pre[256];                          // inclusive candidate counts up to each row (scan)
   alignas(16) float w[kT3S][20];         // x, y, z weights of the staged candidates (rows padded to 16 B)
   alignas(16) int d[kT3S][4];            // first tap relative to the tile (x, y, z), sorted index or -1
   float2 v[kT3S][kT3C];
+  float out[4][16][33];                  // per wave: one finished block, [point][coil column]
 };
 
 __global__ void __launch_bounds__(256)
@@ -248,7 +254,6 @@ k3_spread_tiles(const float2* __restrict__ ys, int L, const int32_t* __restrict_
   const int ntx = Kx / 8, nty = Ky / 8;
   const int t0x = (it.x % ntx) * 8, t0y = ((it.x / ntx) % nty) * 8, t0z = (it.x / (ntx * nty)) * 8;
   const int tid = threadIdx.x;
-  for (int i = tid; i < 512 * kT3C; i += 256) S.acc[i] = make_float2(0.f, 0.f);
   // candidate rows (dz, dy) = (r / 13 - 5, r % 13 - 5), their sorted ranges
   // and the inclusive scan of their sizes (Hillis-Steele over 256 entries)
   int cnt = 0;
@@ -279,15 +284,17 @@ k3_spread_tiles(const float2* __restrict__ ys, int L, const int32_t* __restrict_
     __syncthreads();
   }
 
-  const int lane = tid & 63, wv = tid >> 6;
-  const int c = lane & 15, z = 2 * wv + ((lane >> 4) & 1), q = lane >> 5;
-  float2* const sink = S.dummy + tid;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i16 = lane & 15, k4 = lane >> 4;   // MFMA: A row / B column i16, candidate k4 of a group
+  const int px = i16 & 7, py = i16 >> 3;       // A row i16 = point (row pair + py, px) of a block
   // Staging of a round of 32 candidates: candidate s = tid / 8 is located
   // by the 8 threads (s, j) (the row with pre[r - 1] <= k < pre[r], binary
   // search), which load its 9 weight pairs and 16 coil values (item
   // j + 8 m of 25) into registers; the registers of the next round are
   // loaded while the current round is accumulated, and stored to LDS
-  // between the two barriers that end it.
+  // between the two barriers that end it.  Slots past the item's end hold
+  // zero weights and values.
   const int ss = tid >> 3, sj = tid & 7;
   int4 nd = make_int4(0, 0, 0, -1);
   float2 nv[4];
@@ -330,6 +337,10 @@ k3_spread_tiles(const float2* __restrict__ ys, int L, const int32_t* __restrict_
       else if (e < 25) S.v[ss][e - 9] = nv[m];
     }
   };
+  // acc[z][h]: the wave's block at plane z, coils 8h .. 8h + 7
+  f32x4 acc[8][2];
+#pragma unroll
+  for (int z = 0; z < 8; ++z) acc[z][0] = acc[z][1] = f32x4{0.f, 0.f, 0.f, 0.f};
   if (it.y < it.z) {
     fetch(it.y);
     store();
@@ -339,56 +350,70 @@ k3_spread_tiles(const float2* __restrict__ ys, int L, const int32_t* __restrict_
     const bool more = k0 + kT3S < it.z;
     if (more) fetch(k0 + kT3S);
     const int ns = min(kT3S, it.z - k0);
-    for (int s = 0; s < ns; ++s) {
+    for (int g = 0; g < ns; g += 4) {
+      const int s = g + k4;
       const int4 dd = *reinterpret_cast<const int4*>(S.d[s]);
-      const int tz = z - dd.z;
-      if (tz < 0 || tz >= 6) continue;
-      const float wz = S.w[s][12 + tz];
-      const float4* w4 = reinterpret_cast<const float4*>(S.w[s]);
-      const float4 wa = w4[0], wb = w4[1];
-      const float wxs[6] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y};
-      const float2 v = S.v[s][c];
-      float2 u[6];
-      float2* pt[6];
+      // the group's window on z and y, clipped to the tile (wave-uniform)
+      const int z0 = __builtin_amdgcn_readlane(dd.z, 0), z1 = __builtin_amdgcn_readlane(dd.z, 16);
+      const int z2 = __builtin_amdgcn_readlane(dd.z, 32), z3 = __builtin_amdgcn_readlane(dd.z, 48);
+      const int y0 = __builtin_amdgcn_readlane(dd.y, 0), y1 = __builtin_amdgcn_readlane(dd.y, 16);
+      const int y2 = __builtin_amdgcn_readlane(dd.y, 32), y3 = __builtin_amdgcn_readlane(dd.y, 48);
+      const int zlo = min(min(z0, z1), min(z2, z3)), zhi = max(max(z0, z1), max(z2, z3)) + 6;
+      const int ylo = min(min(y0, y1), min(y2, y3)), yhi = max(max(y0, y1), max(y2, y3)) + 6;
+      const float* ws = S.w[s];
+      const int tx = px - dd.x;
+      const float wx = ws[(unsigned)tx < 6u ? tx : 0];
+      const float wxv = (unsigned)tx < 6u ? wx : 0.f;
+      const float* vs = reinterpret_cast<const float*>(S.v[s]);
+      const float b0 = vs[i16], b1 = vs[16 + i16];
 #pragma unroll
-      for (int tx = 0; tx < 6; ++tx) u[tx] = make_float2(wxs[tx] * v.x, wxs[tx] * v.y);
-      const int ylo = max(dd.y, 0), yhi = min(dd.y + 6, 8);
-      for (int y = ylo + ((q - ylo) & 1); y < yhi; y += 2) {
-        const float f = wz * S.w[s][6 + y - dd.y];
-        float2* rowp = S.acc + ((z * 8 + y) * 8) * kT3C + c;
-        float2 a[6];
-#pragma unroll
-        for (int tx = 0; tx < 6; ++tx) {
-          const int x = dd.x + tx;
-          pt[tx] = (x >= 0 && x < 8) ? rowp + x * kT3C : sink;
-          a[tx] = *pt[tx];
-        }
-#pragma unroll
-        for (int tx = 0; tx < 6; ++tx) {
-          a[tx].x = fmaf(f, u[tx].x, a[tx].x);
-          a[tx].y = fmaf(f, u[tx].y, a[tx].y);
-        }
-#pragma unroll
-        for (int tx = 0; tx < 6; ++tx) *pt[tx] = a[tx];
+      for (int z = 0; z < 8; ++z) {
+        const int yp = (wv - z) & 3;
+        if (z < zlo || z >= zhi || 2 * yp + 1 < ylo || 2 * yp >= yhi) continue;
+        const int tz = z - dd.z, ty = 2 * yp + py - dd.y;
+        const float wz = ws[12 + ((unsigned)tz < 6u ? tz : 0)];
+        const float wy = ws[6 + ((unsigned)ty < 6u ? ty : 0)];
+        const float a = ((unsigned)tz < 6u && (unsigned)ty < 6u) ? wz * wy * wxv : 0.f;
+        acc[z][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[z][0], 0, 0, 0);
+        acc[z][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[z][1], 0, 0, 0);
       }
     }
     __syncthreads();
     if (more) store();
     __syncthreads();
   }
-  // write the tile: thread -> (z, y, x, coil) with the coil fastest (LDS
-  // reads without bank conflicts; 4 x 8 B contiguous per coil in a store)
+  // write the tile block by block: the wave's block goes through its LDS
+  // slot (tile element (4 k4 + r, i16) = point 4 k4 + r, coil column i16 of
+  // half h), then each lane writes 4 points (32 B) of one coil row, a pair
+  // of lanes one 64-byte row segment
   const long long plane = (long long)Ky * Kx, vol = plane * Kz;
-  for (int e = tid; e < 512 * kT3C; e += 256) {
-    const int cc = e % kT3C, pt = e / kT3C;
-    const int x = pt & 7, y = (pt >> 3) & 7, zz = pt >> 6;
-    const int l = l0 + cc;
-    if (l >= L) continue;
-    const float2 val = S.acc[e];
-    if (it.w < 0)
-      grid[(long long)l * vol + (long long)(t0z + zz) * plane + (long long)(t0y + y) * Kx + t0x + x] = val;
-    else
-      partial[((long long)it.w * L + l) * 512 + pt] = val;
+  const int cc = lane >> 2, yy = (lane >> 1) & 1, xh = (lane & 1) * 4;
+  const int col = (cc >> 3) * 16 + (cc & 7) * 2;
+  float (*ob)[33] = S.out[wv];
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    const int yp = (wv - z) & 3;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ob[4 * k4 + r][16 * h + i16] = acc[z][h][r];
+    __syncthreads();
+    if (l0 + cc < L) {
+      float4 q[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int pa = yy * 8 + xh + 2 * u;
+        q[u] = make_float4(ob[pa][col], ob[pa][col + 1], ob[pa + 1][col], ob[pa + 1][col + 1]);
+      }
+      const int y = 2 * yp + yy;
+      float4* dst = it.w < 0
+          ? reinterpret_cast<float4*>(grid + (long long)(l0 + cc) * vol + (long long)(t0z + z) * plane +
+                                      (long long)(t0y + y) * Kx + t0x + xh)
+          : reinterpret_cast<float4*>(partial + ((long long)it.w * L + l0 + cc) * 512 + z * 64 + y * 8 + xh);
+      dst[0] = q[0];
+      dst[1] = q[1];
+    }
+    __syncthreads();
   }
 }
 
