@@ -134,6 +134,11 @@ struct pnp_plan {
   int4* sp_items;
   int4* sp_folds;
   int n_sp_items, n_sp_folds, sp_slots;
+  // 3D interpolation work list: items (tile, first, end, 0) over the
+  // samples whose first-tap cell lies in the tile (its home samples, listed
+  // row by row), in tile order, at most kInterpChunk3 samples an item
+  int4* ip_items;
+  int n_ip_items;
   // 2D adjoint spread work items (strip, part, parts, first slot or -1),
   // heaviest first, and the split strips (strip, first slot, parts, 0);
   // built from the per-(strip, row block) window entry counts adj_cost for
@@ -145,7 +150,7 @@ struct pnp_plan {
   std::vector<int32_t> adj_cost;   // host [ntx][K_y / 8]
   void* block;
   size_t block_bytes;
-  void* block3;             // 3D: the spread work list
+  void* block3;             // 3D: the spread and interpolation work lists
 };
 
 struct pnp_unet;

@@ -158,42 +158,113 @@ k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float
   col_inv<K1, K2, true, OFF>(strip, (OFF)plane, nz, true, tw, lds, u);
 }
 
-// type-2 interpolation: y[l][m] = scale * sum of the 6^3 taps of grid[l]
+// type-2 interpolation from grid regions staged in LDS:
+// y[l][m] = scale * (sum of the 6^3 taps of grid[l] around sample m).  A
+// work item is a chunk of one 8^3 tile's home samples (first-tap cell in
+// [t0, t0 + 8)^3), whose taps all lie in the 13^3 region [t0, t0 + 13)^3
+// (mod K).  The workgroup stages that region for 4 coils in LDS
+// ([z][y][x][coil], 70 KB; each point read once from the grid instead of
+// once per tap), then lane (s, c) sums sample s's taps for coil c from LDS
+// in the order of a direct gather: x fastest, then y, then z.
+constexpr int kI3C = 4;                  // coils per workgroup
+constexpr int kI3R = 13;                 // staged region side: tile + kernel width - 1
+constexpr int kI3Lds = kI3R * kI3R * kI3R * kI3C * (int)sizeof(float2);
+
 __global__ void __launch_bounds__(256)
-k3_interp(const float2* __restrict__ grid, int Kx, int Ky, int Kz, long long M, const int4* __restrict__ j0,
-          const float* __restrict__ wts, float scale, float2* __restrict__ y) {
-  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  const int l = blockIdx.y;
-  const int4 j = j0[m];
-  float w[3][6];
+k3_interp_tiles(const float2* __restrict__ grid, int L, int Kx, int Ky, int Kz, long long M,
+                const int32_t* __restrict__ cell_off, const int32_t* __restrict__ sorted_m,
+                const int32_t* __restrict__ sjx, const float* __restrict__ sw, const int4* __restrict__ items,
+                int nitems, float scale, float2* __restrict__ y) {
+  extern __shared__ float4 lds_raw[];
+  float2* const R = reinterpret_cast<float2*>(lds_raw);
+  __shared__ int rbeg[64], rpre[64];
+  // one workgroup per (item, coil group); each XCD takes a contiguous range
+  // of items of one coil group, whose staged regions overlap in its L2
+  const int lin = xcd_order(blockIdx.x, gridDim.x);
+  const int4 it = items[lin % nitems];
+  const int l0 = (lin / nitems) * kI3C;
+  const int ntx = Kx / 8, nty = Ky / 8;
+  const int t0x = (it.x % ntx) * 8, t0y = ((it.x / ntx) % nty) * 8, t0z = (it.x / (ntx * nty)) * 8;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {  // wave 0: the tile's 64 (z, y) rows, their sorted ranges and inclusive counts
+    const long long row = ((long long)(t0z + (tid >> 3)) * Ky + t0y + (tid & 7)) * Kx + t0x;
+    const int b = cell_off[row];
+    int v = cell_off[row + 8] - b;
+    rbeg[tid] = b;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int t = 0; t < 6; ++t) w[a][t] = wts[(m * 3 + a) * 6 + t];
-  const float2* g = grid + (long long)l * Kz * Ky * Kx;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int tz = 0; tz < 6; ++tz) {
-    int z = j.z + tz;
-    if (z >= Kz) z -= Kz;
-    float2 az = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int ty = 0; ty < 6; ++ty) {
-      int yy = j.y + ty;
-      if (yy >= Ky) yy -= Ky;
-      const float2* row = g + ((long long)z * Ky + yy) * Kx;
-      float2 ay = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int tx = 0; tx < 6; ++tx) {
-        int x = j.x + tx;
-        if (x >= Kx) x -= Kx;
-        ay = cfma(w[0][tx], row[x], ay);
-      }
-      az = cfma(w[1][ty], ay, az);
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (lane >= o) v += u;
     }
-    acc = cfma(w[2][tz], az, acc);
+    rpre[tid] = v;
   }
-  y[(long long)l * M + m] = cscale(acc, scale);
+  // stage the region: lane x (13 of 16 used) of region row (z, y, coil)
+  // loads one point, in batches of 11 rows whose loads are all issued
+  // before their stores; coordinates wrap mod K
+  const long long vol = (long long)Kz * Ky * Kx;
+  {
+    constexpr int kRows = kI3R * kI3R * kI3C, kB = 11, kIt = (kRows + 16 * kB - 1) / (16 * kB);
+    const int x = tid & 15;
+    int gx = t0x + x;
+    if (gx >= Kx) gx -= Kx;
+#pragma unroll 1
+    for (int b = 0; b < kIt; ++b) {
+      float2 v[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int r = (tid >> 4) + 16 * (b * kB + u);
+        const int c = r % kI3C, yz = r / kI3C, yy = yz % kI3R, zz = yz / kI3R;
+        v[u] = make_float2(0.f, 0.f);
+        if (x < kI3R && r < kRows && l0 + c < L) {
+          int gy = t0y + yy, gz = t0z + zz;
+          if (gy >= Ky) gy -= Ky;
+          if (gz >= Kz) gz -= Kz;
+          v[u] = grid[(long long)(l0 + c) * vol + ((long long)gz * Ky + gy) * Kx + gx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int r = (tid >> 4) + 16 * (b * kB + u);
+        const int c = r % kI3C, yz = r / kI3C, yy = yz % kI3R, zz = yz / kI3R;
+        if (x < kI3R && r < kRows) R[((zz * kI3R + yy) * kI3R + x) * kI3C + c] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int c = tid % kI3C;
+  for (int k = it.y + tid / kI3C; k < it.z; k += 256 / kI3C) {
+    int lo = 0, hi = 63;                   // the row with rpre[r - 1] <= k < rpre[r]
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (rpre[mid] > k) hi = mid;
+      else lo = mid + 1;
+    }
+    const int i = rbeg[lo] + k - (lo > 0 ? rpre[lo - 1] : 0);
+    const int dz = lo >> 3, dy = lo & 7, dx = sjx[i] - t0x;
+    float w[3][6];
+    const float2* wp = reinterpret_cast<const float2*>(sw + (long long)i * 18);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      const float2 q = wp[e];
+      w[(2 * e) / 6][(2 * e) % 6] = q.x;
+      w[(2 * e + 1) / 6][(2 * e + 1) % 6] = q.y;
+    }
+    const float2* base = R + ((dz * kI3R + dy) * kI3R + dx) * kI3C + c;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int tz = 0; tz < 6; ++tz) {
+      float2 az = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int ty = 0; ty < 6; ++ty) {
+        const float2* row = base + (tz * kI3R + ty) * kI3R * kI3C;
+        float2 ay = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int tx = 0; tx < 6; ++tx) ay = cfma(w[0][tx], row[tx * kI3C], ay);
+        az = cfma(w[1][ty], ay, az);
+      }
+      acc = cfma(w[2][tz], az, acc);
+    }
+    if (l0 + c < L) y[(long long)(l0 + c) * M + sorted_m[i]] = cscale(acc, scale);
+  }
 }
 
 // k-space values in the plan's sorted sample order, coils contiguous:
@@ -627,13 +698,23 @@ OpWorkspace op3_workspace(const pnp_plan* p, int L, void* ws) {
   return w;
 }
 
+// the oversampled coil grids -> k-space (every sample is the home sample of one tile item)
+static void interp3(const pnp_plan* p, const Dims& d, int L, const float2* grid, float scale, float2* y,
+                    hipStream_t s) {
+  if (p->n_ip_items == 0) return;
+  PNP_HIP(hipFuncSetAttribute((const void*)k3_interp_tiles, hipFuncAttributeMaxDynamicSharedMemorySize, kI3Lds));
+  const long long nb = (long long)p->n_ip_items * ((L + kI3C - 1) / kI3C);
+  if (nb >= (1ll << 31)) fail(PNP_ERR_SHAPE, "3D interpolation work list too long");
+  PNP_LAUNCH(k3_interp_tiles, dim3((unsigned)nb), dim3(256), kI3Lds, s, grid, L, d.Kx, d.Ky, d.Kz, (long long)p->M,
+             p->cell_off, p->sorted_m, p->sorted_jx, p->sorted_w, p->ip_items, p->n_ip_items, scale, y);
+}
+
 void op3_forward(const pnp_plan* p, const float2* x, const float2* smaps, int L, float2* y, const OpWorkspace& w,
                  hipStream_t s) {
   need3(p);
   const Dims d = dims_of(p);
   passes_fwd(p, d, ImgIn{x, CGUpdate{}}, smaps, L, p->ax[0].deapod, p->deapod_yz, w.mid, w.g2, w.grid, s);
-  PNP_LAUNCH(k3_interp, dim3((unsigned)((p->M + 255) / 256), L), dim3(256), 0, s, w.grid, d.Kx, d.Ky, d.Kz,
-             (long long)p->M, p->j0, p->wts, (float)(1.0 / std::sqrt((double)d.N)), y);
+  interp3(p, d, L, w.grid, (float)(1.0 / std::sqrt((double)d.N)), y, s);
 }
 
 // k-space y (or w.ytmp) -> coil-group partials in `dst`
@@ -667,8 +748,7 @@ void op3_normal_parts(const pnp_plan* p, const NormalIn& in, const float2* smaps
   need3(p);
   const Dims d = dims_of(p);
   passes_fwd(p, d, ImgIn{in.x, in.cg}, smaps, L, p->ax[0].deapod, p->deapod_yz, w.mid, w.g2, w.grid, s);
-  PNP_LAUNCH(k3_interp, dim3((unsigned)((p->M + 255) / 256), L), dim3(256), 0, s, w.grid, d.Kx, d.Ky, d.Kz,
-             (long long)p->M, p->j0, p->wts, 1.0f, w.ytmp);
+  interp3(p, d, L, w.grid, 1.0f, w.ytmp, s);
   adjoint_parts3(p, w.ytmp, smaps, L, dcf, (float)(1.0 / (double)d.N), w.part, w, s);
 }
 

@@ -414,9 +414,30 @@ __global__ void k3_tile_cands(const int32_t* __restrict__ cell_off, int Kx, int 
   cnt[t] = (int32_t)c;
 }
 
+// Home samples of every 8^3 grid tile for the tiled 3D interpolation: the
+// samples whose first-tap cell lies in the tile, 8 x 8 row ranges.
+__global__ void k3_tile_home(const int32_t* __restrict__ cell_off, int Kx, int Ky, int Kz,
+                             int32_t* __restrict__ cnt) {
+  const int ntx = Kx / 8, nty = Ky / 8, ntz = Kz / 8;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntx * nty * ntz) return;
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  int c = 0;
+  for (int rz = 0; rz < 8; ++rz)
+    for (int ry = 0; ry < 8; ++ry) {
+      const long long row = ((long long)(tz * 8 + rz) * Ky + ty * 8 + ry) * Kx + tx * 8;
+      c += cell_off[row + 8] - cell_off[row];
+    }
+  cnt[t] = c;
+}
+
 // Work list of the tiled 3D spread: one item per tile, tiles with more than
 // kSpreadChunk3 candidates split into several items with partial slots.
+// Work list of the tiled 3D interpolation: tiles with home samples in tile
+// order (neighbouring tiles, whose staged regions overlap, run together),
+// split into items of at most kInterpChunk3 samples.
 static constexpr int kSpreadChunk3 = 2048;
+static constexpr int kInterpChunk3 = 512;
 
 static void build_spread3(pnp_plan* p, hipStream_t stream) {
   const int Kx = p->ax[0].K, Ky = p->ax[1].K, Kz = p->ax[2].K;
@@ -428,12 +449,18 @@ static void build_spread3(pnp_plan* p, hipStream_t stream) {
     int32_t*& q;
     ~Free() { if (q) (void)hipFree(q); }
   } fr{dcnt};
-  PNP_HIP(hipMalloc((void**)&dcnt, sizeof(int32_t) * nt));
+  PNP_HIP(hipMalloc((void**)&dcnt, 2 * sizeof(int32_t) * nt));
   k3_tile_cands<<<(nt + 255) / 256, 256, 0, stream>>>(p->cell_off, Kx, Ky, Kz, dcnt);
   PNP_CHECK_LAUNCH();
-  std::vector<int32_t> cnt(nt);
+  k3_tile_home<<<(nt + 255) / 256, 256, 0, stream>>>(p->cell_off, Kx, Ky, Kz, dcnt + nt);
+  PNP_CHECK_LAUNCH();
+  std::vector<int32_t> cnt(nt), home(nt);
   PNP_HIP(hipMemcpyAsync(cnt.data(), dcnt, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, stream));
+  PNP_HIP(hipMemcpyAsync(home.data(), dcnt + nt, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, stream));
   PNP_HIP(hipStreamSynchronize(stream));
+  std::vector<int4> ipi;
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < home[t]; k += kInterpChunk3) ipi.push_back(make_int4(t, k, std::min(home[t], k + kInterpChunk3), 0));
   std::vector<int> order(nt);
   for (int t = 0; t < nt; ++t) order[t] = t;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
@@ -456,9 +483,14 @@ static void build_spread3(pnp_plan* p, hipStream_t stream) {
   // candidates but the last)
   std::stable_sort(items.begin(), items.end(), [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
   const size_t bi = align256(sizeof(int4) * items.size()), bf = align256(sizeof(int4) * std::max<size_t>(1, folds.size()));
-  PNP_HIP(hipMalloc(&p->block3, bi + bf));
+  const size_t bp = align256(sizeof(int4) * std::max<size_t>(1, ipi.size()));
+  PNP_HIP(hipMalloc(&p->block3, bi + bf + bp));
   p->sp_items = (int4*)p->block3;
   p->sp_folds = (int4*)((char*)p->block3 + bi);
+  p->ip_items = (int4*)((char*)p->block3 + bi + bf);
+  p->n_ip_items = (int)ipi.size();
+  if (!ipi.empty())
+    PNP_HIP(hipMemcpyAsync(p->ip_items, ipi.data(), sizeof(int4) * ipi.size(), hipMemcpyHostToDevice, stream));
   p->n_sp_items = (int)items.size();
   p->n_sp_folds = (int)folds.size();
   p->sp_slots = slots;
