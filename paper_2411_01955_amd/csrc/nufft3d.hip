@@ -162,11 +162,14 @@ k3_cols_toep(float2* __restrict__ g2, int L, int nz, int Ky, int Kx, const float
 // y[l][m] = scale * (sum of the 6^3 taps of grid[l] around sample m).  A
 // work item is a chunk of one 8^3 tile's home samples (first-tap cell in
 // [t0, t0 + 8)^3), whose taps all lie in the 13^3 region [t0, t0 + 13)^3
-// (mod K).  The workgroup stages that region for 4 coils in LDS
-// ([z][y][x][coil], 70 KB; each point read once from the grid instead of
+// (mod K).  The workgroup stages that region for 2 coils in LDS
+// ([z][y][x][coil], 35 KB; each point read once from the grid instead of
 // once per tap), then lane (s, c) sums sample s's taps for coil c from LDS
-// in the order of a direct gather: x fastest, then y, then z.
-constexpr int kI3C = 4;                  // coils per workgroup
+// in the order of a direct gather: x fastest, then y, then z.  Two coils a
+// workgroup keep four workgroups per CU staging at once (128^3 x 32 coils:
+// 1, 2 and 4 coils per workgroup measured 6.40, 6.12 and 6.93 ms per
+// forward operator).
+constexpr int kI3C = 2;                  // coils per workgroup
 constexpr int kI3R = 13;                 // staged region side: tile + kernel width - 1
 constexpr int kI3Lds = kI3R * kI3R * kI3R * kI3C * (int)sizeof(float2);
 
