@@ -299,13 +299,14 @@ __global__ void k3_sort_y(long long M, int L, const float2* __restrict__ y, cons
 // candidates touches spread over all waves; a wave skips, uniformly, the
 // blocks outside the group's window.  Every tile point is summed by one
 // lane in candidate order: no atomics, a fixed summation order.
-// Candidates are staged 32 at a time (weights, first-tap offsets relative to
-// the tile, the 16 coil values).  The tile goes to the grid in 64-byte row
+// Candidates are staged kT3S at a time (weights, first-tap offsets relative
+// to the tile, the 16 coil values).  The tile goes to the grid in 64-byte row
 // segments, or to its partial slot (heavy tiles), which k3_fold_tiles adds up
 // in slot order.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kT3C = 16;                 // coils per workgroup
-constexpr int kT3S = 32;                 // staged candidates
+constexpr int kT3S = 32;                 // staged candidates (a multiple of 32)
+constexpr int kT3F = kT3S / 32;          // candidates per staging group of 8 threads
 constexpr int kT3Rows = 13 * 13;         // candidate rows per tile
 struct alignas(16) Spread3Lds {
   int rb0[kT3Rows], rc0[kT3Rows], rb1[kT3Rows];   // row: first range start / size, second range start
@@ -362,53 +363,60 @@ k3_spread_tiles(const float2* __restrict__ ys, int L, const int32_t* __restrict_
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i16 = lane & 15, k4 = lane >> 4;   // MFMA: A row / B column i16, candidate k4 of a group
   const int px = i16 & 7, py = i16 >> 3;       // A row i16 = point (row pair + py, px) of a block
-  // Staging of a round of 32 candidates: candidate s = tid / 8 is located
-  // by the 8 threads (s, j) (the row with pre[r - 1] <= k < pre[r], binary
-  // search), which load its 9 weight pairs and 16 coil values (item
-  // j + 8 m of 25) into registers; the registers of the next round are
+  // Staging of a round of kT3S candidates: candidate s = tid / 8 + 32 f is
+  // located by the 8 threads (s mod 32, j) (the row with pre[r - 1] <= k <
+  // pre[r], binary search), which load its 9 weight pairs and 16 coil values
+  // (item j + 8 m of 25) into registers; the registers of the next round are
   // loaded while the current round is accumulated, and stored to LDS
   // between the two barriers that end it.  Slots past the item's end hold
   // zero weights and values.
   const int ss = tid >> 3, sj = tid & 7;
-  int4 nd = make_int4(0, 0, 0, -1);
-  float2 nv[4];
+  int4 nd[kT3F];
+  float2 nv[kT3F][4];
   auto fetch = [&](int kb) {
-    const int k = kb + ss;
-    nd = make_int4(0, 0, 0, -1);
-    if (k < it.z) {
-      int lo = 0, hi = kT3Rows - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (S.pre[mid] > k) hi = mid;
-        else lo = mid + 1;
-      }
-      const int o = k - (lo > 0 ? S.pre[lo - 1] : 0);
-      const int i = o < S.rc0[lo] ? S.rb0[lo] + o : S.rb1[lo] + (o - S.rc0[lo]);
-      nd = make_int4(0, lo % 13 - 5, lo / 13 - 5, i);
-      if (sj == 0) {
-        int ddx = sjx[i] - t0x;
-        if (ddx > 7) ddx -= Kx;
-        nd.x = ddx;
-      }
-    }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int e = sj + 8 * m;
-      float2 val = make_float2(0.f, 0.f);
-      if (nd.w >= 0 && e < 25) {
-        if (e < 9) val = reinterpret_cast<const float2*>(sw + (long long)nd.w * 18)[e];
-        else if (l0 + e - 9 < L) val = ys[(long long)nd.w * L + l0 + e - 9];
+    for (int f = 0; f < kT3F; ++f) {
+      const int k = kb + ss + 32 * f;
+      nd[f] = make_int4(0, 0, 0, -1);
+      if (k < it.z) {
+        int lo = 0, hi = kT3Rows - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (S.pre[mid] > k) hi = mid;
+          else lo = mid + 1;
+        }
+        const int o = k - (lo > 0 ? S.pre[lo - 1] : 0);
+        const int i = o < S.rc0[lo] ? S.rb0[lo] + o : S.rb1[lo] + (o - S.rc0[lo]);
+        nd[f] = make_int4(0, lo % 13 - 5, lo / 13 - 5, i);
+        if (sj == 0) {
+          int ddx = sjx[i] - t0x;
+          if (ddx > 7) ddx -= Kx;
+          nd[f].x = ddx;
+        }
       }
-      nv[m] = val;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int e = sj + 8 * m;
+        float2 val = make_float2(0.f, 0.f);
+        if (nd[f].w >= 0 && e < 25) {
+          if (e < 9) val = reinterpret_cast<const float2*>(sw + (long long)nd[f].w * 18)[e];
+          else if (l0 + e - 9 < L) val = ys[(long long)nd[f].w * L + l0 + e - 9];
+        }
+        nv[f][m] = val;
+      }
     }
   };
   auto store = [&]() {
-    if (sj == 0) *reinterpret_cast<int4*>(S.d[ss]) = nd;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int e = sj + 8 * m;
-      if (e < 9) reinterpret_cast<float2*>(S.w[ss])[e] = nv[m];
-      else if (e < 25) S.v[ss][e - 9] = nv[m];
+    for (int f = 0; f < kT3F; ++f) {
+      const int slot = ss + 32 * f;
+      if (sj == 0) *reinterpret_cast<int4*>(S.d[slot]) = nd[f];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int e = sj + 8 * m;
+        if (e < 9) reinterpret_cast<float2*>(S.w[slot])[e] = nv[f][m];
+        else if (e < 25) S.v[slot][e - 9] = nv[f][m];
+      }
     }
   };
   // acc[z][h]: the wave's block at plane z, coils 8h .. 8h + 7
